@@ -1,0 +1,186 @@
+"""Pins of the oracle's RKL tau-step and spectral rules (App. A)."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.special import eval_legendre, j0
+
+from oracle import exact
+from oracle import operators as op
+from oracle import rkl
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+
+
+def test_coefficients_sum_and_scaling():
+    for s in range(1, 12):
+        w1 = 2.0 / (s * s + s)
+        c = rkl.rkl_coefficients(s)
+        assert len(c) == s
+        assert c[0][0] == 1.0 and c[0][1] == 0.0
+        for j, (mu, nu, mut) in enumerate(c, start=1):
+            assert abs(mu + nu - 1.0) < 1e-15
+            assert abs(mut - mu * w1) < 1e-16
+
+
+def test_s1_theta1_is_one_jacobi_sweep_bruteforce():
+    """s = 1 at tau = tau_max is u <- (sum of six neighbours - h^2 b)/6 (cubic
+    cells), written here cell by cell with explicit periodic index wrapping."""
+    rng = np.random.default_rng(3)
+    n = 4
+    h = 0.25
+    u = rng.standard_normal((n, n, n))
+    b = rng.standard_normal((n, n, n))
+    lv = op.Level(0, (n, n, n), (h, h, h), "periodic")
+    got = rkl.tau_step(u, b, 1, 1.0, lv)
+    want = np.empty_like(u)
+    for k in range(n):
+        for j in range(n):
+            for i in range(n):
+                s = (u[k, j, (i - 1) % n] + u[k, j, (i + 1) % n] + u[k, (j - 1) % n, i]
+                     + u[k, (j + 1) % n, i] + u[(k - 1) % n, j, i] + u[(k + 1) % n, j, i])
+                want[k, j, i] = (s - h * h * b[k, j, i]) / 6.0
+    np.testing.assert_allclose(got, want, atol=1e-13)
+
+
+@pytest.mark.parametrize("s,theta", [(1, 0.9), (2, 0.9), (3, 1.0), (5, 0.7), (8, 0.95)])
+@pytest.mark.parametrize("m", [(1, 1, 1), (2, 5, 3), (8, 8, 8)])
+def test_tau_step_damps_dst_mode_by_legendre(s, theta, m):
+    """With b = 0 one tau-step multiplies an eigenmode of M by
+    R_s = P_s(1 + w1 tau lambda) (eq. RKL1 stability poly); P_s from scipy."""
+    n = 8
+    h = (0.1, 0.12, 0.09)
+    i = np.arange(n)
+    u = (np.sin(math.pi * m[2] * (i + 0.5) / n)[:, None, None]
+         * np.sin(math.pi * m[1] * (i + 0.5) / n)[None, :, None]
+         * np.sin(math.pi * m[0] * (i + 0.5) / n)[None, None, :])
+    lam = -sum(4 * math.sin(math.pi * mm / (2 * n)) ** 2 / hh ** 2 for mm, hh in zip(m, h))
+    lv = op.Level(1, (n, n, n), h, "dirichlet")
+    w1 = 2.0 / (s * s + s)
+    tau = theta * (2.0 / lv.lam) * (s * s + s) / 2.0
+    amp = eval_legendre(s, 1.0 + w1 * tau * lam)
+    got = rkl.tau_step(u, np.zeros_like(u), s, theta, lv)
+    np.testing.assert_allclose(got, amp * u, atol=1e-12)
+
+
+def test_checkerboard_at_tau_max_is_not_damped_and_grows_beyond():
+    """On a cell-centred grid the checkerboard has eigenvalue -Lambda, so at
+    tau = tau_max it maps to P_s(-1) = (-1)^s (undamped); beyond tau_max it grows."""
+    n = 6
+    h = (1 / 6,) * 3
+    idx = np.indices((n, n, n)).sum(axis=0)
+    u = np.where(idx % 2 == 0, 1.0, -1.0)
+    lv = op.Level(1, (n, n, n), h, "dirichlet")
+    for s in (2, 3, 4):
+        got = rkl.tau_step(u, np.zeros_like(u), s, 1.0, lv)
+        np.testing.assert_allclose(np.abs(got), 1.0, atol=1e-12)
+        grown = rkl.tau_step(u, np.zeros_like(u), s, 1.1, lv)
+        assert np.abs(grown).max() > 1.05
+
+
+def test_constant_preserved_periodic():
+    lv = op.Level(0, (6, 6, 6), (0.1, 0.1, 0.1), "periodic")
+    u = np.full((6, 6, 6), 2.5)
+    for s in (1, 2, 5):
+        np.testing.assert_allclose(rkl.tau_step(u, np.zeros_like(u), s, 0.9, lv), 2.5, atol=1e-13)
+
+
+@pytest.mark.parametrize("bc", ["periodic", "dirichlet"])
+def test_exact_solution_is_fixed_point(bc):
+    rng = np.random.default_rng(4)
+    n = 16
+    h = (1 / n,) * 3
+    f = rng.standard_normal((n, n, n))
+    faces = None
+    if bc == "dirichlet":
+        faces = tuple(rng.standard_normal((n, n)) for _ in range(6))
+    else:
+        f -= f.mean()
+    us = exact.exact_solution(f, h, bc, faces)
+    lv = op.Level(0, (n, n, n), h, bc)
+    for s in (1, 2, 4):
+        got = rkl.tau_step(us, f, s, 0.9, lv, faces)
+        assert np.abs(got - us).max() <= 1e-11 * np.abs(us).max()
+
+
+def test_legendre_recursion_matches_scipy():
+    x = np.linspace(-1, 1, 41)
+    for s in (0, 1, 2, 7, 30, 56):
+        np.testing.assert_allclose(rkl.legendre(s, x), eval_legendre(s, x), atol=1e-12)
+
+
+def test_s_opt_global_is_56_for_N64():
+    """App. A.3: the global minimum of m_eff is at s = 56 (modes k <= 6)."""
+    assert rkl.s_opt_global_1d(64) == GOLD["s_opt_global_N64"]["value"]
+    # minimising rho instead of m_eff gives a different s (57): the rule matters
+    rhos = [rkl.spectral_radius_1d(s, 64) for s in range(1, 65)]
+    assert int(np.argmin(rhos)) + 1 != 56
+
+
+def test_first_six_modes_set_the_spectral_radius():
+    """App. A.3: for the 1-D model the first six modes determine rho(R) (checked
+    against all N/2 modes with scipy's Legendre values)."""
+    N = 64
+    k6 = GOLD["spectral_radius_modes"]["value"]
+    for s in range(1, N + 1):
+        full = np.max(np.abs(eval_legendre(s, np.cos(np.arange(1, N // 2 + 1) * math.pi / N))))
+        assert abs(rkl.spectral_radius_1d(s, N, kmax=k6) - full) < 1e-12
+
+
+def test_sk_opt_formula_near_first_zero_of_legendre():
+    """eq. sk_optimal places s_k near the first zero of P_s(cos(k pi/N)); for
+    N = 64 and the paper's k = 1, 5, 32 the formula gives 48, 9, 1 and the
+    first sign change of scipy's P_s lies within one stage of it."""
+    N = 64
+    got = [rkl.s_k_opt_1d(k, N) for k in (1, 5, 32)]
+    assert got == [48, 9, 1]
+    for k, sk in zip((1, 5, 32), got):
+        x = math.cos(k * math.pi / N)
+        vals = [eval_legendre(s, x) for s in range(0, 200)]
+        first = next(s for s in range(1, 200) if vals[s] * vals[s - 1] <= 0 or vals[s] <= 0)
+        assert abs(first - sk) <= 1
+        # |P_s| at s_k is small (the mode is nearly annihilated)
+        assert abs(eval_legendre(sk, x)) < 0.15
+
+
+def test_bessel_approximation_error_within_paper_bound():
+    """App. A.4 figure caption: |lambda_k - sqrt(theta/sin theta) J0((s+1/2) theta)|
+    stays around 1% or below for k = 1, 5, 32 (N = 64).  The asymptotic form is
+    an O(1/s) statement; at s = 1 and k = 32 the gap is 3.2%, so the bound is
+    checked from s = 2 on."""
+    N = 64
+    bound = GOLD["bessel_approx_max_error"]["value"]
+    for k in (1, 5, 32):
+        th = k * math.pi / N
+        s = np.arange(2, N + 1)
+        approx = math.sqrt(th / math.sin(th)) * j0((s + 0.5) * th)
+        exact_v = eval_legendre(s, math.cos(th))
+        assert np.max(np.abs(approx - exact_v)) < bound
+
+
+def test_accelerated_schedule_reduces_to_paper_1d_rule():
+    """On a cubic Dirichlet grid at theta = 1 the 3-D schedule (x_k from the
+    diagonal mode) equals eq. sk_optimal applied for k = N/2 .. 1 with
+    repeated values skipped (App. A.4)."""
+    for N in (4, 8, 16, 32, 64):
+        lv = op.Level(0, (N, N, N), (1.0 / N,) * 3, "dirichlet")
+        want = []
+        for k in range(N // 2, 0, -1):
+            s = rkl.s_k_opt_1d(k, N)
+            if not want or want[-1] != s:
+                want.append(s)
+        assert rkl.accelerated_schedule(lv, 1.0) == want
+    lv = op.Level(0, (64, 64, 64), (1 / 64,) * 3, "dirichlet")
+    assert rkl.accelerated_schedule(lv, 1.0) == [1, 2, 3, 4, 5, 6, 8, 9, 12, 16, 24, 48]
+
+
+def test_accelerated_schedule_small_coarse_grids():
+    """Schedules used by the coarsest solves (theta = 0.9)."""
+    def sched(n, bc):
+        return rkl.accelerated_schedule(op.Level(3, (n, n, n), (0.5,) * 3, bc), 0.9)
+    assert sched(4, "dirichlet") == [1, 3]
+    assert sched(4, "periodic") == [2, 3]
+    assert sched(6, "periodic") == [2, 4]
+    assert sched(6, "dirichlet") == [1, 2, 4]
