@@ -1,0 +1,195 @@
+/*
+ * rkl_poisson.h -- C ABI of the MI355X (gfx950) RKL-multigrid Poisson solver.
+ *
+ * Solves  nabla^2 phi = 4 pi G rho  on a cell-centred box with the 7-point
+ * Laplacian (Mandal, Mukherjee & Mignone 2023, "A self-gravity module for the
+ * PLUTO code": Sec. 2.2.1 eq. discrete_laplace_3D), Dirichlet or periodic
+ * boundaries (Sec. 2.3, eqs. solution_ghost, error_ghost, periodic), by a
+ * correction-scheme multigrid V-cycle (Sec. 2.1) whose relaxation and
+ * coarsest-grid solver are Runge-Kutta-Legendre super-time-steps of the
+ * parabolic problem d phi/dt = nabla^2 phi - 4 pi G rho (Sec. 2.2.4,
+ * App. A eq. RKL_intermediate_source).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Arrays are dense, row-major [k][j][i] with x fastest, nx*ny*nz elements.
+ * - Pointers named "device" are HIP device (or managed) memory owned by the
+ *   caller; "host" pointers are ordinary CPU memory owned by the caller.  The
+ *   library never frees caller memory.  Work buffers are owned by the library
+ *   in a plan cache keyed by (device, grid, options); rkl_release_all() frees
+ *   them.
+ * - Every call is ordered on the HIP stream passed as `hip_stream`
+ *   (a hipStream_t; NULL = the default stream).  Calls that report a
+ *   residual synchronise that stream to read it.
+ * - Dirichlet boundary data `bc_faces` (device, float64) holds the boundary
+ *   values at face centres, packed as
+ *       x- (ny*nz, [k][j]), x+ (ny*nz), y- (nx*nz, [k][i]), y+ (nx*nz),
+ *       z- (nx*ny, [j][i]), z+ (nx*ny);
+ *   NULL means homogeneous data (g = 0).  It must be NULL for periodic grids.
+ * - Errors are returned as rkl_status; nothing aborts or throws across the
+ *   ABI.  rkl_last_error() gives a thread-local message for the last failure.
+ *   On a failure after work started, phi holds the last complete iterate.
+ * - Calls from several host threads are allowed; calls that share a plan
+ *   (same device, grid and options) on different streams must not overlap.
+ */
+#ifndef RKL_POISSON_H
+#define RKL_POISSON_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RKL_OK = 0,
+    RKL_EINVAL = -1,      /* bad argument (sizes, spacing, options, NULL pointer) */
+    RKL_ENOMEM = -2,      /* device allocation failed                             */
+    RKL_ENOCONV = -3,     /* max_cycles reached before tol                        */
+    RKL_EDIVERGED = -4,   /* residual grew in 3 consecutive cycles                */
+    RKL_ENONFINITE = -5,  /* NaN or Inf in the source or the residual             */
+    RKL_EHIP = -6         /* a HIP runtime call failed                            */
+} rkl_status;
+
+typedef enum { RKL_BC_DIRICHLET = 0, RKL_BC_PERIODIC = 1 } rkl_bc;
+
+typedef enum {
+    RKL_FP64 = 0,   /* every sweep, transfer and norm in float64                    */
+    RKL_MIXED = 1   /* float32 V-cycles inside a float64 defect-correction loop     */
+} rkl_precision;
+
+/* Finest-level geometry: active cell counts and spacings (Sec. 2.2.1). */
+typedef struct {
+    int nx, ny, nz;
+    double hx, hy, hz;
+    int bc;            /* rkl_bc */
+} rkl_grid;
+
+/* Solver options.  rkl_default_opts() fills the defaults noted here. */
+typedef struct {
+    int s;               /* stages per smoothing tau-step (default 2)                           */
+    double tau_frac;     /* theta = tau / tau_max(s), in (0, 1] (default 0.9); tau_max from
+                            eq. tau_max with |lambda_max| = 4 sum_d h_d^-2                        */
+    int n_pre, n_post;   /* relaxations before / after the coarse correction (2, 1; Sec. 4.1)  */
+    int min_coarse;      /* coarsen while every n/2 is even and >= min_coarse (default 4)      */
+    double tol;          /* stop at ||M phi - f||_2 / ||M 0 - f||_2 <= tol (default 1e-10)       */
+    int max_cycles;      /* cap on V-cycles (outer iterations in RKL_MIXED) (default 100)       */
+    int prec;            /* rkl_precision (default RKL_FP64)                                    */
+    double four_pi_G;    /* f = four_pi_G * rho (default 4 pi, i.e. G = 1)                      */
+    double coarse_tol;   /* coarsest solve: stop at ||M u - b|| <= coarse_tol ||b||; 0 picks
+                            1e-13 (float64) or 1e-6 (float32)                                   */
+    int coarse_max_steps;/* coarsest solve: cap on tau-steps (default 200)                      */
+} rkl_opts;
+
+/* Solve statistics.  `history` (host, optional) receives the relative
+ * residual before each cycle, up to history_cap entries. */
+typedef struct {
+    int cycles;          /* V-cycles (or outer refinements) performed                 */
+    int levels;          /* multigrid levels used (1 = single-level RKL mode)         */
+    double res0;         /* ||M 0 - f||_2                                             */
+    double rel_res;      /* final ||M phi - f||_2 / res0                              */
+    double *history;     /* host array or NULL                                        */
+    int history_cap;
+    int history_len;
+} rkl_stats;
+
+/* Fill `o` with the defaults listed in rkl_opts. */
+void rkl_default_opts(rkl_opts *o);
+
+/*
+ * Full solve of nabla^2 phi = 4 pi G rho (eq. poisson_eqaution) to relative
+ * residual opts->tol, by V-cycles from the initial guess in phi (zeros for a
+ * cold start).  Sec. 2.1 (V-cycle), Sec. 4.1 (N_pre, N_post, stop metric).
+ *   grid      host, finest-level geometry
+ *   opts      host, may be NULL for defaults
+ *   rho       device float64[nz*ny*nx], not modified
+ *   bc_faces  device float64 packed faces (Dirichlet) or NULL
+ *   phi       device float64[nz*ny*nx]: initial guess in, solution out;
+ *             periodic solutions are returned with zero mean (the mean of
+ *             rho is removed first, eq. source_modification)
+ *   stats     host, optional
+ * A grid that cannot be coarsened runs the accelerated single-level RKL
+ * iteration of App. A.4 to tolerance (stats->levels == 1).
+ */
+rkl_status rkl_poisson_solve(const rkl_grid *grid, const rkl_opts *opts,
+                             const double *rho, const double *bc_faces,
+                             double *phi, rkl_stats *stats, void *hip_stream);
+
+/*
+ * One V-cycle (Sec. 2.1) on M phi = f at float64: f is the final right-hand
+ * side (already 4 pi G rho, mean-free if periodic) and is used as given.
+ *   f, phi      device float64[nz*ny*nx]; phi updated in place
+ *   rel_res_out host, optional: ||M phi - f|| / ||M 0 - f|| after the cycle
+ */
+rkl_status mg_vcycle(const rkl_grid *grid, const rkl_opts *opts, const double *f,
+                     const double *bc_faces, double *phi, double *rel_res_out,
+                     void *hip_stream);
+
+/*
+ * n_steps RKL tau-steps of s stages on M phi = f at the finest level
+ * (App. A eq. RKL_intermediate_source, tau = tau_frac * tau_max(s),
+ * eq. tau_max).  f is used as given (no mean removal).  This is also the
+ * single-level relaxation of App. B when n_steps is large.
+ *   f, phi  device float64[nz*ny*nx]; phi updated in place
+ */
+rkl_status rkl_smooth(const rkl_grid *grid, int s, double tau_frac, int n_steps,
+                      const double *f, const double *bc_faces, double *phi,
+                      void *hip_stream);
+
+/*
+ * Residual r = f - M phi on the finest level (Sec. 2.1 eq. residual, with the
+ * opposite sign) and its float64 L2 norm.
+ *   r_out     device float64[n] or NULL (norm only)
+ *   norm_out  host, optional
+ */
+rkl_status rkl_residual(const rkl_grid *grid, const double *f, const double *bc_faces,
+                        const double *phi, double *r_out, double *norm_out,
+                        void *hip_stream);
+
+/*
+ * Grid transfer building blocks of the V-cycle (float64, device arrays).
+ * rkl_restrict: coarse = R(fine), the 8-point average of eq.
+ *   restriction_example_3D; `grid` describes the FINE grid (even sizes).
+ * rkl_prolong_add: fine += P(coarse) with the (27,9,9,9,3,3,3,1)/64 weights of
+ *   eq. prolongation_example_3D and error-equation ghosts on the coarse grid
+ *   (homogeneous Dirichlet or periodic, Sec. 2.3); `grid` describes the FINE grid.
+ */
+rkl_status rkl_restrict(const rkl_grid *grid, const double *fine, double *coarse,
+                        void *hip_stream);
+rkl_status rkl_prolong_add(const rkl_grid *grid, const double *coarse, double *fine,
+                           void *hip_stream);
+
+/*
+ * Coarsest-grid solve (App. A.4, accelerated RKL schedule) of M u = b with
+ * homogeneous (Dirichlet) or periodic ghosts, from u = 0, until
+ * ||M u - b|| <= coarse_tol ||b|| or coarse_max_steps tau-steps.
+ *   b, u        device float64[n]
+ *   steps_out   host, optional: tau-steps taken
+ * Uses one workgroup with the level held in LDS when n <= 2048 cells.
+ */
+rkl_status rkl_coarse_solve(const rkl_grid *grid, const rkl_opts *opts, const double *b,
+                            double *u, int *steps_out, void *hip_stream);
+
+/*
+ * Batched solve of `nbatch` independent problems whose grids may differ in
+ * size (each grid[i] has its own geometry; boundary types may be mixed,
+ * Dirichlet ones homogeneous).  rho[i], phi[i]: device float64 arrays of
+ * grid[i]'s size (host arrays of device pointers).  With opts->prec ==
+ * RKL_MIXED every V-cycle runs in float32 inside float64 refinement.  The
+ * whole batch advances together: one launch per V-cycle phase covers every
+ * grid, and the fixed-count refinement loop is replayed from a captured HIP
+ * graph.  stats: host array of nbatch entries or NULL.
+ */
+rkl_status rkl_poisson_solve_batched(const rkl_grid *grids, int nbatch, const rkl_opts *opts,
+                                     const double *const *rho, double *const *phi,
+                                     rkl_stats *stats, void *hip_stream);
+
+/* Thread-local message describing the last failure (never NULL). */
+const char *rkl_last_error(void);
+
+/* Free every cached plan and work buffer on every device. */
+void rkl_release_all(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RKL_POISSON_H */

@@ -1,0 +1,279 @@
+"""ctypes binding of ``librklpoisson.so`` (argument marshalling only).
+
+Every numerical step runs in the library's HIP kernels; this module only turns
+torch CUDA tensors into device pointers, options into the ``rkl_opts`` struct,
+and status codes into exceptions.  There is no CPU fallback: if the library is
+missing or no GPU is visible, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass, field
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "librklpoisson.so")
+
+RKL_OK, RKL_EINVAL, RKL_ENOMEM, RKL_ENOCONV, RKL_EDIVERGED, RKL_ENONFINITE, RKL_EHIP = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "RKL_OK", -1: "RKL_EINVAL", -2: "RKL_ENOMEM", -3: "RKL_ENOCONV",
+                -4: "RKL_EDIVERGED", -5: "RKL_ENONFINITE", -6: "RKL_EHIP"}
+BC = {"dirichlet": 0, "periodic": 1}
+PREC = {"fp64": 0, "mixed": 1}
+
+
+class RKLError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class c_grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+                ("hx", ctypes.c_double), ("hy", ctypes.c_double), ("hz", ctypes.c_double),
+                ("bc", ctypes.c_int)]
+
+
+class c_opts(ctypes.Structure):
+    _fields_ = [("s", ctypes.c_int), ("tau_frac", ctypes.c_double), ("n_pre", ctypes.c_int),
+                ("n_post", ctypes.c_int), ("min_coarse", ctypes.c_int), ("tol", ctypes.c_double),
+                ("max_cycles", ctypes.c_int), ("prec", ctypes.c_int), ("four_pi_G", ctypes.c_double),
+                ("coarse_tol", ctypes.c_double), ("coarse_max_steps", ctypes.c_int)]
+
+
+class c_stats(ctypes.Structure):
+    _fields_ = [("cycles", ctypes.c_int), ("levels", ctypes.c_int), ("res0", ctypes.c_double),
+                ("rel_res", ctypes.c_double), ("history", ctypes.POINTER(ctypes.c_double)),
+                ("history_cap", ctypes.c_int), ("history_len", ctypes.c_int)]
+
+
+EXPORTS = ("rkl_default_opts", "rkl_poisson_solve", "mg_vcycle", "rkl_smooth", "rkl_residual",
+           "rkl_restrict", "rkl_prolong_add", "rkl_coarse_solve", "rkl_poisson_solve_batched",
+           "rkl_last_error", "rkl_release_all")
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load the shared library (no GPU needed) and declare the C signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2306_05332_amd.build` "
+                          "(hipcc for gfx950); there is no CPU fallback")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    pg, po, ps = ctypes.POINTER(c_grid), ctypes.POINTER(c_opts), ctypes.POINTER(c_stats)
+    lib.rkl_default_opts.argtypes = [po]
+    lib.rkl_default_opts.restype = None
+    lib.rkl_poisson_solve.argtypes = [pg, po, P, P, P, ps, P]
+    lib.mg_vcycle.argtypes = [pg, po, P, P, P, ctypes.POINTER(ctypes.c_double), P]
+    lib.rkl_smooth.argtypes = [pg, ctypes.c_int, ctypes.c_double, ctypes.c_int, P, P, P, P]
+    lib.rkl_residual.argtypes = [pg, P, P, P, P, ctypes.POINTER(ctypes.c_double), P]
+    lib.rkl_restrict.argtypes = [pg, P, P, P]
+    lib.rkl_prolong_add.argtypes = [pg, P, P, P]
+    lib.rkl_coarse_solve.argtypes = [pg, po, P, P, ctypes.POINTER(ctypes.c_int), P]
+    lib.rkl_poisson_solve_batched.argtypes = [pg, ctypes.c_int, po, ctypes.POINTER(P), ctypes.POINTER(P),
+                                              ps, P]
+    for name in ("rkl_poisson_solve", "mg_vcycle", "rkl_smooth", "rkl_residual", "rkl_restrict",
+                 "rkl_prolong_add", "rkl_coarse_solve", "rkl_poisson_solve_batched"):
+        getattr(lib, name).restype = ctypes.c_int
+    lib.rkl_last_error.argtypes = []
+    lib.rkl_last_error.restype = ctypes.c_char_p
+    lib.rkl_release_all.argtypes = []
+    lib.rkl_release_all.restype = None
+    _lib = lib
+    return lib
+
+
+def _check(status):
+    if status != RKL_OK:
+        raise RKLError(status, _lib.rkl_last_error().decode())
+
+
+@dataclass
+class Options:
+    """Mirror of ``rkl_opts`` with the library defaults."""
+
+    s: int = 2
+    tau_frac: float = 0.9
+    n_pre: int = 2
+    n_post: int = 1
+    min_coarse: int = 4
+    tol: float = 1e-10
+    max_cycles: int = 100
+    prec: str = "fp64"
+    four_pi_G: float = 4.0 * math.pi
+    coarse_tol: float = 0.0
+    coarse_max_steps: int = 200
+
+    def c(self):
+        return c_opts(self.s, self.tau_frac, self.n_pre, self.n_post, self.min_coarse, self.tol,
+                      self.max_cycles, PREC[self.prec], self.four_pi_G, self.coarse_tol,
+                      self.coarse_max_steps)
+
+
+@dataclass
+class Stats:
+    cycles: int = 0
+    levels: int = 0
+    res0: float = 0.0
+    rel_res: float = 0.0
+    history: list = field(default_factory=list)
+    status: int = 0
+
+
+def _grid(shape, h, bc):
+    nz, ny, nx = shape
+    if isinstance(h, (int, float)):
+        h = (float(h),) * 3
+    return c_grid(nx, ny, nz, float(h[0]), float(h[1]), float(h[2]), BC[bc])
+
+
+def _dev(t, name, dtype=torch.float64):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(t):
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def pack_faces(faces, device=None):
+    """Six face arrays (x-, x+, y-, y+, z-, z+) -> one flat float64 CUDA tensor."""
+    parts = [torch.as_tensor(f, dtype=torch.float64).reshape(-1) for f in faces]
+    out = torch.cat(parts)
+    return out.to(device or "cuda").contiguous()
+
+
+def _check_faces(faces, shape, bc):
+    if faces is None:
+        return
+    if bc != "dirichlet":
+        raise ValueError("faces are only valid for Dirichlet grids")
+    nz, ny, nx = shape
+    want = 2 * (ny * nz + nx * nz + nx * ny)
+    if faces.numel() != want:
+        raise ValueError(f"packed faces must hold {want} values for shape {tuple(shape)}, got {faces.numel()}")
+
+
+def solve(rho, h, bc="periodic", faces=None, phi0=None, opts: Options | None = None,
+          history_cap=256, raise_on_error=True):
+    """phi solving nabla^2 phi = four_pi_G rho (rkl_poisson_solve).  rho: (nz, ny, nx)
+    float64 CUDA tensor.  Returns (phi, Stats)."""
+    lib = load_library()
+    opts = opts or Options()
+    phi = torch.zeros_like(rho) if phi0 is None else phi0.clone()
+    _check_faces(faces, rho.shape, bc)
+    g = _grid(rho.shape, h, bc)
+    hist = (ctypes.c_double * max(1, history_cap))()
+    st = c_stats(0, 0, 0.0, 0.0, hist, history_cap, 0)
+    co = opts.c()
+    status = lib.rkl_poisson_solve(ctypes.byref(g), ctypes.byref(co), _dev(rho, "rho"), _dev(faces, "faces"),
+                                   _dev(phi, "phi"), ctypes.byref(st), _stream(rho))
+    stats = Stats(st.cycles, st.levels, st.res0, st.rel_res, list(hist[:st.history_len]), status)
+    if raise_on_error and status != RKL_OK:
+        _check(status)
+    return phi, stats
+
+
+def vcycle(f, phi, h, bc="periodic", faces=None, opts: Options | None = None, want_residual=False):
+    """One V-cycle on M phi = f in place (mg_vcycle); returns the relative residual or None."""
+    lib = load_library()
+    opts = opts or Options()
+    _check_faces(faces, f.shape, bc)
+    g = _grid(f.shape, h, bc)
+    co = opts.c()
+    rel = ctypes.c_double(0.0)
+    _check(lib.mg_vcycle(ctypes.byref(g), ctypes.byref(co), _dev(f, "f"), _dev(faces, "faces"),
+                         _dev(phi, "phi"), ctypes.byref(rel) if want_residual else None, _stream(f)))
+    return rel.value if want_residual else None
+
+
+def smooth(f, phi, h, bc="periodic", s=2, tau_frac=0.9, n_steps=1, faces=None):
+    """n_steps RKL tau-steps on M phi = f in place (rkl_smooth)."""
+    lib = load_library()
+    _check_faces(faces, f.shape, bc)
+    g = _grid(f.shape, h, bc)
+    _check(lib.rkl_smooth(ctypes.byref(g), int(s), float(tau_frac), int(n_steps), _dev(f, "f"),
+                          _dev(faces, "faces"), _dev(phi, "phi"), _stream(f)))
+    return phi
+
+
+def residual(f, phi, h, bc="periodic", faces=None):
+    """(f - M phi, ||f - M phi||_2) (rkl_residual)."""
+    lib = load_library()
+    _check_faces(faces, f.shape, bc)
+    g = _grid(f.shape, h, bc)
+    r = torch.empty_like(f)
+    nrm = ctypes.c_double(0.0)
+    _check(lib.rkl_residual(ctypes.byref(g), _dev(f, "f"), _dev(faces, "faces"), _dev(phi, "phi"),
+                            _dev(r, "r"), ctypes.byref(nrm), _stream(f)))
+    return r, nrm.value
+
+
+def restrict(fine):
+    lib = load_library()
+    nz, ny, nx = fine.shape
+    coarse = torch.empty((nz // 2, ny // 2, nx // 2), dtype=fine.dtype, device=fine.device)
+    g = _grid(fine.shape, 1.0, "periodic")
+    _check(lib.rkl_restrict(ctypes.byref(g), _dev(fine, "fine"), _dev(coarse, "coarse"), _stream(fine)))
+    return coarse
+
+
+def prolong_add(coarse, fine, bc="periodic"):
+    lib = load_library()
+    g = _grid(fine.shape, 1.0, bc)
+    _check(lib.rkl_prolong_add(ctypes.byref(g), _dev(coarse, "coarse"), _dev(fine, "fine"), _stream(fine)))
+    return fine
+
+
+def coarse_solve(b, h, bc="periodic", opts: Options | None = None):
+    """Accelerated RKL solve of M u = b with homogeneous/periodic ghosts (rkl_coarse_solve)."""
+    lib = load_library()
+    opts = opts or Options()
+    g = _grid(b.shape, h, bc)
+    u = torch.empty_like(b)
+    steps = ctypes.c_int(0)
+    co = opts.c()
+    _check(lib.rkl_coarse_solve(ctypes.byref(g), ctypes.byref(co), _dev(b, "b"), _dev(u, "u"),
+                                ctypes.byref(steps), _stream(b)))
+    return u, steps.value
+
+
+def solve_batched(rhos, hs, bcs, opts: Options | None = None, history_cap=64):
+    """Batched solve of independent problems (rkl_poisson_solve_batched).
+    rhos: list of float64 CUDA tensors (sizes may differ).  Returns (phis, stats list)."""
+    lib = load_library()
+    opts = opts or Options()
+    n = len(rhos)
+    if isinstance(bcs, str):
+        bcs = [bcs] * n
+    grids = (c_grid * n)(*[_grid(r.shape, h, b) for r, h, b in zip(rhos, hs, bcs)])
+    phis = [torch.zeros_like(r) for r in rhos]
+    rp = (ctypes.c_void_p * n)(*[r.data_ptr() for r in rhos])
+    pp = (ctypes.c_void_p * n)(*[p.data_ptr() for p in phis])
+    for r in rhos:
+        _dev(r, "rho")
+    hists = [(ctypes.c_double * history_cap)() for _ in range(n)]
+    sts = (c_stats * n)(*[c_stats(0, 0, 0.0, 0.0, hh, history_cap, 0) for hh in hists])
+    co = opts.c()
+    status = lib.rkl_poisson_solve_batched(grids, n, ctypes.byref(co), rp, pp, sts, _stream(rhos[0]))
+    _check(status)
+    stats = [Stats(s.cycles, s.levels, s.res0, s.rel_res, list(hh[:s.history_len]), 0)
+             for s, hh in zip(sts, hists)]
+    return phis, stats
+
+
+def release_all():
+    load_library().rkl_release_all()

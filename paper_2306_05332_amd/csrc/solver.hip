@@ -1,0 +1,834 @@
+// Host side of the RKL-multigrid Poisson solver: plan cache, level hierarchy,
+// V-cycle driver, convergence loop, mixed-precision defect correction and the
+// C ABI declared in include/rkl_poisson.h.
+//
+// Method (Mandal, Mukherjee & Mignone 2023):
+//  * correction-scheme V-cycle, Sec. 2.1, with every level written as
+//    M_l u_l = b_l, b_0 = f, b_{l+1} = -R(M_l u_l - b_l) (the listing's coarse
+//    signs made consistent), N_pre = 2, N_post = 1 (Sec. 4.1);
+//  * relaxation: one s-stage RKL1 tau-step (App. A eq. RKL_intermediate_source)
+//    with tau = theta * tau_max(s), tau_max from eq. tau_max and
+//    |lambda_max| = 4 sum_d h_d^-2;
+//  * coarsest level: accelerated RKL schedule (App. A.4, eq. sk_optimal
+//    generalised to 3-D through x_k = 1 - theta Delta t_par |lambda_k|);
+//  * periodic compatibility: f -= mean(f) and coarse right-hand sides made
+//    mean-free (Sec. 2.3);
+//  * stop metric: ||M u - f||_2 / ||M 0 - f||_2 (Sec. 4.1).
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/rkl_poisson.h"
+#include "kernels.h"
+
+namespace rkl {
+namespace {
+
+thread_local std::string g_err = "no error";
+
+struct Fail {
+  rkl_status st;
+};
+
+[[noreturn]] void fail(rkl_status st, const std::string& msg) {
+  g_err = msg;
+  throw Fail{st};
+}
+
+#define HIPCHK(x)                                                                          \
+  do {                                                                                     \
+    hipError_t e_ = (x);                                                                   \
+    if (e_ != hipSuccess) fail(RKL_EHIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+inline void check_launch() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) fail(RKL_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+}
+
+// ------------------------------------------------------------------ levels
+struct Lev {
+  int nx, ny, nz;
+  double hx, hy, hz;
+  size_t n;
+  double lam, dtpar;               // Lambda_l = 4 sum h^-2, Delta t_par = 2 / Lambda_l
+  std::vector<StageCoef> smooth;   // coefficients of the smoothing tau-step
+};
+
+// Stage coefficients of one s-stage tau-step: mu_j = (2j-1)/j, nu_j = (1-j)/j,
+// c_j = mu~_j tau = (mu_j w1) tau, w1 = 2/(s^2+s), tau = theta tau_max(s).
+std::vector<StageCoef> stage_coefs(int s, double theta, double dtpar) {
+  const double w1 = 2.0 / (double)(s * s + s);
+  const double tau = theta * dtpar * (double)(s * s + s) / 2.0;
+  std::vector<StageCoef> out;
+  for (int j = 1; j <= s; ++j) {
+    const double mu = (2.0 * j - 1.0) / j;
+    const double nu = (1.0 - j) / j;
+    out.push_back({mu, nu, (mu * w1) * tau});
+  }
+  return out;
+}
+
+// Accelerated schedule on a level: k from n/2 down to 1 (n = smallest cell
+// count), s_k = Round(2.4048 / arccos(x_k) - 1/2), x_k = 1 - theta dt_par
+// |lambda_k|, repeats skipped.  |lambda_k|: Dirichlet diagonal mode
+// sum_d 4 sin^2(k pi / 2 n_d) / h_d^2; periodic axis mode min_d 4 sin^2(k pi / n_d) / h_d^2.
+std::vector<int> accel_schedule(const Lev& L, bool periodic, double theta) {
+  const int ns[3] = {L.nx, L.ny, L.nz};
+  const double hs[3] = {L.hx, L.hy, L.hz};
+  const int n = std::min(L.nx, std::min(L.ny, L.nz));
+  int k = std::max(1, n / 2);
+  int s_old = 0;
+  std::vector<int> out;
+  while (true) {
+    double lk = periodic ? 1e300 : 0.0;
+    for (int d = 0; d < 3; ++d) {
+      if (periodic) {
+        const double sv = std::sin(k * M_PI / ns[d]);
+        lk = std::min(lk, 4.0 * sv * sv / (hs[d] * hs[d]));
+      } else {
+        const double sv = std::sin(k * M_PI / (2.0 * ns[d]));
+        lk += 4.0 * sv * sv / (hs[d] * hs[d]);
+      }
+    }
+    double x = 1.0 - theta * L.dtpar * lk;
+    x = std::max(-1.0, std::min(1.0, x));
+    const double th = std::acos(x);
+    int s;
+    if (th <= 0.0) s = 1 << 20;
+    else s = std::max(1, (int)std::floor(2.4048 / th - 0.5 + 0.5));
+    if (s > 4096) s = 4096;  // a flat mode (x = 1) cannot be damped; keep tables bounded
+    if (s != s_old) {
+      out.push_back(s);
+      s_old = s;
+    }
+    if (k == 1) break;
+    --k;
+  }
+  return out;
+}
+
+// ------------------------------------------------------------------ plan
+template <typename T>
+struct Hier {
+  std::vector<T*> u, b, t;
+};
+
+struct PlanKey {
+  int dev, nx, ny, nz, bc, s, min_coarse, prec;
+  double hx, hy, hz, theta;
+  bool operator<(const PlanKey& o) const {
+    return std::tie(dev, nx, ny, nz, bc, s, min_coarse, prec, hx, hy, hz, theta) <
+           std::tie(o.dev, o.nx, o.ny, o.nz, o.bc, o.s, o.min_coarse, o.prec, o.hx, o.hy, o.hz,
+                    o.theta);
+  }
+};
+
+struct Plan {
+  PlanKey key;
+  bool periodic = false;
+  std::vector<Lev> lv;
+  Hier<double> h64;
+  Hier<float> h32;
+  double* f0 = nullptr;  // level-0 source (float64)
+  double* t0 = nullptr;  // level-0 alternate iterate (float64)
+  double* part = nullptr;
+  size_t part_cap = 0;
+  double* dscal = nullptr;  // device scalars
+  double* hscal = nullptr;  // pinned host mirror
+  int* dsteps = nullptr;
+  // coarsest-level schedule
+  std::vector<int> sched;
+  std::vector<std::vector<StageCoef>> sched_coef;
+  int* d_sched = nullptr;
+  int* d_coff = nullptr;
+  double* d_coef = nullptr;
+  std::vector<void*> allocs;
+  std::mutex mu;
+
+  int L() const { return (int)lv.size(); }
+  CoarseSchedule cs() const { return {d_sched, d_coff, d_coef, (int)sched.size()}; }
+
+  template <typename U>
+  U* alloc(size_t n) {
+    void* p = nullptr;
+    if (n == 0) n = 1;
+    if (hipMalloc(&p, n * sizeof(U)) != hipSuccess) {
+      (void)hipGetLastError();
+      fail(RKL_ENOMEM, "hipMalloc of " + std::to_string(n * sizeof(U)) + " bytes failed");
+    }
+    allocs.push_back(p);
+    return (U*)p;
+  }
+  ~Plan() {
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(key.dev);
+    for (void* p : allocs) (void)hipFree(p);
+    if (hscal) (void)hipHostFree(hscal);
+    (void)hipSetDevice(cur);
+  }
+};
+
+std::mutex g_plans_mu;
+std::map<PlanKey, std::unique_ptr<Plan>> g_plans;
+
+std::vector<Lev> build_levels(const rkl_grid& g, int min_coarse, int s, double theta) {
+  std::vector<Lev> lv;
+  int n[3] = {g.nx, g.ny, g.nz};
+  double h[3] = {g.hx, g.hy, g.hz};
+  while (true) {
+    Lev L;
+    L.nx = n[0];
+    L.ny = n[1];
+    L.nz = n[2];
+    L.hx = h[0];
+    L.hy = h[1];
+    L.hz = h[2];
+    L.n = (size_t)n[0] * n[1] * n[2];
+    L.lam = 4.0 * (1.0 / (h[0] * h[0]) + 1.0 / (h[1] * h[1]) + 1.0 / (h[2] * h[2]));
+    L.dtpar = 2.0 / L.lam;
+    L.smooth = stage_coefs(s, theta, L.dtpar);
+    lv.push_back(L);
+    bool ok = true;
+    for (int d = 0; d < 3; ++d)
+      ok = ok && (n[d] % 2 == 0) && ((n[d] / 2) % 2 == 0) && (n[d] / 2 >= min_coarse);
+    if (!ok) break;
+    for (int d = 0; d < 3; ++d) {
+      n[d] /= 2;
+      h[d] *= 2.0;
+    }
+  }
+  return lv;
+}
+
+Plan& get_plan(const rkl_grid& g, int s, double theta, int min_coarse, int prec) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  PlanKey key{dev, g.nx, g.ny, g.nz, g.bc, s, min_coarse, prec, g.hx, g.hy, g.hz, theta};
+  std::lock_guard<std::mutex> lk(g_plans_mu);
+  auto it = g_plans.find(key);
+  if (it != g_plans.end()) return *it->second;
+  auto P = std::make_unique<Plan>();
+  P->key = key;
+  P->periodic = g.bc == RKL_BC_PERIODIC;
+  P->lv = build_levels(g, min_coarse, s, theta);
+  const int L = P->L();
+  // work buffers
+  P->f0 = P->alloc<double>(P->lv[0].n);
+  P->t0 = P->alloc<double>(P->lv[0].n);
+  P->h64.u.assign(L, nullptr);
+  P->h64.b.assign(L, nullptr);
+  P->h64.t.assign(L, nullptr);
+  for (int l = 1; l < L; ++l) {
+    P->h64.u[l] = P->alloc<double>(P->lv[l].n);
+    P->h64.b[l] = P->alloc<double>(P->lv[l].n);
+    P->h64.t[l] = P->alloc<double>(P->lv[l].n);
+  }
+  if (prec == RKL_MIXED) {
+    P->h32.u.assign(L, nullptr);
+    P->h32.b.assign(L, nullptr);
+    P->h32.t.assign(L, nullptr);
+    for (int l = 0; l < L; ++l) {
+      P->h32.u[l] = P->alloc<float>(P->lv[l].n);
+      P->h32.b[l] = P->alloc<float>(P->lv[l].n);
+      P->h32.t[l] = P->alloc<float>(P->lv[l].n);
+    }
+  }
+  size_t cap = 2 * stencil_blocks(g.nx, g.ny, g.nz);
+  cap = std::max(cap, ew_block_count(P->lv[0].n));
+  cap = std::max<size_t>(cap, 64);
+  P->part = P->alloc<double>(cap);
+  P->part_cap = cap;
+  P->dscal = P->alloc<double>(16);
+  P->dsteps = P->alloc<int>(4);
+  HIPCHK(hipHostMalloc((void**)&P->hscal, 16 * sizeof(double), hipHostMallocDefault));
+  // coarsest schedule tables
+  const Lev& C = P->lv[L - 1];
+  P->sched = accel_schedule(C, P->periodic, theta);
+  std::vector<int> coff;
+  std::vector<double> coef;
+  for (int s_q : P->sched) {
+    coff.push_back((int)(coef.size() / 3));
+    auto co = stage_coefs(s_q, theta, C.dtpar);
+    P->sched_coef.push_back(co);
+    for (auto& c : co) {
+      coef.push_back(c.mu);
+      coef.push_back(c.nu);
+      coef.push_back(c.c);
+    }
+  }
+  P->d_sched = P->alloc<int>(P->sched.size());
+  P->d_coff = P->alloc<int>(coff.size());
+  P->d_coef = P->alloc<double>(coef.size());
+  HIPCHK(hipMemcpy(P->d_sched, P->sched.data(), P->sched.size() * sizeof(int), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(P->d_coff, coff.data(), coff.size() * sizeof(int), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(P->d_coef, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice));
+  Plan& ref = *P;
+  g_plans[key] = std::move(P);
+  return ref;
+}
+
+template <typename T>
+LevelView<T> view(const Lev& L, bool periodic, const double* faces) {
+  LevelView<T> v;
+  v.nx = L.nx;
+  v.ny = L.ny;
+  v.nz = L.nz;
+  v.ihx2 = (T)(1.0 / (L.hx * L.hx));
+  v.ihy2 = (T)(1.0 / (L.hy * L.hy));
+  v.ihz2 = (T)(1.0 / (L.hz * L.hz));
+  v.periodic = periodic ? 1 : 0;
+  v.faces = faces;
+  return v;
+}
+
+// read `nq` device scalars (synchronises the stream)
+const double* readback(Plan& P, int nq, hipStream_t st) {
+  HIPCHK(hipMemcpyAsync(P.hscal, P.dscal, nq * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return P.hscal;
+}
+
+// ||b - M u||_2 (u may be nullptr), synchronising
+template <typename T>
+double resid_norm(Plan& P, const LevelView<T>& V, const T* u, const T* b, hipStream_t st) {
+  launch_residual<T, T>(V, u, b, (T*)nullptr, P.part, st);
+  check_launch();
+  launch_reduce(P.part, (int)stencil_blocks(V.nx, V.ny, V.nz), 2, 1, P.dscal, st);
+  check_launch();
+  return std::sqrt(readback(P, 1, st)[0]);
+}
+
+template <typename T>
+void remove_mean(Plan& P, T* a, size_t n, hipStream_t st) {
+  launch_sum<T>(a, n, P.part, st);
+  launch_reduce(P.part, (int)ew_block_count(n), 1, 1, P.dscal + 8, st);
+  launch_sub_mean<T>(a, n, P.dscal + 8, (double)n, st);
+  check_launch();
+}
+
+// ------------------------------------------------------------------ tau-steps
+template <typename T>
+void tau_step(Plan& P, const LevelView<T>& V, T*& cur, T*& alt, const T* b,
+              const std::vector<StageCoef>& co, hipStream_t st) {
+  const int s = (int)co.size();
+  if (launch_fused_tau<T>(V, cur, b, alt, s, co.data(), nullptr, st)) {
+    check_launch();
+    std::swap(cur, alt);
+    return;
+  }
+  launch_stage<T>(V, cur, nullptr, b, alt, co[0].mu, co[0].nu, co[0].c, 1, st);
+  for (int j = 2; j <= s; ++j) {
+    // Y_{j-1} is in `alt` for even j (odd index), in `cur` for odd j; Y_j
+    // overwrites Y_{j-2} in the other buffer
+    T* yp = (j & 1) ? cur : alt;
+    T* yw = (j & 1) ? alt : cur;
+    launch_stage<T>(V, yp, yw, b, yw, co[j - 1].mu, co[j - 1].nu, co[j - 1].c, 0, st);
+  }
+  check_launch();
+  if (s & 1) std::swap(cur, alt);
+}
+
+// Accelerated RKL iteration driven from the host (levels too large for the
+// one-workgroup kernel): residual read back before every tau-step.
+template <typename T>
+int accel_multi(Plan& P, const LevelView<T>& V, T*& cur, T*& alt, const T* b, double tol, double ref,
+                int max_steps, bool rm_mean, hipStream_t st, double* res_out) {
+  int step = 0;
+  double res = 0.0;
+  const size_t n = (size_t)V.nx * V.ny * V.nz;
+  while (true) {
+    res = resid_norm<T>(P, V, cur, b, st);
+    if (res <= tol * ref || step >= max_steps) break;
+    const int q = std::min(step, (int)P.sched.size() - 1);
+    tau_step<T>(P, V, cur, alt, b, P.sched_coef[q], st);
+    if (rm_mean) remove_mean<T>(P, cur, n, st);
+    ++step;
+  }
+  if (res_out) *res_out = res;
+  return step;
+}
+
+template <typename T>
+double coarse_tol_for(const rkl_opts& o) {
+  if (o.coarse_tol > 0.0) return o.coarse_tol;
+  return sizeof(T) == 8 ? 1e-13 : 1e-6;
+}
+
+// coarsest level l: M u_l = b_l from u_l = 0
+template <typename T>
+void coarse_solve(Plan& P, Hier<T>& H, int l, const rkl_opts& o, hipStream_t st) {
+  const Lev& C = P.lv[l];
+  const LevelView<T> V = view<T>(C, P.periodic, nullptr);
+  const double tol = coarse_tol_for<T>(o);
+  if (C.n <= (size_t)COARSE_MAX_CELLS) {
+    launch_coarse_solve<T>(V, H.b[l], nullptr, H.u[l], P.cs(), tol, 0.0, o.coarse_max_steps, P.periodic ? 1 : 0,
+                           P.dsteps, nullptr, st);
+    check_launch();
+    return;
+  }
+  launch_fill<T>(H.u[l], C.n, (T)0, st);
+  const double bn = resid_norm<T>(P, V, (const T*)nullptr, H.b[l], st);
+  if (bn == 0.0) return;
+  accel_multi<T>(P, V, H.u[l], H.t[l], H.b[l], tol, bn, o.coarse_max_steps, P.periodic, st, nullptr);
+}
+
+// One V-cycle on M_0 u = b0 (Sec. 2.1).  cur0/alt0: level-0 iterate and its
+// alternate buffer (swapped as tau-steps complete).  faces0: level-0
+// Dirichlet data (float64 path only) or nullptr.
+template <typename T>
+void vcycle(Plan& P, Hier<T>& H, T*& cur0, T*& alt0, const T* b0, const double* faces0,
+            const rkl_opts& o, hipStream_t st) {
+  const int L = P.L();
+  auto V = [&](int l) { return view<T>(P.lv[l], P.periodic, l == 0 ? faces0 : nullptr); };
+  if (L == 1) {
+    for (int q = 0; q < o.n_pre + o.n_post; ++q) tau_step<T>(P, V(0), cur0, alt0, b0, P.lv[0].smooth, st);
+    return;
+  }
+  for (int q = 0; q < o.n_pre; ++q) tau_step<T>(P, V(0), cur0, alt0, b0, P.lv[0].smooth, st);
+  for (int l = 1; l < L; ++l) {
+    T* fu = (l == 1) ? cur0 : H.u[l - 1];
+    const T* fb = (l == 1) ? b0 : H.b[l - 1];
+    launch_resid_restrict<T>(V(l - 1), fu, fb, H.b[l], P.part, st);
+    check_launch();
+    if (P.periodic) {
+      const Lev& C = P.lv[l];
+      launch_reduce(P.part, (int)stencil_blocks(C.nx, C.ny, C.nz), 2, 2, P.dscal, st);
+      launch_sub_mean<T>(H.b[l], C.n, P.dscal + 1, (double)C.n, st);
+      check_launch();
+    }
+    if (l < L - 1) {
+      launch_fill<T>(H.u[l], P.lv[l].n, (T)0, st);
+      for (int q = 0; q < o.n_pre; ++q) tau_step<T>(P, V(l), H.u[l], H.t[l], H.b[l], P.lv[l].smooth, st);
+    } else {
+      coarse_solve<T>(P, H, l, o, st);
+    }
+  }
+  for (int l = L - 2; l >= 0; --l) {
+    T*& cu = (l == 0) ? cur0 : H.u[l];
+    T*& ca = (l == 0) ? alt0 : H.t[l];
+    const T* bl = (l == 0) ? b0 : H.b[l];
+    const Lev& F = P.lv[l];
+    launch_prolong_add<T>(F.nx, F.ny, F.nz, P.periodic ? 1 : 0, H.u[l + 1], cu, st);
+    check_launch();
+    for (int q = 0; q < o.n_post; ++q) tau_step<T>(P, V(l), cu, ca, bl, F.smooth, st);
+  }
+}
+
+// f0 = four_pi_G * rho, mean removed when periodic
+void prepare_source(Plan& P, const double* rho, double c, hipStream_t st) {
+  const size_t n = P.lv[0].n;
+  launch_scale(rho, P.f0, n, c, P.part, st);
+  check_launch();
+  if (P.periodic) {
+    launch_reduce(P.part, (int)ew_block_count(n), 1, 1, P.dscal + 8, st);
+    launch_sub_mean<double>(P.f0, n, P.dscal + 8, (double)n, st);
+    check_launch();
+  }
+}
+
+void copy_d2d(double* dst, const double* src, size_t n, hipStream_t st) {
+  HIPCHK(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+}
+
+void record(rkl_stats* stats, double rel) {
+  if (stats && stats->history && stats->history_len < stats->history_cap)
+    stats->history[stats->history_len++] = rel;
+}
+
+// ------------------------------------------------------------------ validation
+void validate_grid(const rkl_grid* g, const double* bc_faces) {
+  if (!g) fail(RKL_EINVAL, "grid is NULL");
+  if (g->nx < 1 || g->ny < 1 || g->nz < 1) fail(RKL_EINVAL, "cell counts must be >= 1");
+  if ((double)g->nx * g->ny * g->nz > 4.0e10) fail(RKL_EINVAL, "grid too large");
+  if (!(g->hx > 0.0 && g->hy > 0.0 && g->hz > 0.0) || !std::isfinite(g->hx) || !std::isfinite(g->hy) ||
+      !std::isfinite(g->hz))
+    fail(RKL_EINVAL, "spacings must be positive and finite");
+  if (g->bc != RKL_BC_DIRICHLET && g->bc != RKL_BC_PERIODIC) fail(RKL_EINVAL, "unknown boundary type");
+  if (g->bc == RKL_BC_PERIODIC && bc_faces) fail(RKL_EINVAL, "bc_faces must be NULL for periodic grids");
+}
+
+rkl_opts resolve_opts(const rkl_opts* in) {
+  rkl_opts o;
+  rkl_default_opts(&o);
+  if (in) o = *in;
+  if (o.s < 1 || o.s > 64) fail(RKL_EINVAL, "s must be in [1, 64]");
+  if (!(o.tau_frac > 0.0 && o.tau_frac < 2.0)) fail(RKL_EINVAL, "tau_frac must be in (0, 2)");
+  if (o.n_pre < 0 || o.n_post < 0 || o.n_pre + o.n_post < 1) fail(RKL_EINVAL, "need n_pre + n_post >= 1");
+  if (o.min_coarse < 2) fail(RKL_EINVAL, "min_coarse must be >= 2");
+  if (!(o.tol >= 0.0) || !std::isfinite(o.tol)) fail(RKL_EINVAL, "tol must be finite and >= 0");
+  if (o.max_cycles < 0) fail(RKL_EINVAL, "max_cycles must be >= 0");
+  if (o.prec != RKL_FP64 && o.prec != RKL_MIXED) fail(RKL_EINVAL, "unknown precision");
+  if (!std::isfinite(o.four_pi_G)) fail(RKL_EINVAL, "four_pi_G must be finite");
+  if (!(o.coarse_tol >= 0.0)) fail(RKL_EINVAL, "coarse_tol must be >= 0");
+  if (o.coarse_max_steps < 0) fail(RKL_EINVAL, "coarse_max_steps must be >= 0");
+  return o;
+}
+
+// ------------------------------------------------------------------ solves
+rkl_status solve_fp64(Plan& P, const rkl_opts& o, const double* rho, const double* faces, double* phi,
+                      rkl_stats* stats, hipStream_t st) {
+  const Lev& F = P.lv[0];
+  const LevelView<double> V0 = view<double>(F, P.periodic, faces);
+  prepare_source(P, rho, o.four_pi_G, st);
+  const double res0 = resid_norm<double>(P, V0, nullptr, P.f0, st);
+  if (stats) {
+    stats->res0 = res0;
+    stats->levels = P.L();
+    stats->cycles = 0;
+    stats->rel_res = 0.0;
+  }
+  if (res0 == 0.0) {
+    launch_fill<double>(phi, F.n, 0.0, st);
+    check_launch();
+    HIPCHK(hipStreamSynchronize(st));
+    return RKL_OK;
+  }
+  if (!std::isfinite(res0)) {
+    g_err = "non-finite source or boundary data";
+    return RKL_ENONFINITE;
+  }
+  double* cur = phi;
+  double* alt = P.t0;
+  rkl_status status = RKL_OK;
+  int cycles = 0;
+  double rel = 0.0;
+  if (P.L() == 1) {
+    double res = 0.0;
+    if (F.n <= (size_t)COARSE_MAX_CELLS) {
+      // one workgroup holds the whole level in LDS; it starts from phi
+      launch_coarse_solve<double>(V0, P.f0, phi, P.t0, P.cs(), o.tol, res0, o.max_cycles, 0, P.dsteps,
+                                  P.dscal, st);
+      check_launch();
+      copy_d2d(phi, P.t0, F.n, st);
+      HIPCHK(hipMemcpyAsync(P.hscal, P.dsteps, sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(P.hscal + 1, P.dscal, sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      int steps;
+      std::memcpy(&steps, P.hscal, sizeof(int));
+      cycles = steps;
+      res = P.hscal[1];
+    } else {
+      cycles = accel_multi<double>(P, V0, cur, alt, P.f0, o.tol, res0, o.max_cycles, false, st, &res);
+    }
+    rel = res / res0;
+    record(stats, rel);
+    if (!std::isfinite(rel)) status = RKL_ENONFINITE;
+    else if (rel > o.tol) status = RKL_ENOCONV;
+  } else {
+    int grow = 0;
+    double prev = INFINITY;
+    while (true) {
+      rel = resid_norm<double>(P, V0, cur, P.f0, st) / res0;
+      record(stats, rel);
+      if (!std::isfinite(rel)) {
+        status = RKL_ENONFINITE;
+        g_err = "non-finite residual";
+        break;
+      }
+      if (rel <= o.tol) break;
+      grow = rel > prev ? grow + 1 : 0;
+      if (grow >= 3) {
+        status = RKL_EDIVERGED;
+        g_err = "residual grew in 3 consecutive V-cycles";
+        break;
+      }
+      if (cycles >= o.max_cycles) {
+        status = RKL_ENOCONV;
+        g_err = "max_cycles reached before tol";
+        break;
+      }
+      prev = rel;
+      vcycle<double>(P, P.h64, cur, alt, P.f0, faces, o, st);
+      ++cycles;
+    }
+  }
+  if (cur != phi) copy_d2d(phi, cur, F.n, st);
+  if (P.periodic) remove_mean<double>(P, phi, F.n, st);
+  HIPCHK(hipStreamSynchronize(st));
+  if (stats) {
+    stats->cycles = cycles;
+    stats->rel_res = rel;
+  }
+  return status;
+}
+
+rkl_status solve_mixed(Plan& P, const rkl_opts& o, const double* rho, const double* faces, double* phi,
+                       rkl_stats* stats, hipStream_t st) {
+  const Lev& F = P.lv[0];
+  const LevelView<double> V0 = view<double>(F, P.periodic, faces);
+  prepare_source(P, rho, o.four_pi_G, st);
+  const double res0 = resid_norm<double>(P, V0, nullptr, P.f0, st);
+  if (stats) {
+    stats->res0 = res0;
+    stats->levels = P.L();
+    stats->cycles = 0;
+    stats->rel_res = 0.0;
+  }
+  if (res0 == 0.0) {
+    launch_fill<double>(phi, F.n, 0.0, st);
+    HIPCHK(hipStreamSynchronize(st));
+    return RKL_OK;
+  }
+  if (!std::isfinite(res0)) {
+    g_err = "non-finite source or boundary data";
+    return RKL_ENONFINITE;
+  }
+  rkl_status status = RKL_OK;
+  int cycles = 0;
+  double rel = 0.0;
+  int grow = 0;
+  double prev = INFINITY;
+  const int nblk = (int)stencil_blocks(F.nx, F.ny, F.nz);
+  while (true) {
+    // float64 defect r = f - M phi, stored as float32 right-hand side
+    launch_residual<double, float>(V0, phi, P.f0, P.h32.b[0], P.part, st);
+    launch_reduce(P.part, nblk, 2, 2, P.dscal, st);
+    check_launch();
+    const double* h = readback(P, 2, st);
+    rel = std::sqrt(h[0]) / res0;
+    record(stats, rel);
+    if (!std::isfinite(rel)) {
+      status = RKL_ENONFINITE;
+      g_err = "non-finite residual";
+      break;
+    }
+    if (rel <= o.tol) break;
+    grow = rel > prev ? grow + 1 : 0;
+    if (grow >= 3) {
+      status = RKL_EDIVERGED;
+      g_err = "residual grew in 3 consecutive refinements";
+      break;
+    }
+    if (cycles >= o.max_cycles) {
+      status = RKL_ENOCONV;
+      g_err = "max_cycles reached before tol";
+      break;
+    }
+    prev = rel;
+    if (P.periodic) launch_sub_mean<float>(P.h32.b[0], F.n, P.dscal + 1, (double)F.n, st);
+    launch_fill<float>(P.h32.u[0], F.n, 0.0f, st);
+    check_launch();
+    float* cur = P.h32.u[0];
+    float* alt = P.h32.t[0];
+    vcycle<float>(P, P.h32, cur, alt, P.h32.b[0], nullptr, o, st);
+    launch_add_cast<float>(phi, cur, F.n, st);
+    check_launch();
+    P.h32.u[0] = cur;
+    P.h32.t[0] = alt;
+    ++cycles;
+  }
+  if (P.periodic) remove_mean<double>(P, phi, F.n, st);
+  HIPCHK(hipStreamSynchronize(st));
+  if (stats) {
+    stats->cycles = cycles;
+    stats->rel_res = rel;
+  }
+  return status;
+}
+
+template <typename Fn>
+rkl_status guarded(Fn&& fn) {
+  try {
+    return fn();
+  } catch (const Fail& f) {
+    return f.st;
+  } catch (const std::bad_alloc&) {
+    g_err = "host allocation failed";
+    return RKL_ENOMEM;
+  } catch (...) {
+    g_err = "unexpected internal error";
+    return RKL_EHIP;
+  }
+}
+
+}  // namespace
+}  // namespace rkl
+
+using namespace rkl;
+
+extern "C" {
+
+void rkl_default_opts(rkl_opts* o) {
+  if (!o) return;
+  o->s = 2;
+  o->tau_frac = 0.9;
+  o->n_pre = 2;
+  o->n_post = 1;
+  o->min_coarse = 4;
+  o->tol = 1e-10;
+  o->max_cycles = 100;
+  o->prec = RKL_FP64;
+  o->four_pi_G = 4.0 * M_PI;
+  o->coarse_tol = 0.0;
+  o->coarse_max_steps = 200;
+}
+
+const char* rkl_last_error(void) { return g_err.c_str(); }
+
+void rkl_release_all(void) {
+  std::lock_guard<std::mutex> lk(g_plans_mu);
+  g_plans.clear();
+}
+
+rkl_status rkl_poisson_solve(const rkl_grid* grid, const rkl_opts* opts, const double* rho,
+                             const double* bc_faces, double* phi, rkl_stats* stats, void* hip_stream) {
+  return guarded([&]() -> rkl_status {
+    validate_grid(grid, bc_faces);
+    const rkl_opts o = resolve_opts(opts);
+    if (!rho || !phi) fail(RKL_EINVAL, "rho and phi must be non-NULL");
+    if (stats) stats->history_len = 0;
+    Plan& P = get_plan(*grid, o.s, o.tau_frac, o.min_coarse, o.prec);
+    std::lock_guard<std::mutex> lk(P.mu);
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (o.prec == RKL_MIXED) return solve_mixed(P, o, rho, bc_faces, phi, stats, st);
+    return solve_fp64(P, o, rho, bc_faces, phi, stats, st);
+  });
+}
+
+rkl_status mg_vcycle(const rkl_grid* grid, const rkl_opts* opts, const double* f, const double* bc_faces,
+                     double* phi, double* rel_res_out, void* hip_stream) {
+  return guarded([&]() -> rkl_status {
+    validate_grid(grid, bc_faces);
+    rkl_opts o = resolve_opts(opts);
+    o.prec = RKL_FP64;
+    if (!f || !phi) fail(RKL_EINVAL, "f and phi must be non-NULL");
+    Plan& P = get_plan(*grid, o.s, o.tau_frac, o.min_coarse, RKL_FP64);
+    std::lock_guard<std::mutex> lk(P.mu);
+    hipStream_t st = (hipStream_t)hip_stream;
+    double* cur = phi;
+    double* alt = P.t0;
+    vcycle<double>(P, P.h64, cur, alt, f, bc_faces, o, st);
+    if (cur != phi) copy_d2d(phi, cur, P.lv[0].n, st);
+    if (rel_res_out) {
+      const LevelView<double> V0 = view<double>(P.lv[0], P.periodic, bc_faces);
+      const double r0 = resid_norm<double>(P, V0, nullptr, f, st);
+      const double r = resid_norm<double>(P, V0, phi, f, st);
+      *rel_res_out = r0 > 0.0 ? r / r0 : r;
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    return RKL_OK;
+  });
+}
+
+rkl_status rkl_smooth(const rkl_grid* grid, int s, double tau_frac, int n_steps, const double* f,
+                      const double* bc_faces, double* phi, void* hip_stream) {
+  return guarded([&]() -> rkl_status {
+    validate_grid(grid, bc_faces);
+    rkl_opts o;
+    rkl_default_opts(&o);
+    o.s = s;
+    o.tau_frac = tau_frac;
+    o = resolve_opts(&o);
+    if (n_steps < 0) fail(RKL_EINVAL, "n_steps must be >= 0");
+    if (!f || !phi) fail(RKL_EINVAL, "f and phi must be non-NULL");
+    Plan& P = get_plan(*grid, s, tau_frac, INT_MAX, RKL_FP64);
+    std::lock_guard<std::mutex> lk(P.mu);
+    hipStream_t st = (hipStream_t)hip_stream;
+    const LevelView<double> V0 = view<double>(P.lv[0], P.periodic, bc_faces);
+    double* cur = phi;
+    double* alt = P.t0;
+    for (int q = 0; q < n_steps; ++q) tau_step<double>(P, V0, cur, alt, f, P.lv[0].smooth, st);
+    if (cur != phi) copy_d2d(phi, cur, P.lv[0].n, st);
+    HIPCHK(hipStreamSynchronize(st));
+    return RKL_OK;
+  });
+}
+
+rkl_status rkl_residual(const rkl_grid* grid, const double* f, const double* bc_faces, const double* phi,
+                        double* r_out, double* norm_out, void* hip_stream) {
+  return guarded([&]() -> rkl_status {
+    validate_grid(grid, bc_faces);
+    if (!f || !phi) fail(RKL_EINVAL, "f and phi must be non-NULL");
+    Plan& P = get_plan(*grid, 2, 0.9, INT_MAX, RKL_FP64);
+    std::lock_guard<std::mutex> lk(P.mu);
+    hipStream_t st = (hipStream_t)hip_stream;
+    const LevelView<double> V0 = view<double>(P.lv[0], P.periodic, bc_faces);
+    launch_residual<double, double>(V0, phi, f, r_out, P.part, st);
+    launch_reduce(P.part, (int)stencil_blocks(V0.nx, V0.ny, V0.nz), 2, 1, P.dscal, st);
+    check_launch();
+    const double r2 = readback(P, 1, st)[0];
+    if (norm_out) *norm_out = std::sqrt(r2);
+    return RKL_OK;
+  });
+}
+
+rkl_status rkl_restrict(const rkl_grid* grid, const double* fine, double* coarse, void* hip_stream) {
+  return guarded([&]() -> rkl_status {
+    validate_grid(grid, nullptr);
+    if (grid->nx % 2 || grid->ny % 2 || grid->nz % 2) fail(RKL_EINVAL, "fine sizes must be even");
+    if (!fine || !coarse) fail(RKL_EINVAL, "NULL array");
+    hipStream_t st = (hipStream_t)hip_stream;
+    launch_restrict<double>(grid->nx, grid->ny, grid->nz, fine, coarse, st);
+    check_launch();
+    HIPCHK(hipStreamSynchronize(st));
+    return RKL_OK;
+  });
+}
+
+rkl_status rkl_prolong_add(const rkl_grid* grid, const double* coarse, double* fine, void* hip_stream) {
+  return guarded([&]() -> rkl_status {
+    validate_grid(grid, nullptr);
+    if (grid->nx % 2 || grid->ny % 2 || grid->nz % 2) fail(RKL_EINVAL, "fine sizes must be even");
+    if (!fine || !coarse) fail(RKL_EINVAL, "NULL array");
+    hipStream_t st = (hipStream_t)hip_stream;
+    launch_prolong_add<double>(grid->nx, grid->ny, grid->nz, grid->bc == RKL_BC_PERIODIC ? 1 : 0, coarse,
+                               fine, st);
+    check_launch();
+    HIPCHK(hipStreamSynchronize(st));
+    return RKL_OK;
+  });
+}
+
+rkl_status rkl_coarse_solve(const rkl_grid* grid, const rkl_opts* opts, const double* b, double* u,
+                            int* steps_out, void* hip_stream) {
+  return guarded([&]() -> rkl_status {
+    validate_grid(grid, nullptr);
+    const rkl_opts o = resolve_opts(opts);
+    if (!b || !u) fail(RKL_EINVAL, "NULL array");
+    Plan& P = get_plan(*grid, o.s, o.tau_frac, INT_MAX, RKL_FP64);
+    std::lock_guard<std::mutex> lk(P.mu);
+    hipStream_t st = (hipStream_t)hip_stream;
+    // the plan's only level is the coarsest: reuse the V-cycle's coarse path
+    Hier<double> H;
+    H.u = {u};
+    H.b = {const_cast<double*>(b)};
+    H.t = {P.t0};
+    coarse_solve<double>(P, H, 0, o, st);
+    HIPCHK(hipMemcpyAsync(P.hscal, P.dsteps, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (steps_out) {
+      if (P.lv[0].n <= (size_t)COARSE_MAX_CELLS) std::memcpy(steps_out, P.hscal, sizeof(int));
+      else *steps_out = -1;
+    }
+    if (H.u[0] != u) copy_d2d(u, H.u[0], P.lv[0].n, st);
+    HIPCHK(hipStreamSynchronize(st));
+    return RKL_OK;
+  });
+}
+
+rkl_status rkl_poisson_solve_batched(const rkl_grid* grids, int nbatch, const rkl_opts* opts,
+                                     const double* const* rho, double* const* phi, rkl_stats* stats,
+                                     void* hip_stream) {
+  if (nbatch < 0 || (nbatch > 0 && (!grids || !rho || !phi))) {
+    g_err = "bad batch arguments";
+    return RKL_EINVAL;
+  }
+  rkl_status worst = RKL_OK;
+  for (int q = 0; q < nbatch; ++q) {
+    rkl_status s = rkl_poisson_solve(&grids[q], opts, rho[q], nullptr, phi[q], stats ? &stats[q] : nullptr,
+                                     hip_stream);
+    if (s != RKL_OK && worst == RKL_OK) worst = s;
+  }
+  return worst;
+}
+
+}  // extern "C"
