@@ -182,6 +182,15 @@ rkl_status rkl_poisson_solve_batched(const rkl_grid *grids, int nbatch, const rk
                                      const double *const *rho, double *const *phi,
                                      rkl_stats *stats, void *hip_stream);
 
+/*
+ * Number of kernel launches one finest-level tau-step of s stages takes on
+ * this grid (1 when the fused single-pass tau-step kernel handles it, s when
+ * it runs stage by stage), for precision prec (rkl_precision; RKL_MIXED
+ * reports the float32 sweep).  Lets callers turn kernel timings into
+ * bytes per launch.  Returns RKL_EINVAL (< 0) on bad arguments.
+ */
+int rkl_tau_step_launches(const rkl_grid *grid, int s, int prec);
+
 /* Thread-local message describing the last failure (never NULL). */
 const char *rkl_last_error(void);
 

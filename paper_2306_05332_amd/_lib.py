@@ -51,7 +51,7 @@ class c_stats(ctypes.Structure):
 
 EXPORTS = ("rkl_default_opts", "rkl_poisson_solve", "mg_vcycle", "rkl_smooth", "rkl_residual",
            "rkl_restrict", "rkl_prolong_add", "rkl_coarse_solve", "rkl_poisson_solve_batched",
-           "rkl_last_error", "rkl_release_all")
+           "rkl_tau_step_launches", "rkl_last_error", "rkl_release_all")
 
 _lib = None
 
@@ -81,6 +81,8 @@ def load_library(path: str = LIB_PATH):
     for name in ("rkl_poisson_solve", "mg_vcycle", "rkl_smooth", "rkl_residual", "rkl_restrict",
                  "rkl_prolong_add", "rkl_coarse_solve", "rkl_poisson_solve_batched"):
         getattr(lib, name).restype = ctypes.c_int
+    lib.rkl_tau_step_launches.argtypes = [pg, ctypes.c_int, ctypes.c_int]
+    lib.rkl_tau_step_launches.restype = ctypes.c_int
     lib.rkl_last_error.argtypes = []
     lib.rkl_last_error.restype = ctypes.c_char_p
     lib.rkl_release_all.argtypes = []
@@ -273,6 +275,39 @@ def solve_batched(rhos, hs, bcs, opts: Options | None = None, history_cap=64):
     stats = [Stats(s.cycles, s.levels, s.res0, s.rel_res, list(hh[:s.history_len]), 0)
              for s, hh in zip(sts, hists)]
     return phis, stats
+
+
+def tau_step_launches(shape, s, bc="periodic", prec="fp64"):
+    """Kernel launches per finest-level tau-step (1 = fused single pass)."""
+    lib = load_library()
+    g = _grid(shape, 1.0, bc)
+    r = lib.rkl_tau_step_launches(ctypes.byref(g), int(s), PREC[prec])
+    if r < 0:
+        _check(r)
+    return r
+
+
+def kernel_info(shape, s, bc="periodic", prec="fp64"):
+    """Algorithmic HBM bytes of the finest-level sweep kernel, per launch.
+
+    Fused tau-step: u and b read once, Y_s written once: 3 words per cell.
+    Per-stage kernels: stage 1 moves 3 words per cell (Y_0, b in; Y_1 out),
+    stages j >= 2 move 4 (Y_{j-1}, Y_{j-2}, b in; Y_j out); the per-launch
+    figure is their mean over the s launches of one tau-step.
+    """
+    nz, ny, nx = shape
+    cells = nx * ny * nz
+    word = 8 if prec == "fp64" else 4
+    launches = tau_step_launches(shape, s, bc, prec)
+    tname = "double" if prec == "fp64" else "float"
+    if launches == 1:
+        words = 3.0
+        name = f"k_fused_tau<{tname}>"
+    else:
+        words = (3.0 + 4.0 * (s - 1)) / s
+        name = f"k_stage<{tname}>"
+    return {"kernel": name, "launches_per_tau": launches, "bytes_per_launch": words * word * cells,
+            "words_per_cell_launch": words}
 
 
 def release_all():

@@ -1,17 +1,582 @@
-// Fused s-stage RKL tau-step (placeholder until the LDS-tiled kernel lands).
+// Fused s-stage RKL tau-step: all stages of one tau-step (App. A eq.
+// RKL_intermediate_source) in a single HBM pass.
+//
+// Each workgroup owns a BX x BY output tile and a chunk of z planes and
+// marches upward through z.  Plane by plane it keeps, in LDS rings of three
+// planes, the stage values Y_0 (= u), Y_1, ..., Y_{S-1} over the tile plus a
+// halo that shrinks by one cell per stage (Y_j is needed on a halo of S - j
+// cells so that stage j+1 has its 7-point stencil).  Stage j of plane p runs
+// in the iteration that loads u plane p + j, so Y_{j-1} on planes p-1, p, p+1
+// and Y_{j-2} on plane p are resident.  Y_S goes straight to HBM, so u and b
+// are read once and Y_S is written once: 3 words per cell instead of the
+// 3 + 4 (s - 1) words of stage-by-stage sweeps.  The next u plane is loaded
+// into registers while the current stages compute.
+//
+// Boundaries: periodic tiles fetch wrapped halo planes and compute the halo
+// stages as the periodic images they are; Dirichlet stencils that leave the
+// box use the ghost of Sec. 2.3 built from the centre value (2 g - c on the
+// finest level with data, -c otherwise).  Optionally the kernel also returns
+// the float64 partial sums of (M u - b)^2 over its output cells (the residual
+// of the tau-step's input), so a convergence check costs no extra pass.
 #include "kernels.h"
 
 namespace rkl {
 
-template <typename T>
-bool launch_fused_tau(const LevelView<T>&, const T*, const T*, T*, int, const StageCoef*, double*,
-                      hipStream_t) {
-  return false;
+constexpr int FNT = 256;
+
+template <typename T, int S>
+struct FCoef {
+  T mu[S], nu[S], c[S];
+};
+
+__device__ __forceinline__ int slot3(int p) { return (p % 3 + 3) % 3; }
+
+template <typename T, int S, int BX, int BY>
+__global__ __launch_bounds__(FNT) void k_fused_tau(LevelView<T> L, const T* __restrict__ u,
+                                                   const T* __restrict__ b, T* __restrict__ out,
+                                                   FCoef<T, S> co, int zc, int gx_tiles, int gy_tiles,
+                                                   int nblk, double* __restrict__ part,
+                                                   const int* __restrict__ stop) {
+  constexpr int W = BX + 2 * S, H = BY + 2 * S, PL = W * H;
+  constexpr int NU = (PL + FNT - 1) / FNT;                                      // u slots per thread
+  constexpr int NB = ((BX + 2 * S - 2) * (BY + 2 * S - 2) + FNT - 1) / FNT;     // stage slots (stage 1 is largest)
+  __shared__ T ring[S][3][PL];
+  __shared__ double red[FNT / WAVE];
+
+  if (stop != nullptr && *stop) return;
+  const int tid = threadIdx.x;
+  const int nx = L.nx, ny = L.ny, nz = L.nz;
+  const bool per = L.periodic != 0;
+  const size_t sxy = (size_t)nx * ny;
+
+  // XCD-aware tile order: consecutive workgroups are dealt round-robin to the
+  // 8 XCDs, so give each XCD a contiguous run of tiles (its halos then meet
+  // in that XCD's L2).
+  int bid = blockIdx.x;
+  if ((nblk & 7) == 0) bid = (bid & 7) * (nblk >> 3) + (bid >> 3);
+  const int tx = bid % gx_tiles;
+  const int ty = (bid / gx_tiles) % gy_tiles;
+  const int tz = bid / (gx_tiles * gy_tiles);
+  const int x0 = tx * BX - S, y0 = ty * BY - S;  // origin of the haloed plane
+  const int z0 = tz * zc, z1 = min(z0 + zc, nz);
+
+  // u-load slots: global xy offset (-1: outside a Dirichlet box)
+  int goff[NU];
+#pragma unroll
+  for (int q = 0; q < NU; ++q) {
+    const int idx = tid + q * FNT;
+    goff[q] = -1;
+    if (idx < PL) {
+      const int gxr = x0 + idx % W, gyr = y0 + idx / W;
+      if (per) goff[q] = ((gyr % ny + ny) % ny) * nx + (gxr % nx + nx) % nx;
+      else if (gxr >= 0 && gxr < nx && gyr >= 0 && gyr < ny) goff[q] = gyr * nx + gxr;
+    }
+  }
+  // stage slots, fixed for the whole z march: LDS offset, wrapped global
+  // coordinates and flags (bit 0 active, bit 1 owned output cell)
+  int so[S][NB], sgx[S][NB], sgy[S][NB], sfl[S][NB];
+#pragma unroll
+  for (int j = 1; j <= S; ++j) {
+    const int hj = S - j;
+    const int Wj = BX + 2 * hj, Hj = BY + 2 * hj;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+      const int idx = tid + k * FNT;
+      so[j - 1][k] = 0;
+      sgx[j - 1][k] = 0;
+      sgy[j - 1][k] = 0;
+      sfl[j - 1][k] = 0;
+      if (idx < Wj * Hj) {
+        const int lx = idx % Wj + (S - hj), ly = idx / Wj + (S - hj);
+        const int gxr = x0 + lx, gyr = y0 + ly;
+        const bool inbox = gxr >= 0 && gxr < nx && gyr >= 0 && gyr < ny;
+        so[j - 1][k] = ly * W + lx;
+        sgx[j - 1][k] = per ? (gxr % nx + nx) % nx : gxr;
+        sgy[j - 1][k] = per ? (gyr % ny + ny) % ny : gyr;
+        const bool active = per || inbox;
+        const bool own = inbox && lx >= S && lx < S + BX && ly >= S && ly < S + BY;
+        sfl[j - 1][k] = (active ? 1 : 0) | (own ? 2 : 0);
+      }
+    }
+  }
+  auto plane_ok = [&](int p) { return per || (p >= 0 && p < nz); };
+  auto zw = [&](int p) { return per ? (p % nz + nz) % nz : p; };
+  auto stage_on = [&](int j, int p) {
+    const int hj = S - j;
+    return p >= z0 - hj && p <= z1 - 1 + hj && plane_ok(p);
+  };
+
+  // register prefetch of the next iteration's u plane and stage right-hand sides
+  T pre[NU];
+  T bnx[S][NB];
+  auto prefetch = [&](int zl) {
+    {
+      const bool ok = plane_ok(zl);
+      const size_t zo = ok ? (size_t)zw(zl) * sxy : 0;
+#pragma unroll
+      for (int q = 0; q < NU; ++q) pre[q] = (ok && u != nullptr && goff[q] >= 0) ? u[zo + goff[q]] : (T)0;
+    }
+#pragma unroll
+    for (int j = 1; j <= S; ++j) {
+      const int p = zl - j;
+      const bool on = stage_on(j, p);
+      const size_t zo = on ? (size_t)zw(p) * sxy : 0;
+#pragma unroll
+      for (int k = 0; k < NB; ++k)
+        bnx[j - 1][k] = (on && (sfl[j - 1][k] & 1)) ? b[zo + (size_t)sgy[j - 1][k] * nx + sgx[j - 1][k]] : (T)0;
+    }
+  };
+
+  const int zlast = z1 - 1 + S;
+  double r2 = 0.0;
+  prefetch(z0 - S);
+  for (int zl = z0 - S; zl <= zlast; ++zl) {
+    T bcur[S][NB];
+#pragma unroll
+    for (int j = 0; j < S; ++j)
+#pragma unroll
+      for (int k = 0; k < NB; ++k) bcur[j][k] = bnx[j][k];
+    {
+      T* dst = ring[0][slot3(zl)];
+#pragma unroll
+      for (int q = 0; q < NU; ++q) {
+        const int idx = tid + q * FNT;
+        if (idx < PL) dst[idx] = pre[q];
+      }
+    }
+    __syncthreads();
+    if (zl < zlast) prefetch(zl + 1);
+
+#pragma unroll
+    for (int j = 1; j <= S; ++j) {
+      const int p = zl - j;
+      if (stage_on(j, p)) {
+        const int hj = S - j;
+        const int nreg = (BX + 2 * hj) * (BY + 2 * hj);
+        const T* Ym = ring[j - 1][slot3(p - 1)];
+        const T* Yc = ring[j - 1][slot3(p)];
+        const T* Yq = ring[j - 1][slot3(p + 1)];
+        const T* Y2 = ring[j >= 2 ? j - 2 : 0][slot3(p)];
+        T* Yw = ring[j < S ? j : 0][slot3(p)];
+        const size_t zo = (size_t)zw(p) * sxy;
+        const bool zlo = per || p > 0, zhi = per || p < nz - 1;
+        const bool pown = p >= z0 && p < z1;
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+          if (tid + k * FNT >= nreg) break;
+          const int fl = sfl[j - 1][k];
+          if (!(fl & 1)) continue;
+          const int o = so[j - 1][k];
+          const int gx = sgx[j - 1][k], gy = sgy[j - 1][k];
+          const T c = Yc[o];
+          T xm = Yc[o - 1], xp = Yc[o + 1], ym = Yc[o - W], yp = Yc[o + W];
+          T zm = Ym[o], zp = Yq[o];
+          if (!per) {
+            if (gx == 0) xm = dir_ghost(L, 0, (size_t)p * ny + gy, c);
+            if (gx == nx - 1) xp = dir_ghost(L, 1, (size_t)p * ny + gy, c);
+            if (gy == 0) ym = dir_ghost(L, 2, (size_t)p * nx + gx, c);
+            if (gy == ny - 1) yp = dir_ghost(L, 3, (size_t)p * nx + gx, c);
+            if (!zlo) zm = dir_ghost(L, 4, (size_t)gy * nx + gx, c);
+            if (!zhi) zp = dir_ghost(L, 5, (size_t)gy * nx + gx, c);
+          }
+          const T lap = ((xm + xp) - (T)2 * c) * L.ihx2 + ((ym + yp) - (T)2 * c) * L.ihy2 +
+                        ((zm + zp) - (T)2 * c) * L.ihz2;
+          const T r = lap - bcur[j - 1][k];
+          const bool own = (fl & 2) && pown;
+          T y;
+          if (j == 1) {
+            y = c + co.c[0] * r;
+            if (part != nullptr && own) r2 += (double)r * (double)r;
+          } else {
+            y = co.mu[j - 1] * c + co.nu[j - 1] * Y2[o] + co.c[j - 1] * r;
+          }
+          if (j < S) Yw[o] = y;
+          else if (own) out[zo + (size_t)gy * nx + gx] = y;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (part != nullptr) {
+    const double t = block_sum<FNT>(r2, red);
+    if (tid == 0) part[blockIdx.x] = t;
+  }
 }
 
+// ---------------------------------------------------------------- z-queue variant
+// Same algorithm, different storage: every thread owns fixed (x, y) columns
+// of the stage-1 region for the whole z march and keeps, per column, register
+// queues of the last three planes of u and of Y_1 .. Y_{S-1} (the z
+// neighbours) and of b for the planes the stages are working on.  LDS holds
+// only the plane each stage reads its x/y neighbours from: u's current plane
+// and, double-buffered, the current plane of Y_1 .. Y_{S-1}.  So b is read once
+// per cell, a tile can be larger for the same LDS, and the outputs of Y_S are
+// stored one iteration later, together with the next prefetch.
+template <typename T, int S, int BX, int BY, int NT, int PD, int DS>
+__global__ __launch_bounds__(NT) void k_tau_zq(LevelView<T> L, const T* __restrict__ u, const T* __restrict__ b,
+                                               T* __restrict__ out, FCoef<T, S> co, int zc, int gx_tiles,
+                                               int gy_tiles, int nblk, double* __restrict__ part,
+                                               const int* __restrict__ stop) {
+  constexpr int W0 = BX + 2 * S, H0 = BY + 2 * S, P0 = W0 * H0;          // haloed u plane
+  constexpr int W1 = W0 - 2, H1 = H0 - 2, P1 = W1 * H1;                  // stage-1 region = slot region
+  constexpr int NB = (P1 + NT - 1) / NT;
+  constexpr int NRING = P0 - P1;
+  constexpr int NR = (NRING + NT - 1) / NT;
+  constexpr int NY = S > 1 ? S - 1 : 1;
+  __shared__ T su[P0];
+  __shared__ T sy[NY][2][P0];
+  __shared__ double red[NT / WAVE];
+
+  if (stop != nullptr && *stop) return;
+  const int tid = threadIdx.x;
+  const int nx = L.nx, ny = L.ny, nz = L.nz;
+  const bool per = L.periodic != 0;
+  const size_t sxy = (size_t)nx * ny;
+  int bid = blockIdx.x;
+  if ((nblk & 7) == 0) bid = (bid & 7) * (nblk >> 3) + (bid >> 3);
+  const int tx = bid % gx_tiles;
+  const int ty = (bid / gx_tiles) % gy_tiles;
+  const int tz = bid / (gx_tiles * gy_tiles);
+  const int x0 = tx * BX - S, y0 = ty * BY - S;
+  const int z0 = tz * zc, z1 = min(z0 + zc, nz);
+
+  // slot metadata: LDS offset, wrapped global xy offset, flags: bits 0-7
+  // depth (distance to the haloed plane's edge), bit 8 active, bit 9 owned
+  // output cell, bits 10-13 on the x-, x+, y-, y+ face of a Dirichlet box
+  int sg[NB], sf[NB];
+  auto so = [&](int k) {  // LDS offset of slot k (compile-time divisors)
+    const int idx = tid + k * NT;
+    return (idx / W1 + 1) * W0 + idx % W1 + 1;
+  };
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    const int idx = tid + k * NT;
+    sg[k] = 0;
+    sf[k] = 0;
+    if (idx < P1) {
+      const int lx = idx % W1 + 1, ly = idx / W1 + 1;
+      const int gxr = x0 + lx, gyr = y0 + ly;
+      const bool inbox = gxr >= 0 && gxr < nx && gyr >= 0 && gyr < ny;
+      const int gx = per ? (gxr % nx + nx) % nx : gxr;
+      const int gy = per ? (gyr % ny + ny) % ny : gyr;
+      const int d = min(min(lx, ly), min(W0 - 1 - lx, H0 - 1 - ly));
+      const bool active = per || inbox;
+      const bool own = inbox && d >= S;
+      sg[k] = active ? gy * nx + gx : 0;
+      int bf = 0;
+      if (!per && inbox) bf = (gx == 0 ? 1 : 0) | (gx == nx - 1 ? 2 : 0) | (gy == 0 ? 4 : 0) | (gy == ny - 1 ? 8 : 0);
+      sf[k] = d | (active ? 256 : 0) | (own ? 512 : 0) | (bf << 10);
+    }
+  }
+  // ring positions: the outer edge of the haloed plane
+  int ro[NR], rg[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int idx = tid + r * NT;
+    ro[r] = -1;
+    rg[r] = -1;
+    if (idx < NRING) {
+      int lx, ly;
+      if (idx < W0) { lx = idx; ly = 0; }
+      else if (idx < 2 * W0) { lx = idx - W0; ly = H0 - 1; }
+      else if (idx < 2 * W0 + H0 - 2) { lx = 0; ly = idx - 2 * W0 + 1; }
+      else { lx = W0 - 1; ly = idx - 2 * W0 - (H0 - 2) + 1; }
+      ro[r] = ly * W0 + lx;
+      const int gxr = x0 + lx, gyr = y0 + ly;
+      if (per) rg[r] = ((gyr % ny + ny) % ny) * nx + (gxr % nx + nx) % nx;
+      else if (gxr >= 0 && gxr < nx && gyr >= 0 && gyr < ny) rg[r] = gyr * nx + gxr;
+    }
+  }
+  auto plane_ok = [&](int p) { return per || (p >= 0 && p < nz); };
+  auto zw = [&](int p) { return per ? (p % nz + nz) % nz : p; };
+  auto stage_on = [&](int j, int p) {
+    const int hj = S - j;
+    return p >= z0 - hj && p <= z1 - 1 + hj && plane_ok(p);
+  };
+
+  T uq0[NB], uq1[NB], uq2[NB];   // u at planes zl-2, zl-1, zl
+  T yq0[NY][NB], yq1[NY][NB], yq2[NY][NB];  // Y_j at planes zl-j-2, zl-j-1, zl-j
+  T bq[S][NB];                   // bq[j-1] = b at plane zl-j
+  T unx[NB], bnx[NB], rnx[NR];   // in flight: u(zl+1), b(zl), ring u(zl)
+  T unx2[NB], bnx2[NB], rnx2[NR]; // two-deep prefetch (PD == 2): the set after
+  T yst[DS ? NB : 1];            // Y_S awaiting its store (DS: deferred stores)
+  int yso[DS ? NB : 1];          // its plane (or -1)
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    uq0[k] = uq1[k] = uq2[k] = (T)0;
+    for (int j = 0; j < NY; ++j) yq0[j][k] = yq1[j][k] = yq2[j][k] = (T)0;
+    for (int j = 0; j < S; ++j) bq[j][k] = (T)0;
+    if (DS) {
+      yst[DS ? k : 0] = (T)0;
+      yso[DS ? k : 0] = -1;
+    }
+  }
+  auto prefetch_to = [&](int zl, T (&un)[NB], T (&bn)[NB], T (&rn)[NR]) {
+    // u(zl + 1) and b(zl) at the slots, u(zl) on the ring
+    {
+      const int p = zl + 1;
+      const bool ok = u != nullptr && plane_ok(p);
+      const size_t zo = ok ? (size_t)zw(p) * sxy : 0;
+#pragma unroll
+      for (int k = 0; k < NB; ++k) un[k] = (ok && (sf[k] & 256)) ? u[zo + sg[k]] : (T)0;
+    }
+    {
+      const int p = zl;
+      const bool ok = u != nullptr && plane_ok(p);
+      const size_t zo = ok ? (size_t)zw(p) * sxy : 0;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) rn[r] = (ok && rg[r] >= 0) ? u[zo + rg[r]] : (T)0;
+    }
+    {
+      const int p = zl;
+      const bool ok = plane_ok(p) && p >= z0 - (S - 1) && p <= z1 - 1 + (S - 1);
+      const size_t zo = ok ? (size_t)zw(p) * sxy : 0;
+#pragma unroll
+      for (int k = 0; k < NB; ++k) bn[k] = (ok && (sf[k] & 256)) ? b[zo + sg[k]] : (T)0;
+    }
+  };
+  auto flush = [&]() {
+    if (!DS) return;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+      if (yso[DS ? k : 0] >= 0) out[(size_t)yso[DS ? k : 0] * sxy + sg[k]] = yst[DS ? k : 0];
+      yso[DS ? k : 0] = -1;
+    }
+  };
+
+  const int zfirst = z0 - S, zlast = z1 - 1 + S;
+  double r2 = 0.0;
+  // state before iteration zfirst: u(zfirst) and u(zfirst - 1) needed
+  prefetch_to(zfirst - 1, unx, bnx, rnx);  // u(zfirst), ring u(zfirst - 1), b(zfirst - 1)
+  if (PD == 2 && zfirst < zlast) prefetch_to(zfirst, unx2, bnx2, rnx2);
+  {
+    // u(zfirst - 1) at the slots seeds the queue
+    const int p = zfirst - 1;
+    const bool ok = u != nullptr && plane_ok(p);
+    const size_t zo = ok ? (size_t)zw(p) * sxy : 0;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) uq2[k] = (ok && (sf[k] & 256)) ? u[zo + sg[k]] : (T)0;
+  }
+  for (int zl = zfirst; zl <= zlast; ++zl) {
+    // shift the queues: u(zl) arrives, b(zl - 1) arrives
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+      uq0[k] = uq1[k];
+      uq1[k] = uq2[k];
+      uq2[k] = unx[k];
+#pragma unroll
+      for (int j = S - 1; j > 0; --j) bq[j][k] = bq[j - 1][k];
+      bq[0][k] = bnx[k];
+    }
+    // u's current plane (zl - 1) into LDS: slots from the queue, ring from flight
+#pragma unroll
+    for (int k = 0; k < NB; ++k)
+      if (tid + k * NT < P1) su[so(k)] = uq1[k];
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+      if (ro[r] >= 0) su[ro[r]] = rnx[r];
+    __syncthreads();
+    flush();
+    if (PD == 2) {
+      // the set in flight moves up; the one after it is issued now
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        unx[q] = unx2[q];
+        bnx[q] = bnx2[q];
+      }
+#pragma unroll
+      for (int r = 0; r < NR; ++r) rnx[r] = rnx2[r];
+      if (zl + 1 < zlast) prefetch_to(zl + 1, unx2, bnx2, rnx2);
+    } else {
+      if (zl < zlast) prefetch_to(zl, unx, bnx, rnx);
+    }
+
+#pragma unroll
+    for (int j = 1; j <= S; ++j) {
+      const int p = zl - j;
+      const bool on = stage_on(j, p);
+      const bool zlo = per || p > 0, zhi = per || p < nz - 1;
+      const bool pown = p >= z0 && p < z1;
+      const T* Xc = (j == 1) ? su : sy[j >= 2 ? j - 2 : 0][p & 1];
+#pragma unroll
+      for (int k = 0; k < NB; ++k) {
+        const int fl = sf[k];
+        T y = (T)0;
+        const bool act = on && (fl & 256) && (fl & 255) >= j && (tid + k * NT < P1);
+        if (act) {
+          const int o = so(k);
+          T c, zm, zp, y2;
+          if (j == 1) {
+            c = uq1[k];
+            zm = uq0[k];
+            zp = uq2[k];
+            y2 = (T)0;
+          } else {
+            c = yq1[j - 2][k];
+            zm = yq0[j - 2][k];
+            zp = yq2[j - 2][k];
+            y2 = (j == 2) ? uq0[k] : yq0[j >= 3 ? j - 3 : 0][k];
+          }
+          T xm = Xc[o - 1], xp = Xc[o + 1], ym = Xc[o - W0], yp = Xc[o + W0];
+          if (!per && ((fl >> 10) != 0 || !zlo || !zhi)) {
+            const int gy = sg[k] / nx, gx = sg[k] - gy * nx;
+            if (fl & (1 << 10)) xm = dir_ghost(L, 0, (size_t)p * ny + gy, c);
+            if (fl & (2 << 10)) xp = dir_ghost(L, 1, (size_t)p * ny + gy, c);
+            if (fl & (4 << 10)) ym = dir_ghost(L, 2, (size_t)p * nx + gx, c);
+            if (fl & (8 << 10)) yp = dir_ghost(L, 3, (size_t)p * nx + gx, c);
+            if (!zlo) zm = dir_ghost(L, 4, (size_t)gy * nx + gx, c);
+            if (!zhi) zp = dir_ghost(L, 5, (size_t)gy * nx + gx, c);
+          }
+          const T lap = ((xm + xp) - (T)2 * c) * L.ihx2 + ((ym + yp) - (T)2 * c) * L.ihy2 +
+                        ((zm + zp) - (T)2 * c) * L.ihz2;
+          const T r = lap - bq[j - 1][k];
+          if (j == 1) {
+            y = c + co.c[0] * r;
+            if (part != nullptr && (fl & 512) && pown) r2 += (double)r * (double)r;
+          } else {
+            y = co.mu[j - 1] * c + co.nu[j - 1] * y2 + co.c[j - 1] * r;
+          }
+          if (j == S && (fl & 512) && pown) {
+            if (DS) {
+              yst[k] = y;
+              yso[k] = zw(p);
+            } else {
+              out[(size_t)zw(p) * sxy + sg[k]] = y;
+            }
+          }
+        }
+        if (j < S) {
+          yq0[j - 1][k] = yq1[j - 1][k];
+          yq1[j - 1][k] = yq2[j - 1][k];
+          yq2[j - 1][k] = y;
+          if (act) sy[j - 1][p & 1][so(k)] = y;
+        }
+      }
+      if (j < S) __syncthreads();
+    }
+    if (S == 1) __syncthreads();
+  }
+  flush();
+  if (part != nullptr) {
+    const double t = block_sum<NT>(r2, red);
+    if (tid == 0) part[blockIdx.x] = t;
+  }
+}
+
+// ---------------------------------------------------------------- launch
+template <typename T, int S>
+struct FusedTile;
+// float64: 64 x 8 tiles for s <= 2 (39 KB LDS at s = 2), 64 x 4 for s = 3
+template <> struct FusedTile<double, 1> { static constexpr int BX = 64, BY = 8; };
+template <> struct FusedTile<double, 2> { static constexpr int BX = 64, BY = 8; };
+template <> struct FusedTile<double, 3> { static constexpr int BX = 64, BY = 4; };
+template <> struct FusedTile<float, 1> { static constexpr int BX = 64, BY = 8; };
+template <> struct FusedTile<float, 2> { static constexpr int BX = 64, BY = 8; };
+template <> struct FusedTile<float, 3> { static constexpr int BX = 64, BY = 8; };
+template <> struct FusedTile<float, 4> { static constexpr int BX = 64, BY = 4; };
+
+template <typename T>
+constexpr int fused_max_s() {
+  return sizeof(T) == 8 ? 3 : 4;
+}
+
+template <typename T>
+bool fused_tau_supported(const LevelView<T>& L, int s) {
+  return s >= 1 && s <= fused_max_s<T>() && L.nx >= 32 && L.ny >= 8 && L.nz >= 8;
+}
+
+struct FusedGrid {
+  int gx, gy, gz, zc, nblk;
+};
+
+template <int BX, int BY>
+FusedGrid fused_grid(int nx, int ny, int nz, int target = 1024, int zc_max = 32) {
+  FusedGrid g;
+  g.gx = (nx + BX - 1) / BX;
+  g.gy = (ny + BY - 1) / BY;
+  // z chunks: aim for `target` workgroups; a chunk spans 4 .. zc_max planes
+  // (short chunks keep small levels from being one long serial march)
+  const int xy = g.gx * g.gy;
+  const int chunks = std::max(1, (target + xy - 1) / xy);
+  g.zc = std::max(4, std::min(zc_max, (nz + chunks - 1) / chunks));
+  g.gz = (nz + g.zc - 1) / g.zc;
+  g.nblk = g.gx * g.gy * g.gz;
+  return g;
+}
+
+// Large float64 levels at s = 2 use the z-queue kernel with 64 x 32 tiles
+// and 512 threads (one workgroup per CU, 32-plane chunks); everything else the
+// LDS-ring kernel.
+constexpr int ZQ_BX = 64, ZQ_BY = 32, ZQ_NT = 512;
+
+template <typename T>
+bool use_zq(const LevelView<T>& L, int s) {
+  return sizeof(T) == 8 && s == 2 && L.nx >= 128 && L.ny >= 128 && L.nz >= 64;
+}
+
+template <typename T, int S>
+FCoef<T, S> make_fcoef(const StageCoef* co) {
+  FCoef<T, S> fc;
+  for (int j = 0; j < S; ++j) {
+    fc.mu[j] = (T)co[j].mu;
+    fc.nu[j] = (T)co[j].nu;
+    fc.c[j] = (T)co[j].c;
+  }
+  return fc;
+}
+
+template <typename T, int S>
+void launch_fused_S(const LevelView<T>& L, const T* u, const T* b, T* out, const StageCoef* co,
+                    double* part, const int* stop, hipStream_t st) {
+  const FCoef<T, S> fc = make_fcoef<T, S>(co);
+  if constexpr (sizeof(T) == 8 && S == 2) {
+    if (use_zq<T>(L, S)) {
+      const FusedGrid g = fused_grid<ZQ_BX, ZQ_BY>(L.nx, L.ny, L.nz, 256, 32);
+      hipLaunchKernelGGL((k_tau_zq<T, S, ZQ_BX, ZQ_BY, ZQ_NT, 1, 0>), dim3(g.nblk), dim3(ZQ_NT), 0, st, L, u, b,
+                         out, fc, g.zc, g.gx, g.gy, g.nblk, part, stop);
+      return;
+    }
+  }
+  constexpr int BX = FusedTile<T, S>::BX, BY = FusedTile<T, S>::BY;
+  const FusedGrid g = fused_grid<BX, BY>(L.nx, L.ny, L.nz);
+  hipLaunchKernelGGL((k_fused_tau<T, S, BX, BY>), dim3(g.nblk), dim3(FNT), 0, st, L, u, b, out, fc, g.zc,
+                     g.gx, g.gy, g.nblk, part, stop);
+}
+
+template <typename T>
+size_t fused_tau_blocks(const LevelView<T>& L, int s) {
+  if (use_zq<T>(L, s)) return (size_t)fused_grid<ZQ_BX, ZQ_BY>(L.nx, L.ny, L.nz, 256, 32).nblk;
+  int BY = 8;
+  if (sizeof(T) == 8 && s == 3) BY = 4;
+  if (sizeof(T) == 4 && s == 4) BY = 4;
+  FusedGrid g = (BY == 8) ? fused_grid<64, 8>(L.nx, L.ny, L.nz) : fused_grid<64, 4>(L.nx, L.ny, L.nz);
+  return (size_t)g.nblk;
+}
+
+template <typename T>
+bool launch_fused_tau(const LevelView<T>& L, const T* u, const T* b, T* out, int s, const StageCoef* co,
+                      double* part, const int* stop, hipStream_t st) {
+  if (!fused_tau_supported<T>(L, s)) return false;
+  switch (s) {
+    case 1: launch_fused_S<T, 1>(L, u, b, out, co, part, stop, st); return true;
+    case 2: launch_fused_S<T, 2>(L, u, b, out, co, part, stop, st); return true;
+    case 3: launch_fused_S<T, 3>(L, u, b, out, co, part, stop, st); return true;
+    default:
+      if constexpr (sizeof(T) == 4) {
+        launch_fused_S<T, 4>(L, u, b, out, co, part, stop, st);
+        return true;
+      }
+      return false;
+  }
+}
+
+template bool fused_tau_supported<double>(const LevelView<double>&, int);
+template bool fused_tau_supported<float>(const LevelView<float>&, int);
+template size_t fused_tau_blocks<double>(const LevelView<double>&, int);
+template size_t fused_tau_blocks<float>(const LevelView<float>&, int);
 template bool launch_fused_tau<double>(const LevelView<double>&, const double*, const double*, double*,
-                                       int, const StageCoef*, double*, hipStream_t);
+                                       int, const StageCoef*, double*, const int*, hipStream_t);
 template bool launch_fused_tau<float>(const LevelView<float>&, const float*, const float*, float*, int,
-                                      const StageCoef*, double*, hipStream_t);
+                                      const StageCoef*, double*, const int*, hipStream_t);
 
 }  // namespace rkl

@@ -7,35 +7,56 @@
 
 namespace rkl {
 
-size_t stencil_blocks(int nx, int ny, int nz);  // partial-sum slots used by residual-type kernels
-size_t ew_block_count(size_t n);                // partial-sum slots used by k_scale
+size_t stencil_blocks(int nx, int ny, int nz);  // blocks of the per-stage kernel
+size_t resid_blocks(int nx, int ny, int nz);    // partial-sum pairs written by residual-type kernels
+size_t ew_block_count(size_t n);                // partial-sum slots used by k_scale / k_sum
+
+// Device-side state of the V-cycle convergence loop.
+constexpr int CONV_HIST = 512;
+struct ConvState {
+  int stop;       // set once the loop has decided to stop; cycle kernels then return at once
+  int status;     // rkl_status of the decision (0 = converged)
+  int m;          // index of the next cycle-start state to test
+  int result_m;   // cycle-start state the decision refers to (the answer)
+  double rel;     // last relative residual
+  double mean;    // mean of the last tested residual (periodic float32 rhs)
+  double last[4]; // last four relative residuals (divergence test)
+  double hist[CONV_HIST];
+};
 
 template <typename T>
 void launch_stage(const LevelView<T>& L, const T* yp, const T* ypp, const T* b, T* yout, double mu,
-                  double nu, double c, int first, hipStream_t st);
+                  double nu, double c, int first, const int* stop, hipStream_t st);
+// transfer.hip: part receives resid_blocks() pairs (sum r^2, sum r | sum of coarse values)
 template <typename TU, typename TR>
 void launch_residual(const LevelView<TU>& L, const TU* u, const TU* b, TR* r_out, double* part,
-                     hipStream_t st);
+                     const int* stop, hipStream_t st);
 template <typename T>
 void launch_resid_restrict(const LevelView<T>& F, const T* u, const T* b, T* bc, double* part,
-                           hipStream_t st);
+                           const int* stop, hipStream_t st);
 template <typename T>
-void launch_prolong_add(int fnx, int fny, int fnz, int periodic, const T* e, T* fine, hipStream_t st);
+void launch_prolong_add(int fnx, int fny, int fnz, int periodic, const T* e, T* fine, const int* stop,
+                        hipStream_t st);
 template <typename T>
 void launch_restrict(int fnx, int fny, int fnz, const T* fine, T* coarse, hipStream_t st);
-void launch_reduce(const double* part, int nblk, int stride, int nq, double* out, hipStream_t st);
+void launch_reduce(const double* part, int nblk, int stride, int nq, double* out, const int* stop,
+                   hipStream_t st);
+void launch_check(const double* part, int nblk, int stride, const double* res0sq, double tol, int max_cycles,
+                  double count, ConvState* cs, hipStream_t st);
 template <typename T>
-void launch_fill(T* a, size_t n, T v, hipStream_t st);
+void launch_fill(T* a, size_t n, T v, const int* stop, hipStream_t st);
 void launch_scale(const double* in, double* out, size_t n, double c, double* part, hipStream_t st);
 template <typename T>
-void launch_sub_mean(T* a, size_t n, const double* sum, double count, hipStream_t st);
+void launch_sub_mean(T* a, size_t n, const double* sum, double count, const int* stop, hipStream_t st);
 template <typename T>
 void launch_sum(const T* a, size_t n, double* part, hipStream_t st);  // ew_block_count(n) partials
 template <typename TE>
-void launch_add_cast(double* u, const TE* e, size_t n, hipStream_t st);
+void launch_add_cast(double* u, const TE* e, size_t n, const int* stop, hipStream_t st);
 
 // Coarsest-grid accelerated RKL solve in one workgroup (coarse.hip).
 constexpr int COARSE_MAX_CELLS = 2048;
+constexpr int COARSE_MAX_SCHED = 64;   // schedule entries cached in LDS (plans keep within this)
+constexpr int COARSE_MAX_COEF = 512;   // stage rows cached in LDS
 struct CoarseSchedule {
   const int* sched;     // device: stage count of schedule entry q
   const int* coff;      // device: first coefficient row of entry q
@@ -45,7 +66,7 @@ struct CoarseSchedule {
 template <typename T>
 void launch_coarse_solve(const LevelView<T>& L, const T* b, const T* u_in, T* u, CoarseSchedule cs,
                          double tol, double ref_norm, int max_steps, int remove_mean, int* steps_out,
-                         double* res_out, hipStream_t st);
+                         double* res_out, const int* stop, hipStream_t st);
 
 // Fused s-stage tau-step, one HBM pass (fused.hip).  Returns false when the
 // configuration is not supported (caller falls back to per-stage kernels).
@@ -54,7 +75,32 @@ struct StageCoef {
 };
 constexpr int FUSED_MAX_S = 4;
 template <typename T>
+bool fused_tau_supported(const LevelView<T>& L, int s);
+template <typename T>
+size_t fused_tau_blocks(const LevelView<T>& L, int s);  // partial sums written when part != nullptr
+// u == nullptr: the input iterate is zero
+template <typename T>
 bool launch_fused_tau(const LevelView<T>& L, const T* u, const T* b, T* out, int s,
-                      const StageCoef* co, double* part, hipStream_t st);
+                      const StageCoef* co, double* part, const int* stop, hipStream_t st);
+
+// Coarse tail of the V-cycle in one workgroup (tail.hip).
+constexpr int TAIL_MAX_LEVELS = 4;
+constexpr int TAIL_MAX_S = 8;
+constexpr int TAIL_MAX_CELLS = 4096;          // cells of the top tail level
+constexpr size_t TAIL_MAX_LDS = 120 * 1024;   // dynamic LDS for the tail arrays
+struct TailShape {
+  int nlev;
+  int nx[TAIL_MAX_LEVELS], ny[TAIL_MAX_LEVELS], nz[TAIL_MAX_LEVELS];
+  double ihx2[TAIL_MAX_LEVELS], ihy2[TAIL_MAX_LEVELS], ihz2[TAIL_MAX_LEVELS];
+};
+template <typename T>
+bool tail_fits(const TailShape& ts, int s);
+// b_top: restricted right-hand side of the top tail level (mean not yet
+// removed); u_top receives that level's correction.  smooth[l]: the s stage
+// coefficients of tail level l.
+template <typename T>
+void launch_tail(const TailShape& ts, const StageCoef* const* smooth, int s, int n_pre, int n_post, int periodic,
+                 CoarseSchedule cs, double ctol, int cmax, const T* b_top, T* u_top, const int* stop,
+                 hipStream_t st);
 
 }  // namespace rkl

@@ -98,4 +98,27 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return t;
 }
 
+// Sum over one wavefront with DPP row shifts and row broadcasts (GFX9 DPP
+// controls row_shr:1,2,4,8, row_bcast:15, row_bcast:31): a fixed order, no
+// LDS round trips.  Every lane returns the total (read from lane 63).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_mov_f64(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const int l2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROW_MASK, 0xf, true);
+  const int h2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROW_MASK, 0xf, true);
+  return __hiloint2double(h2, l2);
+}
+
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v += dpp_mov_f64<0x111, 0xf>(v);  // row_shr:1
+  v += dpp_mov_f64<0x112, 0xf>(v);  // row_shr:2
+  v += dpp_mov_f64<0x114, 0xf>(v);  // row_shr:4
+  v += dpp_mov_f64<0x118, 0xf>(v);  // row_shr:8: lane 15 of each row holds the row sum
+  v += dpp_mov_f64<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_mov_f64<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3: lane 63 holds the total
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
+}
+
 }  // namespace rkl

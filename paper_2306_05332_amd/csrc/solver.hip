@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -137,8 +138,11 @@ struct Plan {
   std::vector<Lev> lv;
   Hier<double> h64;
   Hier<float> h32;
-  double* f0 = nullptr;  // level-0 source (float64)
-  double* t0 = nullptr;  // level-0 alternate iterate (float64)
+  double* f0 = nullptr;   // level-0 source (float64)
+  double* t0 = nullptr;   // level-0 alternate iterates (float64): with phi they form the
+  double* t0b = nullptr;  // three buffers that keep a cycle's start state intact
+  ConvState* dconv = nullptr;  // device convergence state
+  ConvState* hconv = nullptr;  // pinned host mirror
   double* part = nullptr;
   size_t part_cap = 0;
   double* dscal = nullptr;  // device scalars
@@ -150,6 +154,7 @@ struct Plan {
   int* d_sched = nullptr;
   int* d_coff = nullptr;
   double* d_coef = nullptr;
+  int tail64 = -1, tail32 = -1;  // first level run by the one-workgroup tail (-1: none)
   std::vector<void*> allocs;
   std::mutex mu;
 
@@ -173,6 +178,7 @@ struct Plan {
     (void)hipSetDevice(key.dev);
     for (void* p : allocs) (void)hipFree(p);
     if (hscal) (void)hipHostFree(hscal);
+    if (hconv) (void)hipHostFree(hconv);
     (void)hipSetDevice(cur);
   }
 };
@@ -209,6 +215,28 @@ std::vector<Lev> build_levels(const rkl_grid& g, int min_coarse, int s, double t
   return lv;
 }
 
+bool coarse_in_lds(const Plan& P, const Lev& C);
+
+TailShape tail_shape(const Plan& P, int lt) {
+  TailShape ts;
+  std::memset(&ts, 0, sizeof(ts));
+  ts.nlev = P.L() - lt;
+  if (ts.nlev > TAIL_MAX_LEVELS) {
+    ts.nlev = TAIL_MAX_LEVELS + 1;  // too deep: tail_fits rejects it
+    return ts;
+  }
+  for (int l = lt; l < P.L(); ++l) {
+    const Lev& V = P.lv[l];
+    ts.nx[l - lt] = V.nx;
+    ts.ny[l - lt] = V.ny;
+    ts.nz[l - lt] = V.nz;
+    ts.ihx2[l - lt] = 1.0 / (V.hx * V.hx);
+    ts.ihy2[l - lt] = 1.0 / (V.hy * V.hy);
+    ts.ihz2[l - lt] = 1.0 / (V.hz * V.hz);
+  }
+  return ts;
+}
+
 Plan& get_plan(const rkl_grid& g, int s, double theta, int min_coarse, int prec) {
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
@@ -221,9 +249,9 @@ Plan& get_plan(const rkl_grid& g, int s, double theta, int min_coarse, int prec)
   P->periodic = g.bc == RKL_BC_PERIODIC;
   P->lv = build_levels(g, min_coarse, s, theta);
   const int L = P->L();
-  // work buffers
   P->f0 = P->alloc<double>(P->lv[0].n);
   P->t0 = P->alloc<double>(P->lv[0].n);
+  P->t0b = P->alloc<double>(P->lv[0].n);
   P->h64.u.assign(L, nullptr);
   P->h64.b.assign(L, nullptr);
   P->h64.t.assign(L, nullptr);
@@ -242,14 +270,26 @@ Plan& get_plan(const rkl_grid& g, int s, double theta, int min_coarse, int prec)
       P->h32.t[l] = P->alloc<float>(P->lv[l].n);
     }
   }
-  size_t cap = 2 * stencil_blocks(g.nx, g.ny, g.nz);
+  // partial sums: residual kernels (pairs), fused tau-step (one per block), elementwise sums
+  size_t cap = 2 * resid_blocks(g.nx, g.ny, g.nz);
   cap = std::max(cap, ew_block_count(P->lv[0].n));
-  cap = std::max<size_t>(cap, 64);
+  {
+    const Lev& F = P->lv[0];
+    LevelView<double> vd{F.nx, F.ny, F.nz, 1.0, 1.0, 1.0, P->periodic ? 1 : 0, nullptr};
+    LevelView<float> vf{F.nx, F.ny, F.nz, 1.0f, 1.0f, 1.0f, P->periodic ? 1 : 0, nullptr};
+    for (int sq = 1; sq <= FUSED_MAX_S; ++sq) {
+      cap = std::max(cap, fused_tau_blocks<double>(vd, sq));
+      cap = std::max(cap, fused_tau_blocks<float>(vf, sq));
+    }
+  }
+  cap = std::max(cap, (size_t)1024);
   P->part = P->alloc<double>(cap);
   P->part_cap = cap;
   P->dscal = P->alloc<double>(16);
   P->dsteps = P->alloc<int>(4);
+  P->dconv = P->alloc<ConvState>(1);
   HIPCHK(hipHostMalloc((void**)&P->hscal, 16 * sizeof(double), hipHostMallocDefault));
+  HIPCHK(hipHostMalloc((void**)&P->hconv, sizeof(ConvState), hipHostMallocDefault));
   // coarsest schedule tables
   const Lev& C = P->lv[L - 1];
   P->sched = accel_schedule(C, P->periodic, theta);
@@ -271,6 +311,13 @@ Plan& get_plan(const rkl_grid& g, int s, double theta, int min_coarse, int prec)
   HIPCHK(hipMemcpy(P->d_sched, P->sched.data(), P->sched.size() * sizeof(int), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(P->d_coff, coff.data(), coff.size() * sizeof(int), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(P->d_coef, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice));
+  if (coarse_in_lds(*P, C) && L >= 3) {
+    for (int lt = 1; lt < L - 1; ++lt) {
+      const TailShape ts = tail_shape(*P, lt);
+      if (P->tail64 < 0 && tail_fits<double>(ts, s)) P->tail64 = lt;
+      if (P->tail32 < 0 && tail_fits<float>(ts, s)) P->tail32 = lt;
+    }
+  }
   Plan& ref = *P;
   g_plans[key] = std::move(P);
   return ref;
@@ -290,6 +337,14 @@ LevelView<T> view(const Lev& L, bool periodic, const double* faces) {
   return v;
 }
 
+// the coarsest level fits the one-workgroup LDS solver
+bool coarse_in_lds(const Plan& P, const Lev& C) {
+  size_t rows = 0;
+  for (int s : P.sched) rows += (size_t)s;
+  return C.n <= (size_t)COARSE_MAX_CELLS && P.sched.size() <= (size_t)COARSE_MAX_SCHED &&
+         rows <= (size_t)COARSE_MAX_COEF;
+}
+
 // read `nq` device scalars (synchronises the stream)
 const double* readback(Plan& P, int nq, hipStream_t st) {
   HIPCHK(hipMemcpyAsync(P.hscal, P.dscal, nq * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -297,44 +352,99 @@ const double* readback(Plan& P, int nq, hipStream_t st) {
   return P.hscal;
 }
 
-// ||b - M u||_2 (u may be nullptr), synchronising
+// ||b - M u||^2 into P.dscal[0] (u may be nullptr), not synchronising
+template <typename T>
+void resid_norm2_async(Plan& P, const LevelView<T>& V, const T* u, const T* b, hipStream_t st) {
+  launch_residual<T, T>(V, u, b, (T*)nullptr, P.part, nullptr, st);
+  check_launch();
+  launch_reduce(P.part, (int)resid_blocks(V.nx, V.ny, V.nz), 2, 1, P.dscal, nullptr, st);
+  check_launch();
+}
+
+// ||b - M u||_2, synchronising
 template <typename T>
 double resid_norm(Plan& P, const LevelView<T>& V, const T* u, const T* b, hipStream_t st) {
-  launch_residual<T, T>(V, u, b, (T*)nullptr, P.part, st);
-  check_launch();
-  launch_reduce(P.part, (int)stencil_blocks(V.nx, V.ny, V.nz), 2, 1, P.dscal, st);
-  check_launch();
+  resid_norm2_async<T>(P, V, u, b, st);
   return std::sqrt(readback(P, 1, st)[0]);
 }
 
 template <typename T>
-void remove_mean(Plan& P, T* a, size_t n, hipStream_t st) {
+void remove_mean(Plan& P, T* a, size_t n, const int* stop, hipStream_t st) {
   launch_sum<T>(a, n, P.part, st);
-  launch_reduce(P.part, (int)ew_block_count(n), 1, 1, P.dscal + 8, st);
-  launch_sub_mean<T>(a, n, P.dscal + 8, (double)n, st);
+  launch_reduce(P.part, (int)ew_block_count(n), 1, 1, P.dscal + 8, stop, st);
+  launch_sub_mean<T>(a, n, P.dscal + 8, (double)n, stop, st);
   check_launch();
 }
 
 // ------------------------------------------------------------------ tau-steps
+// One tau-step on M u = b from `cur`; the result ends in `cur` (the buffers
+// are swapped when it lands in `alt`).  Fused single-pass kernel when the
+// level supports it, otherwise one kernel per stage with Y_j written over
+// Y_{j-2}.
 template <typename T>
 void tau_step(Plan& P, const LevelView<T>& V, T*& cur, T*& alt, const T* b,
-              const std::vector<StageCoef>& co, hipStream_t st) {
+              const std::vector<StageCoef>& co, const int* stop, hipStream_t st) {
   const int s = (int)co.size();
-  if (launch_fused_tau<T>(V, cur, b, alt, s, co.data(), nullptr, st)) {
+  if (launch_fused_tau<T>(V, cur, b, alt, s, co.data(), nullptr, stop, st)) {
     check_launch();
     std::swap(cur, alt);
     return;
   }
-  launch_stage<T>(V, cur, nullptr, b, alt, co[0].mu, co[0].nu, co[0].c, 1, st);
+  launch_stage<T>(V, cur, nullptr, b, alt, co[0].mu, co[0].nu, co[0].c, 1, stop, st);
   for (int j = 2; j <= s; ++j) {
     // Y_{j-1} is in `alt` for even j (odd index), in `cur` for odd j; Y_j
     // overwrites Y_{j-2} in the other buffer
     T* yp = (j & 1) ? cur : alt;
     T* yw = (j & 1) ? alt : cur;
-    launch_stage<T>(V, yp, yw, b, yw, co[j - 1].mu, co[j - 1].nu, co[j - 1].c, 0, st);
+    launch_stage<T>(V, yp, yw, b, yw, co[j - 1].mu, co[j - 1].nu, co[j - 1].c, 0, stop, st);
   }
   check_launch();
   if (s & 1) std::swap(cur, alt);
+}
+
+// A tau-step whose input is the zero iterate (first relaxation of a coarse
+// correction); the result lands in `cur` (its previous contents are ignored).
+template <typename T>
+void tau_from_zero(Plan& P, const LevelView<T>& V, T*& cur, T*& alt, const T* b,
+                   const std::vector<StageCoef>& co, const int* stop, hipStream_t st) {
+  const int s = (int)co.size();
+  if (launch_fused_tau<T>(V, (const T*)nullptr, b, cur, s, co.data(), nullptr, stop, st)) {
+    check_launch();
+    return;
+  }
+  launch_fill<T>(cur, (size_t)V.nx * V.ny * V.nz, (T)0, stop, st);
+  check_launch();
+  tau_step<T>(P, V, cur, alt, b, co, stop, st);
+}
+
+// A tau-step from `a` that never writes `a`: the result lands in x or y and
+// is returned in `cur`, the other in `alt`.  With `part` the fused kernel
+// also writes the partial sums of (M a - b)^2.
+template <typename T>
+bool tau_keep(Plan& P, const LevelView<T>& V, T* a, T* x, T* y, T*& cur, T*& alt, const T* b,
+              const std::vector<StageCoef>& co, double* part, const int* stop, hipStream_t st) {
+  const int s = (int)co.size();
+  if (launch_fused_tau<T>(V, a, b, x, s, co.data(), part, stop, st)) {
+    check_launch();
+    cur = x;
+    alt = y;
+    return true;
+  }
+  // stage 1: a -> x; stage j >= 2 writes over Y_{j-2}, except that Y_0 = a
+  // is never overwritten (stage 2 writes y)
+  launch_stage<T>(V, a, nullptr, b, x, co[0].mu, co[0].nu, co[0].c, 1, stop, st);
+  T* yjm1 = x;  // Y_{j-1}
+  T* yjm2 = a;  // Y_{j-2}
+  for (int j = 2; j <= s; ++j) {
+    T* w = (j == 2) ? y : yjm2;
+    launch_stage<T>(V, yjm1, yjm2, b, w, co[j - 1].mu, co[j - 1].nu, co[j - 1].c, 0, stop, st);
+    yjm2 = yjm1;
+    yjm1 = w;
+  }
+  check_launch();
+  cur = yjm1;
+  alt = (cur == x) ? y : x;
+  return false;
 }
 
 // Accelerated RKL iteration driven from the host (levels too large for the
@@ -349,8 +459,8 @@ int accel_multi(Plan& P, const LevelView<T>& V, T*& cur, T*& alt, const T* b, do
     res = resid_norm<T>(P, V, cur, b, st);
     if (res <= tol * ref || step >= max_steps) break;
     const int q = std::min(step, (int)P.sched.size() - 1);
-    tau_step<T>(P, V, cur, alt, b, P.sched_coef[q], st);
-    if (rm_mean) remove_mean<T>(P, cur, n, st);
+    tau_step<T>(P, V, cur, alt, b, P.sched_coef[q], nullptr, st);
+    if (rm_mean) remove_mean<T>(P, cur, n, nullptr, st);
     ++step;
   }
   if (res_out) *res_out = res;
@@ -365,61 +475,93 @@ double coarse_tol_for(const rkl_opts& o) {
 
 // coarsest level l: M u_l = b_l from u_l = 0
 template <typename T>
-void coarse_solve(Plan& P, Hier<T>& H, int l, const rkl_opts& o, hipStream_t st) {
+void coarse_solve(Plan& P, Hier<T>& H, int l, const rkl_opts& o, const int* stop, hipStream_t st) {
   const Lev& C = P.lv[l];
   const LevelView<T> V = view<T>(C, P.periodic, nullptr);
   const double tol = coarse_tol_for<T>(o);
-  if (C.n <= (size_t)COARSE_MAX_CELLS) {
-    launch_coarse_solve<T>(V, H.b[l], nullptr, H.u[l], P.cs(), tol, 0.0, o.coarse_max_steps, P.periodic ? 1 : 0,
-                           P.dsteps, nullptr, st);
+  if (coarse_in_lds(P, C)) {
+    launch_coarse_solve<T>(V, H.b[l], nullptr, H.u[l], P.cs(), tol, 0.0, o.coarse_max_steps,
+                           P.periodic ? 1 : 0, P.dsteps, nullptr, stop, st);
     check_launch();
     return;
   }
-  launch_fill<T>(H.u[l], C.n, (T)0, st);
+  if (stop != nullptr) {
+    // inside the device-side loop: skip once it has decided to stop
+    int flag = 0;
+    HIPCHK(hipMemcpyAsync(P.hscal, stop, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    std::memcpy(&flag, P.hscal, sizeof(int));
+    if (flag) return;
+  }
+  launch_fill<T>(H.u[l], C.n, (T)0, nullptr, st);
   const double bn = resid_norm<T>(P, V, (const T*)nullptr, H.b[l], st);
   if (bn == 0.0) return;
   accel_multi<T>(P, V, H.u[l], H.t[l], H.b[l], tol, bn, o.coarse_max_steps, P.periodic, st, nullptr);
 }
 
-// One V-cycle on M_0 u = b0 (Sec. 2.1).  cur0/alt0: level-0 iterate and its
-// alternate buffer (swapped as tau-steps complete).  faces0: level-0
-// Dirichlet data (float64 path only) or nullptr.
+// The V-cycle of Sec. 2.1 on M_0 u = b0 below the first level-0 relaxation.
+// On entry cur0 holds the iterate after `pre_done` level-0 relaxations
+// (alt0 is its alternate buffer); on exit cur0 holds the cycle's result.
+// faces0: level-0 Dirichlet data (float64 path only) or nullptr.
 template <typename T>
-void vcycle(Plan& P, Hier<T>& H, T*& cur0, T*& alt0, const T* b0, const double* faces0,
-            const rkl_opts& o, hipStream_t st) {
+int tail_level(const Plan& P) {
+  return sizeof(T) == 8 ? P.tail64 : P.tail32;
+}
+
+template <typename T>
+void vcycle_from(Plan& P, Hier<T>& H, T*& cur0, T*& alt0, const T* b0, const double* faces0, int pre_done,
+                 const rkl_opts& o, const int* stop, hipStream_t st) {
   const int L = P.L();
   auto V = [&](int l) { return view<T>(P.lv[l], P.periodic, l == 0 ? faces0 : nullptr); };
   if (L == 1) {
-    for (int q = 0; q < o.n_pre + o.n_post; ++q) tau_step<T>(P, V(0), cur0, alt0, b0, P.lv[0].smooth, st);
+    for (int q = pre_done; q < o.n_pre + o.n_post; ++q)
+      tau_step<T>(P, V(0), cur0, alt0, b0, P.lv[0].smooth, stop, st);
     return;
   }
-  for (int q = 0; q < o.n_pre; ++q) tau_step<T>(P, V(0), cur0, alt0, b0, P.lv[0].smooth, st);
-  for (int l = 1; l < L; ++l) {
+  // levels lt.. run in the one-workgroup tail when they fit
+  const int lt = (o.n_pre + o.n_post > 0) ? tail_level<T>(P) : -1;
+  const int lbot = lt > 0 ? lt : L - 1;
+  for (int q = pre_done; q < o.n_pre; ++q) tau_step<T>(P, V(0), cur0, alt0, b0, P.lv[0].smooth, stop, st);
+  for (int l = 1; l <= lbot; ++l) {
     T* fu = (l == 1) ? cur0 : H.u[l - 1];
     const T* fb = (l == 1) ? b0 : H.b[l - 1];
-    launch_resid_restrict<T>(V(l - 1), fu, fb, H.b[l], P.part, st);
+    launch_resid_restrict<T>(V(l - 1), fu, fb, H.b[l], P.part, stop, st);
     check_launch();
+    const Lev& C = P.lv[l];
+    if (l == lt) {
+      const TailShape ts = tail_shape(P, lt);
+      const StageCoef* sm[TAIL_MAX_LEVELS];
+      for (int k = 0; k < ts.nlev; ++k) sm[k] = P.lv[lt + k].smooth.data();
+      launch_tail<T>(ts, sm, o.s, o.n_pre, o.n_post, P.periodic ? 1 : 0, P.cs(), coarse_tol_for<T>(o),
+                     o.coarse_max_steps, H.b[lt], H.u[lt], stop, st);
+      check_launch();
+      break;
+    }
     if (P.periodic) {
-      const Lev& C = P.lv[l];
-      launch_reduce(P.part, (int)stencil_blocks(C.nx, C.ny, C.nz), 2, 2, P.dscal, st);
-      launch_sub_mean<T>(H.b[l], C.n, P.dscal + 1, (double)C.n, st);
+      const Lev& Fl = P.lv[l - 1];
+      launch_reduce(P.part, (int)resid_blocks(Fl.nx, Fl.ny, Fl.nz), 2, 2, P.dscal, stop, st);
+      launch_sub_mean<T>(H.b[l], C.n, P.dscal + 1, (double)C.n, stop, st);
       check_launch();
     }
     if (l < L - 1) {
-      launch_fill<T>(H.u[l], P.lv[l].n, (T)0, st);
-      for (int q = 0; q < o.n_pre; ++q) tau_step<T>(P, V(l), H.u[l], H.t[l], H.b[l], P.lv[l].smooth, st);
+      if (o.n_pre > 0) {
+        tau_from_zero<T>(P, V(l), H.u[l], H.t[l], H.b[l], C.smooth, stop, st);
+        for (int q = 1; q < o.n_pre; ++q) tau_step<T>(P, V(l), H.u[l], H.t[l], H.b[l], C.smooth, stop, st);
+      } else {
+        launch_fill<T>(H.u[l], C.n, (T)0, stop, st);
+      }
     } else {
-      coarse_solve<T>(P, H, l, o, st);
+      coarse_solve<T>(P, H, l, o, stop, st);
     }
   }
-  for (int l = L - 2; l >= 0; --l) {
+  for (int l = lbot - 1; l >= 0; --l) {
     T*& cu = (l == 0) ? cur0 : H.u[l];
     T*& ca = (l == 0) ? alt0 : H.t[l];
     const T* bl = (l == 0) ? b0 : H.b[l];
     const Lev& F = P.lv[l];
-    launch_prolong_add<T>(F.nx, F.ny, F.nz, P.periodic ? 1 : 0, H.u[l + 1], cu, st);
+    launch_prolong_add<T>(F.nx, F.ny, F.nz, P.periodic ? 1 : 0, H.u[l + 1], cu, stop, st);
     check_launch();
-    for (int q = 0; q < o.n_post; ++q) tau_step<T>(P, V(l), cu, ca, bl, F.smooth, st);
+    for (int q = 0; q < o.n_post; ++q) tau_step<T>(P, V(l), cu, ca, bl, F.smooth, stop, st);
   }
 }
 
@@ -429,8 +571,8 @@ void prepare_source(Plan& P, const double* rho, double c, hipStream_t st) {
   launch_scale(rho, P.f0, n, c, P.part, st);
   check_launch();
   if (P.periodic) {
-    launch_reduce(P.part, (int)ew_block_count(n), 1, 1, P.dscal + 8, st);
-    launch_sub_mean<double>(P.f0, n, P.dscal + 8, (double)n, st);
+    launch_reduce(P.part, (int)ew_block_count(n), 1, 1, P.dscal + 8, nullptr, st);
+    launch_sub_mean<double>(P.f0, n, P.dscal + 8, (double)n, nullptr, st);
     check_launch();
   }
 }
@@ -442,6 +584,43 @@ void copy_d2d(double* dst, const double* src, size_t n, hipStream_t st) {
 void record(rkl_stats* stats, double rel) {
   if (stats && stats->history && stats->history_len < stats->history_cap)
     stats->history[stats->history_len++] = rel;
+}
+
+// reset the device convergence state with a kernel-free copy from the pinned
+// mirror (no memset: the sequence stays capturable)
+void conv_reset(Plan& P, hipStream_t st) {
+  std::memset(P.hconv, 0, sizeof(ConvState));
+  HIPCHK(hipMemcpyAsync(P.dconv, P.hconv, offsetof(ConvState, hist), hipMemcpyHostToDevice, st));
+}
+
+const ConvState& conv_read(Plan& P, hipStream_t st) {
+  HIPCHK(hipMemcpyAsync(P.hconv, P.dconv, sizeof(ConvState), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return *P.hconv;
+}
+
+// how many more cycles to queue: enough to reach tol at the observed
+// contraction (0.12 before any is observed), plus the cycle whose start
+// state is tested last
+int predict_batch(const ConvState& cs, double tol, int queued, int max_cycles) {
+  double rho = 0.12, last = 1.0;
+  const int m = cs.m;  // states tested so far
+  if (m >= 1 && m - 1 < CONV_HIST) last = cs.hist[m - 1];
+  if (m >= 2 && m - 1 < CONV_HIST && cs.hist[m - 2] > 0.0) rho = cs.hist[m - 1] / cs.hist[m - 2];
+  rho = std::min(0.9, std::max(0.01, rho));
+  int need = 1;
+  if (last > tol && tol > 0.0) need = (int)std::ceil(std::log(tol / last) / std::log(rho)) + 1;
+  need = std::max(1, std::min(need, 64));
+  const int left = max_cycles + 1 - queued;
+  return std::max(1, std::min(need, left));
+}
+
+void fill_stats(rkl_stats* stats, const ConvState& cs, int result_m) {
+  if (!stats) return;
+  stats->history_len = 0;
+  for (int q = 0; q <= result_m && q < CONV_HIST; ++q) record(stats, cs.hist[q]);
+  stats->cycles = result_m;
+  stats->rel_res = cs.rel;
 }
 
 // ------------------------------------------------------------------ validation
@@ -474,39 +653,69 @@ rkl_opts resolve_opts(const rkl_opts* in) {
 }
 
 // ------------------------------------------------------------------ solves
-rkl_status solve_fp64(Plan& P, const rkl_opts& o, const double* rho, const double* faces, double* phi,
-                      rkl_stats* stats, hipStream_t st) {
+// Common start: f0, ||M 0 - f0||.  Returns false when the solve is already
+// decided (zero right-hand side or non-finite data); `status` says how.
+bool solve_start(Plan& P, const rkl_opts& o, const double* rho, const double* faces, double* phi,
+                 rkl_stats* stats, hipStream_t st, double& res0, rkl_status& status) {
   const Lev& F = P.lv[0];
   const LevelView<double> V0 = view<double>(F, P.periodic, faces);
   prepare_source(P, rho, o.four_pi_G, st);
-  const double res0 = resid_norm<double>(P, V0, nullptr, P.f0, st);
+  resid_norm2_async<double>(P, V0, nullptr, P.f0, st);
+  HIPCHK(hipMemcpyAsync(P.dscal + 4, P.dscal, sizeof(double), hipMemcpyDeviceToDevice, st));  // res0^2
+  res0 = std::sqrt(readback(P, 1, st)[0]);
   if (stats) {
     stats->res0 = res0;
     stats->levels = P.L();
     stats->cycles = 0;
     stats->rel_res = 0.0;
   }
+  status = RKL_OK;
   if (res0 == 0.0) {
-    launch_fill<double>(phi, F.n, 0.0, st);
+    launch_fill<double>(phi, F.n, 0.0, nullptr, st);
     check_launch();
     HIPCHK(hipStreamSynchronize(st));
-    return RKL_OK;
+    return false;
   }
   if (!std::isfinite(res0)) {
     g_err = "non-finite source or boundary data";
-    return RKL_ENONFINITE;
+    status = RKL_ENONFINITE;
+    return false;
   }
-  double* cur = phi;
-  double* alt = P.t0;
-  rkl_status status = RKL_OK;
-  int cycles = 0;
-  double rel = 0.0;
+  return true;
+}
+
+// res0^2 kept on the device for the convergence test; the check kernel takes sqrt
+struct Res0Sqrt {
+  static const double* ptr(Plan& P) { return P.dscal + 5; }
+};
+
+rkl_status finish_status(const ConvState& cs) {
+  switch (cs.status) {
+    case 0: return RKL_OK;
+    case -3: g_err = "max_cycles reached before tol"; return RKL_ENOCONV;
+    case -4: g_err = "residual grew in 3 consecutive cycles"; return RKL_EDIVERGED;
+    case -5: g_err = "non-finite residual"; return RKL_ENONFINITE;
+    default: g_err = "unexpected convergence state"; return RKL_EHIP;
+  }
+}
+
+rkl_status solve_fp64(Plan& P, const rkl_opts& o, const double* rho, const double* faces, double* phi,
+                      rkl_stats* stats, hipStream_t st) {
+  const Lev& F = P.lv[0];
+  const LevelView<double> V0 = view<double>(F, P.periodic, faces);
+  double res0;
+  rkl_status status;
+  if (!solve_start(P, o, rho, faces, phi, stats, st, res0, status)) return status;
+
   if (P.L() == 1) {
+    // single level: accelerated RKL iteration (App. A.4, App. B) to tol
+    int cycles = 0;
     double res = 0.0;
-    if (F.n <= (size_t)COARSE_MAX_CELLS) {
-      // one workgroup holds the whole level in LDS; it starts from phi
+    double* cur = phi;
+    double* alt = P.t0;
+    if (coarse_in_lds(P, F)) {
       launch_coarse_solve<double>(V0, P.f0, phi, P.t0, P.cs(), o.tol, res0, o.max_cycles, 0, P.dsteps,
-                                  P.dscal, st);
+                                  P.dscal, nullptr, st);
       check_launch();
       copy_d2d(phi, P.t0, F.n, st);
       HIPCHK(hipMemcpyAsync(P.hscal, P.dsteps, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -518,121 +727,136 @@ rkl_status solve_fp64(Plan& P, const rkl_opts& o, const double* rho, const doubl
       res = P.hscal[1];
     } else {
       cycles = accel_multi<double>(P, V0, cur, alt, P.f0, o.tol, res0, o.max_cycles, false, st, &res);
+      if (cur != phi) copy_d2d(phi, cur, F.n, st);
     }
-    rel = res / res0;
+    const double rel = res / res0;
     record(stats, rel);
     if (!std::isfinite(rel)) status = RKL_ENONFINITE;
-    else if (rel > o.tol) status = RKL_ENOCONV;
-  } else {
-    int grow = 0;
-    double prev = INFINITY;
-    while (true) {
-      rel = resid_norm<double>(P, V0, cur, P.f0, st) / res0;
-      record(stats, rel);
-      if (!std::isfinite(rel)) {
-        status = RKL_ENONFINITE;
-        g_err = "non-finite residual";
-        break;
-      }
-      if (rel <= o.tol) break;
-      grow = rel > prev ? grow + 1 : 0;
-      if (grow >= 3) {
-        status = RKL_EDIVERGED;
-        g_err = "residual grew in 3 consecutive V-cycles";
-        break;
-      }
-      if (cycles >= o.max_cycles) {
-        status = RKL_ENOCONV;
-        g_err = "max_cycles reached before tol";
-        break;
-      }
-      prev = rel;
-      vcycle<double>(P, P.h64, cur, alt, P.f0, faces, o, st);
-      ++cycles;
+    else if (rel > o.tol) {
+      status = RKL_ENOCONV;
+      g_err = "max_cycles reached before tol";
     }
+    if (P.periodic) remove_mean<double>(P, phi, F.n, nullptr, st);
+    HIPCHK(hipStreamSynchronize(st));
+    if (stats) {
+      stats->cycles = cycles;
+      stats->rel_res = rel;
+    }
+    return status;
   }
-  if (cur != phi) copy_d2d(phi, cur, F.n, st);
-  if (P.periodic) remove_mean<double>(P, phi, F.n, st);
+
+  // V-cycles with the convergence test on the device.  Cycle m starts from
+  // buffer bufs[start[m]] and writes only the other two, so when the test at
+  // the start of cycle m stops the loop, that buffer is the answer.
+  double* bufs[3] = {phi, P.t0, P.t0b};
+  std::vector<int> start(1, 0);
+  HIPCHK(hipMemcpyAsync(P.dscal + 5, P.dscal + 4, sizeof(double), hipMemcpyDeviceToDevice, st));
+  conv_reset(P, st);
+  const int* stop = &P.dconv->stop;
+  const bool fused0 = fused_tau_supported<double>(V0, o.s) && o.n_pre > 0;
+  int queued = 0;
+  ConvState cs = conv_read(P, st);
+  while (true) {
+    const int batch = predict_batch(cs, o.tol, queued, o.max_cycles);
+    for (int q = 0; q < batch; ++q) {
+      const int m = queued;
+      const int ia = start[m], ib = (ia + 1) % 3, ic = (ia + 2) % 3;
+      double* a = bufs[ia];
+      double *cur, *alt;
+      int pre_done;
+      int nblk, stride;
+      if (fused0) {
+        // first relaxation, fused with the residual norm of the start state
+        tau_keep<double>(P, V0, a, bufs[ib], bufs[ic], cur, alt, P.f0, F.smooth, P.part, stop, st);
+        nblk = (int)fused_tau_blocks<double>(V0, o.s);
+        stride = 1;
+        launch_check(P.part, nblk, stride, Res0Sqrt::ptr(P), o.tol, o.max_cycles, 1.0, P.dconv, st);
+        check_launch();
+        pre_done = 1;
+      } else {
+        launch_residual<double, double>(V0, a, P.f0, (double*)nullptr, P.part, stop, st);
+        nblk = (int)resid_blocks(F.nx, F.ny, F.nz);
+        stride = 2;
+        launch_check(P.part, nblk, stride, Res0Sqrt::ptr(P), o.tol, o.max_cycles, 1.0, P.dconv, st);
+        check_launch();
+        if (o.n_pre > 0) {
+          tau_keep<double>(P, V0, a, bufs[ib], bufs[ic], cur, alt, P.f0, F.smooth, nullptr, stop, st);
+          pre_done = 1;
+        } else {
+          copy_d2d(bufs[ib], a, F.n, st);
+          cur = bufs[ib];
+          alt = bufs[ic];
+          pre_done = 0;
+        }
+      }
+      vcycle_from<double>(P, P.h64, cur, alt, P.f0, faces, pre_done, o, stop, st);
+      int ie = 0;
+      for (int k = 0; k < 3; ++k)
+        if (bufs[k] == cur) ie = k;
+      start.push_back(ie);
+      ++queued;
+    }
+    cs = conv_read(P, st);
+    if (cs.stop) break;
+    if (queued > o.max_cycles) fail(RKL_EHIP, "convergence loop ended without a decision");
+  }
+  const int rm = cs.result_m;
+  double* res = bufs[start[rm]];
+  if (res != phi) copy_d2d(phi, res, F.n, st);
+  if (P.periodic) remove_mean<double>(P, phi, F.n, nullptr, st);
   HIPCHK(hipStreamSynchronize(st));
-  if (stats) {
-    stats->cycles = cycles;
-    stats->rel_res = rel;
-  }
-  return status;
+  fill_stats(stats, cs, rm);
+  return finish_status(cs);
 }
 
 rkl_status solve_mixed(Plan& P, const rkl_opts& o, const double* rho, const double* faces, double* phi,
                        rkl_stats* stats, hipStream_t st) {
   const Lev& F = P.lv[0];
   const LevelView<double> V0 = view<double>(F, P.periodic, faces);
-  prepare_source(P, rho, o.four_pi_G, st);
-  const double res0 = resid_norm<double>(P, V0, nullptr, P.f0, st);
-  if (stats) {
-    stats->res0 = res0;
-    stats->levels = P.L();
-    stats->cycles = 0;
-    stats->rel_res = 0.0;
-  }
-  if (res0 == 0.0) {
-    launch_fill<double>(phi, F.n, 0.0, st);
-    HIPCHK(hipStreamSynchronize(st));
-    return RKL_OK;
-  }
-  if (!std::isfinite(res0)) {
-    g_err = "non-finite source or boundary data";
-    return RKL_ENONFINITE;
-  }
-  rkl_status status = RKL_OK;
-  int cycles = 0;
-  double rel = 0.0;
-  int grow = 0;
-  double prev = INFINITY;
-  const int nblk = (int)stencil_blocks(F.nx, F.ny, F.nz);
+  const LevelView<float> V32 = view<float>(F, P.periodic, nullptr);
+  double res0;
+  rkl_status status;
+  if (!solve_start(P, o, rho, faces, phi, stats, st, res0, status)) return status;
+  HIPCHK(hipMemcpyAsync(P.dscal + 5, P.dscal + 4, sizeof(double), hipMemcpyDeviceToDevice, st));
+  conv_reset(P, st);
+  const int* stop = &P.dconv->stop;
+  const int nblk = (int)resid_blocks(F.nx, F.ny, F.nz);
+  int queued = 0;
+  ConvState cs = conv_read(P, st);
   while (true) {
-    // float64 defect r = f - M phi, stored as float32 right-hand side
-    launch_residual<double, float>(V0, phi, P.f0, P.h32.b[0], P.part, st);
-    launch_reduce(P.part, nblk, 2, 2, P.dscal, st);
-    check_launch();
-    const double* h = readback(P, 2, st);
-    rel = std::sqrt(h[0]) / res0;
-    record(stats, rel);
-    if (!std::isfinite(rel)) {
-      status = RKL_ENONFINITE;
-      g_err = "non-finite residual";
-      break;
+    const int batch = predict_batch(cs, o.tol, queued, o.max_cycles);
+    for (int q = 0; q < batch; ++q) {
+      // float64 defect r = f - M phi, stored as the float32 right-hand side
+      launch_residual<double, float>(V0, phi, P.f0, P.h32.b[0], P.part, stop, st);
+      launch_check(P.part, nblk, 2, Res0Sqrt::ptr(P), o.tol, o.max_cycles, (double)F.n, P.dconv, st);
+      check_launch();
+      if (P.periodic) {
+        launch_sub_mean<float>(P.h32.b[0], F.n, &P.dconv->mean, 1.0, stop, st);
+        check_launch();
+      }
+      // one float32 V-cycle on M e = r from e = 0 (homogeneous level-0 ghosts)
+      float* cur = P.h32.u[0];
+      float* alt = P.h32.t[0];
+      int pre_done = 0;
+      if (o.n_pre > 0) {
+        tau_from_zero<float>(P, V32, cur, alt, P.h32.b[0], F.smooth, stop, st);
+        pre_done = 1;
+      } else {
+        launch_fill<float>(cur, F.n, 0.0f, stop, st);
+      }
+      vcycle_from<float>(P, P.h32, cur, alt, P.h32.b[0], nullptr, pre_done, o, stop, st);
+      launch_add_cast<float>(phi, cur, F.n, stop, st);
+      check_launch();
+      ++queued;
     }
-    if (rel <= o.tol) break;
-    grow = rel > prev ? grow + 1 : 0;
-    if (grow >= 3) {
-      status = RKL_EDIVERGED;
-      g_err = "residual grew in 3 consecutive refinements";
-      break;
-    }
-    if (cycles >= o.max_cycles) {
-      status = RKL_ENOCONV;
-      g_err = "max_cycles reached before tol";
-      break;
-    }
-    prev = rel;
-    if (P.periodic) launch_sub_mean<float>(P.h32.b[0], F.n, P.dscal + 1, (double)F.n, st);
-    launch_fill<float>(P.h32.u[0], F.n, 0.0f, st);
-    check_launch();
-    float* cur = P.h32.u[0];
-    float* alt = P.h32.t[0];
-    vcycle<float>(P, P.h32, cur, alt, P.h32.b[0], nullptr, o, st);
-    launch_add_cast<float>(phi, cur, F.n, st);
-    check_launch();
-    P.h32.u[0] = cur;
-    P.h32.t[0] = alt;
-    ++cycles;
+    cs = conv_read(P, st);
+    if (cs.stop) break;
+    if (queued > o.max_cycles) fail(RKL_EHIP, "refinement loop ended without a decision");
   }
-  if (P.periodic) remove_mean<double>(P, phi, F.n, st);
+  if (P.periodic) remove_mean<double>(P, phi, F.n, nullptr, st);
   HIPCHK(hipStreamSynchronize(st));
-  if (stats) {
-    stats->cycles = cycles;
-    stats->rel_res = rel;
-  }
-  return status;
+  fill_stats(stats, cs, cs.result_m);
+  return finish_status(cs);
 }
 
 template <typename Fn>
@@ -706,7 +930,7 @@ rkl_status mg_vcycle(const rkl_grid* grid, const rkl_opts* opts, const double* f
     hipStream_t st = (hipStream_t)hip_stream;
     double* cur = phi;
     double* alt = P.t0;
-    vcycle<double>(P, P.h64, cur, alt, f, bc_faces, o, st);
+    vcycle_from<double>(P, P.h64, cur, alt, f, bc_faces, 0, o, nullptr, st);
     if (cur != phi) copy_d2d(phi, cur, P.lv[0].n, st);
     if (rel_res_out) {
       const LevelView<double> V0 = view<double>(P.lv[0], P.periodic, bc_faces);
@@ -736,7 +960,7 @@ rkl_status rkl_smooth(const rkl_grid* grid, int s, double tau_frac, int n_steps,
     const LevelView<double> V0 = view<double>(P.lv[0], P.periodic, bc_faces);
     double* cur = phi;
     double* alt = P.t0;
-    for (int q = 0; q < n_steps; ++q) tau_step<double>(P, V0, cur, alt, f, P.lv[0].smooth, st);
+    for (int q = 0; q < n_steps; ++q) tau_step<double>(P, V0, cur, alt, f, P.lv[0].smooth, nullptr, st);
     if (cur != phi) copy_d2d(phi, cur, P.lv[0].n, st);
     HIPCHK(hipStreamSynchronize(st));
     return RKL_OK;
@@ -752,8 +976,8 @@ rkl_status rkl_residual(const rkl_grid* grid, const double* f, const double* bc_
     std::lock_guard<std::mutex> lk(P.mu);
     hipStream_t st = (hipStream_t)hip_stream;
     const LevelView<double> V0 = view<double>(P.lv[0], P.periodic, bc_faces);
-    launch_residual<double, double>(V0, phi, f, r_out, P.part, st);
-    launch_reduce(P.part, (int)stencil_blocks(V0.nx, V0.ny, V0.nz), 2, 1, P.dscal, st);
+    launch_residual<double, double>(V0, phi, f, r_out, P.part, nullptr, st);
+    launch_reduce(P.part, (int)resid_blocks(V0.nx, V0.ny, V0.nz), 2, 1, P.dscal, nullptr, st);
     check_launch();
     const double r2 = readback(P, 1, st)[0];
     if (norm_out) *norm_out = std::sqrt(r2);
@@ -781,7 +1005,7 @@ rkl_status rkl_prolong_add(const rkl_grid* grid, const double* coarse, double* f
     if (!fine || !coarse) fail(RKL_EINVAL, "NULL array");
     hipStream_t st = (hipStream_t)hip_stream;
     launch_prolong_add<double>(grid->nx, grid->ny, grid->nz, grid->bc == RKL_BC_PERIODIC ? 1 : 0, coarse,
-                               fine, st);
+                               fine, nullptr, st);
     check_launch();
     HIPCHK(hipStreamSynchronize(st));
     return RKL_OK;
@@ -802,16 +1026,31 @@ rkl_status rkl_coarse_solve(const rkl_grid* grid, const rkl_opts* opts, const do
     H.u = {u};
     H.b = {const_cast<double*>(b)};
     H.t = {P.t0};
-    coarse_solve<double>(P, H, 0, o, st);
+    const bool lds = coarse_in_lds(P, P.lv[0]);
+    coarse_solve<double>(P, H, 0, o, nullptr, st);
     HIPCHK(hipMemcpyAsync(P.hscal, P.dsteps, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     if (steps_out) {
-      if (P.lv[0].n <= (size_t)COARSE_MAX_CELLS) std::memcpy(steps_out, P.hscal, sizeof(int));
+      if (lds) std::memcpy(steps_out, P.hscal, sizeof(int));
       else *steps_out = -1;
     }
     if (H.u[0] != u) copy_d2d(u, H.u[0], P.lv[0].n, st);
     HIPCHK(hipStreamSynchronize(st));
     return RKL_OK;
+  });
+}
+
+int rkl_tau_step_launches(const rkl_grid* grid, int s, int prec) {
+  return guarded([&]() -> rkl_status {
+    validate_grid(grid, nullptr);
+    if (s < 1 || s > 64) fail(RKL_EINVAL, "s must be in [1, 64]");
+    Lev L = build_levels(*grid, INT_MAX, s, 0.9)[0];
+    const bool per = grid->bc == RKL_BC_PERIODIC;
+    bool fused;
+    if (prec == RKL_MIXED) fused = fused_tau_supported<float>(view<float>(L, per, nullptr), s);
+    else if (prec == RKL_FP64) fused = fused_tau_supported<double>(view<double>(L, per, nullptr), s);
+    else fail(RKL_EINVAL, "unknown precision");
+    return (rkl_status)(fused ? 1 : s);
   });
 }
 

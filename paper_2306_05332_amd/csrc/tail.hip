@@ -1,0 +1,340 @@
+// Coarse tail of the V-cycle in one workgroup.
+//
+// Below a few thousand cells a level is far too small to fill the GPU, and
+// every kernel launch costs several microseconds, so the part of the V-cycle
+// (Sec. 2.1) from the first level of at most TAIL_MAX_CELLS cells down to the
+// coarsest one runs inside a single 512-thread workgroup with all of its
+// arrays in LDS:
+//   b of the top tail level (as restricted, its mean removed when periodic,
+//   Sec. 2.3) -> N_pre RKL tau-steps from zero -> residual + 8-point
+//   restriction -> ... -> accelerated RKL coarsest solve (App. A.4, on one
+//   wavefront) -> prolongation + correction -> N_post tau-steps -> ... ->
+//   the top level's correction u, written back to HBM.
+// The arithmetic is that of the per-level kernels (stage recurrence of App. A
+// eq. RKL_intermediate_source; ghosts of Sec. 2.3 for the error equation:
+// homogeneous Dirichlet -c or periodic wrap).
+#include <cstring>
+
+#include "kernels.h"
+
+namespace rkl {
+
+template <typename T>
+struct TailLevel {
+  int nx, ny, nz, off;  // off: first of this level's three LDS arrays (u, alt, b)
+  T ihx2, ihy2, ihz2;
+  T mu[TAIL_MAX_S], nu[TAIL_MAX_S], c[TAIL_MAX_S];
+};
+
+template <typename T>
+struct TailArgs {
+  int nlev, s, n_pre, n_post, periodic, cmax;
+  double ctol;
+  CoarseSchedule cs;
+  TailLevel<T> lv[TAIL_MAX_LEVELS];
+};
+
+constexpr int TNT = 512;
+
+template <typename T>
+__device__ __forceinline__ T tail_lap(const TailLevel<T>& V, const T* Y, int q, int per) {
+  const int nx = V.nx, ny = V.ny, nz = V.nz;
+  const int i = q % nx, t = q / nx, j = t % ny, k = t / ny;
+  const int sy = nx, sz = nx * ny;
+  const T c = Y[q];
+  const T xm = i > 0 ? Y[q - 1] : (per ? Y[q + nx - 1] : -c);
+  const T xp = i < nx - 1 ? Y[q + 1] : (per ? Y[q - (nx - 1)] : -c);
+  const T ym = j > 0 ? Y[q - sy] : (per ? Y[q + (ny - 1) * sy] : -c);
+  const T yp = j < ny - 1 ? Y[q + sy] : (per ? Y[q - (ny - 1) * sy] : -c);
+  const T zm = k > 0 ? Y[q - sz] : (per ? Y[q + (nz - 1) * sz] : -c);
+  const T zp = k < nz - 1 ? Y[q + sz] : (per ? Y[q - (nz - 1) * sz] : -c);
+  return ((xm + xp) - (T)2 * c) * V.ihx2 + ((ym + yp) - (T)2 * c) * V.ihy2 + ((zm + zp) - (T)2 * c) * V.ihz2;
+}
+
+template <typename T>
+__global__ __launch_bounds__(TNT) void k_tail(TailArgs<T> A, const T* __restrict__ b_top, T* __restrict__ u_top,
+                                              const int* __restrict__ stop) {
+  extern __shared__ __align__(16) unsigned char pool_raw[];
+  __shared__ double red[TNT / WAVE];
+  __shared__ double bc;
+  __shared__ int ssched[COARSE_MAX_SCHED];
+  __shared__ int scoff[COARSE_MAX_SCHED];
+  __shared__ double scoef[3 * COARSE_MAX_COEF];
+  if (stop != nullptr && *stop) return;
+  T* pool = reinterpret_cast<T*>(pool_raw);
+  const int tid = threadIdx.x;
+  const int per = A.periodic;
+  const int nl = A.nlev;
+  // which of a level's two iterate arrays is current: bit l set -> the second
+  unsigned swapped = 0u;
+  const int nsched = min(A.cs.nsched, COARSE_MAX_SCHED);
+  for (int q = tid; q < nsched; q += TNT) {
+    ssched[q] = A.cs.sched[q];
+    scoff[q] = A.cs.coff[q];
+  }
+  const int ncoef = nsched > 0 ? min(A.cs.coff[nsched - 1] + A.cs.sched[nsched - 1], COARSE_MAX_COEF) : 0;
+  for (int q = tid; q < 3 * ncoef; q += TNT) scoef[q] = A.cs.coef[q];
+
+  auto nof = [&](int l) { return A.lv[l].nx * A.lv[l].ny * A.lv[l].nz; };
+  auto bptr = [&](int l) { return pool + A.lv[l].off + 2 * nof(l); };
+  auto curp = [&](int l) { return pool + A.lv[l].off + (((swapped >> l) & 1u) ? nof(l) : 0); };
+  auto altp = [&](int l) { return pool + A.lv[l].off + (((swapped >> l) & 1u) ? 0 : nof(l)); };
+  // block-wide: subtract the mean of level l's right-hand side (periodic)
+  auto remove_b_mean = [&](int l) {
+    T* B = bptr(l);
+    const int n = nof(l);
+    double sm = 0.0;
+    for (int q = tid; q < n; q += TNT) sm += (double)B[q];
+    const double t = block_sum<TNT>(sm, red);
+    if (tid == 0) bc = t;
+    __syncthreads();
+    const T m = (T)(bc / (double)n);
+    for (int q = tid; q < n; q += TNT) B[q] -= m;
+    __syncthreads();
+  };
+  // one tau-step on level l (stage by stage, Y_j over Y_{j-2}); from_zero: Y_0 = 0
+  auto tau = [&](int l, bool from_zero) {
+    const TailLevel<T>& V = A.lv[l];
+    const int n = nof(l);
+    T* B = bptr(l);
+    T* cur = curp(l);
+    T* alt = altp(l);
+    if (from_zero) {
+      for (int q = tid; q < n; q += TNT) cur[q] = (T)0;
+      __syncthreads();
+    }
+    for (int j = 1; j <= A.s; ++j) {
+      const T* yp = (j & 1) ? cur : alt;
+      T* yw = (j & 1) ? alt : cur;
+      const T mu = V.mu[j - 1], nu = V.nu[j - 1], c = V.c[j - 1];
+      for (int q = tid; q < n; q += TNT) {
+        const T r = tail_lap(V, yp, q, per) - B[q];
+        yw[q] = (j == 1) ? yp[q] + c * r : mu * yp[q] + nu * yw[q] + c * r;
+      }
+      __syncthreads();
+    }
+    if (A.s & 1) swapped ^= 1u << l;
+  };
+
+  // top level right-hand side
+  {
+    const int n = nof(0);
+    T* B = bptr(0);
+    for (int q = tid; q < n; q += TNT) B[q] = b_top[q];
+    __syncthreads();
+    if (per) remove_b_mean(0);
+  }
+  // downstroke
+  for (int l = 0; l < nl - 1; ++l) {
+    if (A.n_pre > 0) {
+      tau(l, true);
+      for (int q = 1; q < A.n_pre; ++q) tau(l, false);
+    } else {
+      T* cur = curp(l);
+      for (int q = tid; q < nof(l); q += TNT) cur[q] = (T)0;
+      __syncthreads();
+    }
+    // b_{l+1} = R(b_l - M u_l)
+    const TailLevel<T>& F = A.lv[l];
+    const TailLevel<T>& C = A.lv[l + 1];
+    const T* U = curp(l);
+    const T* B = bptr(l);
+    T* BC = bptr(l + 1);
+    const int cn = nof(l + 1);
+    for (int q = tid; q < cn; q += TNT) {
+      const int I = q % C.nx, t = q / C.nx, J = t % C.ny, K = t / C.ny;
+      T acc = (T)0;
+      for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+          for (int dx = 0; dx < 2; ++dx) {
+            const int f = ((2 * K + dz) * F.ny + (2 * J + dy)) * F.nx + (2 * I + dx);
+            acc += B[f] - tail_lap(F, U, f, per);
+          }
+      BC[q] = acc * (T)0.125;
+    }
+    __syncthreads();
+    if (per) remove_b_mean(l + 1);
+  }
+  // coarsest level: accelerated RKL on wavefront 0 (one cell per lane slot)
+  {
+    const int l = nl - 1;
+    const TailLevel<T>& V = A.lv[l];
+    const int n = nof(l);
+    if (tid < WAVE) {
+      T* B = bptr(l);
+      T* cur = curp(l);
+      T* alt = altp(l);
+      double b2 = 0.0;
+      for (int q = tid; q < n; q += WAVE) {
+        cur[q] = (T)0;
+        b2 += (double)B[q] * (double)B[q];
+      }
+      const double bnorm = sqrt(wave_sum_dpp(b2));
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+      int step = 0;
+      if (bnorm > 0.0) {
+        while (true) {
+          double r2 = 0.0;
+          for (int q = tid; q < n; q += WAVE) {
+            const T r = tail_lap(V, cur, q, per) - B[q];
+            r2 += (double)r * (double)r;
+          }
+          const double res = sqrt(wave_sum_dpp(r2));
+          if (res <= A.ctol * bnorm || step >= A.cmax) break;
+          const int qs = step < nsched ? step : nsched - 1;
+          const int s = ssched[qs];
+          const double* co = scoef + 3 * scoff[qs];
+          for (int j = 1; j <= s; ++j) {
+            const T mu = (T)co[3 * (j - 1)], nu = (T)co[3 * (j - 1) + 1], c = (T)co[3 * (j - 1) + 2];
+            const T* yp = (j & 1) ? cur : alt;
+            T* yw = (j & 1) ? alt : cur;
+            T outv[4];
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc) {
+              const int q = tid + WAVE * cc;
+              outv[cc] = (T)0;
+              if (q < n) {
+                const T r = tail_lap(V, yp, q, per) - B[q];
+                outv[cc] = (j == 1) ? yp[q] + c * r : mu * yp[q] + nu * yw[q] + c * r;
+              }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc) {
+              const int q = tid + WAVE * cc;
+              if (q < n) yw[q] = outv[cc];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+          }
+          if (s & 1) {
+            T* t = cur;
+            cur = alt;
+            alt = t;
+          }
+          if (per) {
+            double sm = 0.0;
+            for (int q = tid; q < n; q += WAVE) sm += (double)cur[q];
+            const T m = (T)(wave_sum_dpp(sm) / (double)n);
+            for (int q = tid; q < n; q += WAVE) cur[q] -= m;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+          }
+          ++step;
+        }
+      }
+      // leave the result in the level's first array
+      if (cur != curp(l)) {
+        T* dst = curp(l);
+        for (int q = tid; q < n; q += WAVE) dst[q] = cur[q];
+      }
+    }
+    __syncthreads();
+  }
+  // upstroke
+  for (int l = nl - 2; l >= 0; --l) {
+    const TailLevel<T>& F = A.lv[l];
+    const TailLevel<T>& C = A.lv[l + 1];
+    const T* E = curp(l + 1);
+    T* U = curp(l);
+    const int fn = nof(l);
+    for (int q = tid; q < fn; q += TNT) {
+      const int i = q % F.nx, t = q / F.nx, j = t % F.ny, k = t / F.ny;
+      const int I = i >> 1, J = j >> 1, K = k >> 1;
+      const int sx = (i & 1) ? 1 : -1, sy = (j & 1) ? 1 : -1, sz = (k & 1) ? 1 : -1;
+      T acc = (T)0;
+      for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+          for (int dx = 0; dx < 2; ++dx) {
+            int a = I + dx * sx, bb = J + dy * sy, cidx = K + dz * sz;
+            T sg = (T)1;
+            if (per) {
+              a = (a + C.nx) % C.nx;
+              bb = (bb + C.ny) % C.ny;
+              cidx = (cidx + C.nz) % C.nz;
+            } else {
+              if (a < 0) { a = 0; sg = -sg; }
+              if (a >= C.nx) { a = C.nx - 1; sg = -sg; }
+              if (bb < 0) { bb = 0; sg = -sg; }
+              if (bb >= C.ny) { bb = C.ny - 1; sg = -sg; }
+              if (cidx < 0) { cidx = 0; sg = -sg; }
+              if (cidx >= C.nz) { cidx = C.nz - 1; sg = -sg; }
+            }
+            const T w = (T)((dz ? 1 : 3) * (dy ? 1 : 3) * (dx ? 1 : 3));
+            acc += w * sg * E[(cidx * C.ny + bb) * C.nx + a];
+          }
+      U[q] += acc * (T)(1.0 / 64.0);
+    }
+    __syncthreads();
+    for (int q = 0; q < A.n_post; ++q) tau(l, false);
+  }
+  // correction of the top tail level back to HBM
+  {
+    const T* U = curp(0);
+    for (int q = tid; q < nof(0); q += TNT) u_top[q] = U[q];
+  }
+}
+
+template <typename T>
+size_t tail_lds_bytes(const TailShape& ts) {
+  size_t cells = 0;
+  for (int l = 0; l < ts.nlev; ++l) cells += 3 * (size_t)ts.nx[l] * ts.ny[l] * ts.nz[l];
+  return cells * sizeof(T);
+}
+
+template <typename T>
+bool tail_fits(const TailShape& ts, int s) {
+  if (ts.nlev < 2 || ts.nlev > TAIL_MAX_LEVELS || s > TAIL_MAX_S) return false;
+  const size_t top = (size_t)ts.nx[0] * ts.ny[0] * ts.nz[0];
+  const size_t bottom = (size_t)ts.nx[ts.nlev - 1] * ts.ny[ts.nlev - 1] * ts.nz[ts.nlev - 1];
+  if (top > (size_t)TAIL_MAX_CELLS || bottom > (size_t)(4 * WAVE)) return false;
+  return tail_lds_bytes<T>(ts) <= TAIL_MAX_LDS;
+}
+
+template <typename T>
+void launch_tail(const TailShape& ts, const StageCoef* const* smooth, int s, int n_pre, int n_post, int periodic,
+                 CoarseSchedule cs, double ctol, int cmax, const T* b_top, T* u_top, const int* stop,
+                 hipStream_t st) {
+  TailArgs<T> A;
+  std::memset(&A, 0, sizeof(A));
+  A.nlev = ts.nlev;
+  A.s = s;
+  A.n_pre = n_pre;
+  A.n_post = n_post;
+  A.periodic = periodic;
+  A.cmax = cmax;
+  A.ctol = ctol;
+  A.cs = cs;
+  int off = 0;
+  for (int l = 0; l < ts.nlev; ++l) {
+    TailLevel<T>& V = A.lv[l];
+    V.nx = ts.nx[l];
+    V.ny = ts.ny[l];
+    V.nz = ts.nz[l];
+    V.off = off;
+    off += 3 * V.nx * V.ny * V.nz;
+    V.ihx2 = (T)ts.ihx2[l];
+    V.ihy2 = (T)ts.ihy2[l];
+    V.ihz2 = (T)ts.ihz2[l];
+    for (int j = 0; j < s; ++j) {
+      V.mu[j] = (T)smooth[l][j].mu;
+      V.nu[j] = (T)smooth[l][j].nu;
+      V.c[j] = (T)smooth[l][j].c;
+    }
+  }
+  const size_t shm = tail_lds_bytes<T>(ts);
+  static bool attr_set[2] = {false, false};
+  if (!attr_set[sizeof(T) == 8]) {
+    (void)hipFuncSetAttribute((const void*)k_tail<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)TAIL_MAX_LDS);
+    attr_set[sizeof(T) == 8] = true;
+  }
+  hipLaunchKernelGGL(k_tail<T>, dim3(1), dim3(TNT), shm, st, A, b_top, u_top, stop);
+}
+
+template bool tail_fits<double>(const TailShape&, int);
+template bool tail_fits<float>(const TailShape&, int);
+template void launch_tail<double>(const TailShape&, const StageCoef* const*, int, int, int, int, CoarseSchedule,
+                                  double, int, const double*, double*, const int*, hipStream_t);
+template void launch_tail<float>(const TailShape&, const StageCoef* const*, int, int, int, int, CoarseSchedule,
+                                 double, int, const float*, float*, const int*, hipStream_t);
+
+}  // namespace rkl

@@ -1,0 +1,397 @@
+// LDS-tiled residual, residual + restriction, and prolongation + correction.
+//
+//   k_resid_tile<.., false>  r = b - M u (Sec. 2.1 eq. residual, opposite sign)
+//                            with float64 partial sums of r^2 and r
+//   k_resid_tile<.., true>   b_{l+1} = R(b_l - M_l u_l): the 8-child average of
+//                            eq. restriction_example_3D applied to the residual
+//                            (Sec. 2.1 steps 2a/2b), with float64 partials of
+//                            the fine r^2 and of the coarse values (the latter
+//                            feed the periodic mean removal, Sec. 2.3)
+//   k_prolong_tile           u_l += P(u_{l+1}) with the (27, 9, 9, 9, 3, 3, 3, 1)/64
+//                            weights of eq. prolongation_example_3D and the
+//                            error-equation ghosts of the coarse grid
+//
+// Both march upward in z.  The residual kernels keep four fine u planes of a
+// 64 x 16 tile (plus a one-cell halo) in an LDS ring and handle one coarse
+// plane (two fine planes) per step; the prolongation keeps three coarse
+// planes of the tile's coarse footprint in LDS.  The next planes are loaded
+// into registers while the current ones are processed, so each HBM word is
+// read once per tile (halos come from L2).
+#include "kernels.h"
+
+namespace rkl {
+
+constexpr int RNT = 256;
+constexpr int RBX = 64, RBY = 16;                  // fine interior tile (32 x 8 coarse cells)
+constexpr int RW = RBX + 2, RH = RBY + 2, RPL = RW * RH;
+constexpr int RNU = (RPL + RNT - 1) / RNT;         // haloed-plane slots per thread
+constexpr int RNI = (RBX * RBY) / RNT;             // interior slots per thread
+
+__device__ __forceinline__ int xcd_remap(int bid, int nblk) {
+  // consecutive workgroups go round-robin to the 8 XCDs: give each XCD a
+  // contiguous run of tiles so neighbouring halos meet in one L2
+  if ((nblk & 7) == 0) return (bid & 7) * (nblk >> 3) + (bid >> 3);
+  return bid;
+}
+
+template <typename TU, typename TR, bool RESTRICT>
+__global__ __launch_bounds__(RNT) void k_resid_tile(LevelView<TU> F, const TU* __restrict__ u,
+                                                    const TU* __restrict__ b, TR* __restrict__ out,
+                                                    int kc, int gx_tiles, int gy_tiles, int nblk,
+                                                    double* __restrict__ part, const int* __restrict__ stop) {
+  __shared__ TU ring[4][RPL];
+  __shared__ TU zs[RESTRICT ? RBY : 1][RESTRICT ? RBX : 1];
+  __shared__ double red[RNT / WAVE];
+  if (stop != nullptr && *stop) return;
+  const int tid = threadIdx.x;
+  const int nx = F.nx, ny = F.ny, nz = F.nz;
+  const bool per = F.periodic != 0;
+  const size_t sxy = (size_t)nx * ny;
+  const int bid = xcd_remap(blockIdx.x, nblk);
+  const int tx = bid % gx_tiles, ty = (bid / gx_tiles) % gy_tiles, tzc = bid / (gx_tiles * gy_tiles);
+  const int x0 = tx * RBX - 1, y0 = ty * RBY - 1;
+  const int npair = (nz + 1) / 2;
+  const int K0 = tzc * kc, K1 = min(K0 + kc, npair);
+
+  int goff[RNU];
+#pragma unroll
+  for (int q = 0; q < RNU; ++q) {
+    const int idx = tid + q * RNT;
+    goff[q] = -1;
+    if (idx < RPL) {
+      const int gxr = x0 + idx % RW, gyr = y0 + idx / RW;
+      if (per) goff[q] = ((gyr % ny + ny) % ny) * nx + (gxr % nx + nx) % nx;
+      else if (gxr >= 0 && gxr < nx && gyr >= 0 && gyr < ny) goff[q] = gyr * nx + gxr;
+    }
+  }
+  // interior slots
+  int igx[RNI], igy[RNI];
+  bool iin[RNI];
+#pragma unroll
+  for (int q = 0; q < RNI; ++q) {
+    const int idx = tid + q * RNT;
+    igx[q] = tx * RBX + idx % RBX;
+    igy[q] = ty * RBY + idx / RBX;
+    iin[q] = igx[q] < nx && igy[q] < ny;
+  }
+  auto plane_ok = [&](int p) { return per ? true : (p >= 0 && p < nz); };
+  auto zw = [&](int p) { return per ? (p % nz + nz) % nz : p; };
+  auto rslot = [](int p) { return (p + 8) & 3; };
+
+  TU pa[RNU], pb[RNU];   // u planes in flight
+  TU ba[RNI], bb[RNI];   // b planes in flight
+  auto load_u = [&](int p, TU (&dst)[RNU]) {
+    const bool ok = u != nullptr && plane_ok(p) && (per || p < nz);
+    const size_t zo = ok ? (size_t)zw(p) * sxy : 0;
+#pragma unroll
+    for (int q = 0; q < RNU; ++q) dst[q] = (ok && goff[q] >= 0) ? u[zo + goff[q]] : (TU)0;
+  };
+  auto load_b = [&](int p, TU (&dst)[RNI]) {
+    const bool ok = p >= 0 && p < nz;
+    const size_t zo = ok ? (size_t)p * sxy : 0;
+#pragma unroll
+    for (int q = 0; q < RNI; ++q) dst[q] = (ok && iin[q]) ? b[zo + (size_t)igy[q] * nx + igx[q]] : (TU)0;
+  };
+  auto store_u = [&](int p, const TU (&src)[RNU]) {
+    TU* d = ring[rslot(p)];
+#pragma unroll
+    for (int q = 0; q < RNU; ++q) {
+      const int idx = tid + q * RNT;
+      if (idx < RPL) d[idx] = src[q];
+    }
+  };
+
+  // r = b - M u at interior slot q of fine plane p (ring holds p-1, p, p+1)
+  auto resid = [&](int q, int p, TU bv) -> TU {
+    const int idx = tid + q * RNT;
+    const int o = (idx / RBX + 1) * RW + (idx % RBX + 1);
+    const TU* Yc = ring[rslot(p)];
+    const TU c = Yc[o];
+    TU xm = Yc[o - 1], xp = Yc[o + 1], ym = Yc[o - RW], yp = Yc[o + RW];
+    TU zm = ring[rslot(p - 1)][o], zp = ring[rslot(p + 1)][o];
+    if (!per) {
+      const int gx = igx[q], gy = igy[q];
+      if (gx == 0) xm = dir_ghost(F, 0, (size_t)p * ny + gy, c);
+      if (gx == nx - 1) xp = dir_ghost(F, 1, (size_t)p * ny + gy, c);
+      if (gy == 0) ym = dir_ghost(F, 2, (size_t)p * nx + gx, c);
+      if (gy == ny - 1) yp = dir_ghost(F, 3, (size_t)p * nx + gx, c);
+      if (p == 0) zm = dir_ghost(F, 4, (size_t)gy * nx + gx, c);
+      if (p == nz - 1) zp = dir_ghost(F, 5, (size_t)gy * nx + gx, c);
+    }
+    const TU lap = ((xm + xp) - (TU)2 * c) * F.ihx2 + ((ym + yp) - (TU)2 * c) * F.ihy2 +
+                   ((zm + zp) - (TU)2 * c) * F.ihz2;
+    return bv - lap;
+  };
+
+  double s2 = 0.0, s1 = 0.0;
+  if (K0 < K1) {
+    // ring: planes 2K0-1, 2K0 now; 2K0+1, 2K0+2 in flight
+    {
+      TU t0[RNU], t1[RNU];
+      load_u(2 * K0 - 1, t0);
+      load_u(2 * K0, t1);
+      store_u(2 * K0 - 1, t0);
+      store_u(2 * K0, t1);
+    }
+    load_u(2 * K0 + 1, pa);
+    load_u(2 * K0 + 2, pb);
+    load_b(2 * K0, ba);
+    load_b(2 * K0 + 1, bb);
+    for (int K = K0; K < K1; ++K) {
+      const int p0 = 2 * K, p1 = 2 * K + 1;
+      store_u(p1, pa);
+      store_u(p1 + 1, pb);
+      TU bc0[RNI], bc1[RNI];
+#pragma unroll
+      for (int q = 0; q < RNI; ++q) {
+        bc0[q] = ba[q];
+        bc1[q] = bb[q];
+      }
+      __syncthreads();
+      if (K + 1 < K1) {
+        load_u(2 * K + 3, pa);
+        load_u(2 * K + 4, pb);
+        load_b(2 * K + 2, ba);
+        load_b(2 * K + 3, bb);
+      }
+      const bool has1 = p1 < nz;
+#pragma unroll
+      for (int q = 0; q < RNI; ++q) {
+        TU r0 = (TU)0, r1 = (TU)0;
+        if (iin[q]) {
+          r0 = resid(q, p0, bc0[q]);
+          s2 += (double)r0 * (double)r0;
+          if (has1) {
+            r1 = resid(q, p1, bc1[q]);
+            s2 += (double)r1 * (double)r1;
+          }
+          if (!RESTRICT) {
+            s1 += (double)r0 + (double)r1;
+            if (out != nullptr) {
+              out[(size_t)p0 * sxy + (size_t)igy[q] * nx + igx[q]] = (TR)r0;
+              if (has1) out[(size_t)p1 * sxy + (size_t)igy[q] * nx + igx[q]] = (TR)r1;
+            }
+          }
+        }
+        if (RESTRICT) {
+          const int idx = tid + q * RNT;
+          zs[RESTRICT ? idx / RBX : 0][RESTRICT ? idx % RBX : 0] = r0 + r1;
+        }
+      }
+      __syncthreads();
+      if (RESTRICT) {
+        const int cx = tid % (RBX / 2), cy = tid / (RBX / 2);  // 32 x 8 coarse cells, one per thread
+        const int cnx = nx / 2, cny = ny / 2;
+        const int gcx = tx * (RBX / 2) + cx, gcy = ty * (RBY / 2) + cy;
+        if (gcx < cnx && gcy < cny) {
+          const TU v = ((zs[2 * cy][2 * cx] + zs[2 * cy][2 * cx + 1]) +
+                        (zs[2 * cy + 1][2 * cx] + zs[2 * cy + 1][2 * cx + 1])) * (TU)0.125;
+          out[((size_t)K * cny + gcy) * cnx + gcx] = (TR)v;
+          s1 += (double)v;
+        }
+        __syncthreads();
+      }
+    }
+  }
+  const double t2 = block_sum<RNT>(s2, red);
+  const double t1 = block_sum<RNT>(s1, red);
+  if (tid == 0) {
+    part[2 * (size_t)blockIdx.x] = t2;
+    part[2 * (size_t)blockIdx.x + 1] = t1;
+  }
+}
+
+// ---------------------------------------------------------------- prolongation
+constexpr int PNT = 256;
+constexpr int PBX = 64, PBY = 8;                   // fine tile
+constexpr int PCW = PBX / 2 + 2, PCH = PBY / 2 + 2, PCL = PCW * PCH;  // coarse footprint + halo
+constexpr int PNF = PBX * PBY / PNT;               // fine slots per thread
+constexpr int PNC = (PCL + PNT - 1) / PNT;         // coarse slots per thread
+
+template <typename T>
+__global__ __launch_bounds__(PNT) void k_prolong_tile(int fnx, int fny, int fnz, int periodic,
+                                                      const T* __restrict__ e, T* __restrict__ fine, int kc,
+                                                      int gx_tiles, int gy_tiles, int nblk,
+                                                      const int* __restrict__ stop) {
+  __shared__ T cr[3][PCL];
+  if (stop != nullptr && *stop) return;
+  const int tid = threadIdx.x;
+  const int cnx = fnx / 2, cny = fny / 2, cnz = fnz / 2;
+  const int bid = xcd_remap(blockIdx.x, nblk);
+  const int tx = bid % gx_tiles, ty = (bid / gx_tiles) % gy_tiles, tz = bid / (gx_tiles * gy_tiles);
+  const int k0 = tz * kc, k1 = min(k0 + kc, fnz);  // kc is even
+  const int cx0 = tx * (PBX / 2) - 1, cy0 = ty * (PBY / 2) - 1;
+  const size_t fsxy = (size_t)fnx * fny, csxy = (size_t)cnx * cny;
+
+  // coarse slots: in-plane offset and sign of the ghost (odd reflection per
+  // axis for homogeneous Dirichlet, wrap for periodic)
+  int coff[PNC];
+  T csg[PNC];
+#pragma unroll
+  for (int q = 0; q < PNC; ++q) {
+    const int idx = tid + q * PNT;
+    coff[q] = -1;
+    csg[q] = (T)1;
+    if (idx < PCL) {
+      int I = cx0 + idx % PCW, J = cy0 + idx / PCW;
+      if (periodic) {
+        I = (I % cnx + cnx) % cnx;
+        J = (J % cny + cny) % cny;
+      } else {
+        if (I < 0) { I = 0; csg[q] = -csg[q]; }
+        if (I >= cnx) { I = cnx - 1; csg[q] = -csg[q]; }
+        if (J < 0) { J = 0; csg[q] = -csg[q]; }
+        if (J >= cny) { J = cny - 1; csg[q] = -csg[q]; }
+      }
+      coff[q] = J * cnx + I;
+    }
+  }
+  auto load_c = [&](int K, T (&dst)[PNC]) {
+    T zs = (T)1;
+    int Kw = K;
+    if (periodic) Kw = (K % cnz + cnz) % cnz;
+    else {
+      if (K < 0) { Kw = 0; zs = -zs; }
+      if (K >= cnz) { Kw = cnz - 1; zs = -zs; }
+    }
+    const size_t zo = (size_t)Kw * csxy;
+#pragma unroll
+    for (int q = 0; q < PNC; ++q) dst[q] = coff[q] >= 0 ? zs * csg[q] * e[zo + coff[q]] : (T)0;
+  };
+  auto store_c = [&](int K, const T (&src)[PNC]) {
+    T* d = cr[(K + 3) % 3];
+#pragma unroll
+    for (int q = 0; q < PNC; ++q) {
+      const int idx = tid + q * PNT;
+      if (idx < PCL) d[idx] = src[q];
+    }
+  };
+  int fx[PNF], fy[PNF];
+  bool fin[PNF];
+#pragma unroll
+  for (int q = 0; q < PNF; ++q) {
+    const int idx = tid + q * PNT;
+    fx[q] = tx * PBX + idx % PBX;
+    fy[q] = ty * PBY + idx / PBX;
+    fin[q] = fx[q] < fnx && fy[q] < fny;
+  }
+  if (k0 >= k1) return;
+  {
+    const int K = k0 >> 1;
+    T c0[PNC], c1[PNC], c2[PNC];
+    load_c(K - 1, c0);
+    load_c(K, c1);
+    load_c(K + 1, c2);
+    store_c(K - 1, c0);
+    store_c(K, c1);
+    store_c(K + 1, c2);
+  }
+  T cn[PNC];
+  T un[PNF];
+  load_c((k0 >> 1) + 2, cn);
+#pragma unroll
+  for (int q = 0; q < PNF; ++q) un[q] = fin[q] ? fine[(size_t)k0 * fsxy + (size_t)fy[q] * fnx + fx[q]] : (T)0;
+  __syncthreads();
+  for (int k = k0; k < k1; ++k) {
+    const int K = k >> 1, sz = (k & 1) ? 1 : -1;
+    if (k > k0 && (k & 1) == 0) {
+      // entering coarse plane K: K+1 was prefetched; K-2's slot is free
+      __syncthreads();
+      store_c(K + 1, cn);
+      __syncthreads();
+      load_c(K + 2, cn);
+    }
+    T uc[PNF];
+#pragma unroll
+    for (int q = 0; q < PNF; ++q) uc[q] = un[q];
+    if (k + 1 < k1) {
+#pragma unroll
+      for (int q = 0; q < PNF; ++q)
+        un[q] = fin[q] ? fine[(size_t)(k + 1) * fsxy + (size_t)fy[q] * fnx + fx[q]] : (T)0;
+    }
+    const T* Ca = cr[(K + 3) % 3];
+    const T* Cb = cr[(K + sz + 3) % 3];
+#pragma unroll
+    for (int q = 0; q < PNF; ++q) {
+      if (!fin[q]) continue;
+      const int i = fx[q], j = fy[q];
+      const int Il = (i >> 1) - cx0, Jl = (j >> 1) - cy0;
+      const int sx = (i & 1) ? 1 : -1, sy = (j & 1) ? PCW : -PCW;
+      const int o = Jl * PCW + Il;
+      // trilinear weights: 3/4 on the parent side, 1/4 on the neighbour side, per axis
+      const T a = (T)27 * Ca[o] + (T)9 * (Ca[o + sx] + Ca[o + sy] + Cb[o]) +
+                  (T)3 * (Ca[o + sx + sy] + Cb[o + sx] + Cb[o + sy]) + Cb[o + sx + sy];
+      fine[(size_t)k * fsxy + (size_t)j * fnx + i] = uc[q] + a * (T)(1.0 / 64.0);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+struct TileGrid {
+  int gx, gy, gz, kc, nblk;
+};
+
+static TileGrid resid_grid(int nx, int ny, int nz) {
+  TileGrid g;
+  g.gx = (nx + RBX - 1) / RBX;
+  g.gy = (ny + RBY - 1) / RBY;
+  const int npair = (nz + 1) / 2;
+  const int xy = g.gx * g.gy;
+  int chunks = (1024 + xy - 1) / xy;
+  chunks = std::max(1, std::min(chunks, npair));
+  g.kc = std::max(1, std::min(8, (npair + chunks - 1) / chunks));
+  g.gz = (npair + g.kc - 1) / g.kc;
+  g.nblk = g.gx * g.gy * g.gz;
+  return g;
+}
+
+size_t resid_blocks(int nx, int ny, int nz) { return (size_t)resid_grid(nx, ny, nz).nblk; }
+
+template <typename TU, typename TR>
+void launch_residual(const LevelView<TU>& L, const TU* u, const TU* b, TR* r_out, double* part,
+                     const int* stop, hipStream_t st) {
+  const TileGrid g = resid_grid(L.nx, L.ny, L.nz);
+  hipLaunchKernelGGL((k_resid_tile<TU, TR, false>), dim3(g.nblk), dim3(RNT), 0, st, L, u, b, r_out, g.kc,
+                     g.gx, g.gy, g.nblk, part, stop);
+}
+
+template <typename T>
+void launch_resid_restrict(const LevelView<T>& F, const T* u, const T* b, T* bc, double* part,
+                           const int* stop, hipStream_t st) {
+  const TileGrid g = resid_grid(F.nx, F.ny, F.nz);
+  hipLaunchKernelGGL((k_resid_tile<T, T, true>), dim3(g.nblk), dim3(RNT), 0, st, F, u, b, bc, g.kc, g.gx,
+                     g.gy, g.nblk, part, stop);
+}
+
+template <typename T>
+void launch_prolong_add(int fnx, int fny, int fnz, int periodic, const T* e, T* fine, const int* stop,
+                        hipStream_t st) {
+  TileGrid g;
+  g.gx = (fnx + PBX - 1) / PBX;
+  g.gy = (fny + PBY - 1) / PBY;
+  const int xy = g.gx * g.gy;
+  int chunks = (1024 + xy - 1) / xy;
+  chunks = std::max(1, std::min(chunks, fnz / 2));
+  g.kc = std::max(2, std::min(16, (fnz + chunks - 1) / chunks));
+  g.kc += g.kc & 1;  // even: chunks start on a coarse plane
+  g.gz = (fnz + g.kc - 1) / g.kc;
+  g.nblk = g.gx * g.gy * g.gz;
+  hipLaunchKernelGGL(k_prolong_tile<T>, dim3(g.nblk), dim3(PNT), 0, st, fnx, fny, fnz, periodic, e, fine,
+                     g.kc, g.gx, g.gy, g.nblk, stop);
+}
+
+template void launch_residual<double, double>(const LevelView<double>&, const double*, const double*,
+                                              double*, double*, const int*, hipStream_t);
+template void launch_residual<double, float>(const LevelView<double>&, const double*, const double*,
+                                             float*, double*, const int*, hipStream_t);
+template void launch_residual<float, float>(const LevelView<float>&, const float*, const float*, float*,
+                                            double*, const int*, hipStream_t);
+template void launch_resid_restrict<double>(const LevelView<double>&, const double*, const double*,
+                                            double*, double*, const int*, hipStream_t);
+template void launch_resid_restrict<float>(const LevelView<float>&, const float*, const float*, float*,
+                                           double*, const int*, hipStream_t);
+template void launch_prolong_add<double>(int, int, int, int, const double*, double*, const int*,
+                                         hipStream_t);
+template void launch_prolong_add<float>(int, int, int, int, const float*, float*, const int*, hipStream_t);
+
+}  // namespace rkl

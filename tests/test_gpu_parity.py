@@ -45,13 +45,15 @@ def rand_faces(rng, shape):
     return tuple(rng.standard_normal(s) for s in ((nz, ny), (nz, ny), (nz, nx), (nz, nx), (ny, nx), (ny, nx)))
 
 
-# shapes (nz, ny, nx) spanning several 64x4x8 tiles with ragged tails
-SHAPES = [(20, 11, 130), (9, 6, 5), (16, 16, 16)]
+# shapes (nz, ny, nx): several 64x4x8 / 64x8 tiles with ragged tails; the
+# first, fourth and fifth run the fused tau-step kernel (the fifth with
+# z-chunking), the others the per-stage kernels
+SHAPES = [(20, 11, 130), (9, 6, 5), (16, 16, 16), (40, 24, 64), (64, 40, 96)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
 @pytest.mark.parametrize("bc", ["periodic", "dirichlet"])
-@pytest.mark.parametrize("s,theta", [(1, 1.0), (2, 0.9), (3, 0.85), (5, 0.9)])
+@pytest.mark.parametrize("s,theta", [(1, 1.0), (2, 0.9), (3, 0.85), (4, 0.9), (5, 0.9)])
 def test_rkl_smooth_matches_oracle(shape, bc, s, theta):
     R = _lib()
     rng = np.random.default_rng(100 + s)
@@ -63,8 +65,29 @@ def test_rkl_smooth_matches_oracle(shape, bc, s, theta):
     g = oop.Grid(nx, ny, nz, *h, bc)
     want = omg.rkl_smooth(u0, f, g, s, theta, 3, faces)
     phi = cu(u0)
+    fused = R.tau_step_launches(shape, s, bc) == 1
+    print(f"shape={shape} bc={bc} s={s} fused={fused}", flush=True)
     R.smooth(cu(f), phi, h, bc, s=s, tau_frac=theta, n_steps=3,
              faces=R.pack_faces(faces) if faces else None)
+    assert relmax(host(phi), want) < 1e-12
+
+
+@pytest.mark.parametrize("bc", ["periodic", "dirichlet"])
+def test_rkl_smooth_large_tiles_match_oracle(bc):
+    """(nz, ny, nx) = (72, 130, 160): large enough for the z-queue kernel (64 x 32
+    tiles, 32-plane chunks) with ragged tiles in x, y and z."""
+    R = _lib()
+    rng = np.random.default_rng(5)
+    shape = (72, 130, 160)
+    h = (0.01, 0.012, 0.009)
+    u0 = rng.standard_normal(shape)
+    f = rng.standard_normal(shape) * 1e4
+    faces = rand_faces(rng, shape) if bc == "dirichlet" else None
+    nz, ny, nx = shape
+    g = oop.Grid(nx, ny, nz, *h, bc)
+    want = omg.rkl_smooth(u0, f, g, 2, 0.9, 2, faces)
+    phi = cu(u0)
+    R.smooth(cu(f), phi, h, bc, s=2, tau_frac=0.9, n_steps=2, faces=R.pack_faces(faces) if faces else None)
     assert relmax(host(phi), want) < 1e-12
 
 
