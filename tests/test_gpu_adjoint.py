@@ -1,0 +1,129 @@
+"""The adjoint backward of the differentiable solve (torch.autograd.Function).
+
+L = sum(w * phi) is linear in rho, so central differences are exact up to the
+solver's own error divided by the step.  With the step 1e-6 along unit-norm
+directions that error must be far below the convergence tolerance, so both
+solves of a difference run the same fixed number of V-cycles (tol = 0): the
+solver is then one fixed linear map and the difference isolates its
+derivative, leaving only the rounding of L itself: the bound is
+max(1e-6 |dL|, 64 u (|L+| + |L-|) / (2 eps)) with u the float64 unit roundoff
+(at eps = 1e-6 the second term dominates when |L| >> |dL|).  The oracle's adjoint
+(its own CPU solves) gives an element-by-element reference on a subset of the
+batch.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import multigrid as omg
+from oracle import operators as oop
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _lib():
+    import paper_2306_05332_amd as R
+    return R
+
+
+def _fd(R, rho, d, wt, h, eps, cycles):
+    """central difference of L = sum(w phi) with K fixed V-cycles per solve"""
+    o = R.Options(tol=0.0, max_cycles=cycles)
+    out = []
+    for sgn in (1.0, -1.0):
+        flat = (rho + sgn * eps * d).reshape((-1,) + tuple(rho.shape[-3:]))
+        tot = 0.0
+        for q in range(flat.shape[0]):
+            phi, st = R.solve(flat[q].contiguous(), h, "periodic", opts=o, raise_on_error=False)
+            assert st.cycles == cycles
+            tot += float((wt.reshape(flat.shape)[q] * phi).sum())
+        out.append(tot)
+    return (out[0] - out[1]) / (2 * eps), abs(out[0]) + abs(out[1])
+
+
+U64 = 2.0 ** -53
+
+
+def fd_bound(an, lsum, eps):
+    return max(1e-6 * abs(an), 64 * U64 * lsum / (2 * eps))
+
+
+def test_adjoint_matches_fd_and_oracle_small():
+    R = _lib()
+    rng = np.random.default_rng(51)
+    n = 32
+    rhos = np.stack([W.gaussian_blobs(n, 8, rng=rng).rho for _ in range(2)])
+    w = rng.standard_normal(rhos.shape)
+    h = (1.0 / n,) * 3
+    opts = R.Options(tol=1e-13)
+    rho = torch.from_numpy(rhos).cuda().requires_grad_(True)
+    wt = torch.from_numpy(w).cuda()
+    phi = R.poisson_solve(rho, h, "periodic", opts=opts)
+    L = (wt * phi).sum()
+    L.backward()
+    g = rho.grad.detach().cpu().numpy()
+    grid = oop.Grid(n, n, n, *h, "periodic")
+    for q in range(2):
+        want, _ = omg.adjoint_solve(w[q], grid, omg.Options(tol=1e-13))
+        assert np.abs(g[q] - want).max() <= 1e-9 * np.abs(want).max()
+    eps = 1e-6
+    _, st = R.solve(rho[0].detach().contiguous(), h, "periodic", opts=opts)
+    for _ in range(4):
+        d = rng.standard_normal(rhos.shape)
+        d /= np.linalg.norm(d)
+        dt = torch.from_numpy(d).cuda()
+        with torch.no_grad():
+            fd, lsum = _fd(R, rho.detach(), dt, wt, h, eps, st.cycles + 1)
+        an = float(np.sum(g * d))
+        print(f"fd={fd:.12e} adjoint={an:.12e} |L+|+|L-|={lsum:.3e} bound={fd_bound(an, lsum, eps):.2e}")
+        assert abs(fd - an) <= fd_bound(an, lsum, eps)
+
+
+def test_adjoint_dirichlet_matches_oracle():
+    R = _lib()
+    rng = np.random.default_rng(52)
+    p = W.uniform_sphere(32)
+    w = rng.standard_normal(p.shape)
+    opts = R.Options(tol=1e-13)
+    rho = torch.from_numpy(p.rho).cuda().requires_grad_(True)
+    phi = R.poisson_solve(rho, p.h, "dirichlet", faces=R.pack_faces(p.faces), opts=opts)
+    (torch.from_numpy(w).cuda() * phi).sum().backward()
+    grid = oop.Grid(32, 32, 32, *p.h, "dirichlet")
+    want, _ = omg.adjoint_solve(w, grid, omg.Options(tol=1e-13))
+    g = rho.grad.cpu().numpy()
+    assert np.abs(g - want).max() <= 1e-9 * np.abs(want).max()
+
+
+def test_adjoint_batch_128_fd_directions():
+    """The differentiation workload: 8 periodic 128^3 blob densities, L = sum(w phi)
+    with w ~ N(0,1); 16 unit random directions; FD step 1e-6; oracle adjoint on
+    one member of the batch."""
+    R = _lib()
+    rhos, w, dirs = W.adjoint_inputs(128, nbatch=8, ndirs=16, seed=5)
+    h = (1.0 / 128,) * 3
+    opts = R.Options(tol=1e-13)
+    rho = torch.from_numpy(rhos).cuda().requires_grad_(True)
+    wt = torch.from_numpy(w).cuda()
+    phi = R.poisson_solve(rho, h, "periodic", opts=opts)
+    (wt * phi).sum().backward()
+    g = rho.grad.detach()
+    eps = 1e-6
+    _, st = R.solve(rho[0].detach().contiguous(), h, "periodic", opts=opts)
+    worst = 0.0
+    for d in dirs:
+        dt = torch.from_numpy(d).cuda()
+        with torch.no_grad():
+            fd, lsum = _fd(R, rho.detach(), dt, wt, h, eps, st.cycles + 1)
+        an = float((g * dt).sum())
+        worst = max(worst, abs(fd - an) / fd_bound(an, lsum, eps))
+        print(f"fd={fd:.10e} adjoint={an:.10e} rel={abs(fd - an) / abs(an):.2e} "
+              f"bound={fd_bound(an, lsum, eps) / abs(an):.2e}")
+    print(f"adjoint vs FD: worst error / bound over 16 directions {worst:.2f}")
+    assert worst <= 1.0
+    grid = oop.Grid(128, 128, 128, *h, "periodic")
+    want, _ = omg.adjoint_solve(w[0], grid, omg.Options(tol=1e-12))
+    got = g[0].cpu().numpy()
+    assert np.abs(got - want).max() <= 1e-9 * np.abs(want).max()
