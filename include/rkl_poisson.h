@@ -89,6 +89,7 @@ typedef struct {
     double *history;     /* host array or NULL                                        */
     int history_cap;
     int history_len;
+    int status;          /* this solve's rkl_status (per member in batched calls)     */
 } rkl_stats;
 
 /* Fill `o` with the defaults listed in rkl_opts. */
@@ -107,7 +108,8 @@ void rkl_default_opts(rkl_opts *o);
  *             rho is removed first, eq. source_modification)
  *   stats     host, optional
  * A grid that cannot be coarsened runs the accelerated single-level RKL
- * iteration of App. A.4 to tolerance (stats->levels == 1).
+ * iteration of App. A.4 to tolerance (stats->levels == 1), in float64 for
+ * either precision.
  */
 rkl_status rkl_poisson_solve(const rkl_grid *grid, const rkl_opts *opts,
                              const double *rho, const double *bc_faces,
@@ -169,14 +171,25 @@ rkl_status rkl_coarse_solve(const rkl_grid *grid, const rkl_opts *opts, const do
                             double *u, int *steps_out, void *hip_stream);
 
 /*
- * Batched solve of `nbatch` independent problems whose grids may differ in
- * size (each grid[i] has its own geometry; boundary types may be mixed,
- * Dirichlet ones homogeneous).  rho[i], phi[i]: device float64 arrays of
- * grid[i]'s size (host arrays of device pointers).  With opts->prec ==
- * RKL_MIXED every V-cycle runs in float32 inside float64 refinement.  The
- * whole batch advances together: one launch per V-cycle phase covers every
- * grid, and the fixed-count refinement loop is replayed from a captured HIP
- * graph.  stats: host array of nbatch entries or NULL.
+ * Batched solve of `nbatch` independent problems M phi_i = 4 pi G rho_i
+ * (same equations, options and stopping rule as rkl_poisson_solve, Sec. 2.2
+ * and 2.4; Dirichlet members take homogeneous faces).
+ *   grids   host array of nbatch grids; sizes and boundary types may differ
+ *   rho     host array of nbatch device pointers, float64[grid i's n] each
+ *   phi     host array of nbatch device pointers (outputs, owned by caller)
+ *   stats   host array of nbatch entries or NULL; each entry's history
+ *           buffer (if any) receives that member's residual history
+ * Members with identical grids form a class held in contiguous library-owned
+ * buffers; every phase of a class's V-cycle is one launch over all members,
+ * and each member has its own device-side convergence state, so converged
+ * members drop out while the others continue.  The refinement loop
+ * (float64 defect, V-cycle on the correction at the working precision,
+ * float64 update) is captured once into a HIP graph and replayed until every
+ * member has stopped.  A class whose hierarchy does not end in the
+ * one-workgroup coarse tail is solved member by member with the single-solve
+ * path.  Returns the first non-OK member status in class order (each member's
+ * own outcome is in stats[i]); phi of periodic members is mean-free.  Calls
+ * on one process are serialised.  Buffers persist until rkl_release_all.
  */
 rkl_status rkl_poisson_solve_batched(const rkl_grid *grids, int nbatch, const rkl_opts *opts,
                                      const double *const *rho, double *const *phi,

@@ -46,7 +46,7 @@ class c_opts(ctypes.Structure):
 class c_stats(ctypes.Structure):
     _fields_ = [("cycles", ctypes.c_int), ("levels", ctypes.c_int), ("res0", ctypes.c_double),
                 ("rel_res", ctypes.c_double), ("history", ctypes.POINTER(ctypes.c_double)),
-                ("history_cap", ctypes.c_int), ("history_len", ctypes.c_int)]
+                ("history_cap", ctypes.c_int), ("history_len", ctypes.c_int), ("status", ctypes.c_int)]
 
 
 EXPORTS = ("rkl_default_opts", "rkl_poisson_solve", "mg_vcycle", "rkl_smooth", "rkl_residual",
@@ -179,7 +179,7 @@ def solve(rho, h, bc="periodic", faces=None, phi0=None, opts: Options | None = N
     _check_faces(faces, rho.shape, bc)
     g = _grid(rho.shape, h, bc)
     hist = (ctypes.c_double * max(1, history_cap))()
-    st = c_stats(0, 0, 0.0, 0.0, hist, history_cap, 0)
+    st = c_stats(0, 0, 0.0, 0.0, hist, history_cap, 0, 0)
     co = opts.c()
     status = lib.rkl_poisson_solve(ctypes.byref(g), ctypes.byref(co), _dev(rho, "rho"), _dev(faces, "faces"),
                                    _dev(phi, "phi"), ctypes.byref(st), _stream(rho))
@@ -253,14 +253,20 @@ def coarse_solve(b, h, bc="periodic", opts: Options | None = None):
     return u, steps.value
 
 
-def solve_batched(rhos, hs, bcs, opts: Options | None = None, history_cap=64):
+def solve_batched(rhos, hs, bcs, opts: Options | None = None, history_cap=64, raise_on_error=True):
     """Batched solve of independent problems (rkl_poisson_solve_batched).
-    rhos: list of float64 CUDA tensors (sizes may differ).  Returns (phis, stats list)."""
+    rhos: list of float64 CUDA tensors (sizes may differ), hs: spacing per
+    member, bcs: one boundary type or one per member.  Returns (phis, stats
+    list); each Stats carries its member's own status."""
     lib = load_library()
     opts = opts or Options()
     n = len(rhos)
     if isinstance(bcs, str):
         bcs = [bcs] * n
+    if len(hs) != n or len(bcs) != n:
+        raise ValueError("rhos, hs and bcs must have the same length")
+    if n == 0:
+        return [], []
     grids = (c_grid * n)(*[_grid(r.shape, h, b) for r, h, b in zip(rhos, hs, bcs)])
     phis = [torch.zeros_like(r) for r in rhos]
     rp = (ctypes.c_void_p * n)(*[r.data_ptr() for r in rhos])
@@ -268,11 +274,12 @@ def solve_batched(rhos, hs, bcs, opts: Options | None = None, history_cap=64):
     for r in rhos:
         _dev(r, "rho")
     hists = [(ctypes.c_double * history_cap)() for _ in range(n)]
-    sts = (c_stats * n)(*[c_stats(0, 0, 0.0, 0.0, hh, history_cap, 0) for hh in hists])
+    sts = (c_stats * n)(*[c_stats(0, 0, 0.0, 0.0, hh, history_cap, 0, 0) for hh in hists])
     co = opts.c()
     status = lib.rkl_poisson_solve_batched(grids, n, ctypes.byref(co), rp, pp, sts, _stream(rhos[0]))
-    _check(status)
-    stats = [Stats(s.cycles, s.levels, s.res0, s.rel_res, list(hh[:s.history_len]), 0)
+    if status in (RKL_EINVAL, RKL_ENOMEM, RKL_EHIP) or (raise_on_error and status != RKL_OK):
+        _check(status)
+    stats = [Stats(s.cycles, s.levels, s.res0, s.rel_res, list(hh[:s.history_len]), s.status)
              for s, hh in zip(sts, hists)]
     return phis, stats
 

@@ -36,7 +36,15 @@ __global__ __launch_bounds__(FNT) void k_fused_tau(LevelView<T> L, const T* __re
                                                    const T* __restrict__ b, T* __restrict__ out,
                                                    FCoef<T, S> co, int zc, int gx_tiles, int gy_tiles,
                                                    int nblk, double* __restrict__ part,
-                                                   const int* __restrict__ stop) {
+                                                   Batch bt, const int* __restrict__ stop) {
+  {
+    const long long mb = blockIdx.y;
+    if (u != nullptr) u += mb * bt.s0;
+    b += mb * bt.s0;
+    out += mb * bt.s0;
+    if (part != nullptr) part += mb * bt.part_stride;
+    if (stop != nullptr) stop += mb * bt.stop_stride;
+  }
   constexpr int W = BX + 2 * S, H = BY + 2 * S, PL = W * H;
   constexpr int NU = (PL + FNT - 1) / FNT;                                      // u slots per thread
   constexpr int NB = ((BX + 2 * S - 2) * (BY + 2 * S - 2) + FNT - 1) / FNT;     // stage slots (stage 1 is largest)
@@ -216,7 +224,15 @@ template <typename T, int S, int BX, int BY, int NT, int PD, int DS>
 __global__ __launch_bounds__(NT) void k_tau_zq(LevelView<T> L, const T* __restrict__ u, const T* __restrict__ b,
                                                T* __restrict__ out, FCoef<T, S> co, int zc, int gx_tiles,
                                                int gy_tiles, int nblk, double* __restrict__ part,
-                                               const int* __restrict__ stop) {
+                                               Batch bt, const int* __restrict__ stop) {
+  {
+    const long long mb = blockIdx.y;
+    if (u != nullptr) u += mb * bt.s0;
+    b += mb * bt.s0;
+    out += mb * bt.s0;
+    if (part != nullptr) part += mb * bt.part_stride;
+    if (stop != nullptr) stop += mb * bt.stop_stride;
+  }
   constexpr int W0 = BX + 2 * S, H0 = BY + 2 * S, P0 = W0 * H0;          // haloed u plane
   constexpr int W1 = W0 - 2, H1 = H0 - 2, P1 = W1 * H1;                  // stage-1 region = slot region
   constexpr int NB = (P1 + NT - 1) / NT;
@@ -482,7 +498,7 @@ constexpr int fused_max_s() {
 
 template <typename T>
 bool fused_tau_supported(const LevelView<T>& L, int s) {
-  return s >= 1 && s <= fused_max_s<T>() && L.nx >= 32 && L.ny >= 8 && L.nz >= 8;
+  return s >= 1 && s <= fused_max_s<T>() && L.nx >= 16 && L.ny >= 8 && L.nz >= 8;
 }
 
 struct FusedGrid {
@@ -527,20 +543,20 @@ FCoef<T, S> make_fcoef(const StageCoef* co) {
 
 template <typename T, int S>
 void launch_fused_S(const LevelView<T>& L, const T* u, const T* b, T* out, const StageCoef* co,
-                    double* part, const int* stop, hipStream_t st) {
+                    double* part, const int* stop, const Batch& bt, hipStream_t st) {
   const FCoef<T, S> fc = make_fcoef<T, S>(co);
   if constexpr (sizeof(T) == 8 && S == 2) {
     if (use_zq<T>(L, S)) {
       const FusedGrid g = fused_grid<ZQ_BX, ZQ_BY>(L.nx, L.ny, L.nz, 256, 32);
-      hipLaunchKernelGGL((k_tau_zq<T, S, ZQ_BX, ZQ_BY, ZQ_NT, 1, 0>), dim3(g.nblk), dim3(ZQ_NT), 0, st, L, u, b,
-                         out, fc, g.zc, g.gx, g.gy, g.nblk, part, stop);
+      hipLaunchKernelGGL((k_tau_zq<T, S, ZQ_BX, ZQ_BY, ZQ_NT, 1, 0>), dim3(g.nblk, bt.nb), dim3(ZQ_NT), 0, st, L,
+                         u, b, out, fc, g.zc, g.gx, g.gy, g.nblk, part, bt, stop);
       return;
     }
   }
   constexpr int BX = FusedTile<T, S>::BX, BY = FusedTile<T, S>::BY;
   const FusedGrid g = fused_grid<BX, BY>(L.nx, L.ny, L.nz);
-  hipLaunchKernelGGL((k_fused_tau<T, S, BX, BY>), dim3(g.nblk), dim3(FNT), 0, st, L, u, b, out, fc, g.zc,
-                     g.gx, g.gy, g.nblk, part, stop);
+  hipLaunchKernelGGL((k_fused_tau<T, S, BX, BY>), dim3(g.nblk, bt.nb), dim3(FNT), 0, st, L, u, b, out, fc,
+                     g.zc, g.gx, g.gy, g.nblk, part, bt, stop);
 }
 
 template <typename T>
@@ -555,15 +571,15 @@ size_t fused_tau_blocks(const LevelView<T>& L, int s) {
 
 template <typename T>
 bool launch_fused_tau(const LevelView<T>& L, const T* u, const T* b, T* out, int s, const StageCoef* co,
-                      double* part, const int* stop, hipStream_t st) {
+                      double* part, const int* stop, hipStream_t st, const Batch& bt) {
   if (!fused_tau_supported<T>(L, s)) return false;
   switch (s) {
-    case 1: launch_fused_S<T, 1>(L, u, b, out, co, part, stop, st); return true;
-    case 2: launch_fused_S<T, 2>(L, u, b, out, co, part, stop, st); return true;
-    case 3: launch_fused_S<T, 3>(L, u, b, out, co, part, stop, st); return true;
+    case 1: launch_fused_S<T, 1>(L, u, b, out, co, part, stop, bt, st); return true;
+    case 2: launch_fused_S<T, 2>(L, u, b, out, co, part, stop, bt, st); return true;
+    case 3: launch_fused_S<T, 3>(L, u, b, out, co, part, stop, bt, st); return true;
     default:
       if constexpr (sizeof(T) == 4) {
-        launch_fused_S<T, 4>(L, u, b, out, co, part, stop, st);
+        launch_fused_S<T, 4>(L, u, b, out, co, part, stop, bt, st);
         return true;
       }
       return false;
@@ -575,8 +591,8 @@ template bool fused_tau_supported<float>(const LevelView<float>&, int);
 template size_t fused_tau_blocks<double>(const LevelView<double>&, int);
 template size_t fused_tau_blocks<float>(const LevelView<float>&, int);
 template bool launch_fused_tau<double>(const LevelView<double>&, const double*, const double*, double*,
-                                       int, const StageCoef*, double*, const int*, hipStream_t);
+                                       int, const StageCoef*, double*, const int*, hipStream_t, const Batch&);
 template bool launch_fused_tau<float>(const LevelView<float>&, const float*, const float*, float*, int,
-                                      const StageCoef*, double*, const int*, hipStream_t);
+                                      const StageCoef*, double*, const int*, hipStream_t, const Batch&);
 
 }  // namespace rkl

@@ -30,28 +30,34 @@ void launch_stage(const LevelView<T>& L, const T* yp, const T* ypp, const T* b, 
 // transfer.hip: part receives resid_blocks() pairs (sum r^2, sum r | sum of coarse values)
 template <typename TU, typename TR>
 void launch_residual(const LevelView<TU>& L, const TU* u, const TU* b, TR* r_out, double* part,
-                     const int* stop, hipStream_t st);
+                     const int* stop, hipStream_t st, const Batch& bt = single_batch());
 template <typename T>
 void launch_resid_restrict(const LevelView<T>& F, const T* u, const T* b, T* bc, double* part,
-                           const int* stop, hipStream_t st);
+                           const int* stop, hipStream_t st, const Batch& bt = single_batch());
 template <typename T>
 void launch_prolong_add(int fnx, int fny, int fnz, int periodic, const T* e, T* fine, const int* stop,
-                        hipStream_t st);
+                        hipStream_t st, const Batch& bt = single_batch());
 template <typename T>
 void launch_restrict(int fnx, int fny, int fnz, const T* fine, T* coarse, hipStream_t st);
 void launch_reduce(const double* part, int nblk, int stride, int nq, double* out, const int* stop,
-                   hipStream_t st);
+                   hipStream_t st, const Batch& bt = single_batch());
 void launch_check(const double* part, int nblk, int stride, const double* res0sq, double tol, int max_cycles,
-                  double count, ConvState* cs, hipStream_t st);
+                  double count, ConvState* cs, hipStream_t st, const Batch& bt = single_batch());
+void launch_scale_tab(const double* const* tab, double* out, size_t n, double c, double* part, hipStream_t st,
+                      const Batch& bt);
+void launch_copy_tab(double* const* tab, const double* src, size_t n, hipStream_t st, const Batch& bt);
 template <typename T>
-void launch_fill(T* a, size_t n, T v, const int* stop, hipStream_t st);
+void launch_fill(T* a, size_t n, T v, const int* stop, hipStream_t st, const Batch& bt = single_batch());
 void launch_scale(const double* in, double* out, size_t n, double c, double* part, hipStream_t st);
 template <typename T>
-void launch_sub_mean(T* a, size_t n, const double* sum, double count, const int* stop, hipStream_t st);
+void launch_sub_mean(T* a, size_t n, const double* sum, double count, const int* stop, hipStream_t st,
+                     const Batch& bt = single_batch());
 template <typename T>
-void launch_sum(const T* a, size_t n, double* part, hipStream_t st);  // ew_block_count(n) partials
+void launch_sum(const T* a, size_t n, double* part, hipStream_t st,
+                const Batch& bt = single_batch());  // ew_block_count(n) partials
 template <typename TE>
-void launch_add_cast(double* u, const TE* e, size_t n, const int* stop, hipStream_t st);
+void launch_add_cast(double* u, const TE* e, size_t n, const int* stop, hipStream_t st,
+                     const Batch& bt = single_batch());
 
 // Coarsest-grid accelerated RKL solve in one workgroup (coarse.hip).
 constexpr int COARSE_MAX_CELLS = 2048;
@@ -81,7 +87,8 @@ size_t fused_tau_blocks(const LevelView<T>& L, int s);  // partial sums written 
 // u == nullptr: the input iterate is zero
 template <typename T>
 bool launch_fused_tau(const LevelView<T>& L, const T* u, const T* b, T* out, int s,
-                      const StageCoef* co, double* part, const int* stop, hipStream_t st);
+                      const StageCoef* co, double* part, const int* stop, hipStream_t st,
+                      const Batch& bt = single_batch());
 
 // Coarse tail of the V-cycle in one workgroup (tail.hip).
 constexpr int TAIL_MAX_LEVELS = 4;
@@ -98,9 +105,10 @@ bool tail_fits(const TailShape& ts, int s);
 // b_top: restricted right-hand side of the top tail level (mean not yet
 // removed); u_top receives that level's correction.  smooth[l]: the s stage
 // coefficients of tail level l.
+void tail_prepare();
 template <typename T>
 void launch_tail(const TailShape& ts, const StageCoef* const* smooth, int s, int n_pre, int n_post, int periodic,
                  CoarseSchedule cs, double ctol, int cmax, const T* b_top, T* u_top, const int* stop,
-                 hipStream_t st);
+                 hipStream_t st, const Batch& bt = single_batch());
 
 }  // namespace rkl

@@ -79,8 +79,14 @@ __global__ __launch_bounds__(NT) void k_restrict(int fnx, int fny, int fnz, cons
 constexpr int RED_NT = 1024;
 __global__ __launch_bounds__(RED_NT) void k_reduce(const double* __restrict__ part, int nblk,
                                                    int stride, int nq, double* __restrict__ out,
-                                                   const int* __restrict__ stop) {
+                                                   Batch bt, const int* __restrict__ stop) {
   __shared__ double sh[RED_NT / WAVE];
+  {
+    const long long mb = blockIdx.x;  // one workgroup per member; out stride s0
+    part += mb * bt.part_stride;
+    out += mb * bt.s0;
+    if (stop != nullptr) stop += mb * bt.stop_stride;
+  }
   if (stop != nullptr && *stop) return;
   for (int q = 0; q < nq; ++q) {
     double v = 0.0;
@@ -99,8 +105,15 @@ __global__ __launch_bounds__(RED_NT) void k_reduce(const double* __restrict__ pa
 // float32 right-hand side of the mixed-precision loop.
 __global__ __launch_bounds__(RED_NT) void k_check(const double* __restrict__ part, int nblk, int stride,
                                                   const double* __restrict__ res0sq, double tol,
-                                                  int max_cycles, double count, ConvState* __restrict__ cs) {
+                                                  int max_cycles, double count, ConvState* __restrict__ cs,
+                                                  Batch bt) {
   __shared__ double sh[RED_NT / WAVE];
+  {
+    const long long mb = blockIdx.x;  // one workgroup per member
+    part += mb * bt.part_stride;
+    res0sq += mb;
+    cs += mb;
+  }
   if (cs->stop) return;
   double v2 = 0.0, v1 = 0.0;
   for (int b = threadIdx.x; b < nblk; b += RED_NT) {
@@ -136,7 +149,10 @@ __global__ __launch_bounds__(RED_NT) void k_check(const double* __restrict__ par
 constexpr int EW_NT = 256;
 
 template <typename T>
-__global__ __launch_bounds__(EW_NT) void k_fill(T* __restrict__ a, size_t n, T v, const int* __restrict__ stop) {
+__global__ __launch_bounds__(EW_NT) void k_fill(T* __restrict__ a, size_t n, T v, Batch bt,
+                                                const int* __restrict__ stop) {
+  a += (long long)blockIdx.y * bt.s0;
+  if (stop != nullptr) stop += (long long)blockIdx.y * bt.stop_stride;
   if (stop != nullptr && *stop) return;
   for (size_t q = (size_t)blockIdx.x * EW_NT + threadIdx.x; q < n; q += (size_t)gridDim.x * EW_NT)
     a[q] = v;
@@ -156,11 +172,39 @@ __global__ __launch_bounds__(EW_NT) void k_scale(const double* __restrict__ in, 
   if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
+// out (member m at out + m * s0) = c * tab[m], float64 block partials per member
+__global__ __launch_bounds__(EW_NT) void k_scale_tab(const double* const* __restrict__ tab, double* __restrict__ out,
+                                                     size_t n, double c, double* __restrict__ part, Batch bt) {
+  __shared__ double sh[EW_NT / WAVE];
+  const double* in = tab[blockIdx.y];
+  out += (long long)blockIdx.y * bt.s0;
+  part += (long long)blockIdx.y * bt.part_stride;
+  double s = 0.0;
+  for (size_t q = (size_t)blockIdx.x * EW_NT + threadIdx.x; q < n; q += (size_t)gridDim.x * EW_NT) {
+    const double v = c * in[q];
+    out[q] = v;
+    s += v;
+  }
+  const double t = block_sum<EW_NT>(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// tab[m] = src (member m at src + m * s0)
+__global__ __launch_bounds__(EW_NT) void k_copy_tab(double* const* __restrict__ tab, const double* __restrict__ src,
+                                                    size_t n, Batch bt) {
+  double* dst = tab[blockIdx.y];
+  src += (long long)blockIdx.y * bt.s0;
+  for (size_t q = (size_t)blockIdx.x * EW_NT + threadIdx.x; q < n; q += (size_t)gridDim.x * EW_NT) dst[q] = src[q];
+}
+
 // a -= sum[0] / count
 template <typename T>
 __global__ __launch_bounds__(EW_NT) void k_sub_mean(T* __restrict__ a, size_t n,
-                                                    const double* __restrict__ sum, double count,
+                                                    const double* __restrict__ sum, double count, Batch bt,
                                                     const int* __restrict__ stop) {
+  a += (long long)blockIdx.y * bt.s0;
+  sum += (long long)blockIdx.y * bt.s1;
+  if (stop != nullptr) stop += (long long)blockIdx.y * bt.stop_stride;
   if (stop != nullptr && *stop) return;
   const T m = (T)(sum[0] / count);
   for (size_t q = (size_t)blockIdx.x * EW_NT + threadIdx.x; q < n; q += (size_t)gridDim.x * EW_NT)
@@ -169,8 +213,11 @@ __global__ __launch_bounds__(EW_NT) void k_sub_mean(T* __restrict__ a, size_t n,
 
 // part[blk] = float64 sum of a over the block's share
 template <typename T>
-__global__ __launch_bounds__(EW_NT) void k_sum(const T* __restrict__ a, size_t n, double* __restrict__ part) {
+__global__ __launch_bounds__(EW_NT) void k_sum(const T* __restrict__ a, size_t n, double* __restrict__ part,
+                                               Batch bt) {
   __shared__ double sh[EW_NT / WAVE];
+  a += (long long)blockIdx.y * bt.s0;
+  part += (long long)blockIdx.y * bt.part_stride;
   double s = 0.0;
   for (size_t q = (size_t)blockIdx.x * EW_NT + threadIdx.x; q < n; q += (size_t)gridDim.x * EW_NT)
     s += (double)a[q];
@@ -181,7 +228,10 @@ __global__ __launch_bounds__(EW_NT) void k_sum(const T* __restrict__ a, size_t n
 // u64 += (double) e
 template <typename TE>
 __global__ __launch_bounds__(EW_NT) void k_add_cast(double* __restrict__ u, const TE* __restrict__ e,
-                                                    size_t n, const int* __restrict__ stop) {
+                                                    size_t n, Batch bt, const int* __restrict__ stop) {
+  u += (long long)blockIdx.y * bt.s0;
+  e += (long long)blockIdx.y * bt.s1;
+  if (stop != nullptr) stop += (long long)blockIdx.y * bt.stop_stride;
   if (stop != nullptr && *stop) return;
   for (size_t q = (size_t)blockIdx.x * EW_NT + threadIdx.x; q < n; q += (size_t)gridDim.x * EW_NT)
     u[q] += (double)e[q];
@@ -218,19 +268,28 @@ void launch_restrict(int fnx, int fny, int fnz, const T* fine, T* coarse, hipStr
 }
 
 void launch_reduce(const double* part, int nblk, int stride, int nq, double* out, const int* stop,
-                   hipStream_t st) {
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(RED_NT), 0, st, part, nblk, stride, nq, out, stop);
+                   hipStream_t st, const Batch& bt) {
+  hipLaunchKernelGGL(k_reduce, dim3(bt.nb), dim3(RED_NT), 0, st, part, nblk, stride, nq, out, bt, stop);
 }
 
 void launch_check(const double* part, int nblk, int stride, const double* res0sq, double tol, int max_cycles,
-                  double count, ConvState* cs, hipStream_t st) {
-  hipLaunchKernelGGL(k_check, dim3(1), dim3(RED_NT), 0, st, part, nblk, stride, res0sq, tol, max_cycles, count,
-                     cs);
+                  double count, ConvState* cs, hipStream_t st, const Batch& bt) {
+  hipLaunchKernelGGL(k_check, dim3(bt.nb), dim3(RED_NT), 0, st, part, nblk, stride, res0sq, tol, max_cycles,
+                     count, cs, bt);
+}
+
+void launch_scale_tab(const double* const* tab, double* out, size_t n, double c, double* part, hipStream_t st,
+                      const Batch& bt) {
+  hipLaunchKernelGGL(k_scale_tab, dim3(ew_blocks(n), bt.nb), dim3(EW_NT), 0, st, tab, out, n, c, part, bt);
+}
+
+void launch_copy_tab(double* const* tab, const double* src, size_t n, hipStream_t st, const Batch& bt) {
+  hipLaunchKernelGGL(k_copy_tab, dim3(ew_blocks(n), bt.nb), dim3(EW_NT), 0, st, tab, src, n, bt);
 }
 
 template <typename T>
-void launch_fill(T* a, size_t n, T v, const int* stop, hipStream_t st) {
-  hipLaunchKernelGGL(k_fill<T>, dim3(ew_blocks(n)), dim3(EW_NT), 0, st, a, n, v, stop);
+void launch_fill(T* a, size_t n, T v, const int* stop, hipStream_t st, const Batch& bt) {
+  hipLaunchKernelGGL(k_fill<T>, dim3(ew_blocks(n), bt.nb), dim3(EW_NT), 0, st, a, n, v, bt, stop);
 }
 
 void launch_scale(const double* in, double* out, size_t n, double c, double* part, hipStream_t st) {
@@ -238,18 +297,19 @@ void launch_scale(const double* in, double* out, size_t n, double c, double* par
 }
 
 template <typename T>
-void launch_sub_mean(T* a, size_t n, const double* sum, double count, const int* stop, hipStream_t st) {
-  hipLaunchKernelGGL(k_sub_mean<T>, dim3(ew_blocks(n)), dim3(EW_NT), 0, st, a, n, sum, count, stop);
+void launch_sub_mean(T* a, size_t n, const double* sum, double count, const int* stop, hipStream_t st,
+                     const Batch& bt) {
+  hipLaunchKernelGGL(k_sub_mean<T>, dim3(ew_blocks(n), bt.nb), dim3(EW_NT), 0, st, a, n, sum, count, bt, stop);
 }
 
 template <typename T>
-void launch_sum(const T* a, size_t n, double* part, hipStream_t st) {
-  hipLaunchKernelGGL(k_sum<T>, dim3(ew_blocks(n)), dim3(EW_NT), 0, st, a, n, part);
+void launch_sum(const T* a, size_t n, double* part, hipStream_t st, const Batch& bt) {
+  hipLaunchKernelGGL(k_sum<T>, dim3(ew_blocks(n), bt.nb), dim3(EW_NT), 0, st, a, n, part, bt);
 }
 
 template <typename TE>
-void launch_add_cast(double* u, const TE* e, size_t n, const int* stop, hipStream_t st) {
-  hipLaunchKernelGGL(k_add_cast<TE>, dim3(ew_blocks(n)), dim3(EW_NT), 0, st, u, e, n, stop);
+void launch_add_cast(double* u, const TE* e, size_t n, const int* stop, hipStream_t st, const Batch& bt) {
+  hipLaunchKernelGGL(k_add_cast<TE>, dim3(ew_blocks(n), bt.nb), dim3(EW_NT), 0, st, u, e, n, bt, stop);
 }
 
 // explicit instantiations
@@ -258,13 +318,14 @@ template void launch_stage<double>(const LevelView<double>&, const double*, cons
 template void launch_stage<float>(const LevelView<float>&, const float*, const float*, const float*,
                                   float*, double, double, double, int, const int*, hipStream_t);
 template void launch_restrict<double>(int, int, int, const double*, double*, hipStream_t);
-template void launch_fill<double>(double*, size_t, double, const int*, hipStream_t);
-template void launch_fill<float>(float*, size_t, float, const int*, hipStream_t);
-template void launch_sub_mean<double>(double*, size_t, const double*, double, const int*, hipStream_t);
-template void launch_sub_mean<float>(float*, size_t, const double*, double, const int*, hipStream_t);
-template void launch_sum<double>(const double*, size_t, double*, hipStream_t);
-template void launch_sum<float>(const float*, size_t, double*, hipStream_t);
-template void launch_add_cast<float>(double*, const float*, size_t, const int*, hipStream_t);
-template void launch_add_cast<double>(double*, const double*, size_t, const int*, hipStream_t);
+template void launch_fill<double>(double*, size_t, double, const int*, hipStream_t, const Batch&);
+template void launch_fill<float>(float*, size_t, float, const int*, hipStream_t, const Batch&);
+template void launch_sub_mean<double>(double*, size_t, const double*, double, const int*, hipStream_t,
+                                      const Batch&);
+template void launch_sub_mean<float>(float*, size_t, const double*, double, const int*, hipStream_t, const Batch&);
+template void launch_sum<double>(const double*, size_t, double*, hipStream_t, const Batch&);
+template void launch_sum<float>(const float*, size_t, double*, hipStream_t, const Batch&);
+template void launch_add_cast<float>(double*, const float*, size_t, const int*, hipStream_t, const Batch&);
+template void launch_add_cast<double>(double*, const double*, size_t, const int*, hipStream_t, const Batch&);
 
 }  // namespace rkl

@@ -17,6 +17,17 @@ namespace rkl {
 
 constexpr int WAVE = 64;  // CDNA wavefront width
 
+// A batch of identical grids handled by one launch: member m (blockIdx.y, or
+// blockIdx.x for kernels with one workgroup per member) finds its arrays at
+// base + m * stride.  A single solve is the batch {1, 0, 0, 0, 0}.
+struct Batch {
+  int nb;            // members
+  long long s0, s1;  // element strides of the primary and secondary arrays
+  int stop_stride;   // ints between members' stop flags
+  int part_stride;   // doubles between members' partial-sum blocks
+};
+inline Batch single_batch() { return Batch{1, 0, 0, 0, 0}; }
+
 template <typename T>
 struct LevelView {
   int nx, ny, nz;

@@ -383,13 +383,15 @@ void remove_mean(Plan& P, T* a, size_t n, const int* stop, hipStream_t st) {
 // Y_{j-2}.
 template <typename T>
 void tau_step(Plan& P, const LevelView<T>& V, T*& cur, T*& alt, const T* b,
-              const std::vector<StageCoef>& co, const int* stop, hipStream_t st) {
+              const std::vector<StageCoef>& co, const int* stop, hipStream_t st,
+              const Batch& bt = single_batch()) {
   const int s = (int)co.size();
-  if (launch_fused_tau<T>(V, cur, b, alt, s, co.data(), nullptr, stop, st)) {
+  if (launch_fused_tau<T>(V, cur, b, alt, s, co.data(), nullptr, stop, st, bt)) {
     check_launch();
     std::swap(cur, alt);
     return;
   }
+  if (bt.nb > 1) fail(RKL_EINVAL, "batched solves need the fused tau-step on every level above the tail");
   launch_stage<T>(V, cur, nullptr, b, alt, co[0].mu, co[0].nu, co[0].c, 1, stop, st);
   for (int j = 2; j <= s; ++j) {
     // Y_{j-1} is in `alt` for even j (odd index), in `cur` for odd j; Y_j
@@ -406,12 +408,14 @@ void tau_step(Plan& P, const LevelView<T>& V, T*& cur, T*& alt, const T* b,
 // correction); the result lands in `cur` (its previous contents are ignored).
 template <typename T>
 void tau_from_zero(Plan& P, const LevelView<T>& V, T*& cur, T*& alt, const T* b,
-                   const std::vector<StageCoef>& co, const int* stop, hipStream_t st) {
+                   const std::vector<StageCoef>& co, const int* stop, hipStream_t st,
+                   const Batch& bt = single_batch()) {
   const int s = (int)co.size();
-  if (launch_fused_tau<T>(V, (const T*)nullptr, b, cur, s, co.data(), nullptr, stop, st)) {
+  if (launch_fused_tau<T>(V, (const T*)nullptr, b, cur, s, co.data(), nullptr, stop, st, bt)) {
     check_launch();
     return;
   }
+  if (bt.nb > 1) fail(RKL_EINVAL, "batched solves need the fused tau-step on every level above the tail");
   launch_fill<T>(cur, (size_t)V.nx * V.ny * V.nz, (T)0, stop, st);
   check_launch();
   tau_step<T>(P, V, cur, alt, b, co, stop, st);
@@ -508,24 +512,43 @@ int tail_level(const Plan& P) {
   return sizeof(T) == 8 ? P.tail64 : P.tail32;
 }
 
+// Batch geometry of the V-cycle: nb members whose level-l arrays are nb
+// contiguous blocks of n_l cells; stop flags and partial sums strided per
+// member; dsum: two doubles per member of scratch for periodic means.
+struct VBatch {
+  int nb = 1;
+  int stop_stride = 0;
+  int part_stride = 0;
+  double* dsum = nullptr;
+  double* part = nullptr;  // nullptr: the plan's own buffer
+};
+
 template <typename T>
 void vcycle_from(Plan& P, Hier<T>& H, T*& cur0, T*& alt0, const T* b0, const double* faces0, int pre_done,
-                 const rkl_opts& o, const int* stop, hipStream_t st) {
+                 const rkl_opts& o, const int* stop, hipStream_t st, const VBatch& vb) {
   const int L = P.L();
+  double* part = vb.part ? vb.part : P.part;
   auto V = [&](int l) { return view<T>(P.lv[l], P.periodic, l == 0 ? faces0 : nullptr); };
+  auto B1 = [&](int l) { return Batch{vb.nb, (long long)P.lv[l].n, 0, vb.stop_stride, vb.part_stride}; };
+  auto B2 = [&](int l, int l2) {
+    return Batch{vb.nb, (long long)P.lv[l].n, (long long)P.lv[l2].n, vb.stop_stride, vb.part_stride};
+  };
   if (L == 1) {
+    if (vb.nb > 1) fail(RKL_EINVAL, "batched solves need at least two levels");
     for (int q = pre_done; q < o.n_pre + o.n_post; ++q)
       tau_step<T>(P, V(0), cur0, alt0, b0, P.lv[0].smooth, stop, st);
     return;
   }
   // levels lt.. run in the one-workgroup tail when they fit
-  const int lt = (o.n_pre + o.n_post > 0) ? tail_level<T>(P) : -1;
+  const int lt = tail_level<T>(P);
+  if (vb.nb > 1 && lt <= 0) fail(RKL_EINVAL, "batched solves need the one-workgroup coarse tail");
   const int lbot = lt > 0 ? lt : L - 1;
-  for (int q = pre_done; q < o.n_pre; ++q) tau_step<T>(P, V(0), cur0, alt0, b0, P.lv[0].smooth, stop, st);
+  for (int q = pre_done; q < o.n_pre; ++q)
+    tau_step<T>(P, V(0), cur0, alt0, b0, P.lv[0].smooth, stop, st, B1(0));
   for (int l = 1; l <= lbot; ++l) {
     T* fu = (l == 1) ? cur0 : H.u[l - 1];
     const T* fb = (l == 1) ? b0 : H.b[l - 1];
-    launch_resid_restrict<T>(V(l - 1), fu, fb, H.b[l], P.part, stop, st);
+    launch_resid_restrict<T>(V(l - 1), fu, fb, H.b[l], part, stop, st, B2(l - 1, l));
     check_launch();
     const Lev& C = P.lv[l];
     if (l == lt) {
@@ -533,24 +556,28 @@ void vcycle_from(Plan& P, Hier<T>& H, T*& cur0, T*& alt0, const T* b0, const dou
       const StageCoef* sm[TAIL_MAX_LEVELS];
       for (int k = 0; k < ts.nlev; ++k) sm[k] = P.lv[lt + k].smooth.data();
       launch_tail<T>(ts, sm, o.s, o.n_pre, o.n_post, P.periodic ? 1 : 0, P.cs(), coarse_tol_for<T>(o),
-                     o.coarse_max_steps, H.b[lt], H.u[lt], stop, st);
+                     o.coarse_max_steps, H.b[lt], H.u[lt], stop, st, B1(lt));
       check_launch();
       break;
     }
     if (P.periodic) {
       const Lev& Fl = P.lv[l - 1];
-      launch_reduce(P.part, (int)resid_blocks(Fl.nx, Fl.ny, Fl.nz), 2, 2, P.dscal, stop, st);
-      launch_sub_mean<T>(H.b[l], C.n, P.dscal + 1, (double)C.n, stop, st);
+      Batch br{vb.nb, 2, 0, vb.stop_stride, vb.part_stride};  // two sums per member
+      launch_reduce(part, (int)resid_blocks(Fl.nx, Fl.ny, Fl.nz), 2, 2, vb.dsum, stop, st, br);
+      Batch bs{vb.nb, (long long)C.n, 2, vb.stop_stride, 0};
+      launch_sub_mean<T>(H.b[l], C.n, vb.dsum + 1, (double)C.n, stop, st, bs);
       check_launch();
     }
     if (l < L - 1) {
       if (o.n_pre > 0) {
-        tau_from_zero<T>(P, V(l), H.u[l], H.t[l], H.b[l], C.smooth, stop, st);
-        for (int q = 1; q < o.n_pre; ++q) tau_step<T>(P, V(l), H.u[l], H.t[l], H.b[l], C.smooth, stop, st);
+        tau_from_zero<T>(P, V(l), H.u[l], H.t[l], H.b[l], C.smooth, stop, st, B1(l));
+        for (int q = 1; q < o.n_pre; ++q)
+          tau_step<T>(P, V(l), H.u[l], H.t[l], H.b[l], C.smooth, stop, st, B1(l));
       } else {
-        launch_fill<T>(H.u[l], C.n, (T)0, stop, st);
+        launch_fill<T>(H.u[l], C.n, (T)0, stop, st, B1(l));
       }
     } else {
+      if (vb.nb > 1) fail(RKL_EINVAL, "batched solves need the one-workgroup coarse tail");
       coarse_solve<T>(P, H, l, o, stop, st);
     }
   }
@@ -559,9 +586,9 @@ void vcycle_from(Plan& P, Hier<T>& H, T*& cur0, T*& alt0, const T* b0, const dou
     T*& ca = (l == 0) ? alt0 : H.t[l];
     const T* bl = (l == 0) ? b0 : H.b[l];
     const Lev& F = P.lv[l];
-    launch_prolong_add<T>(F.nx, F.ny, F.nz, P.periodic ? 1 : 0, H.u[l + 1], cu, stop, st);
+    launch_prolong_add<T>(F.nx, F.ny, F.nz, P.periodic ? 1 : 0, H.u[l + 1], cu, stop, st, B2(l, l + 1));
     check_launch();
-    for (int q = 0; q < o.n_post; ++q) tau_step<T>(P, V(l), cu, ca, bl, F.smooth, stop, st);
+    for (int q = 0; q < o.n_post; ++q) tau_step<T>(P, V(l), cu, ca, bl, F.smooth, stop, st, B1(l));
   }
 }
 
@@ -789,7 +816,7 @@ rkl_status solve_fp64(Plan& P, const rkl_opts& o, const double* rho, const doubl
           pre_done = 0;
         }
       }
-      vcycle_from<double>(P, P.h64, cur, alt, P.f0, faces, pre_done, o, stop, st);
+      vcycle_from<double>(P, P.h64, cur, alt, P.f0, faces, pre_done, o, stop, st, VBatch{1, 0, 0, P.dscal});
       int ie = 0;
       for (int k = 0; k < 3; ++k)
         if (bufs[k] == cur) ie = k;
@@ -844,7 +871,7 @@ rkl_status solve_mixed(Plan& P, const rkl_opts& o, const double* rho, const doub
       } else {
         launch_fill<float>(cur, F.n, 0.0f, stop, st);
       }
-      vcycle_from<float>(P, P.h32, cur, alt, P.h32.b[0], nullptr, pre_done, o, stop, st);
+      vcycle_from<float>(P, P.h32, cur, alt, P.h32.b[0], nullptr, pre_done, o, stop, st, VBatch{1, 0, 0, P.dscal});
       launch_add_cast<float>(phi, cur, F.n, stop, st);
       check_launch();
       ++queued;
@@ -857,6 +884,348 @@ rkl_status solve_mixed(Plan& P, const rkl_opts& o, const double* rho, const doub
   HIPCHK(hipStreamSynchronize(st));
   fill_stats(stats, cs, cs.result_m);
   return finish_status(cs);
+}
+
+
+// One full solve.  A single-level grid runs the float64 accelerated RKL
+// iteration whatever the precision asks: with no coarse grid there is no
+// float32 V-cycle to refine.
+rkl_status solve_one(const rkl_grid& g, const rkl_opts& o, const double* rho, const double* faces, double* phi,
+                     rkl_stats* stats, hipStream_t st) {
+  Plan* P = &get_plan(g, o.s, o.tau_frac, o.min_coarse, o.prec);
+  const bool mixed = o.prec == RKL_MIXED && P->L() > 1;
+  if (o.prec == RKL_MIXED && !mixed) P = &get_plan(g, o.s, o.tau_frac, o.min_coarse, RKL_FP64);
+  std::lock_guard<std::mutex> lk(P->mu);
+  const rkl_status r = mixed ? solve_mixed(*P, o, rho, faces, phi, stats, st) : solve_fp64(*P, o, rho, faces, phi, stats, st);
+  if (stats) stats->status = r;
+  return r;
+}
+
+// ------------------------------------------------------------------ batched solves
+// Members with identical grids form a class.  A class owns contiguous
+// buffers (member m at m * n_l on level l) and every kernel of its V-cycle
+// covers all members in one launch; each member has its own convergence state
+// and stop flag, so converged members idle (their workgroups return at once)
+// while the others go on.  The defect-correction form of the loop (float64
+// residual, a V-cycle on the correction equation from zero at the inner
+// precision, float64 update) serves both precisions.
+struct ClassKey {
+  int dev, nx, ny, nz, bc, s, min_coarse, prec, nb;
+  double hx, hy, hz, theta;
+  bool operator<(const ClassKey& o) const {
+    return std::tie(dev, nx, ny, nz, bc, s, min_coarse, prec, nb, hx, hy, hz, theta) <
+           std::tie(o.dev, o.nx, o.ny, o.nz, o.bc, o.s, o.min_coarse, o.prec, o.nb, o.hx, o.hy, o.hz, o.theta);
+  }
+};
+
+struct ClassPlan {
+  Plan* base = nullptr;  // level descriptors, schedule tables and tail choice of one member
+  int nb = 0;
+  int part_stride = 0;
+  double *f0 = nullptr, *phi = nullptr, *res0sq = nullptr, *dsum = nullptr, *part = nullptr;
+  double** tab_in = nullptr;
+  double** tab_out = nullptr;
+  ConvState* conv = nullptr;
+  ConvState* hconv = nullptr;
+  Hier<float> h32;
+  Hier<double> h64;
+  std::vector<void*> allocs;
+  template <typename U>
+  U* alloc(size_t n) {
+    void* p = nullptr;
+    if (n == 0) n = 1;
+    if (hipMalloc(&p, n * sizeof(U)) != hipSuccess) {
+      (void)hipGetLastError();
+      fail(RKL_ENOMEM, "hipMalloc of " + std::to_string(n * sizeof(U)) + " bytes failed");
+    }
+    allocs.push_back(p);
+    return (U*)p;
+  }
+  ~ClassPlan() {
+    for (void* p : allocs) (void)hipFree(p);
+    if (hconv) (void)hipHostFree(hconv);
+  }
+};
+
+std::map<ClassKey, std::unique_ptr<ClassPlan>> g_classes;
+
+ClassPlan& get_class(const rkl_grid& g, const rkl_opts& o, int nb) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  ClassKey key{dev, g.nx, g.ny, g.nz, g.bc, o.s, o.min_coarse, o.prec, nb, g.hx, g.hy, g.hz, o.tau_frac};
+  Plan& base = get_plan(g, o.s, o.tau_frac, o.min_coarse, o.prec);
+  std::lock_guard<std::mutex> lk(g_plans_mu);
+  auto it = g_classes.find(key);
+  if (it != g_classes.end()) return *it->second;
+  if (nb > 65535) fail(RKL_EINVAL, "at most 65535 members per grid class");
+  auto C = std::make_unique<ClassPlan>();
+  C->base = &base;
+  C->nb = nb;
+  const Lev& F = base.lv[0];
+  const int L = base.L();
+  size_t ps = 2 * resid_blocks(F.nx, F.ny, F.nz);
+  ps = std::max(ps, ew_block_count(F.n));
+  {
+    LevelView<double> vd{F.nx, F.ny, F.nz, 1.0, 1.0, 1.0, base.periodic ? 1 : 0, nullptr};
+    LevelView<float> vf{F.nx, F.ny, F.nz, 1.0f, 1.0f, 1.0f, base.periodic ? 1 : 0, nullptr};
+    ps = std::max(ps, fused_tau_blocks<double>(vd, o.s));
+    ps = std::max(ps, fused_tau_blocks<float>(vf, o.s));
+  }
+  C->part_stride = (int)ps;
+  C->f0 = C->alloc<double>((size_t)nb * F.n);
+  C->phi = C->alloc<double>((size_t)nb * F.n);
+  C->res0sq = C->alloc<double>(nb);
+  C->dsum = C->alloc<double>(2 * (size_t)nb);
+  C->part = C->alloc<double>((size_t)nb * ps);
+  C->tab_in = C->alloc<double*>(nb);
+  C->tab_out = C->alloc<double*>(nb);
+  C->conv = C->alloc<ConvState>(nb);
+  HIPCHK(hipHostMalloc((void**)&C->hconv, (size_t)nb * sizeof(ConvState), hipHostMallocDefault));
+  auto make = [&](auto& H, auto tag) {
+    using U = decltype(tag);
+    H.u.assign(L, nullptr);
+    H.b.assign(L, nullptr);
+    H.t.assign(L, nullptr);
+    for (int l = 0; l < L; ++l) {
+      H.u[l] = C->template alloc<U>((size_t)nb * base.lv[l].n);
+      H.b[l] = C->template alloc<U>((size_t)nb * base.lv[l].n);
+      H.t[l] = C->template alloc<U>((size_t)nb * base.lv[l].n);
+    }
+  };
+  if (o.prec == RKL_MIXED) make(C->h32, 0.0f);
+  else make(C->h64, 0.0);
+  ClassPlan& ref = *C;
+  g_classes[key] = std::move(C);
+  return ref;
+}
+
+constexpr int CONV_INTS = (int)(sizeof(ConvState) / sizeof(int));
+constexpr int CONV_DOUBLES = (int)(sizeof(ConvState) / sizeof(double));
+
+// one outer iteration for every member of the class (stream-ordered, no sync)
+template <typename T>
+void class_iteration(ClassPlan& C, Hier<T>& H, const rkl_opts& o, hipStream_t st) {
+  Plan& P = *C.base;
+  const Lev& F = P.lv[0];
+  const int nb = C.nb, ps = C.part_stride;
+  const int* stop = &C.conv->stop;
+  const LevelView<double> V0 = view<double>(F, P.periodic, nullptr);
+  const LevelView<T> VT = view<T>(F, P.periodic, nullptr);
+  launch_residual<double, T>(V0, C.phi, C.f0, H.b[0], C.part, stop, st, Batch{nb, (long long)F.n, 0, CONV_INTS, ps});
+  launch_check(C.part, (int)resid_blocks(F.nx, F.ny, F.nz), 2, C.res0sq, o.tol, o.max_cycles, (double)F.n, C.conv,
+               st, Batch{nb, 0, 0, 0, ps});
+  check_launch();
+  if (P.periodic) {
+    launch_sub_mean<T>(H.b[0], F.n, &C.conv->mean, 1.0, stop, st,
+                       Batch{nb, (long long)F.n, CONV_DOUBLES, CONV_INTS, 0});
+    check_launch();
+  }
+  T* cur = H.u[0];
+  T* alt = H.t[0];
+  const Batch b0{nb, (long long)F.n, 0, CONV_INTS, ps};
+  int pre_done = 0;
+  if (o.n_pre > 0) {
+    tau_from_zero<T>(P, VT, cur, alt, H.b[0], F.smooth, stop, st, b0);
+    pre_done = 1;
+  } else {
+    launch_fill<T>(cur, F.n, (T)0, stop, st, b0);
+  }
+  vcycle_from<T>(P, H, cur, alt, H.b[0], nullptr, pre_done, o, stop, st, VBatch{nb, CONV_INTS, ps, C.dsum, C.part});
+  launch_add_cast<T>(C.phi, cur, F.n, stop, st, Batch{nb, (long long)F.n, (long long)F.n, CONV_INTS, 0});
+  check_launch();
+}
+
+void class_iterations(ClassPlan& C, const rkl_opts& o, int k, hipStream_t st) {
+  for (int q = 0; q < k; ++q) {
+    if (o.prec == RKL_MIXED) class_iteration<float>(C, C.h32, o, st);
+    else class_iteration<double>(C, C.h64, o, st);
+  }
+}
+
+// f0 = 4 pi G rho (mean-free when periodic), phi = 0, ||M 0 - f0||^2 and a
+// reset convergence state for every member; returns ||M 0 - f0|| per member.
+// A zero right-hand side is tested against 1 instead, which stops it at once
+// with phi = 0.
+std::vector<double> class_start(ClassPlan& C, const rkl_opts& o, const double* const* rho, double* const* phi,
+                                hipStream_t st) {
+  Plan& P = *C.base;
+  const Lev& F = P.lv[0];
+  const int nb = C.nb, ps = C.part_stride;
+  HIPCHK(hipMemcpyAsync(C.tab_in, rho, nb * sizeof(double*), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(C.tab_out, phi, nb * sizeof(double*), hipMemcpyHostToDevice, st));
+  launch_scale_tab(C.tab_in, C.f0, F.n, o.four_pi_G, C.part, st, Batch{nb, (long long)F.n, 0, 0, ps});
+  check_launch();
+  if (P.periodic) {
+    launch_reduce(C.part, (int)ew_block_count(F.n), 1, 1, C.dsum, nullptr, st, Batch{nb, 2, 0, 0, ps});
+    launch_sub_mean<double>(C.f0, F.n, C.dsum, (double)F.n, nullptr, st, Batch{nb, (long long)F.n, 2, 0, 0});
+  }
+  const LevelView<double> V0 = view<double>(F, P.periodic, nullptr);
+  launch_residual<double, double>(V0, nullptr, C.f0, (double*)nullptr, C.part, nullptr, st,
+                                  Batch{nb, (long long)F.n, 0, 0, ps});
+  launch_reduce(C.part, (int)resid_blocks(F.nx, F.ny, F.nz), 2, 1, C.res0sq, nullptr, st, Batch{nb, 1, 0, 0, ps});
+  launch_fill<double>(C.phi, F.n, 0.0, nullptr, st, Batch{nb, (long long)F.n, 0, 0, 0});
+  check_launch();
+  // zero right-hand sides: relative residual 0 at once (phi stays 0)
+  std::vector<double> r0(nb), res0(nb);
+  HIPCHK(hipMemcpyAsync(r0.data(), C.res0sq, nb * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  bool fix = false;
+  for (int m = 0; m < nb; ++m) {
+    res0[m] = std::sqrt(r0[m]);
+    if (r0[m] == 0.0) {
+      r0[m] = 1.0;
+      fix = true;
+    }
+  }
+  if (fix) {
+    HIPCHK(hipMemcpyAsync(C.res0sq, r0.data(), nb * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  std::memset(C.hconv, 0, (size_t)nb * sizeof(ConvState));
+  HIPCHK(hipMemcpyAsync(C.conv, C.hconv, (size_t)nb * sizeof(ConvState), hipMemcpyHostToDevice, st));
+  return res0;
+}
+
+// final mean removal (periodic) and copy-out to the caller's arrays
+void class_finish(ClassPlan& C, hipStream_t st) {
+  Plan& P = *C.base;
+  const Lev& F = P.lv[0];
+  const int nb = C.nb, ps = C.part_stride;
+  if (P.periodic) {
+    launch_sum<double>(C.phi, F.n, C.part, st, Batch{nb, (long long)F.n, 0, 0, ps});
+    launch_reduce(C.part, (int)ew_block_count(F.n), 1, 1, C.dsum, nullptr, st, Batch{nb, 2, 0, 0, ps});
+    launch_sub_mean<double>(C.phi, F.n, C.dsum, (double)F.n, nullptr, st, Batch{nb, (long long)F.n, 2, 0, 0});
+  }
+  launch_copy_tab(C.tab_out, C.phi, F.n, st, Batch{nb, (long long)F.n, 0, 0, 0});
+  check_launch();
+}
+
+// options that the captured kernels take as arguments
+struct LoopSig {
+  std::vector<std::pair<ClassPlan*, int>> cls;  // classes and iterations captured
+  double tol, coarse_tol;
+  int max_cycles, n_pre, n_post, coarse_max_steps;
+  bool operator==(const LoopSig& o) const {
+    return cls == o.cls && tol == o.tol && coarse_tol == o.coarse_tol && max_cycles == o.max_cycles &&
+           n_pre == o.n_pre && n_post == o.n_post && coarse_max_steps == o.coarse_max_steps;
+  }
+};
+
+struct GraphCache {
+  LoopSig sig;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t stream = nullptr;
+  ~GraphCache() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (stream) (void)hipStreamDestroy(stream);
+  }
+};
+std::unique_ptr<GraphCache> g_graph;
+
+// Capture `iters` outer iterations of every class into one graph (cached).
+hipGraphExec_t batch_graph(std::vector<ClassPlan*>& cls, const rkl_opts& o, int iters) {
+  LoopSig sig{{}, o.tol, o.coarse_tol, o.max_cycles, o.n_pre, o.n_post, o.coarse_max_steps};
+  for (auto* c : cls) sig.cls.push_back({c, iters});
+  if (g_graph && g_graph->sig == sig) return g_graph->exec;
+  tail_prepare();
+  auto G = std::make_unique<GraphCache>();
+  G->sig = sig;
+  HIPCHK(hipStreamCreateWithFlags(&G->stream, hipStreamNonBlocking));
+  HIPCHK(hipStreamBeginCapture(G->stream, hipStreamCaptureModeThreadLocal));
+  for (auto* c : cls) class_iterations(*c, o, iters, G->stream);
+  hipGraph_t graph = nullptr;
+  HIPCHK(hipStreamEndCapture(G->stream, &graph));
+  HIPCHK(hipGraphInstantiate(&G->exec, graph, nullptr, nullptr, 0));
+  (void)hipGraphDestroy(graph);
+  g_graph = std::move(G);
+  return g_graph->exec;
+}
+
+// A class runs batched when its hierarchy ends in the one-workgroup tail and
+// every level above the tail takes the fused tau-step.
+template <typename T>
+bool class_ok(Plan& P, const rkl_opts& o) {
+  const int lt = tail_level<T>(P);
+  if (P.L() < 2 || lt <= 0) return false;
+  for (int l = 0; l < lt; ++l)
+    if (!fused_tau_supported<T>(view<T>(P.lv[l], P.periodic, nullptr), o.s)) return false;
+  return true;
+}
+
+rkl_status solve_batched(const rkl_grid* grids, int nbatch, const rkl_opts& o, const double* const* rho,
+                         double* const* phi, rkl_stats* stats, hipStream_t st) {
+  // group members by grid
+  std::map<std::tuple<int, int, int, double, double, double, int>, std::vector<int>> groups;
+  for (int q = 0; q < nbatch; ++q) {
+    const rkl_grid& g = grids[q];
+    groups[std::make_tuple(g.nx, g.ny, g.nz, g.hx, g.hy, g.hz, g.bc)].push_back(q);
+  }
+  std::vector<ClassPlan*> cls;
+  std::vector<std::vector<int>> members;
+  std::vector<int> single;  // members solved one by one
+  for (auto& kv : groups) {
+    const rkl_grid& g = grids[kv.second[0]];
+    Plan& P = get_plan(g, o.s, o.tau_frac, o.min_coarse, o.prec);
+    const bool ok = o.prec == RKL_MIXED ? class_ok<float>(P, o) : class_ok<double>(P, o);
+    if (!ok) {
+      single.insert(single.end(), kv.second.begin(), kv.second.end());
+      continue;
+    }
+    cls.push_back(&get_class(g, o, (int)kv.second.size()));
+    members.push_back(kv.second);
+  }
+  rkl_status worst = RKL_OK;
+  for (int q : single) {
+    const rkl_status s = solve_one(grids[q], o, rho[q], nullptr, phi[q], stats ? &stats[q] : nullptr, st);
+    if (s != RKL_OK && worst == RKL_OK) worst = s;
+  }
+  if (cls.empty()) return worst;
+  std::vector<std::vector<double>> res0(cls.size());
+  for (size_t c = 0; c < cls.size(); ++c) {
+    std::vector<const double*> rp;
+    std::vector<double*> pp;
+    for (int q : members[c]) {
+      rp.push_back(rho[q]);
+      pp.push_back(phi[q]);
+    }
+    res0[c] = class_start(*cls[c], o, rp.data(), pp.data(), st);
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  // iterations per graph launch: enough for the predicted contraction
+  const int iters = std::max(1, std::min(o.max_cycles + 1, (int)std::ceil(std::log(std::max(o.tol, 1e-300)) /
+                                                                             std::log(0.12)) + 1));
+  hipGraphExec_t ex = batch_graph(cls, o, iters);
+  int launched = 0;
+  while (true) {
+    HIPCHK(hipGraphLaunch(ex, st));
+    launched += iters;
+    bool all = true;
+    for (auto* c : cls) {
+      HIPCHK(hipMemcpyAsync(c->hconv, c->conv, (size_t)c->nb * sizeof(ConvState), hipMemcpyDeviceToHost, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    for (auto* c : cls)
+      for (int m = 0; m < c->nb; ++m) all = all && c->hconv[m].stop;
+    if (all) break;
+    if (launched > o.max_cycles + 1) fail(RKL_EHIP, "batched loop ended without a decision");
+  }
+  for (size_t c = 0; c < cls.size(); ++c) {
+    class_finish(*cls[c], st);
+    for (int m = 0; m < cls[c]->nb; ++m) {
+      const ConvState& cs = cls[c]->hconv[m];
+      const rkl_status s = finish_status(cs);
+      if (s != RKL_OK && worst == RKL_OK) worst = s;
+      if (stats) {
+        rkl_stats& S = stats[members[c][m]];
+        S.levels = cls[c]->base->L();
+        S.res0 = res0[c][m];
+        S.status = s;
+        fill_stats(&S, cs, cs.result_m);
+      }
+    }
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  return worst;
 }
 
 template <typename Fn>
@@ -900,6 +1269,8 @@ const char* rkl_last_error(void) { return g_err.c_str(); }
 
 void rkl_release_all(void) {
   std::lock_guard<std::mutex> lk(g_plans_mu);
+  g_graph.reset();
+  g_classes.clear();
   g_plans.clear();
 }
 
@@ -910,11 +1281,7 @@ rkl_status rkl_poisson_solve(const rkl_grid* grid, const rkl_opts* opts, const d
     const rkl_opts o = resolve_opts(opts);
     if (!rho || !phi) fail(RKL_EINVAL, "rho and phi must be non-NULL");
     if (stats) stats->history_len = 0;
-    Plan& P = get_plan(*grid, o.s, o.tau_frac, o.min_coarse, o.prec);
-    std::lock_guard<std::mutex> lk(P.mu);
-    hipStream_t st = (hipStream_t)hip_stream;
-    if (o.prec == RKL_MIXED) return solve_mixed(P, o, rho, bc_faces, phi, stats, st);
-    return solve_fp64(P, o, rho, bc_faces, phi, stats, st);
+    return solve_one(*grid, o, rho, bc_faces, phi, stats, (hipStream_t)hip_stream);
   });
 }
 
@@ -930,7 +1297,7 @@ rkl_status mg_vcycle(const rkl_grid* grid, const rkl_opts* opts, const double* f
     hipStream_t st = (hipStream_t)hip_stream;
     double* cur = phi;
     double* alt = P.t0;
-    vcycle_from<double>(P, P.h64, cur, alt, f, bc_faces, 0, o, nullptr, st);
+    vcycle_from<double>(P, P.h64, cur, alt, f, bc_faces, 0, o, nullptr, st, VBatch{1, 0, 0, P.dscal});
     if (cur != phi) copy_d2d(phi, cur, P.lv[0].n, st);
     if (rel_res_out) {
       const LevelView<double> V0 = view<double>(P.lv[0], P.periodic, bc_faces);
@@ -1057,17 +1424,23 @@ int rkl_tau_step_launches(const rkl_grid* grid, int s, int prec) {
 rkl_status rkl_poisson_solve_batched(const rkl_grid* grids, int nbatch, const rkl_opts* opts,
                                      const double* const* rho, double* const* phi, rkl_stats* stats,
                                      void* hip_stream) {
-  if (nbatch < 0 || (nbatch > 0 && (!grids || !rho || !phi))) {
-    g_err = "bad batch arguments";
-    return RKL_EINVAL;
-  }
-  rkl_status worst = RKL_OK;
-  for (int q = 0; q < nbatch; ++q) {
-    rkl_status s = rkl_poisson_solve(&grids[q], opts, rho[q], nullptr, phi[q], stats ? &stats[q] : nullptr,
-                                     hip_stream);
-    if (s != RKL_OK && worst == RKL_OK) worst = s;
-  }
-  return worst;
+  return guarded([&]() -> rkl_status {
+    if (nbatch < 0) fail(RKL_EINVAL, "nbatch must be >= 0");
+    if (nbatch == 0) return RKL_OK;
+    if (!grids || !rho || !phi) fail(RKL_EINVAL, "grids, rho and phi must be non-NULL");
+    for (int q = 0; q < nbatch; ++q) {
+      validate_grid(&grids[q], nullptr);
+      if (!rho[q] || !phi[q]) fail(RKL_EINVAL, "NULL member array");
+      if (stats) {
+        stats[q].history_len = 0;
+        stats[q].status = RKL_OK;
+      }
+    }
+    const rkl_opts o = resolve_opts(opts);
+    static std::mutex batch_mu;
+    std::lock_guard<std::mutex> lk(batch_mu);
+    return solve_batched(grids, nbatch, o, rho, phi, stats, (hipStream_t)hip_stream);
+  });
 }
 
 }  // extern "C"

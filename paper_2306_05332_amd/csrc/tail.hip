@@ -53,7 +53,13 @@ __device__ __forceinline__ T tail_lap(const TailLevel<T>& V, const T* Y, int q, 
 
 template <typename T>
 __global__ __launch_bounds__(TNT) void k_tail(TailArgs<T> A, const T* __restrict__ b_top, T* __restrict__ u_top,
-                                              const int* __restrict__ stop) {
+                                              Batch bt, const int* __restrict__ stop) {
+  {
+    const long long mb = blockIdx.x;  // one workgroup per member
+    b_top += mb * bt.s0;
+    u_top += mb * bt.s0;
+    if (stop != nullptr) stop += mb * bt.stop_stride;
+  }
   extern __shared__ __align__(16) unsigned char pool_raw[];
   __shared__ double red[TNT / WAVE];
   __shared__ double bc;
@@ -289,10 +295,22 @@ bool tail_fits(const TailShape& ts, int s) {
   return tail_lds_bytes<T>(ts) <= TAIL_MAX_LDS;
 }
 
+// Raise the dynamic LDS limit of both tail kernels (once per process; a
+// stream capture must not be the first caller).
+void tail_prepare() {
+  static bool done = false;
+  if (done) return;
+  (void)hipFuncSetAttribute((const void*)k_tail<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)TAIL_MAX_LDS);
+  (void)hipFuncSetAttribute((const void*)k_tail<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)TAIL_MAX_LDS);
+  done = true;
+}
+
 template <typename T>
 void launch_tail(const TailShape& ts, const StageCoef* const* smooth, int s, int n_pre, int n_post, int periodic,
                  CoarseSchedule cs, double ctol, int cmax, const T* b_top, T* u_top, const int* stop,
-                 hipStream_t st) {
+                 hipStream_t st, const Batch& bt) {
   TailArgs<T> A;
   std::memset(&A, 0, sizeof(A));
   A.nlev = ts.nlev;
@@ -321,20 +339,15 @@ void launch_tail(const TailShape& ts, const StageCoef* const* smooth, int s, int
     }
   }
   const size_t shm = tail_lds_bytes<T>(ts);
-  static bool attr_set[2] = {false, false};
-  if (!attr_set[sizeof(T) == 8]) {
-    (void)hipFuncSetAttribute((const void*)k_tail<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)TAIL_MAX_LDS);
-    attr_set[sizeof(T) == 8] = true;
-  }
-  hipLaunchKernelGGL(k_tail<T>, dim3(1), dim3(TNT), shm, st, A, b_top, u_top, stop);
+  tail_prepare();
+  hipLaunchKernelGGL(k_tail<T>, dim3(bt.nb), dim3(TNT), shm, st, A, b_top, u_top, bt, stop);
 }
 
 template bool tail_fits<double>(const TailShape&, int);
 template bool tail_fits<float>(const TailShape&, int);
 template void launch_tail<double>(const TailShape&, const StageCoef* const*, int, int, int, int, CoarseSchedule,
-                                  double, int, const double*, double*, const int*, hipStream_t);
+                                  double, int, const double*, double*, const int*, hipStream_t, const Batch&);
 template void launch_tail<float>(const TailShape&, const StageCoef* const*, int, int, int, int, CoarseSchedule,
-                                 double, int, const float*, float*, const int*, hipStream_t);
+                                 double, int, const float*, float*, const int*, hipStream_t, const Batch&);
 
 }  // namespace rkl

@@ -38,7 +38,16 @@ template <typename TU, typename TR, bool RESTRICT>
 __global__ __launch_bounds__(RNT) void k_resid_tile(LevelView<TU> F, const TU* __restrict__ u,
                                                     const TU* __restrict__ b, TR* __restrict__ out,
                                                     int kc, int gx_tiles, int gy_tiles, int nblk,
-                                                    double* __restrict__ part, const int* __restrict__ stop) {
+                                                    double* __restrict__ part, Batch bt,
+                                                    const int* __restrict__ stop) {
+  {
+    const long long mb = blockIdx.y;
+    if (u != nullptr) u += mb * bt.s0;
+    b += mb * bt.s0;
+    if (out != nullptr) out += mb * (RESTRICT ? bt.s1 : bt.s0);
+    part += mb * bt.part_stride;
+    if (stop != nullptr) stop += mb * bt.stop_stride;
+  }
   __shared__ TU ring[4][RPL];
   __shared__ TU zs[RESTRICT ? RBY : 1][RESTRICT ? RBX : 1];
   __shared__ double red[RNT / WAVE];
@@ -211,8 +220,14 @@ constexpr int PNC = (PCL + PNT - 1) / PNT;         // coarse slots per thread
 template <typename T>
 __global__ __launch_bounds__(PNT) void k_prolong_tile(int fnx, int fny, int fnz, int periodic,
                                                       const T* __restrict__ e, T* __restrict__ fine, int kc,
-                                                      int gx_tiles, int gy_tiles, int nblk,
+                                                      int gx_tiles, int gy_tiles, int nblk, Batch bt,
                                                       const int* __restrict__ stop) {
+  {
+    const long long mb = blockIdx.y;
+    e += mb * bt.s1;
+    fine += mb * bt.s0;
+    if (stop != nullptr) stop += mb * bt.stop_stride;
+  }
   __shared__ T cr[3][PCL];
   if (stop != nullptr && *stop) return;
   const int tid = threadIdx.x;
@@ -349,23 +364,23 @@ size_t resid_blocks(int nx, int ny, int nz) { return (size_t)resid_grid(nx, ny, 
 
 template <typename TU, typename TR>
 void launch_residual(const LevelView<TU>& L, const TU* u, const TU* b, TR* r_out, double* part,
-                     const int* stop, hipStream_t st) {
+                     const int* stop, hipStream_t st, const Batch& bt) {
   const TileGrid g = resid_grid(L.nx, L.ny, L.nz);
-  hipLaunchKernelGGL((k_resid_tile<TU, TR, false>), dim3(g.nblk), dim3(RNT), 0, st, L, u, b, r_out, g.kc,
-                     g.gx, g.gy, g.nblk, part, stop);
+  hipLaunchKernelGGL((k_resid_tile<TU, TR, false>), dim3(g.nblk, bt.nb), dim3(RNT), 0, st, L, u, b, r_out,
+                     g.kc, g.gx, g.gy, g.nblk, part, bt, stop);
 }
 
 template <typename T>
 void launch_resid_restrict(const LevelView<T>& F, const T* u, const T* b, T* bc, double* part,
-                           const int* stop, hipStream_t st) {
+                           const int* stop, hipStream_t st, const Batch& bt) {
   const TileGrid g = resid_grid(F.nx, F.ny, F.nz);
-  hipLaunchKernelGGL((k_resid_tile<T, T, true>), dim3(g.nblk), dim3(RNT), 0, st, F, u, b, bc, g.kc, g.gx,
-                     g.gy, g.nblk, part, stop);
+  hipLaunchKernelGGL((k_resid_tile<T, T, true>), dim3(g.nblk, bt.nb), dim3(RNT), 0, st, F, u, b, bc, g.kc,
+                     g.gx, g.gy, g.nblk, part, bt, stop);
 }
 
 template <typename T>
 void launch_prolong_add(int fnx, int fny, int fnz, int periodic, const T* e, T* fine, const int* stop,
-                        hipStream_t st) {
+                        hipStream_t st, const Batch& bt) {
   TileGrid g;
   g.gx = (fnx + PBX - 1) / PBX;
   g.gy = (fny + PBY - 1) / PBY;
@@ -376,22 +391,23 @@ void launch_prolong_add(int fnx, int fny, int fnz, int periodic, const T* e, T* 
   g.kc += g.kc & 1;  // even: chunks start on a coarse plane
   g.gz = (fnz + g.kc - 1) / g.kc;
   g.nblk = g.gx * g.gy * g.gz;
-  hipLaunchKernelGGL(k_prolong_tile<T>, dim3(g.nblk), dim3(PNT), 0, st, fnx, fny, fnz, periodic, e, fine,
-                     g.kc, g.gx, g.gy, g.nblk, stop);
+  hipLaunchKernelGGL(k_prolong_tile<T>, dim3(g.nblk, bt.nb), dim3(PNT), 0, st, fnx, fny, fnz, periodic, e,
+                     fine, g.kc, g.gx, g.gy, g.nblk, bt, stop);
 }
 
 template void launch_residual<double, double>(const LevelView<double>&, const double*, const double*,
-                                              double*, double*, const int*, hipStream_t);
+                                              double*, double*, const int*, hipStream_t, const Batch&);
 template void launch_residual<double, float>(const LevelView<double>&, const double*, const double*,
-                                             float*, double*, const int*, hipStream_t);
+                                             float*, double*, const int*, hipStream_t, const Batch&);
 template void launch_residual<float, float>(const LevelView<float>&, const float*, const float*, float*,
-                                            double*, const int*, hipStream_t);
+                                            double*, const int*, hipStream_t, const Batch&);
 template void launch_resid_restrict<double>(const LevelView<double>&, const double*, const double*,
-                                            double*, double*, const int*, hipStream_t);
+                                            double*, double*, const int*, hipStream_t, const Batch&);
 template void launch_resid_restrict<float>(const LevelView<float>&, const float*, const float*, float*,
-                                           double*, const int*, hipStream_t);
+                                           double*, const int*, hipStream_t, const Batch&);
 template void launch_prolong_add<double>(int, int, int, int, const double*, double*, const int*,
-                                         hipStream_t);
-template void launch_prolong_add<float>(int, int, int, int, const float*, float*, const int*, hipStream_t);
+                                         hipStream_t, const Batch&);
+template void launch_prolong_add<float>(int, int, int, int, const float*, float*, const int*, hipStream_t,
+                                        const Batch&);
 
 }  // namespace rkl
