@@ -65,7 +65,8 @@ typedef struct {
 
 /* Solver options.  rkl_default_opts() fills the defaults noted here. */
 typedef struct {
-    int s;               /* stages per smoothing tau-step (default 2)                           */
+    int s;               /* stages per smoothing tau-step (default 2; 0: the tuned stage count  */
+                         /* of rkl_tune_set_s for the grid, else 2)                             */
     double tau_frac;     /* theta = tau / tau_max(s), in (0, 1] (default 0.9); tau_max from
                             eq. tau_max with |lambda_max| = 4 sum_d h_d^-2                        */
     int n_pre, n_post;   /* relaxations before / after the coarse correction (2, 1; Sec. 4.1)  */
@@ -203,6 +204,54 @@ rkl_status rkl_poisson_solve_batched(const rkl_grid *grids, int nbatch, const rk
  * bytes per launch.  Returns RKL_EINVAL (< 0) on bad arguments.
  */
 int rkl_tau_step_launches(const rkl_grid *grid, int s, int prec);
+
+/*
+ * Tile tuning of the fused tau-step (the smoother of Sec. 2.2.3 run as one
+ * HBM pass per tau-step).  A variant is a tile family and shape; `target` is
+ * the workgroup count the z-chunking aims for.  Variants compute identical
+ * values cell by cell; only the order of the float64 norm partials differs.
+ *   variant 0  built-in choice (in rkl_tune_set: erase the entry)
+ *           1  LDS ring, 64 x 8 tiles        2  LDS ring, 64 x 4 tiles
+ *           3  z-queue, 64 x 32 tiles        4  z-queue, 64 x 16 tiles
+ *              (z-queue: s = 2 or 3 only)
+ * Entries are keyed by (nx, ny, nz, bc, prec, s) of one multigrid LEVEL
+ * (prec RKL_FP64: float64 sweeps; RKL_MIXED: the float32 sweeps of the
+ * mixed path) and take effect at the next solve.  The table is per process.
+ */
+typedef struct {
+    int nx, ny, nz;      /* level shape                                      */
+    int bc;              /* rkl_bc                                           */
+    int prec;            /* rkl_precision                                    */
+    int s;               /* stages per tau-step                              */
+    int variant;         /* see above                                        */
+    int target;          /* workgroups aimed for (>= 1)                      */
+    double us;           /* rkl_autotune: mean launch time in microseconds   */
+} rkl_tune_entry;
+
+/* Install n entries (host array).  RKL_EINVAL for a malformed entry or a
+ * variant not built for that (s, prec); then nothing is installed. */
+rkl_status rkl_tune_set(const rkl_tune_entry *entries, int n);
+/* Drop every tile entry and every stage-count entry. */
+rkl_status rkl_tune_clear(void);
+/* The choice in effect for a level (variant 0 if no fused tau-step applies). */
+rkl_status rkl_tune_get(const rkl_grid *level, int s, int prec, rkl_tune_entry *out);
+/*
+ * Time every variant and target on one level shape: reps launches each on
+ * library-allocated scratch (freed before return), HIP events on hip_stream.
+ * Installs the fastest; writes up to cap results sorted by time (host array)
+ * and the number measured to *n_results.  Synchronises the stream.
+ */
+rkl_status rkl_autotune(const rkl_grid *level, int s, int prec, int reps, rkl_tune_entry *results,
+                        int cap, int *n_results, void *hip_stream);
+/* Stage count used when opts->s == 0 for this grid and precision (a timed
+ * choice; without an entry s = 2).  s = 0 erases the entry. */
+rkl_status rkl_tune_set_s(const rkl_grid *grid, int prec, int s);
+/* Multigrid level shapes of `grid` (coarsening by 2 while every n/2 is an
+ * even integer >= min_coarse, Sec. 2.2.2): returns the level count L (or a
+ * negative rkl_status) and writes up to cap (nx, ny, nz) triples to nxyz. */
+int rkl_level_shapes(const rkl_grid *grid, int min_coarse, int *nxyz, int cap);
+/* Name of a variant ("ring64x8", ...; "heuristic" for 0 or unknown). */
+const char *rkl_variant_name(int variant);
 
 /* Thread-local message describing the last failure (never NULL). */
 const char *rkl_last_error(void);

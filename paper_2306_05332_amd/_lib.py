@@ -49,9 +49,17 @@ class c_stats(ctypes.Structure):
                 ("history_cap", ctypes.c_int), ("history_len", ctypes.c_int), ("status", ctypes.c_int)]
 
 
+class c_tune(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int), ("bc", ctypes.c_int),
+                ("prec", ctypes.c_int), ("s", ctypes.c_int), ("variant", ctypes.c_int), ("target", ctypes.c_int),
+                ("us", ctypes.c_double)]
+
+
 EXPORTS = ("rkl_default_opts", "rkl_poisson_solve", "mg_vcycle", "rkl_smooth", "rkl_residual",
            "rkl_restrict", "rkl_prolong_add", "rkl_coarse_solve", "rkl_poisson_solve_batched",
-           "rkl_tau_step_launches", "rkl_last_error", "rkl_release_all")
+           "rkl_tau_step_launches", "rkl_tune_set", "rkl_tune_clear", "rkl_tune_get", "rkl_autotune",
+           "rkl_tune_set_s", "rkl_level_shapes", "rkl_variant_name", "rkl_last_error", "rkl_release_all")
+VARIANTS = {0: "heuristic", 1: "ring64x8", 2: "ring64x4", 3: "zq64x32", 4: "zq64x16"}
 
 _lib = None
 
@@ -83,12 +91,36 @@ def load_library(path: str = LIB_PATH):
         getattr(lib, name).restype = ctypes.c_int
     lib.rkl_tau_step_launches.argtypes = [pg, ctypes.c_int, ctypes.c_int]
     lib.rkl_tau_step_launches.restype = ctypes.c_int
+    pt = ctypes.POINTER(c_tune)
+    lib.rkl_tune_set.argtypes = [pt, ctypes.c_int]
+    lib.rkl_tune_clear.argtypes = []
+    lib.rkl_tune_get.argtypes = [pg, ctypes.c_int, ctypes.c_int, pt]
+    lib.rkl_autotune.argtypes = [pg, ctypes.c_int, ctypes.c_int, ctypes.c_int, pt, ctypes.c_int,
+                                 ctypes.POINTER(ctypes.c_int), P]
+    lib.rkl_tune_set_s.argtypes = [pg, ctypes.c_int, ctypes.c_int]
+    lib.rkl_level_shapes.argtypes = [pg, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_int]
+    for name in ("rkl_tune_set", "rkl_tune_clear", "rkl_tune_get", "rkl_autotune", "rkl_tune_set_s",
+                 "rkl_level_shapes"):
+        getattr(lib, name).restype = ctypes.c_int
+    lib.rkl_variant_name.argtypes = [ctypes.c_int]
+    lib.rkl_variant_name.restype = ctypes.c_char_p
     lib.rkl_last_error.argtypes = []
     lib.rkl_last_error.restype = ctypes.c_char_p
     lib.rkl_release_all.argtypes = []
     lib.rkl_release_all.restype = None
     _lib = lib
+    install_default_tuning()
     return lib
+
+
+def install_default_tuning():
+    """Install the stored tile table (``RKL_TUNING``: a path, or ``none``)."""
+    path = os.environ.get("RKL_TUNING", "")
+    if path.lower() == "none":
+        return 0
+    from . import autotune
+    path = path or autotune.DEFAULT_TABLE
+    return autotune.load(path) if os.path.exists(path) else 0
 
 
 def _check(status):
@@ -149,6 +181,10 @@ def _dev(t, name, dtype=torch.float64):
 
 def _stream(t):
     return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _current_stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
 def pack_faces(faces, device=None):
@@ -315,6 +351,71 @@ def kernel_info(shape, s, bc="periodic", prec="fp64"):
         name = f"k_stage<{tname}>"
     return {"kernel": name, "launches_per_tau": launches, "bytes_per_launch": words * word * cells,
             "words_per_cell_launch": words}
+
+
+# ---------------------------------------------------------------- tuning
+BC_NAMES = {v: k for k, v in BC.items()}
+PREC_NAMES = {v: k for k, v in PREC.items()}
+
+
+def _entry_dict(e):
+    return {"nx": e.nx, "ny": e.ny, "nz": e.nz, "bc": BC_NAMES[e.bc], "prec": PREC_NAMES[e.prec], "s": e.s,
+            "variant": VARIANTS.get(e.variant, str(e.variant)), "target": e.target, "us": e.us}
+
+
+def _entry_c(d):
+    inv = {v: k for k, v in VARIANTS.items()}
+    var = d["variant"]
+    var = inv[var] if isinstance(var, str) else int(var)
+    return c_tune(int(d["nx"]), int(d["ny"]), int(d["nz"]), BC[d["bc"]], PREC[d["prec"]], int(d["s"]), var,
+                  int(d.get("target", 0)), float(d.get("us", 0.0)))
+
+
+def tune_set(entries):
+    """Install tile choices (dicts as returned by autotune_level / tune_get)."""
+    lib = load_library()
+    arr = (c_tune * max(1, len(entries)))(*[_entry_c(d) for d in entries])
+    _check(lib.rkl_tune_set(arr, len(entries)))
+
+
+def tune_clear():
+    _check(load_library().rkl_tune_clear())
+
+
+def tune_get(shape, s, bc="periodic", prec="fp64"):
+    """The tile choice in effect for a level of shape (nz, ny, nx)."""
+    lib = load_library()
+    out = c_tune()
+    _check(lib.rkl_tune_get(ctypes.byref(_grid(shape, 1.0, bc)), int(s), PREC[prec], ctypes.byref(out)))
+    return _entry_dict(out)
+
+
+def autotune_level(shape, s, bc="periodic", prec="fp64", reps=20, h=1.0):
+    """Time every variant/target on one level (GPU); installs the fastest and
+    returns all measurements, fastest first."""
+    lib = load_library()
+    cap = 64
+    res = (c_tune * cap)()
+    n = ctypes.c_int(0)
+    _check(lib.rkl_autotune(ctypes.byref(_grid(shape, h, bc)), int(s), PREC[prec], int(reps), res, cap,
+                            ctypes.byref(n), _current_stream()))
+    return [_entry_dict(res[q]) for q in range(min(n.value, cap))]
+
+
+def tune_set_s(shape, s, bc="periodic", prec="fp64"):
+    """Stage count used for this grid when Options.s == 0 (0 erases)."""
+    lib = load_library()
+    _check(lib.rkl_tune_set_s(ctypes.byref(_grid(shape, 1.0, bc)), PREC[prec], int(s)))
+
+
+def level_shapes(shape, min_coarse=4, bc="periodic"):
+    """Multigrid level shapes (nz, ny, nx), finest first."""
+    lib = load_library()
+    buf = (ctypes.c_int * (3 * 64))()
+    L = lib.rkl_level_shapes(ctypes.byref(_grid(shape, 1.0, bc)), int(min_coarse), buf, 64)
+    if L < 0:
+        _check(L)
+    return [(buf[3 * q + 2], buf[3 * q + 1], buf[3 * q]) for q in range(min(L, 64))]
 
 
 def release_all():

@@ -25,12 +25,18 @@ from . import _lib
 
 
 def _solve_many(src, h, bc, faces, opts):
-    """Solve for every trailing 3-D block of ``src`` (float64 CUDA)."""
+    """Solve for every trailing 3-D block of ``src`` (float64 CUDA): one
+    batched call (one grid class) when there are several blocks and no
+    Dirichlet face data, else one solve per block."""
     shape = src.shape
-    flat = src.reshape((-1,) + tuple(shape[-3:]))
+    flat = src.reshape((-1,) + tuple(shape[-3:])).contiguous()
+    nb = flat.shape[0]
+    if nb > 1 and faces is None:
+        phis, _ = _lib.solve_batched([flat[q] for q in range(nb)], [h] * nb, bc, opts=opts)
+        return torch.stack(phis).reshape(shape)
     outs = []
-    for q in range(flat.shape[0]):
-        phi, st = _lib.solve(flat[q].contiguous(), h, bc, faces=faces, opts=opts)
+    for q in range(nb):
+        phi, _ = _lib.solve(flat[q], h, bc, faces=faces, opts=opts)
         outs.append(phi)
     return torch.stack(outs).reshape(shape)
 

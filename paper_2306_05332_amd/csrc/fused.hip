@@ -18,6 +18,10 @@
 // finest level with data, -c otherwise).  Optionally the kernel also returns
 // the float64 partial sums of (M u - b)^2 over its output cells (the residual
 // of the tau-step's input), so a convergence check costs no extra pass.
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "kernels.h"
 
 namespace rkl {
@@ -480,16 +484,13 @@ __global__ __launch_bounds__(NT) void k_tau_zq(LevelView<T> L, const T* __restri
 }
 
 // ---------------------------------------------------------------- launch
+// Variants (tile family and shape) and the workgroup target that sets the
+// z-chunk length.  Every variant computes the same cells with the same
+// arithmetic; they differ only in how a level is cut into workgroups.
 template <typename T, int S>
-struct FusedTile;
-// float64: 64 x 8 tiles for s <= 2 (39 KB LDS at s = 2), 64 x 4 for s = 3
-template <> struct FusedTile<double, 1> { static constexpr int BX = 64, BY = 8; };
-template <> struct FusedTile<double, 2> { static constexpr int BX = 64, BY = 8; };
-template <> struct FusedTile<double, 3> { static constexpr int BX = 64, BY = 4; };
-template <> struct FusedTile<float, 1> { static constexpr int BX = 64, BY = 8; };
-template <> struct FusedTile<float, 2> { static constexpr int BX = 64, BY = 8; };
-template <> struct FusedTile<float, 3> { static constexpr int BX = 64, BY = 8; };
-template <> struct FusedTile<float, 4> { static constexpr int BX = 64, BY = 4; };
+constexpr bool zq_instantiated() {
+  return S == 2 || S == 3;
+}
 
 template <typename T>
 constexpr int fused_max_s() {
@@ -501,17 +502,38 @@ bool fused_tau_supported(const LevelView<T>& L, int s) {
   return s >= 1 && s <= fused_max_s<T>() && L.nx >= 16 && L.ny >= 8 && L.nz >= 8;
 }
 
+template <typename T>
+bool fused_variant_ok(int variant, int s) {
+  if (s < 1 || s > fused_max_s<T>()) return false;
+  switch (variant) {
+    case FV_RING_64x8:
+    case FV_RING_64x4: return true;
+    case FV_ZQ_64x32:
+    case FV_ZQ_64x16: return s == 2 || s == 3;
+    default: return false;
+  }
+}
+
+static void variant_tile(int variant, int& bx, int& by) {
+  bx = 64;
+  switch (variant) {
+    case FV_RING_64x4: by = 4; break;
+    case FV_ZQ_64x32: by = 32; break;
+    case FV_ZQ_64x16: by = 16; break;
+    default: by = 8; break;
+  }
+}
+
 struct FusedGrid {
   int gx, gy, gz, zc, nblk;
 };
 
-template <int BX, int BY>
-FusedGrid fused_grid(int nx, int ny, int nz, int target = 1024, int zc_max = 32) {
+// z chunks: aim for `target` workgroups; a chunk spans 4 .. zc_max planes
+// (short chunks keep small levels from being one long serial march)
+static FusedGrid fused_grid(int bx, int by, int nx, int ny, int nz, int target, int zc_max = 32) {
   FusedGrid g;
-  g.gx = (nx + BX - 1) / BX;
-  g.gy = (ny + BY - 1) / BY;
-  // z chunks: aim for `target` workgroups; a chunk spans 4 .. zc_max planes
-  // (short chunks keep small levels from being one long serial march)
+  g.gx = (nx + bx - 1) / bx;
+  g.gy = (ny + by - 1) / by;
   const int xy = g.gx * g.gy;
   const int chunks = std::max(1, (target + xy - 1) / xy);
   g.zc = std::max(4, std::min(zc_max, (nz + chunks - 1) / chunks));
@@ -520,14 +542,61 @@ FusedGrid fused_grid(int nx, int ny, int nz, int target = 1024, int zc_max = 32)
   return g;
 }
 
-// Large float64 levels at s = 2 use the z-queue kernel with 64 x 32 tiles
-// and 512 threads (one workgroup per CU, 32-plane chunks); everything else the
-// LDS-ring kernel.
-constexpr int ZQ_BX = 64, ZQ_BY = 32, ZQ_NT = 512;
+size_t fused_tau_blocks_max(int nx, int ny, int nz) {
+  // smallest tile (64 x 4) and shortest chunk (4 planes) over all variants
+  return (size_t)((nx + 63) / 64) * ((ny + 3) / 4) * ((nz + 3) / 4);
+}
+
+// ---- tuning table
+namespace {
+struct TuneKey {
+  int nx, ny, nz, periodic, dbl, s;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(nx, ny, nz, periodic, dbl, s) < std::tie(o.nx, o.ny, o.nz, o.periodic, o.dbl, o.s);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, FusedChoice> g_tune;
+int g_tune_gen = 0;
+}  // namespace
+
+void tune_install(int nx, int ny, int nz, int periodic, int dbl, int s, FusedChoice c) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  const TuneKey k{nx, ny, nz, periodic ? 1 : 0, dbl ? 1 : 0, s};
+  if (c.variant == FV_HEUR) g_tune.erase(k);
+  else g_tune[k] = c;
+  ++g_tune_gen;
+}
+
+void tune_clear() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.clear();
+  ++g_tune_gen;
+}
+
+int tune_generation() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  return g_tune_gen;
+}
+
+// Built-in choice: large float64 levels at s = 2 take the z-queue kernel
+// with 64 x 32 tiles and 512 threads (about one workgroup per CU); the rest
+// the LDS-ring kernel with 64 x 8 tiles (64 x 4 where the ring is deepest).
+template <typename T>
+FusedChoice fused_heuristic(const LevelView<T>& L, int s) {
+  if (sizeof(T) == 8 && s == 2 && L.nx >= 128 && L.ny >= 128 && L.nz >= 64) return FusedChoice{FV_ZQ_64x32, 256};
+  const bool deep = (sizeof(T) == 8 && s == 3) || (sizeof(T) == 4 && s == 4);
+  return FusedChoice{deep ? FV_RING_64x4 : FV_RING_64x8, 1024};
+}
 
 template <typename T>
-bool use_zq(const LevelView<T>& L, int s) {
-  return sizeof(T) == 8 && s == 2 && L.nx >= 128 && L.ny >= 128 && L.nz >= 64;
+FusedChoice fused_choice(const LevelView<T>& L, int s) {
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(TuneKey{L.nx, L.ny, L.nz, L.periodic ? 1 : 0, sizeof(T) == 8 ? 1 : 0, s});
+    if (it != g_tune.end() && fused_variant_ok<T>(it->second.variant, s)) return it->second;
+  }
+  return fused_heuristic<T>(L, s);
 }
 
 template <typename T, int S>
@@ -542,57 +611,91 @@ FCoef<T, S> make_fcoef(const StageCoef* co) {
 }
 
 template <typename T, int S>
-void launch_fused_S(const LevelView<T>& L, const T* u, const T* b, T* out, const StageCoef* co,
+void launch_fused_S(const LevelView<T>& L, FusedChoice c, const T* u, const T* b, T* out, const StageCoef* co,
                     double* part, const int* stop, const Batch& bt, hipStream_t st) {
   const FCoef<T, S> fc = make_fcoef<T, S>(co);
-  if constexpr (sizeof(T) == 8 && S == 2) {
-    if (use_zq<T>(L, S)) {
-      const FusedGrid g = fused_grid<ZQ_BX, ZQ_BY>(L.nx, L.ny, L.nz, 256, 32);
-      hipLaunchKernelGGL((k_tau_zq<T, S, ZQ_BX, ZQ_BY, ZQ_NT, 1, 0>), dim3(g.nblk, bt.nb), dim3(ZQ_NT), 0, st, L,
-                         u, b, out, fc, g.zc, g.gx, g.gy, g.nblk, part, bt, stop);
+  int bx, by;
+  variant_tile(c.variant, bx, by);
+  const FusedGrid g = fused_grid(bx, by, L.nx, L.ny, L.nz, c.target);
+  if constexpr (zq_instantiated<T, S>()) {
+    if (c.variant == FV_ZQ_64x32) {
+      hipLaunchKernelGGL((k_tau_zq<T, S, 64, 32, 512, 1, 0>), dim3(g.nblk, bt.nb), dim3(512), 0, st, L, u, b, out,
+                         fc, g.zc, g.gx, g.gy, g.nblk, part, bt, stop);
+      return;
+    }
+    if (c.variant == FV_ZQ_64x16) {
+      hipLaunchKernelGGL((k_tau_zq<T, S, 64, 16, 256, 1, 0>), dim3(g.nblk, bt.nb), dim3(256), 0, st, L, u, b, out,
+                         fc, g.zc, g.gx, g.gy, g.nblk, part, bt, stop);
       return;
     }
   }
-  constexpr int BX = FusedTile<T, S>::BX, BY = FusedTile<T, S>::BY;
-  const FusedGrid g = fused_grid<BX, BY>(L.nx, L.ny, L.nz);
-  hipLaunchKernelGGL((k_fused_tau<T, S, BX, BY>), dim3(g.nblk, bt.nb), dim3(FNT), 0, st, L, u, b, out, fc,
-                     g.zc, g.gx, g.gy, g.nblk, part, bt, stop);
+  if (c.variant == FV_RING_64x4) {
+    hipLaunchKernelGGL((k_fused_tau<T, S, 64, 4>), dim3(g.nblk, bt.nb), dim3(FNT), 0, st, L, u, b, out, fc, g.zc,
+                       g.gx, g.gy, g.nblk, part, bt, stop);
+    return;
+  }
+  hipLaunchKernelGGL((k_fused_tau<T, S, 64, 8>), dim3(g.nblk, bt.nb), dim3(FNT), 0, st, L, u, b, out, fc, g.zc,
+                     g.gx, g.gy, g.nblk, part, bt, stop);
+}
+
+template <typename T>
+size_t fused_tau_blocks_as(const LevelView<T>& L, FusedChoice c) {
+  int bx, by;
+  variant_tile(c.variant, bx, by);
+  return (size_t)fused_grid(bx, by, L.nx, L.ny, L.nz, c.target).nblk;
 }
 
 template <typename T>
 size_t fused_tau_blocks(const LevelView<T>& L, int s) {
-  if (use_zq<T>(L, s)) return (size_t)fused_grid<ZQ_BX, ZQ_BY>(L.nx, L.ny, L.nz, 256, 32).nblk;
-  int BY = 8;
-  if (sizeof(T) == 8 && s == 3) BY = 4;
-  if (sizeof(T) == 4 && s == 4) BY = 4;
-  FusedGrid g = (BY == 8) ? fused_grid<64, 8>(L.nx, L.ny, L.nz) : fused_grid<64, 4>(L.nx, L.ny, L.nz);
-  return (size_t)g.nblk;
+  return fused_tau_blocks_as<T>(L, fused_choice<T>(L, s));
 }
 
 template <typename T>
-bool launch_fused_tau(const LevelView<T>& L, const T* u, const T* b, T* out, int s, const StageCoef* co,
-                      double* part, const int* stop, hipStream_t st, const Batch& bt) {
-  if (!fused_tau_supported<T>(L, s)) return false;
+bool launch_fused_tau_as(const LevelView<T>& L, FusedChoice c, const T* u, const T* b, T* out, int s,
+                         const StageCoef* co, double* part, const int* stop, hipStream_t st, const Batch& bt) {
+  if (!fused_tau_supported<T>(L, s) || !fused_variant_ok<T>(c.variant, s) || c.target < 1) return false;
   switch (s) {
-    case 1: launch_fused_S<T, 1>(L, u, b, out, co, part, stop, bt, st); return true;
-    case 2: launch_fused_S<T, 2>(L, u, b, out, co, part, stop, bt, st); return true;
-    case 3: launch_fused_S<T, 3>(L, u, b, out, co, part, stop, bt, st); return true;
+    case 1: launch_fused_S<T, 1>(L, c, u, b, out, co, part, stop, bt, st); return true;
+    case 2: launch_fused_S<T, 2>(L, c, u, b, out, co, part, stop, bt, st); return true;
+    case 3: launch_fused_S<T, 3>(L, c, u, b, out, co, part, stop, bt, st); return true;
     default:
       if constexpr (sizeof(T) == 4) {
-        launch_fused_S<T, 4>(L, u, b, out, co, part, stop, bt, st);
+        launch_fused_S<T, 4>(L, c, u, b, out, co, part, stop, bt, st);
         return true;
       }
       return false;
   }
 }
 
-template bool fused_tau_supported<double>(const LevelView<double>&, int);
-template bool fused_tau_supported<float>(const LevelView<float>&, int);
-template size_t fused_tau_blocks<double>(const LevelView<double>&, int);
-template size_t fused_tau_blocks<float>(const LevelView<float>&, int);
-template bool launch_fused_tau<double>(const LevelView<double>&, const double*, const double*, double*,
-                                       int, const StageCoef*, double*, const int*, hipStream_t, const Batch&);
-template bool launch_fused_tau<float>(const LevelView<float>&, const float*, const float*, float*, int,
-                                      const StageCoef*, double*, const int*, hipStream_t, const Batch&);
+template <typename T>
+bool launch_fused_tau(const LevelView<T>& L, const T* u, const T* b, T* out, int s, const StageCoef* co,
+                      double* part, const int* stop, hipStream_t st, const Batch& bt) {
+  if (!fused_tau_supported<T>(L, s)) return false;
+  return launch_fused_tau_as<T>(L, fused_choice<T>(L, s), u, b, out, s, co, part, stop, st, bt);
+}
+
+const char* fused_variant_name(int variant) {
+  switch (variant) {
+    case FV_RING_64x8: return "ring64x8";
+    case FV_RING_64x4: return "ring64x4";
+    case FV_ZQ_64x32: return "zq64x32";
+    case FV_ZQ_64x16: return "zq64x16";
+    default: return "heuristic";
+  }
+}
+
+#define RKL_FUSED_INST(T)                                                                                         \
+  template bool fused_tau_supported<T>(const LevelView<T>&, int);                                                 \
+  template bool fused_variant_ok<T>(int, int);                                                                    \
+  template FusedChoice fused_choice<T>(const LevelView<T>&, int);                                                 \
+  template size_t fused_tau_blocks<T>(const LevelView<T>&, int);                                                  \
+  template size_t fused_tau_blocks_as<T>(const LevelView<T>&, FusedChoice);                                       \
+  template bool launch_fused_tau<T>(const LevelView<T>&, const T*, const T*, T*, int, const StageCoef*, double*,  \
+                                    const int*, hipStream_t, const Batch&);                                       \
+  template bool launch_fused_tau_as<T>(const LevelView<T>&, FusedChoice, const T*, const T*, T*, int,             \
+                                       const StageCoef*, double*, const int*, hipStream_t, const Batch&);
+RKL_FUSED_INST(double)
+RKL_FUSED_INST(float)
+#undef RKL_FUSED_INST
 
 }  // namespace rkl

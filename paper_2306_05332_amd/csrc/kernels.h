@@ -90,6 +90,30 @@ bool launch_fused_tau(const LevelView<T>& L, const T* u, const T* b, T* out, int
                       const StageCoef* co, double* part, const int* stop, hipStream_t st,
                       const Batch& bt = single_batch());
 
+// Fused tau-step variants: tile family and shape, plus the workgroup count
+// the z-chunk length aims for.  A tuning table keyed by (level shape,
+// boundary, precision, s) overrides the built-in choice.
+enum : int { FV_HEUR = 0, FV_RING_64x8 = 1, FV_RING_64x4 = 2, FV_ZQ_64x32 = 3, FV_ZQ_64x16 = 4, FV_COUNT = 5 };
+struct FusedChoice {
+  int variant;
+  int target;
+};
+template <typename T>
+bool fused_variant_ok(int variant, int s);
+template <typename T>
+FusedChoice fused_choice(const LevelView<T>& L, int s);
+template <typename T>
+size_t fused_tau_blocks_as(const LevelView<T>& L, FusedChoice c);
+template <typename T>
+bool launch_fused_tau_as(const LevelView<T>& L, FusedChoice c, const T* u, const T* b, T* out, int s,
+                         const StageCoef* co, double* part, const int* stop, hipStream_t st,
+                         const Batch& bt = single_batch());
+size_t fused_tau_blocks_max(int nx, int ny, int nz);  // over every variant and target
+void tune_install(int nx, int ny, int nz, int periodic, int dbl, int s, FusedChoice c);  // FV_HEUR erases
+void tune_clear();
+int tune_generation();
+const char* fused_variant_name(int variant);
+
 // Coarse tail of the V-cycle in one workgroup (tail.hip).
 constexpr int TAIL_MAX_LEVELS = 4;
 constexpr int TAIL_MAX_S = 8;

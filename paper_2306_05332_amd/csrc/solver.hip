@@ -273,15 +273,7 @@ Plan& get_plan(const rkl_grid& g, int s, double theta, int min_coarse, int prec)
   // partial sums: residual kernels (pairs), fused tau-step (one per block), elementwise sums
   size_t cap = 2 * resid_blocks(g.nx, g.ny, g.nz);
   cap = std::max(cap, ew_block_count(P->lv[0].n));
-  {
-    const Lev& F = P->lv[0];
-    LevelView<double> vd{F.nx, F.ny, F.nz, 1.0, 1.0, 1.0, P->periodic ? 1 : 0, nullptr};
-    LevelView<float> vf{F.nx, F.ny, F.nz, 1.0f, 1.0f, 1.0f, P->periodic ? 1 : 0, nullptr};
-    for (int sq = 1; sq <= FUSED_MAX_S; ++sq) {
-      cap = std::max(cap, fused_tau_blocks<double>(vd, sq));
-      cap = std::max(cap, fused_tau_blocks<float>(vf, sq));
-    }
-  }
+  cap = std::max(cap, fused_tau_blocks_max(P->lv[0].nx, P->lv[0].ny, P->lv[0].nz));
   cap = std::max(cap, (size_t)1024);
   P->part = P->alloc<double>(cap);
   P->part_cap = cap;
@@ -666,7 +658,7 @@ rkl_opts resolve_opts(const rkl_opts* in) {
   rkl_opts o;
   rkl_default_opts(&o);
   if (in) o = *in;
-  if (o.s < 1 || o.s > 64) fail(RKL_EINVAL, "s must be in [1, 64]");
+  if (o.s < 0 || o.s > 64) fail(RKL_EINVAL, "s must be in [0, 64] (0: tuned or default)");
   if (!(o.tau_frac > 0.0 && o.tau_frac < 2.0)) fail(RKL_EINVAL, "tau_frac must be in (0, 2)");
   if (o.n_pre < 0 || o.n_post < 0 || o.n_pre + o.n_post < 1) fail(RKL_EINVAL, "need n_pre + n_post >= 1");
   if (o.min_coarse < 2) fail(RKL_EINVAL, "min_coarse must be >= 2");
@@ -887,6 +879,22 @@ rkl_status solve_mixed(Plan& P, const rkl_opts& o, const double* rho, const doub
 }
 
 
+// s = 0 in the options asks for the stage count recorded for the grid (a
+// timed choice made by the tuner), else the default s = 2.
+std::mutex g_s_mu;
+std::map<std::tuple<int, int, int, int, int>, int> g_auto_s;  // (nx, ny, nz, bc, prec) -> s
+
+int auto_s(const rkl_grid& g, int prec) {
+  std::lock_guard<std::mutex> lk(g_s_mu);
+  auto it = g_auto_s.find(std::make_tuple(g.nx, g.ny, g.nz, (int)g.bc, prec));
+  return it == g_auto_s.end() ? 2 : it->second;
+}
+
+rkl_opts with_s(rkl_opts o, const rkl_grid& g) {
+  if (o.s == 0) o.s = auto_s(g, o.prec);
+  return o;
+}
+
 // One full solve.  A single-level grid runs the float64 accelerated RKL
 // iteration whatever the precision asks: with no coarse grid there is no
 // float32 V-cycle to refine.
@@ -921,6 +929,7 @@ struct ClassKey {
 struct ClassPlan {
   Plan* base = nullptr;  // level descriptors, schedule tables and tail choice of one member
   int nb = 0;
+  int s = 2;             // stages per tau-step of this class
   int part_stride = 0;
   double *f0 = nullptr, *phi = nullptr, *res0sq = nullptr, *dsum = nullptr, *part = nullptr;
   double** tab_in = nullptr;
@@ -965,12 +974,7 @@ ClassPlan& get_class(const rkl_grid& g, const rkl_opts& o, int nb) {
   const int L = base.L();
   size_t ps = 2 * resid_blocks(F.nx, F.ny, F.nz);
   ps = std::max(ps, ew_block_count(F.n));
-  {
-    LevelView<double> vd{F.nx, F.ny, F.nz, 1.0, 1.0, 1.0, base.periodic ? 1 : 0, nullptr};
-    LevelView<float> vf{F.nx, F.ny, F.nz, 1.0f, 1.0f, 1.0f, base.periodic ? 1 : 0, nullptr};
-    ps = std::max(ps, fused_tau_blocks<double>(vd, o.s));
-    ps = std::max(ps, fused_tau_blocks<float>(vf, o.s));
-  }
+  ps = std::max(ps, fused_tau_blocks_max(F.nx, F.ny, F.nz));
   C->part_stride = (int)ps;
   C->f0 = C->alloc<double>((size_t)nb * F.n);
   C->phi = C->alloc<double>((size_t)nb * F.n);
@@ -994,6 +998,7 @@ ClassPlan& get_class(const rkl_grid& g, const rkl_opts& o, int nb) {
   };
   if (o.prec == RKL_MIXED) make(C->h32, 0.0f);
   else make(C->h64, 0.0);
+  C->s = o.s;
   ClassPlan& ref = *C;
   g_classes[key] = std::move(C);
   return ref;
@@ -1035,7 +1040,8 @@ void class_iteration(ClassPlan& C, Hier<T>& H, const rkl_opts& o, hipStream_t st
   check_launch();
 }
 
-void class_iterations(ClassPlan& C, const rkl_opts& o, int k, hipStream_t st) {
+void class_iterations(ClassPlan& C, rkl_opts o, int k, hipStream_t st) {
+  o.s = C.s;
   for (int q = 0; q < k; ++q) {
     if (o.prec == RKL_MIXED) class_iteration<float>(C, C.h32, o, st);
     else class_iteration<double>(C, C.h64, o, st);
@@ -1105,9 +1111,11 @@ struct LoopSig {
   std::vector<std::pair<ClassPlan*, int>> cls;  // classes and iterations captured
   double tol, coarse_tol;
   int max_cycles, n_pre, n_post, coarse_max_steps;
+  int tune_gen;  // kernel variants are chosen at capture time
   bool operator==(const LoopSig& o) const {
     return cls == o.cls && tol == o.tol && coarse_tol == o.coarse_tol && max_cycles == o.max_cycles &&
-           n_pre == o.n_pre && n_post == o.n_post && coarse_max_steps == o.coarse_max_steps;
+           n_pre == o.n_pre && n_post == o.n_post && coarse_max_steps == o.coarse_max_steps &&
+           tune_gen == o.tune_gen;
   }
 };
 
@@ -1124,7 +1132,7 @@ std::unique_ptr<GraphCache> g_graph;
 
 // Capture `iters` outer iterations of every class into one graph (cached).
 hipGraphExec_t batch_graph(std::vector<ClassPlan*>& cls, const rkl_opts& o, int iters) {
-  LoopSig sig{{}, o.tol, o.coarse_tol, o.max_cycles, o.n_pre, o.n_post, o.coarse_max_steps};
+  LoopSig sig{{}, o.tol, o.coarse_tol, o.max_cycles, o.n_pre, o.n_post, o.coarse_max_steps, tune_generation()};
   for (auto* c : cls) sig.cls.push_back({c, iters});
   if (g_graph && g_graph->sig == sig) return g_graph->exec;
   tail_prepare();
@@ -1165,18 +1173,20 @@ rkl_status solve_batched(const rkl_grid* grids, int nbatch, const rkl_opts& o, c
   std::vector<int> single;  // members solved one by one
   for (auto& kv : groups) {
     const rkl_grid& g = grids[kv.second[0]];
-    Plan& P = get_plan(g, o.s, o.tau_frac, o.min_coarse, o.prec);
-    const bool ok = o.prec == RKL_MIXED ? class_ok<float>(P, o) : class_ok<double>(P, o);
+    const rkl_opts og = with_s(o, g);
+    Plan& P = get_plan(g, og.s, og.tau_frac, og.min_coarse, og.prec);
+    const bool ok = og.prec == RKL_MIXED ? class_ok<float>(P, og) : class_ok<double>(P, og);
     if (!ok) {
       single.insert(single.end(), kv.second.begin(), kv.second.end());
       continue;
     }
-    cls.push_back(&get_class(g, o, (int)kv.second.size()));
+    cls.push_back(&get_class(g, og, (int)kv.second.size()));
     members.push_back(kv.second);
   }
   rkl_status worst = RKL_OK;
   for (int q : single) {
-    const rkl_status s = solve_one(grids[q], o, rho[q], nullptr, phi[q], stats ? &stats[q] : nullptr, st);
+    const rkl_status s =
+        solve_one(grids[q], with_s(o, grids[q]), rho[q], nullptr, phi[q], stats ? &stats[q] : nullptr, st);
     if (s != RKL_OK && worst == RKL_OK) worst = s;
   }
   if (cls.empty()) return worst;
@@ -1226,6 +1236,95 @@ rkl_status solve_batched(const rkl_grid* grids, int nbatch, const rkl_opts& o, c
   }
   HIPCHK(hipStreamSynchronize(st));
   return worst;
+}
+
+// ------------------------------------------------------------------ tuning
+// scratch device memory owned by one tuning call
+struct DevScratch {
+  std::vector<void*> p;
+  void* get(size_t bytes) {
+    void* q = nullptr;
+    if (hipMalloc(&q, std::max<size_t>(bytes, 8)) != hipSuccess) {
+      (void)hipGetLastError();
+      fail(RKL_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    p.push_back(q);
+    return q;
+  }
+  ~DevScratch() {
+    for (void* q : p) (void)hipFree(q);
+  }
+};
+
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  EventPair() {
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+  }
+  ~EventPair() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+
+// Time every fused tau-step variant and workgroup target on one level shape
+// (reps launches each, HIP events on the caller's stream) and install the
+// fastest in the tuning table.
+template <typename T>
+int autotune_level(const rkl_grid& g, int s, int prec, int reps, rkl_tune_entry* res, int cap, hipStream_t st) {
+  const Lev Lv = build_levels(g, INT_MAX, s, 0.9)[0];
+  const bool per = g.bc == RKL_BC_PERIODIC;
+  const LevelView<T> V = view<T>(Lv, per, nullptr);
+  if (!fused_tau_supported<T>(V, s))
+    fail(RKL_EINVAL, "no fused tau-step for this shape and s (needs nx >= 16, ny >= 8, nz >= 8, s <= " +
+                         std::to_string(sizeof(T) == 8 ? 3 : 4) + ")");
+  DevScratch mem;
+  T* u = (T*)mem.get(Lv.n * sizeof(T));
+  T* o = (T*)mem.get(Lv.n * sizeof(T));
+  T* b = (T*)mem.get(Lv.n * sizeof(T));
+  double* part = (double*)mem.get(fused_tau_blocks_max(Lv.nx, Lv.ny, Lv.nz) * sizeof(double));
+  launch_fill<T>(u, Lv.n, (T)1, nullptr, st);
+  launch_fill<T>(b, Lv.n, (T)0, nullptr, st);
+  check_launch();
+  EventPair ev;
+  std::vector<rkl_tune_entry> all;
+  const int targets[] = {128, 256, 512, 1024, 2048};
+  for (int v = 1; v < FV_COUNT; ++v) {
+    if (!fused_variant_ok<T>(v, s)) continue;
+    for (int tg : targets) {
+      const FusedChoice c{v, tg};
+      for (int w = 0; w < 2; ++w) {
+        launch_fused_tau_as<T>(V, c, u, b, o, s, Lv.smooth.data(), part, nullptr, st);
+        std::swap(u, o);
+      }
+      HIPCHK(hipEventRecord(ev.a, st));
+      for (int r = 0; r < reps; ++r) {
+        launch_fused_tau_as<T>(V, c, u, b, o, s, Lv.smooth.data(), part, nullptr, st);
+        std::swap(u, o);
+      }
+      HIPCHK(hipEventRecord(ev.b, st));
+      HIPCHK(hipEventSynchronize(ev.b));
+      check_launch();
+      float ms = 0.0f;
+      HIPCHK(hipEventElapsedTime(&ms, ev.a, ev.b));
+      rkl_tune_entry e;
+      e.nx = g.nx;
+      e.ny = g.ny;
+      e.nz = g.nz;
+      e.bc = g.bc;
+      e.prec = prec;
+      e.s = s;
+      e.variant = v;
+      e.target = tg;
+      e.us = 1000.0 * (double)ms / reps;
+      all.push_back(e);
+    }
+  }
+  std::sort(all.begin(), all.end(), [](const rkl_tune_entry& a, const rkl_tune_entry& b) { return a.us < b.us; });
+  tune_install(g.nx, g.ny, g.nz, per ? 1 : 0, sizeof(T) == 8 ? 1 : 0, s, FusedChoice{all[0].variant, all[0].target});
+  for (int q = 0; q < (int)all.size() && q < cap; ++q) res[q] = all[q];
+  return (int)all.size();
 }
 
 template <typename Fn>
@@ -1278,7 +1377,7 @@ rkl_status rkl_poisson_solve(const rkl_grid* grid, const rkl_opts* opts, const d
                              const double* bc_faces, double* phi, rkl_stats* stats, void* hip_stream) {
   return guarded([&]() -> rkl_status {
     validate_grid(grid, bc_faces);
-    const rkl_opts o = resolve_opts(opts);
+    const rkl_opts o = with_s(resolve_opts(opts), *grid);
     if (!rho || !phi) fail(RKL_EINVAL, "rho and phi must be non-NULL");
     if (stats) stats->history_len = 0;
     return solve_one(*grid, o, rho, bc_faces, phi, stats, (hipStream_t)hip_stream);
@@ -1291,6 +1390,7 @@ rkl_status mg_vcycle(const rkl_grid* grid, const rkl_opts* opts, const double* f
     validate_grid(grid, bc_faces);
     rkl_opts o = resolve_opts(opts);
     o.prec = RKL_FP64;
+    o = with_s(o, *grid);
     if (!f || !phi) fail(RKL_EINVAL, "f and phi must be non-NULL");
     Plan& P = get_plan(*grid, o.s, o.tau_frac, o.min_coarse, RKL_FP64);
     std::lock_guard<std::mutex> lk(P.mu);
@@ -1383,7 +1483,7 @@ rkl_status rkl_coarse_solve(const rkl_grid* grid, const rkl_opts* opts, const do
                             int* steps_out, void* hip_stream) {
   return guarded([&]() -> rkl_status {
     validate_grid(grid, nullptr);
-    const rkl_opts o = resolve_opts(opts);
+    const rkl_opts o = with_s(resolve_opts(opts), *grid);
     if (!b || !u) fail(RKL_EINVAL, "NULL array");
     Plan& P = get_plan(*grid, o.s, o.tau_frac, INT_MAX, RKL_FP64);
     std::lock_guard<std::mutex> lk(P.mu);
@@ -1442,5 +1542,101 @@ rkl_status rkl_poisson_solve_batched(const rkl_grid* grids, int nbatch, const rk
     return solve_batched(grids, nbatch, o, rho, phi, stats, (hipStream_t)hip_stream);
   });
 }
+
+rkl_status rkl_tune_set(const rkl_tune_entry* entries, int n) {
+  return guarded([&]() -> rkl_status {
+    if (n < 0 || (n > 0 && !entries)) fail(RKL_EINVAL, "entries must hold n >= 0 items");
+    for (int q = 0; q < n; ++q) {
+      const rkl_tune_entry& e = entries[q];
+      if (e.nx < 1 || e.ny < 1 || e.nz < 1 || (e.bc != RKL_BC_DIRICHLET && e.bc != RKL_BC_PERIODIC) ||
+          (e.prec != RKL_FP64 && e.prec != RKL_MIXED) || e.variant < 0 || e.variant >= FV_COUNT ||
+          (e.variant != FV_HEUR && e.target < 1))
+        fail(RKL_EINVAL, "malformed tuning entry " + std::to_string(q));
+      const bool ok = e.prec == RKL_FP64 ? fused_variant_ok<double>(e.variant, e.s) : fused_variant_ok<float>(e.variant, e.s);
+      if (e.variant != FV_HEUR && !ok) fail(RKL_EINVAL, "variant not available for this s and precision in entry " + std::to_string(q));
+    }
+    for (int q = 0; q < n; ++q) {
+      const rkl_tune_entry& e = entries[q];
+      tune_install(e.nx, e.ny, e.nz, e.bc == RKL_BC_PERIODIC, e.prec == RKL_FP64, e.s, FusedChoice{e.variant, e.target});
+    }
+    return RKL_OK;
+  });
+}
+
+rkl_status rkl_tune_clear(void) {
+  return guarded([&]() -> rkl_status {
+    tune_clear();
+    std::lock_guard<std::mutex> lk(g_s_mu);
+    g_auto_s.clear();
+    return RKL_OK;
+  });
+}
+
+rkl_status rkl_tune_get(const rkl_grid* level, int s, int prec, rkl_tune_entry* out) {
+  return guarded([&]() -> rkl_status {
+    validate_grid(level, nullptr);
+    if (!out) fail(RKL_EINVAL, "out must be non-NULL");
+    if (s < 1 || s > 64) fail(RKL_EINVAL, "s must be in [1, 64]");
+    const Lev Lv = build_levels(*level, INT_MAX, s, 0.9)[0];
+    const bool per = level->bc == RKL_BC_PERIODIC;
+    FusedChoice c{FV_HEUR, 0};
+    if (prec == RKL_FP64) {
+      const LevelView<double> V = view<double>(Lv, per, nullptr);
+      if (fused_tau_supported<double>(V, s)) c = fused_choice<double>(V, s);
+    } else if (prec == RKL_MIXED) {
+      const LevelView<float> V = view<float>(Lv, per, nullptr);
+      if (fused_tau_supported<float>(V, s)) c = fused_choice<float>(V, s);
+    } else {
+      fail(RKL_EINVAL, "unknown precision");
+    }
+    *out = rkl_tune_entry{level->nx, level->ny, level->nz, (int)level->bc, prec, s, c.variant, c.target, 0.0};
+    return RKL_OK;
+  });
+}
+
+rkl_status rkl_autotune(const rkl_grid* level, int s, int prec, int reps, rkl_tune_entry* results, int cap,
+                        int* n_results, void* hip_stream) {
+  return guarded([&]() -> rkl_status {
+    validate_grid(level, nullptr);
+    if (reps < 1 || reps > 100000) fail(RKL_EINVAL, "reps must be in [1, 100000]");
+    if (cap < 0 || (cap > 0 && !results)) fail(RKL_EINVAL, "results must hold cap >= 0 entries");
+    int n;
+    if (prec == RKL_FP64) n = autotune_level<double>(*level, s, prec, reps, results, cap, (hipStream_t)hip_stream);
+    else if (prec == RKL_MIXED) n = autotune_level<float>(*level, s, prec, reps, results, cap, (hipStream_t)hip_stream);
+    else fail(RKL_EINVAL, "unknown precision");
+    if (n_results) *n_results = n;
+    return RKL_OK;
+  });
+}
+
+rkl_status rkl_tune_set_s(const rkl_grid* grid, int prec, int s) {
+  return guarded([&]() -> rkl_status {
+    validate_grid(grid, nullptr);
+    if (prec != RKL_FP64 && prec != RKL_MIXED) fail(RKL_EINVAL, "unknown precision");
+    if (s < 0 || s > 64) fail(RKL_EINVAL, "s must be in [0, 64] (0 erases the entry)");
+    std::lock_guard<std::mutex> lk(g_s_mu);
+    const auto k = std::make_tuple(grid->nx, grid->ny, grid->nz, (int)grid->bc, prec);
+    if (s == 0) g_auto_s.erase(k);
+    else g_auto_s[k] = s;
+    return RKL_OK;
+  });
+}
+
+int rkl_level_shapes(const rkl_grid* grid, int min_coarse, int* nxyz, int cap) {
+  return guarded([&]() -> rkl_status {
+    validate_grid(grid, nullptr);
+    if (min_coarse < 2) fail(RKL_EINVAL, "min_coarse must be >= 2");
+    if (cap < 0 || (cap > 0 && !nxyz)) fail(RKL_EINVAL, "nxyz must hold 3 * cap ints");
+    const std::vector<Lev> lv = build_levels(*grid, min_coarse, 2, 0.9);
+    for (int l = 0; l < (int)lv.size() && l < cap; ++l) {
+      nxyz[3 * l] = lv[l].nx;
+      nxyz[3 * l + 1] = lv[l].ny;
+      nxyz[3 * l + 2] = lv[l].nz;
+    }
+    return (rkl_status)lv.size();
+  });
+}
+
+const char* rkl_variant_name(int variant) { return fused_variant_name(variant); }
 
 }  // extern "C"

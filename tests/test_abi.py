@@ -64,7 +64,7 @@ def test_invalid_grid_rejected_without_gpu(lib, bad):
     assert len(lib.rkl_last_error()) > 0
 
 
-@pytest.mark.parametrize("bad", [dict(s=0), dict(s=65), dict(tau_frac=0.0), dict(tau_frac=2.5),
+@pytest.mark.parametrize("bad", [dict(s=-1), dict(s=65), dict(tau_frac=0.0), dict(tau_frac=2.5),
                                  dict(n_pre=0, n_post=0), dict(min_coarse=1), dict(tol=-1.0),
                                  dict(max_cycles=-1), dict(prec=5)])
 def test_invalid_options_rejected_without_gpu(lib, bad):
@@ -103,3 +103,70 @@ def test_product_path_has_no_cpu_fallback():
             L.load_library("/nonexistent/librklpoisson.so")
         finally:
             L._lib = L._lib_saved
+
+
+# ---------------------------------------------------------------- tuning table (host only)
+def test_level_shapes_follow_the_coarsening_rule(lib):
+    """Level shapes from the library equal the oracle's hierarchy (coarsen by 2
+    while every n/2 is an even integer >= min_coarse)."""
+    from oracle import operators as oop
+    from paper_2306_05332_amd import _lib
+    for shape in [(256, 256, 256), (48, 48, 48), (20, 20, 20), (5, 6, 9), (32, 64, 128), (96, 40, 24)]:
+        nz, ny, nx = shape
+        want = [lv.shape for lv in oop.build_hierarchy(oop.Grid(nx, ny, nz, 1.0, 1.0, 1.0, "periodic"), 4)]
+        assert _lib.level_shapes(shape, 4) == want, shape
+    assert _lib.level_shapes((256, 256, 256))[-1] == (4, 4, 4)
+    assert len(_lib.level_shapes((256, 256, 256))) == 7
+
+
+def test_tuning_table_install_query_erase(lib):
+    from paper_2306_05332_amd import _lib
+    _lib.tune_clear()
+    try:
+        shape = (256, 256, 256)
+        assert _lib.tune_get(shape, 2, "periodic", "fp64")["variant"] == "zq64x32"
+        assert _lib.tune_get(shape, 3, "periodic", "fp64")["variant"] == "ring64x4"
+        assert _lib.tune_get((8, 8, 8), 2, "periodic", "fp64")["variant"] == "heuristic"  # no fused step
+        e = {"nx": 256, "ny": 256, "nz": 256, "bc": "periodic", "prec": "fp64", "s": 2, "variant": "ring64x4",
+             "target": 512}
+        _lib.tune_set([e])
+        got = _lib.tune_get(shape, 2, "periodic", "fp64")
+        assert (got["variant"], got["target"]) == ("ring64x4", 512)
+        # other keys untouched
+        assert _lib.tune_get(shape, 2, "dirichlet", "fp64")["variant"] == "zq64x32"
+        assert _lib.tune_get(shape, 2, "periodic", "mixed")["variant"] == "ring64x8"
+        _lib.tune_set([dict(e, variant=0)])
+        assert _lib.tune_get(shape, 2, "periodic", "fp64")["variant"] == "zq64x32"
+        # a variant not built for the (s, precision) pair is refused, and nothing is installed
+        with pytest.raises(_lib.RKLError):
+            _lib.tune_set([dict(e, variant="ring64x8"), dict(e, s=1, variant="zq64x16")])
+        assert _lib.tune_get(shape, 2, "periodic", "fp64")["variant"] == "zq64x32"
+        with pytest.raises(_lib.RKLError):
+            _lib.tune_set([dict(e, target=0)])
+    finally:
+        _lib.tune_clear()
+        _lib.install_default_tuning()
+
+
+def test_tuning_json_round_trip(lib, tmp_path):
+    from paper_2306_05332_amd import _lib, autotune
+    _lib.tune_clear()
+    try:
+        tiles = [{"nx": 128, "ny": 128, "nz": 128, "bc": "periodic", "prec": "mixed", "s": 2, "variant": "zq64x16",
+                  "target": 1024, "us": 12.5}]
+        path = str(tmp_path / "t.json")
+        autotune.save(path, tiles, [{"nx": 64, "ny": 64, "nz": 64, "bc": "periodic", "prec": "fp64", "s": 3}])
+        assert autotune.load(path) == 2
+        got = _lib.tune_get((128, 128, 128), 2, "periodic", "mixed")
+        assert (got["variant"], got["target"]) == ("zq64x16", 1024)
+    finally:
+        _lib.tune_clear()
+        _lib.install_default_tuning()
+
+
+def test_stored_table_is_valid(lib):
+    """The committed table installs (every variant it names is built)."""
+    from paper_2306_05332_amd import autotune
+    if not os.path.exists(autotune.DEFAULT_TABLE):
+        pytest.skip("no stored tuning table")
+    assert autotune.load() > 0

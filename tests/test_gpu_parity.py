@@ -218,7 +218,7 @@ def test_status_codes_on_gpu():
     phi, st = R.solve(torch.zeros_like(rho), p.h, "periodic")
     assert st.status == 0 and float(phi.abs().max()) == 0.0
     with pytest.raises(R.RKLError):
-        R.solve(rho, p.h, "periodic", opts=R.Options(s=0))
+        R.solve(rho, p.h, "periodic", opts=R.Options(s=-1))
 
 
 def test_warm_start_converges_in_fewer_cycles():
