@@ -8,19 +8,31 @@ with the default V-cycle (s = 2, theta = 0.9, N_pre = 2, N_post = 1, down to 4^3
 Printed on one JSON line:
   value        finest-level cell-updates/s: 256^3 x (RKL stages applied on the
                finest level per solve) / wall time per solve
-  roofline     the finest-level RKL sweep kernel, timed with HIP events on the
-               solver's stream: algorithmic bytes per launch / mean duration
-               against the 8 TB/s HBM peak
+  roofline     the finest-level fused tau-step kernel, timed with HIP events on
+               the solver's stream over 40 back-to-back launches: algorithmic
+               bytes per launch (u and b read, Y_s written: 3 words per cell) /
+               mean duration, against the 8 TB/s HBM peak; `traffic` is the
+               HBM bytes per launch that rocprofv3 counted (FETCH_SIZE +
+               WRITE_SIZE, each scaled by the same counter on a plain copy of
+               known size), read from the committed counter summary when it was
+               taken on the current kernel sources, else null
   cpu_baseline the CPU oracle (numpy, float64) on a bounded sample of the same
-               workload: two V-cycles from a cold start
-Also: time to 1e-10 for the float64 and mixed-precision paths, cycles, and the
-max-norm error of each against the exact discrete solution (FFT).
+               workload: V-cycles from a cold start
+Also: time to 1e-10 for the float64 and mixed-precision paths, cycles, the
+max-norm error of each against the exact discrete solution (FFT), the batched
+96-grid workload, and the adjoint (forward + backward) of 8 x 128^3 solves.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+       python bench.py --pmc-probe                 (program run under rocprofv3 --pmc)
+       python bench.py --summarize-pmc FETCH_DIR WRITE_DIR   (counter summary text)
+       python bench.py --summarize-trace TRACE_DIR          (kernel-trace summary text)
 """
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import math
 import os
@@ -36,6 +48,11 @@ METRIC = "cell-updates/s and time-to-1e-10 residual at 256^3 (mixed vs FP64); HB
 HBM_PEAK_GBS = 8000.0
 N = 256
 TOL = 1e-10
+SWEEP_STEPS = 40
+COPY_BYTES = 256 * 1024 * 1024  # plain copy used to scale the HBM counters
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "fused_tau_256_fp64_pmc.txt")
+KERNEL_SOURCES = ["paper_2306_05332_amd/csrc/fused.hip", "paper_2306_05332_amd/csrc/kernels.h",
+                  "paper_2306_05332_amd/csrc/rkl_device.h", "paper_2306_05332_amd/tuning/gfx950.json"]
 
 
 def parse():
@@ -44,7 +61,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--sweep-steps", type=int, default=40, help="tau-steps in the kernel timing region")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched and adjoint workloads")
+    ap.add_argument("--cpu-cycles", type=int, default=4, help="oracle V-cycles in the CPU baseline sample")
+    ap.add_argument("--pmc-probe", action="store_true")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--summarize-trace", metavar="TRACE_DIR")
     return ap.parse_args()
 
 
@@ -58,12 +79,189 @@ def cpu_model():
     return platform.processor() or "unknown"
 
 
+def sources_digest():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        p = os.path.join(ROOT, rel)
+        if os.path.exists(p):
+            h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def kernel_symbol(R, shape, s, prec="fp64"):
+    """Demangled name prefix of the finest-level tau-step kernel in effect."""
+    tname = "double" if prec == "fp64" else "float"
+    v = R.tune_get(shape, s, "periodic", prec)["variant"]
+    return {"ring64x8": f"rkl::k_fused_tau<{tname}, {s}, 64, 8>",
+            "ring64x4": f"rkl::k_fused_tau<{tname}, {s}, 64, 4>",
+            "zq64x32": f"rkl::k_tau_zq<{tname}, {s}, 64, 32, 512, 1, 0>",
+            "zq64x16": f"rkl::k_tau_zq<{tname}, {s}, 64, 16, 256, 1, 0>"}.get(v, f"rkl::k_stage<{tname}>")
+
+
+def sweep_inputs(torch, W, dev):
+    prob = W.gaussian_blobs(N, 16, seed=2)
+    rho = torch.from_numpy(prob.rho).to(dev)
+    f = (4.0 * math.pi) * (rho - rho.mean())
+    return prob, rho, f
+
+
+def read_traffic():
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel sources and tuning table."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None, "no counter summary"
+    kv = {}
+    for line in open(PMC_SUMMARY):
+        if ":" in line and not line.startswith(" "):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("sources_sha256_16") != sources_digest():
+        return None, "kernel sources changed since the counters were taken"
+    try:
+        return float(kv["traffic_bytes_per_launch"]), "counters on the current sources"
+    except (KeyError, ValueError):
+        return None, "malformed counter summary"
+
+
+# ---------------------------------------------------------------- profiler helpers
+def _rows(path):
+    with open(path, newline="") as fh:
+        return list(csv.DictReader(fh))
+
+
+def _find(d, suffix):
+    hits = sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True))
+    if not hits:
+        raise SystemExit(f"no *{suffix} under {d}")
+    return hits[0]
+
+
+def summarize_pmc(fetch_dir, write_dir):
+    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the copy and of the
+    finest-level tau-step kernel -> scaled HBM bytes per launch."""
+    import paper_2306_05332_amd as R
+    R.load_library()
+    ksym = kernel_symbol(R, (N, N, N), 2)
+
+    def per_kernel(d, counter):
+        rows = [r for r in _rows(_find(d, "counter_collection.csv")) if r.get("Counter_Name") == counter]
+        copy = [float(r["Counter_Value"]) for r in rows if "copy" in r["Kernel_Name"].lower()
+                and int(r.get("Grid_Size", r.get("Grid_Size_X", "0")) or 0) > 0]
+        kern = [float(r["Counter_Value"]) for r in rows if ksym in r["Kernel_Name"]]
+        return copy, kern
+
+    cf, kf = per_kernel(fetch_dir, "FETCH_SIZE")
+    cw, kw = per_kernel(write_dir, "WRITE_SIZE")
+    if not (cf and kf and cw and kw):
+        raise SystemExit("counter rows for the copy or the tau-step kernel are missing")
+    kib = COPY_BYTES / 1024.0
+    sf = kib / max(cf)          # known bytes / counted, read side
+    sw = kib / max(cw)          # write side
+    fetch = sorted(kf)[len(kf) // 2] * 1024.0 * sf
+    write = sorted(kw)[len(kw) // 2] * 1024.0 * sw
+    alg = 3 * 8 * N ** 3
+    lines = [
+        "HBM traffic of the finest-level fused tau-step kernel, 256^3 float64, s = 2",
+        "commands (run from /tmp with TMPDIR=/tmp; <repo> is the repository root):",
+        "  rocprofv3 --pmc FETCH_SIZE --output-format csv -d <FETCH_DIR> -o pmc -- python3 <repo>/bench.py --pmc-probe",
+        "  rocprofv3 --pmc WRITE_SIZE --output-format csv -d <WRITE_DIR> -o pmc -- python3 <repo>/bench.py --pmc-probe",
+        "  python3 <repo>/bench.py --summarize-pmc <FETCH_DIR> <WRITE_DIR>",
+        f"kernel: {ksym}",
+        f"copy_bytes: {COPY_BYTES}",
+        f"copy_fetch_kib_per_dispatch: {max(cf):.1f}",
+        f"copy_write_kib_per_dispatch: {max(cw):.1f}",
+        f"fetch_scale: {sf:.4f}",
+        f"write_scale: {sw:.4f}",
+        f"kernel_dispatches_counted: {len(kf)} fetch, {len(kw)} write",
+        f"kernel_fetch_kib_median: {sorted(kf)[len(kf) // 2]:.1f}",
+        f"kernel_write_kib_median: {sorted(kw)[len(kw) // 2]:.1f}",
+        f"fetch_bytes_per_launch: {fetch:.0f}",
+        f"write_bytes_per_launch: {write:.0f}",
+        f"traffic_bytes_per_launch: {fetch + write:.0f}",
+        f"algorithmic_bytes_per_launch: {alg}",
+        f"traffic_over_algorithmic: {(fetch + write) / alg:.3f}",
+        f"sources_sha256_16: {sources_digest()}",
+    ]
+    print("\n".join(lines))
+
+
+def summarize_trace(d):
+    """rocprofv3 --kernel-trace --stats of the bench command: the top kernels
+    by total time, and the finest-level tau-step kernel's mean duration over
+    its 256^3 launches and over the 40-launch sweep that bench.py times."""
+    import paper_2306_05332_amd as R
+    R.load_library()
+    ksym = kernel_symbol(R, (N, N, N), 2)
+    stats = _rows(_find(d, "kernel_stats.csv"))
+    trace = _rows(_find(d, "kernel_trace.csv"))
+    out = ["Kernel trace of the bench command",
+           "command (from /tmp, TMPDIR=/tmp):",
+           "  rocprofv3 --kernel-trace --stats --output-format csv -d <DIR> -o bench -- "
+           "python3 <repo>/bench.py --no-cpu-baseline --no-extras --steps 3 --warmup 1",
+           "  python3 <repo>/bench.py --summarize-trace <DIR>",
+           "", "top kernels (rocprofv3 kernel_stats):",
+           f"  {'calls':>6} {'total_ms':>9} {'avg_us':>8} {'pct':>6}  name"]
+    for r in stats[:14]:
+        name = r["Name"].split("(")[0].replace("void ", "")
+        out.append(f"  {int(r['Calls']):>6} {float(r['TotalDurationNs']) / 1e6:>9.3f} "
+                   f"{float(r['AverageNs']) / 1e3:>8.2f} {float(r['Percentage']):>6.2f}  {name}")
+    mine = [r for r in trace if ksym in r["Kernel_Name"]]
+    dur = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in mine]
+    # the timed sweep: the last SWEEP_STEPS dispatches of the longest run of
+    # consecutive dispatches of this kernel (2 untimed warm-up launches precede it)
+    order = sorted(trace, key=lambda r: int(r["Start_Timestamp"]))
+    best, cur = [], []
+    for r in order:
+        if ksym in r["Kernel_Name"]:
+            cur.append(r)
+            if len(cur) > len(best):
+                best = list(cur)
+        else:
+            cur = []
+    best = best[-SWEEP_STEPS:]
+    sw = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in best]
+    span = (int(best[-1]["End_Timestamp"]) - int(best[0]["Start_Timestamp"])) / 1e3 / len(best)
+    out += ["", f"finest-level tau-step kernel: {ksym}",
+            f"  all launches (levels 256^3 and 128^3 share this kernel): {len(dur)}, mean {sum(dur) / len(dur):.2f} us",
+            f"  timed sweep at 256^3: {len(sw)} launches, mean duration {sum(sw) / len(sw):.2f} us "
+            f"(min {min(sw):.2f}, max {max(sw):.2f}); first start to last end / launches {span:.2f} us",
+            f"  algorithmic bytes per launch: {3 * 8 * N ** 3} -> "
+            f"{3 * 8 * N ** 3 / (sum(sw) / len(sw)) / 1e3:.1f} GB/s over the sweep"]
+    print("\n".join(out))
+
+
+# ---------------------------------------------------------------- probes
+def pmc_probe():
+    """A plain copy of COPY_BYTES (three times) and ten finest-level tau-steps."""
+    import torch
+
+    import paper_2306_05332_amd as R
+    import workloads as W
+    dev = torch.device("cuda:0")
+    R.load_library()
+    a = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    _, rho, f = sweep_inputs(torch, W, dev)
+    u = torch.zeros_like(rho)
+    R.smooth(f, u, (1.0 / N,) * 3, "periodic", s=2, tau_frac=0.9, n_steps=10)
+    torch.cuda.synchronize()
+    print("pmc probe done", flush=True)
+
+
 def main():
     args = parse()
+    if args.summarize_pmc:
+        return summarize_pmc(*args.summarize_pmc)
+    if args.summarize_trace:
+        return summarize_trace(args.summarize_trace)
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (this solver's path is single-GPU); got --gpus {args.gpus}",
               file=sys.stderr)
         sys.exit(2)
+    if args.pmc_probe:
+        return pmc_probe()
     import numpy as np
     import torch
 
@@ -77,8 +275,7 @@ def main():
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
 
-    prob = W.gaussian_blobs(N, 16, seed=2)
-    rho = torch.from_numpy(prob.rho).to(dev)
+    prob, rho, f = sweep_inputs(torch, W, dev)
     h = prob.h
     opts = R.Options(tol=TOL)
     opts_mixed = R.Options(tol=TOL, prec="mixed")
@@ -111,22 +308,22 @@ def main():
     t_mixed = (time.perf_counter() - t0) / args.steps
     print(f"# mixed solve: {t_mixed * 1e3:.3f} ms, outer={stm.cycles}, rel_res={stm.rel_res:.3e}", flush=True)
 
-    # ---------------- dominant kernel: finest-level RKL sweep, HIP events on the solver's stream
-    f = (4.0 * math.pi) * (rho - rho.mean())
+    # ---------------- dominant kernel: finest-level tau-step, HIP events on the solver's stream
     u = torch.zeros_like(rho)
     R.smooth(f, u, h, "periodic", s=opts.s, tau_frac=opts.tau_frac, n_steps=2)  # warm
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
-    ksteps = args.sweep_steps
     ev0.record(stream)
-    R.smooth(f, u, h, "periodic", s=opts.s, tau_frac=opts.tau_frac, n_steps=ksteps)
+    R.smooth(f, u, h, "periodic", s=opts.s, tau_frac=opts.tau_frac, n_steps=SWEEP_STEPS)
     ev1.record(stream)
     torch.cuda.synchronize()
     sweep_ms = ev0.elapsed_time(ev1)
     info = R.kernel_info(tuple(rho.shape), opts.s, "periodic", "fp64")
-    launches = ksteps * info["launches_per_tau"]
+    launches = SWEEP_STEPS * info["launches_per_tau"]
     t_launch_s = sweep_ms * 1e-3 / launches
     achieved = info["bytes_per_launch"] / t_launch_s / 1e9
+    traffic, traffic_note = read_traffic()
+    print(f"# sweep: {t_launch_s * 1e6:.2f} us per launch, {achieved:.0f} GB/s", flush=True)
 
     # ---------------- accuracy vs the exact discrete solution (CPU FFT)
     from oracle import exact
@@ -138,7 +335,11 @@ def main():
     stages0 = st.cycles * (opts.n_pre + opts.n_post) * opts.s
     value = n3 * stages0 / t_fp64
 
-    # ---------------- CPU oracle baseline (bounded sample: 2 V-cycles)
+    extras = {}
+    if not args.no_extras:
+        extras = run_extras(R, W, torch, args)
+
+    # ---------------- CPU oracle baseline (bounded sample)
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import multigrid as omg
@@ -147,7 +348,7 @@ def main():
         fo = omg.prepare_source(prob.rho, g, omg.Options())
         lv = oop.build_hierarchy(g)
         uo = np.zeros(g.shape)
-        ncyc = 2
+        ncyc = args.cpu_cycles
         t0 = time.perf_counter()
         for _ in range(ncyc):
             uo = omg.vcycle(uo, fo, lv, omg.Options())
@@ -183,12 +384,65 @@ def main():
         "max_rel_err_vs_exact": {"fp64": err64, "mixed": errm},
         "vcycle_cell_updates_per_s": n3 * st.cycles / t_fp64,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": info["kernel"], "bytes_per_launch": info["bytes_per_launch"],
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_note": traffic_note,
+                     "kernel": kernel_symbol(R, (N, N, N), opts.s), "bytes_per_launch": info["bytes_per_launch"],
                      "mean_launch_us": t_launch_s * 1e6, "launches_timed": launches},
         "cpu_baseline": cpu,
     }
+    out.update(extras)
     print(json.dumps(out), flush=True)
+
+
+def run_extras(R, W, torch, args):
+    """The batched workload (96 periodic grids of 32^3..128^3, mixed, tol 1e-8)
+    and the adjoint workload (8 x 128^3, forward + backward, float64)."""
+    out = {}
+    probs = W.batch_blob_problems(seed=4)
+    rhos = [torch.from_numpy(p.rho).cuda() for p in probs]
+    hs = [p.h for p in probs]
+    cells = sum(p.rho.size for p in probs)
+    ob = R.Options(tol=1e-8, prec="mixed")
+    R.solve_batched(rhos, hs, "periodic", opts=ob)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 3
+    for _ in range(reps):
+        _, sts = R.solve_batched(rhos, hs, "periodic", opts=ob)
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for r, hh in zip(rhos, hs):
+        R.solve(r, hh, "periodic", opts=ob)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    cyc = [s.cycles for s in sts]
+    out["batched"] = {"grids": len(probs), "cells": cells, "prec": "mixed", "tol": 1e-8, "ms": tb * 1e3,
+                      "sequential_ms": ts * 1e3, "speedup_vs_sequential": ts / tb,
+                      "cycles_min_max": [min(cyc), max(cyc)],
+                      "vcycle_cell_updates_per_s": sum(p.rho.size * s.cycles for p, s in zip(probs, sts)) / tb}
+    print(f"# batched: {tb * 1e3:.2f} ms ({ts * 1e3:.1f} ms one by one)", flush=True)
+    del rhos
+
+    rhos, w, _ = W.adjoint_inputs(128, nbatch=8, ndirs=1, seed=5)
+    rho = torch.from_numpy(rhos).cuda().requires_grad_(True)
+    wt = torch.from_numpy(w).cuda()
+    h = (1.0 / 128,) * 3
+    oa = R.Options(tol=1e-10)
+    for rep in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        phi = R.poisson_solve(rho, h, "periodic", opts=oa)
+        loss = (wt * phi).sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        rho.grad = None
+    out["adjoint"] = {"grids": 8, "n": 128, "prec": "fp64", "tol": 1e-10, "forward_ms": (t1 - t0) * 1e3,
+                      "backward_ms": (t2 - t1) * 1e3}
+    print(f"# adjoint 8x128^3: forward {(t1 - t0) * 1e3:.2f} ms, backward {(t2 - t1) * 1e3:.2f} ms", flush=True)
+    return out
 
 
 if __name__ == "__main__":

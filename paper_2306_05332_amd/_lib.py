@@ -345,7 +345,9 @@ def kernel_info(shape, s, bc="periodic", prec="fp64"):
     tname = "double" if prec == "fp64" else "float"
     if launches == 1:
         words = 3.0
-        name = f"k_fused_tau<{tname}>"
+        v = tune_get(shape, s, bc, prec)
+        name = {"zq64x32": f"k_tau_zq<{tname}, {s}, 64, 32>", "zq64x16": f"k_tau_zq<{tname}, {s}, 64, 16>",
+                "ring64x4": f"k_fused_tau<{tname}, {s}, 64, 4>"}.get(v["variant"], f"k_fused_tau<{tname}, {s}, 64, 8>")
     else:
         words = (3.0 + 4.0 * (s - 1)) / s
         name = f"k_stage<{tname}>"
