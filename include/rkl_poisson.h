@@ -214,6 +214,10 @@ int rkl_tau_step_launches(const rkl_grid *grid, int s, int prec);
  *           1  LDS ring, 64 x 8 tiles        2  LDS ring, 64 x 4 tiles
  *           3  z-queue, 64 x 32 tiles        4  z-queue, 64 x 16 tiles
  *              (z-queue: s = 2 or 3 only)
+ *           5  strip, 4 wavefronts of 64 columns x 8 rows per workgroup
+ *           6  strip, 1 wavefront of 64 columns x 8 rows per workgroup
+ *           7  strip, 4 wavefronts of 64 columns x 4 rows per workgroup
+ *              (strip: s <= 2 in float64, s <= 3 in float32)
  * Entries are keyed by (nx, ny, nz, bc, prec, s) of one multigrid LEVEL
  * (prec RKL_FP64: float64 sweeps; RKL_MIXED: the float32 sweeps of the
  * mixed path) and take effect at the next solve.  The table is per process.

@@ -59,7 +59,8 @@ EXPORTS = ("rkl_default_opts", "rkl_poisson_solve", "mg_vcycle", "rkl_smooth", "
            "rkl_restrict", "rkl_prolong_add", "rkl_coarse_solve", "rkl_poisson_solve_batched",
            "rkl_tau_step_launches", "rkl_tune_set", "rkl_tune_clear", "rkl_tune_get", "rkl_autotune",
            "rkl_tune_set_s", "rkl_level_shapes", "rkl_variant_name", "rkl_last_error", "rkl_release_all")
-VARIANTS = {0: "heuristic", 1: "ring64x8", 2: "ring64x4", 3: "zq64x32", 4: "zq64x16"}
+VARIANTS = {0: "heuristic", 1: "ring64x8", 2: "ring64x4", 3: "zq64x32", 4: "zq64x16", 5: "strip8x4",
+            6: "strip8x1", 7: "strip4x4"}
 
 _lib = None
 

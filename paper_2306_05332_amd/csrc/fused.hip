@@ -28,10 +28,6 @@ namespace rkl {
 
 constexpr int FNT = 256;
 
-template <typename T, int S>
-struct FCoef {
-  T mu[S], nu[S], c[S];
-};
 
 __device__ __forceinline__ int slot3(int p) { return (p % 3 + 3) % 3; }
 
@@ -505,13 +501,30 @@ bool fused_tau_supported(const LevelView<T>& L, int s) {
 template <typename T>
 bool fused_variant_ok(int variant, int s) {
   if (s < 1 || s > fused_max_s<T>()) return false;
+  const bool dbl = sizeof(T) == 8;
   switch (variant) {
     case FV_RING_64x8:
     case FV_RING_64x4: return true;
     case FV_ZQ_64x32:
     case FV_ZQ_64x16: return s == 2 || s == 3;
+    case FV_STRIP_8x4:
+    case FV_STRIP_8x1:
+    case FV_STRIP_4x4: return dbl ? s <= 2 : s <= 3;
     default: return false;
   }
+}
+
+template <typename T, int S>
+constexpr bool strip_instantiated() {
+  return sizeof(T) == 8 ? S <= 2 : S <= 3;
+}
+
+static bool is_strip(int variant) {
+  return variant == FV_STRIP_8x4 || variant == FV_STRIP_8x1 || variant == FV_STRIP_4x4;
+}
+static void strip_shape(int variant, int& R, int& WY) {
+  R = variant == FV_STRIP_4x4 ? 4 : 8;
+  WY = variant == FV_STRIP_8x1 ? 1 : 4;
 }
 
 static void variant_tile(int variant, int& bx, int& by) {
@@ -543,8 +556,11 @@ static FusedGrid fused_grid(int bx, int by, int nx, int ny, int nz, int target, 
 }
 
 size_t fused_tau_blocks_max(int nx, int ny, int nz) {
-  // smallest tile (64 x 4) and shortest chunk (4 planes) over all variants
-  return (size_t)((nx + 63) / 64) * ((ny + 3) / 4) * ((nz + 3) / 4);
+  // shortest chunk (4 planes) with the smallest tile of each family: 64 x 4
+  // (ring), 56 output columns x 4 rows (strip, s <= 4)
+  const size_t ring = (size_t)((nx + 63) / 64) * ((ny + 3) / 4) * ((nz + 3) / 4);
+  const size_t strip = (size_t)((nx + 55) / 56) * ((ny + 3) / 4) * ((nz + 3) / 4);
+  return std::max(ring, strip);
 }
 
 // ---- tuning table
@@ -579,14 +595,19 @@ int tune_generation() {
   return g_tune_gen;
 }
 
-// Built-in choice: large float64 levels at s = 2 take the z-queue kernel
-// with 64 x 32 tiles and 512 threads (about one workgroup per CU); the rest
-// the LDS-ring kernel with 64 x 8 tiles (64 x 4 where the ring is deepest).
+// Built-in choice (what the tuner picked on gfx950 for most shapes): the
+// strip kernel, 8-row strips for large float64 levels and 4-row strips
+// otherwise; stage counts the strip kernel is not built for take the
+// z-queue kernel on large levels and the LDS-ring kernel on small ones.
 template <typename T>
 FusedChoice fused_heuristic(const LevelView<T>& L, int s) {
-  if (sizeof(T) == 8 && s == 2 && L.nx >= 128 && L.ny >= 128 && L.nz >= 64) return FusedChoice{FV_ZQ_64x32, 256};
-  const bool deep = (sizeof(T) == 8 && s == 3) || (sizeof(T) == 4 && s == 4);
-  return FusedChoice{deep ? FV_RING_64x4 : FV_RING_64x8, 1024};
+  if (fused_variant_ok<T>(FV_STRIP_4x4, s)) {
+    const bool big = (size_t)L.nx * L.ny * L.nz >= ((size_t)192 * 192 * 192);
+    if (sizeof(T) == 8 && L.periodic && big) return FusedChoice{FV_STRIP_8x4, 1024};
+    return FusedChoice{FV_STRIP_4x4, 1024};
+  }
+  if (fused_variant_ok<T>(FV_ZQ_64x32, s) && L.nx >= 128 && L.ny >= 128 && L.nz >= 64) return FusedChoice{FV_ZQ_64x32, 256};
+  return FusedChoice{FV_RING_64x4, 1024};
 }
 
 template <typename T>
@@ -614,6 +635,13 @@ template <typename T, int S>
 void launch_fused_S(const LevelView<T>& L, FusedChoice c, const T* u, const T* b, T* out, const StageCoef* co,
                     double* part, const int* stop, const Batch& bt, hipStream_t st) {
   const FCoef<T, S> fc = make_fcoef<T, S>(co);
+  if (is_strip(c.variant)) {
+    if constexpr (strip_instantiated<T, S>()) {
+      if (c.variant == FV_STRIP_8x4) return launch_strip<T, S, 8, 4>(L, c.target, u, b, out, fc, part, stop, bt, st);
+      if (c.variant == FV_STRIP_8x1) return launch_strip<T, S, 8, 1>(L, c.target, u, b, out, fc, part, stop, bt, st);
+      if (c.variant == FV_STRIP_4x4) return launch_strip<T, S, 4, 4>(L, c.target, u, b, out, fc, part, stop, bt, st);
+    }
+  }
   int bx, by;
   variant_tile(c.variant, bx, by);
   const FusedGrid g = fused_grid(bx, by, L.nx, L.ny, L.nz, c.target);
@@ -639,7 +667,12 @@ void launch_fused_S(const LevelView<T>& L, FusedChoice c, const T* u, const T* b
 }
 
 template <typename T>
-size_t fused_tau_blocks_as(const LevelView<T>& L, FusedChoice c) {
+size_t fused_tau_blocks_as(const LevelView<T>& L, FusedChoice c, int s) {
+  if (is_strip(c.variant)) {
+    int R, WY;
+    strip_shape(c.variant, R, WY);
+    return (size_t)strip_grid(s, R, WY, L.nx, L.ny, L.nz, c.target).nblk;
+  }
   int bx, by;
   variant_tile(c.variant, bx, by);
   return (size_t)fused_grid(bx, by, L.nx, L.ny, L.nz, c.target).nblk;
@@ -647,7 +680,7 @@ size_t fused_tau_blocks_as(const LevelView<T>& L, FusedChoice c) {
 
 template <typename T>
 size_t fused_tau_blocks(const LevelView<T>& L, int s) {
-  return fused_tau_blocks_as<T>(L, fused_choice<T>(L, s));
+  return fused_tau_blocks_as<T>(L, fused_choice<T>(L, s), s);
 }
 
 template <typename T>
@@ -680,6 +713,9 @@ const char* fused_variant_name(int variant) {
     case FV_RING_64x4: return "ring64x4";
     case FV_ZQ_64x32: return "zq64x32";
     case FV_ZQ_64x16: return "zq64x16";
+    case FV_STRIP_8x4: return "strip8x4";
+    case FV_STRIP_8x1: return "strip8x1";
+    case FV_STRIP_4x4: return "strip4x4";
     default: return "heuristic";
   }
 }
@@ -689,7 +725,7 @@ const char* fused_variant_name(int variant) {
   template bool fused_variant_ok<T>(int, int);                                                                    \
   template FusedChoice fused_choice<T>(const LevelView<T>&, int);                                                 \
   template size_t fused_tau_blocks<T>(const LevelView<T>&, int);                                                  \
-  template size_t fused_tau_blocks_as<T>(const LevelView<T>&, FusedChoice);                                       \
+  template size_t fused_tau_blocks_as<T>(const LevelView<T>&, FusedChoice, int);                                  \
   template bool launch_fused_tau<T>(const LevelView<T>&, const T*, const T*, T*, int, const StageCoef*, double*,  \
                                     const int*, hipStream_t, const Batch&);                                       \
   template bool launch_fused_tau_as<T>(const LevelView<T>&, FusedChoice, const T*, const T*, T*, int,             \

@@ -93,7 +93,17 @@ bool launch_fused_tau(const LevelView<T>& L, const T* u, const T* b, T* out, int
 // Fused tau-step variants: tile family and shape, plus the workgroup count
 // the z-chunk length aims for.  A tuning table keyed by (level shape,
 // boundary, precision, s) overrides the built-in choice.
-enum : int { FV_HEUR = 0, FV_RING_64x8 = 1, FV_RING_64x4 = 2, FV_ZQ_64x32 = 3, FV_ZQ_64x16 = 4, FV_COUNT = 5 };
+enum : int {
+  FV_HEUR = 0,
+  FV_RING_64x8 = 1,
+  FV_RING_64x4 = 2,
+  FV_ZQ_64x32 = 3,
+  FV_ZQ_64x16 = 4,
+  FV_STRIP_8x4 = 5,   // strip kernel: R = 8 rows per lane, 4 wavefronts per workgroup
+  FV_STRIP_8x1 = 6,   // R = 8, one wavefront per workgroup
+  FV_STRIP_4x4 = 7,   // R = 4, 4 wavefronts per workgroup
+  FV_COUNT = 8
+};
 struct FusedChoice {
   int variant;
   int target;
@@ -103,12 +113,22 @@ bool fused_variant_ok(int variant, int s);
 template <typename T>
 FusedChoice fused_choice(const LevelView<T>& L, int s);
 template <typename T>
-size_t fused_tau_blocks_as(const LevelView<T>& L, FusedChoice c);
+size_t fused_tau_blocks_as(const LevelView<T>& L, FusedChoice c, int s);
 template <typename T>
 bool launch_fused_tau_as(const LevelView<T>& L, FusedChoice c, const T* u, const T* b, T* out, int s,
                          const StageCoef* co, double* part, const int* stop, hipStream_t st,
                          const Batch& bt = single_batch());
 size_t fused_tau_blocks_max(int nx, int ny, int nz);  // over every variant and target
+
+// Strip form of the fused tau-step (strip.hip): one wavefront per 64-column x
+// strip of R = 8 or 4 rows, 4 or 1 wavefronts per workgroup stacked in y.
+struct StripGrid {
+  int ox, gx, gy, zc, gz, nblk;
+};
+StripGrid strip_grid(int s, int R, int WY, int nx, int ny, int nz, int target);
+template <typename T, int S, int R, int WY>
+void launch_strip(const LevelView<T>& L, int target, const T* u, const T* b, T* out, const FCoef<T, S>& fc,
+                  double* part, const int* stop, const Batch& bt, hipStream_t st);
 void tune_install(int nx, int ny, int nz, int periodic, int dbl, int s, FusedChoice c);  // FV_HEUR erases
 void tune_clear();
 int tune_generation();

@@ -28,6 +28,13 @@ struct Batch {
 };
 inline Batch single_batch() { return Batch{1, 0, 0, 0, 0}; }
 
+// Stage coefficients of one s-stage tau-step in the working precision:
+// Y_j = mu[j-1] Y_{j-1} + nu[j-1] Y_{j-2} + c[j-1] (M Y_{j-1} - b).
+template <typename T, int S>
+struct FCoef {
+  T mu[S], nu[S], c[S];
+};
+
 template <typename T>
 struct LevelView {
   int nx, ny, nz;

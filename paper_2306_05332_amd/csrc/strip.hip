@@ -1,0 +1,306 @@
+// Fused s-stage RKL tau-step (App. A eq. RKL_intermediate_source), strip
+// form: every wavefront works on its own and keeps its whole working set in
+// registers.
+//
+// A wavefront's 64 lanes hold 64 consecutive x columns; the middle 64 - 2S
+// are its output columns and S on each side are halo (stage j is valid on
+// lanes j .. 63 - j, so after S stages the output lanes are exact).  Each
+// lane owns a strip of R output rows in y plus S halo rows on either side,
+// and the wavefront marches up through a chunk of z planes.  The x
+// neighbours of a value come from the adjacent lanes by wavefront DPP shifts,
+// the y neighbours are the lane's own adjacent rows, and the z neighbours are
+// the lane's queue of the last three planes; so the inner loop has no LDS
+// traffic and no barrier.  Stage 1 of plane z runs in the iteration that
+// receives u(z + 1); stage j of plane z - j + 1 follows in the same
+// iteration.  The next planes of u and b are loaded at the top of an
+// iteration and consumed at its end.  u and b are read once (halo rows and
+// planes are read again by the neighbouring strip or chunk, mostly from
+// cache) and Y_S is written once: 3 words of HBM traffic per cell.
+//
+// Boundaries (Sec. 2.3): periodic boxes wrap rows, planes and columns
+// (a wavefront may hold several periods of a short axis); Dirichlet stencils
+// that leave the box take the ghost 2 g - c (finest level with face data) or
+// -c, built from the centre value of the operand being differentiated.
+// Optionally the kernel returns float64 partial sums of (M u - b)^2 over its
+// output cells (the residual of the tau-step's input).
+#include "kernels.h"
+
+namespace rkl {
+
+constexpr int DPP_WAVE_SHL1 = 0x130;  // dst[i] = src[i + 1]
+constexpr int DPP_WAVE_SHR1 = 0x138;  // dst[i] = src[i - 1]
+
+template <int CTRL>
+__device__ __forceinline__ float wshift(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, true));
+}
+
+template <int CTRL>
+__device__ __forceinline__ double wshift(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+
+template <typename T, int S, int R, int WY, bool PER, bool UZ>
+__global__ __launch_bounds__(64 * WY) void k_tau_strip(LevelView<T> L, const T* __restrict__ u,
+                                                       const T* __restrict__ b, T* __restrict__ out,
+                                                       FCoef<T, S> co, int zc, int gx_tiles, int gy_tiles,
+                                                       int nblk, double* __restrict__ part, Batch bt,
+                                                       const int* __restrict__ stop) {
+  {
+    const long long mb = blockIdx.y;
+    if (!UZ) u += mb * bt.s0;
+    b += mb * bt.s0;
+    out += mb * bt.s0;
+    if (part != nullptr) part += mb * bt.part_stride;
+    if (stop != nullptr) stop += mb * bt.stop_stride;
+  }
+  constexpr int NU = R + 2 * S;   // rows held per lane
+  constexpr int OX = 64 - 2 * S;  // output columns per wavefront
+  constexpr int NY = S > 1 ? S - 1 : 1;
+  __shared__ double red[WY];
+  if (stop != nullptr && *stop) return;
+
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nx = L.nx, ny = L.ny, nz = L.nz;
+  const long long sxy = (long long)nx * ny;
+  int bid = blockIdx.x;
+  if ((nblk & 7) == 0) bid = (bid & 7) * (nblk >> 3) + (bid >> 3);  // neighbouring tiles on one XCD
+  const int tx = bid % gx_tiles;
+  const int ty = (bid / gx_tiles) % gy_tiles;
+  const int tz = bid / (gx_tiles * gy_tiles);
+  const int gxu = tx * OX - S + lane;        // column of this lane (unwrapped)
+  const int y0 = (ty * WY + w) * R - S;      // row of strip index 0 (unwrapped, wave-uniform)
+  const int z0 = tz * zc, z1 = min(z0 + zc, nz);
+  const bool xin = gxu >= 0 && gxu < nx;
+  const int gx = PER ? ((gxu % nx) + nx) % nx : min(max(gxu, 0), nx - 1);
+  const unsigned xb = (unsigned)gx * (unsigned)sizeof(T);  // byte offset of this lane's column
+  const bool xown = lane >= S && lane < 64 - S && xin;
+  const bool xlo = !PER && gxu == 0, xhi = !PER && gxu == nx - 1;
+
+  long long yoff[NU];    // row offsets in elements (wrapped or clamped), wave-uniform
+  unsigned rin = 0;      // bit i: row i lies in the box
+#pragma unroll
+  for (int i = 0; i < NU; ++i) {
+    const int gyu = y0 + i;
+    const bool in = gyu >= 0 && gyu < ny;
+    const int gy = PER ? ((gyu % ny) + ny) % ny : min(max(gyu, 0), ny - 1);
+    yoff[i] = (long long)gy * nx;
+    if (in) rin |= 1u << i;
+  }
+  // plane p -> element offset of its (wrapped or clamped) plane; advanced by one
+  // plane per iteration without divisions
+  auto plane0 = [&](int p) -> long long {
+    const int q = PER ? ((p % nz) + nz) % nz : min(max(p, 0), nz - 1);
+    return (long long)q * sxy;
+  };
+  const long long nzs = (long long)nz * sxy;
+  auto next_plane = [&](long long off, int p_next) -> long long {
+    // off: offset of plane p_next - 1
+    if (PER) return off + sxy == nzs ? 0 : off + sxy;
+    return (p_next <= 0 || p_next >= nz) ? off : off + sxy;
+  };
+  auto row = [&](const T* __restrict__ a, long long poff, int i) -> T {
+    const char* base = (const char*)(a + poff + yoff[i]);
+    return *(const T*)(base + xb);
+  };
+  auto pin = [&](int p) { return PER || (p >= 0 && p < nz); };
+
+  // Dirichlet ghost of face f at face index fi for centre value c
+  auto ghost = [&](int f, long long fi, T c) -> T {
+    if (L.faces != nullptr) return (T)(2.0 * L.faces[face_off(f, nx, ny, nz) + fi]) - c;
+    return -c;
+  };
+  // 7-point M applied to the centre row i of plane p: X = centre plane,
+  // Zm / Zp = planes below and above
+  auto lap = [&](const T(&Zm)[NU], const T(&X)[NU], const T(&Zp)[NU], int i, int p) -> T {
+    const T c = X[i];
+    T xm = wshift<DPP_WAVE_SHR1>(c), xp = wshift<DPP_WAVE_SHL1>(c);
+    T ym = X[i - 1], yp = X[i + 1], zm = Zm[i], zp = Zp[i];
+    if (!PER) {
+      const int gyu = y0 + i;
+      const int gy = min(max(gyu, 0), ny - 1);
+      if (xlo) xm = ghost(0, (long long)p * ny + gy, c);
+      if (xhi) xp = ghost(1, (long long)p * ny + gy, c);
+      if (gyu == 0) ym = ghost(2, (long long)p * nx + gx, c);
+      if (gyu == ny - 1) yp = ghost(3, (long long)p * nx + gx, c);
+      if (p == 0) zm = ghost(4, (long long)gy * nx + gx, c);
+      if (p == nz - 1) zp = ghost(5, (long long)gy * nx + gx, c);
+    }
+    return ((xm + xp) - (T)2 * c) * L.ihx2 + ((ym + yp) - (T)2 * c) * L.ihy2 + ((zm + zp) - (T)2 * c) * L.ihz2;
+  };
+
+  T U0[NU], U1[NU], U2[NU], UN[NU];  // u at planes zl-1, zl, zl+1; zl+2 in flight
+  T Yq[NY][3][NU];                   // Y_j at planes zl-j-1, zl-j, zl-j+1 (after stage j of iteration zl)
+  T Bq[S][NU], BN[NU];               // b at planes zl, zl-1, ..; zl+1 in flight
+  const int zs = z0 - (S - 1), ze = z1 + S - 2;  // iterations: stage 1 of plane zl, stage j of zl - j + 1
+  long long ou = plane0(zs - 1);   // plane offset of the last u plane loaded
+  long long ob = plane0(zs);       // plane offset of the last b plane loaded
+  long long oo = plane0(zs - S + 1);  // plane offset of the stage-S output plane of iteration zs
+#pragma unroll
+  for (int i = 0; i < NU; ++i) {
+    for (int j = 0; j < NY; ++j) Yq[j][0][i] = Yq[j][1][i] = Yq[j][2][i] = (T)0;
+    for (int j = 0; j < S; ++j) Bq[j][i] = (T)0;
+  }
+  // rows outside a Dirichlet box and planes outside it read as 0
+#pragma unroll
+  for (int i = 0; i < NU; ++i) U0[i] = (UZ || !pin(zs - 1) || !(PER || ((rin >> i) & 1u))) ? (T)0 : row(u, ou, i);
+  ou = next_plane(ou, zs);
+#pragma unroll
+  for (int i = 0; i < NU; ++i) U1[i] = (UZ || !pin(zs) || !(PER || ((rin >> i) & 1u))) ? (T)0 : row(u, ou, i);
+  ou = next_plane(ou, zs + 1);
+#pragma unroll
+  for (int i = 0; i < NU; ++i) U2[i] = (UZ || !pin(zs + 1) || !(PER || ((rin >> i) & 1u))) ? (T)0 : row(u, ou, i);
+#pragma unroll
+  for (int i = 1; i < NU - 1; ++i) Bq[0][i] = (!pin(zs) || !(PER || ((rin >> i) & 1u))) ? (T)0 : row(b, ob, i);
+  double r2 = 0.0;
+  T YS[NU];  // Y_S of the iteration's output plane, stored after the queues advance
+
+  for (int zl = zs; zl <= ze; ++zl) {
+    // next planes: loads issued now, consumed at the end of the iteration
+    // (unconditional: the plane index is wrapped or clamped into the box)
+    ou = next_plane(ou, zl + 2);
+    ob = next_plane(ob, zl + 1);
+    if (!UZ) {
+#pragma unroll
+      for (int i = 0; i < NU; ++i) UN[i] = row(u, ou, i);
+    }
+#pragma unroll
+    for (int i = 1; i < NU - 1; ++i) BN[i] = row(b, ob, i);
+    // stage 1 at plane zl, rows 1 .. NU-2
+    {
+      const int p = zl;
+      const bool on = pin(p) && p >= z0 - (S - 1) && p <= z1 - 1 + (S - 1);
+      const bool pown = p >= z0 && p < z1;
+      if (on) {
+#pragma unroll
+        for (int i = 1; i < NU - 1; ++i) {
+          const T res = lap(U0, U1, U2, i, p) - Bq[0][i];
+          const T y = U1[i] + co.c[0] * res;
+          if (part != nullptr && pown && i >= S && i < S + R && xown && ((rin >> i) & 1u))
+            r2 += (double)res * (double)res;
+          if constexpr (S == 1) YS[i] = y;
+          else Yq[0][2][i] = y;
+        }
+      }
+    }
+    // stages 2 .. S at planes zl - j + 1, rows j .. NU-1-j
+#pragma unroll
+    for (int j = 2; j <= S; ++j) {
+      const int p = zl - j + 1;
+      const bool on = pin(p) && p >= z0 - (S - j) && p <= z1 - 1 + (S - j);
+      if (on) {
+#pragma unroll
+        for (int i = j; i < NU - j; ++i) {
+          const T(&Xm)[NU] = Yq[j - 2][0];
+          const T(&Xc)[NU] = Yq[j - 2][1];
+          const T(&Xp)[NU] = Yq[j - 2][2];
+          const T y2 = (j == 2) ? U0[i] : Yq[j >= 3 ? j - 3 : 0][0][i];
+          const T res = lap(Xm, Xc, Xp, i, p) - Bq[j - 1][i];
+          const T y = co.mu[j - 1] * Xc[i] + co.nu[j - 1] * y2 + co.c[j - 1] * res;
+          if (j == S) YS[i] = y;
+          else Yq[j - 1][2][i] = y;
+        }
+      }
+    }
+    // advance the queues; Dirichlet planes outside the box and rows outside it read as 0
+    const bool un_ok = pin(zl + 2), bn_ok = pin(zl + 1);
+#pragma unroll
+    for (int i = 0; i < NU; ++i) {
+      const bool rok = PER || ((rin >> i) & 1u);
+      U0[i] = U1[i];
+      U1[i] = U2[i];
+      U2[i] = (UZ || !un_ok || !rok) ? (T)0 : UN[i];
+#pragma unroll
+      for (int j = NY - 1; j >= 0; --j) {
+        Yq[j][0][i] = Yq[j][1][i];
+        Yq[j][1][i] = Yq[j][2][i];
+      }
+#pragma unroll
+      for (int j = S - 1; j > 0; --j) Bq[j][i] = Bq[j - 1][i];
+      Bq[0][i] = (!bn_ok || !rok) ? (T)0 : BN[i];
+    }
+    // stores after the wait for the loads above, so that the next
+    // iteration's wait does not also wait for these writes
+    __builtin_amdgcn_sched_barrier(0);
+    {
+      const int p = zl - S + 1;
+      if (p >= z0 && p < z1) {
+#pragma unroll
+        for (int i = S; i < S + R; ++i)
+          if (xown && ((rin >> i) & 1u)) *(T*)((char*)(out + oo + yoff[i]) + xb) = YS[i];
+      }
+    }
+    oo = next_plane(oo, zl - S + 2);
+  }
+  if (part != nullptr) {
+    const double t = wave_sum_dpp(r2);
+    if (lane == 0) red[w] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < WY; ++q) s += red[q];
+      part[blockIdx.x] = s;
+    }
+  }
+}
+
+StripGrid strip_grid(int s, int R, int WY, int nx, int ny, int nz, int target) {
+  StripGrid g;
+  g.ox = 64 - 2 * s;
+  g.gx = (nx + g.ox - 1) / g.ox;
+  g.gy = (ny + R * WY - 1) / (R * WY);
+  const int xy = g.gx * g.gy;
+  const int chunks = std::max(1, (target + xy - 1) / xy);
+  g.zc = std::max(4, std::min(64, (nz + chunks - 1) / chunks));
+  g.gz = (nz + g.zc - 1) / g.zc;
+  g.nblk = g.gx * g.gy * g.gz;
+  return g;
+}
+
+template <typename T, int S, int R, int WY>
+void launch_strip(const LevelView<T>& L, int target, const T* u, const T* b, T* out, const FCoef<T, S>& fc,
+                  double* part, const int* stop, const Batch& bt, hipStream_t st) {
+  const StripGrid g = strip_grid(S, R, WY, L.nx, L.ny, L.nz, target);
+  const dim3 grid(g.nblk, bt.nb), block(64 * WY);
+  if (L.periodic) {
+    if (u == nullptr)
+      hipLaunchKernelGGL((k_tau_strip<T, S, R, WY, true, true>), grid, block, 0, st, L, u, b, out, fc, g.zc, g.gx,
+                         g.gy, g.nblk, part, bt, stop);
+    else
+      hipLaunchKernelGGL((k_tau_strip<T, S, R, WY, true, false>), grid, block, 0, st, L, u, b, out, fc, g.zc, g.gx,
+                         g.gy, g.nblk, part, bt, stop);
+  } else {
+    if (u == nullptr)
+      hipLaunchKernelGGL((k_tau_strip<T, S, R, WY, false, true>), grid, block, 0, st, L, u, b, out, fc, g.zc, g.gx,
+                         g.gy, g.nblk, part, bt, stop);
+    else
+      hipLaunchKernelGGL((k_tau_strip<T, S, R, WY, false, false>), grid, block, 0, st, L, u, b, out, fc, g.zc,
+                         g.gx, g.gy, g.nblk, part, bt, stop);
+  }
+}
+
+#define RKL_STRIP_INST(T, S, R, WY)                                                                          \
+  template void launch_strip<T, S, R, WY>(const LevelView<T>&, int, const T*, const T*, T*, const FCoef<T, S>&, \
+                                          double*, const int*, const Batch&, hipStream_t);
+RKL_STRIP_INST(double, 1, 8, 4)
+RKL_STRIP_INST(double, 2, 8, 4)
+RKL_STRIP_INST(double, 1, 8, 1)
+RKL_STRIP_INST(double, 2, 8, 1)
+RKL_STRIP_INST(float, 1, 8, 4)
+RKL_STRIP_INST(float, 2, 8, 4)
+RKL_STRIP_INST(float, 3, 8, 4)
+RKL_STRIP_INST(float, 1, 8, 1)
+RKL_STRIP_INST(float, 2, 8, 1)
+RKL_STRIP_INST(float, 3, 8, 1)
+RKL_STRIP_INST(double, 1, 4, 4)
+RKL_STRIP_INST(double, 2, 4, 4)
+RKL_STRIP_INST(float, 1, 4, 4)
+RKL_STRIP_INST(float, 2, 4, 4)
+RKL_STRIP_INST(float, 3, 4, 4)
+#undef RKL_STRIP_INST
+
+}  // namespace rkl

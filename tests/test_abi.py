@@ -124,8 +124,9 @@ def test_tuning_table_install_query_erase(lib):
     _lib.tune_clear()
     try:
         shape = (256, 256, 256)
-        assert _lib.tune_get(shape, 2, "periodic", "fp64")["variant"] == "zq64x32"
-        assert _lib.tune_get(shape, 3, "periodic", "fp64")["variant"] == "ring64x4"
+        assert _lib.tune_get(shape, 2, "periodic", "fp64")["variant"] == "strip8x4"
+        assert _lib.tune_get(shape, 3, "periodic", "fp64")["variant"] == "zq64x32"
+        assert _lib.tune_get((16, 16, 16), 3, "periodic", "fp64")["variant"] == "ring64x4"
         assert _lib.tune_get((8, 8, 8), 2, "periodic", "fp64")["variant"] == "heuristic"  # no fused step
         e = {"nx": 256, "ny": 256, "nz": 256, "bc": "periodic", "prec": "fp64", "s": 2, "variant": "ring64x4",
              "target": 512}
@@ -133,14 +134,14 @@ def test_tuning_table_install_query_erase(lib):
         got = _lib.tune_get(shape, 2, "periodic", "fp64")
         assert (got["variant"], got["target"]) == ("ring64x4", 512)
         # other keys untouched
-        assert _lib.tune_get(shape, 2, "dirichlet", "fp64")["variant"] == "zq64x32"
-        assert _lib.tune_get(shape, 2, "periodic", "mixed")["variant"] == "ring64x8"
+        assert _lib.tune_get(shape, 2, "dirichlet", "fp64")["variant"] == "strip4x4"
+        assert _lib.tune_get(shape, 2, "periodic", "mixed")["variant"] == "strip4x4"
         _lib.tune_set([dict(e, variant=0)])
-        assert _lib.tune_get(shape, 2, "periodic", "fp64")["variant"] == "zq64x32"
+        assert _lib.tune_get(shape, 2, "periodic", "fp64")["variant"] == "strip8x4"
         # a variant not built for the (s, precision) pair is refused, and nothing is installed
         with pytest.raises(_lib.RKLError):
             _lib.tune_set([dict(e, variant="ring64x8"), dict(e, s=1, variant="zq64x16")])
-        assert _lib.tune_get(shape, 2, "periodic", "fp64")["variant"] == "zq64x32"
+        assert _lib.tune_get(shape, 2, "periodic", "fp64")["variant"] == "strip8x4"
         with pytest.raises(_lib.RKLError):
             _lib.tune_set([dict(e, target=0)])
     finally:

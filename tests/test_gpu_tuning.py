@@ -45,14 +45,20 @@ def _restore_table():
 # ragged in x, y and z for every tile shape; the last one spans several
 # z-queue tiles in x and y
 VSHAPES = [(20, 11, 130), (16, 16, 16), (40, 24, 64), (72, 130, 160)]
-VARIANTS = ["ring64x8", "ring64x4", "zq64x32", "zq64x16"]
+VARIANTS = ["ring64x8", "ring64x4", "zq64x32", "zq64x16", "strip8x4", "strip8x1", "strip4x4"]
+# stage counts each variant is built for: (float64, float32)
+SUPPORT = {"ring64x8": ((1, 2, 3), (1, 2, 3, 4)), "ring64x4": ((1, 2, 3), (1, 2, 3, 4)),
+           "zq64x32": ((2, 3), (2, 3)), "zq64x16": ((2, 3), (2, 3)),
+           "strip8x4": ((1, 2), (1, 2, 3)), "strip8x1": ((1, 2), (1, 2, 3)), "strip4x4": ((1, 2), (1, 2, 3))}
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("shape", VSHAPES)
 @pytest.mark.parametrize("bc", ["periodic", "dirichlet"])
-@pytest.mark.parametrize("s", [2, 3])
+@pytest.mark.parametrize("s", [1, 2, 3])
 def test_forced_variant_matches_oracle(variant, shape, bc, s):
+    if s not in SUPPORT[variant][0]:
+        pytest.skip(f"{variant} is not built for float64 s = {s}")
     R = _lib()
     nz, ny, nx = shape
     target = 128 if (nx + ny) % 2 else 2048
@@ -73,16 +79,27 @@ def test_forced_variant_matches_oracle(variant, shape, bc, s):
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
-def test_forced_variant_float32_solve(variant):
+@pytest.mark.parametrize("bc", ["periodic", "dirichlet"])
+@pytest.mark.parametrize("s", [2, 3])
+def test_forced_variant_float32_solve(variant, bc, s):
     """The float32 sweeps of the mixed path with each variant on every level
-    that runs a fused tau-step: the solve still reaches u*."""
+    that runs a fused tau-step: the solve still reaches u*, in the same number
+    of outer iterations as with the built-in choice (all variants compute the
+    same values)."""
+    if s not in SUPPORT[variant][1]:
+        pytest.skip(f"{variant} is not built for float32 s = {s}")
     R = _lib()
-    p = W.gaussian_blobs(64, 8, seed=9)
-    R.tune_set([{"nx": n, "ny": n, "nz": n, "bc": "periodic", "prec": "mixed", "s": 2, "variant": variant,
+    p = W.gaussian_blobs(64, 8, seed=9) if bc == "periodic" else W.uniform_sphere(64)
+    rho = cu(p.rho)
+    o = R.Options(tol=1e-10, prec="mixed", s=s)
+    R.tune_clear()
+    _, ref = R.solve(rho, p.h, bc, opts=o)
+    R.tune_set([{"nx": n, "ny": n, "nz": n, "bc": bc, "prec": "mixed", "s": s, "variant": variant,
                  "target": 512} for n in (64, 32, 16)])
-    phi, st = R.solve(cu(p.rho), p.h, "periodic", opts=R.Options(tol=1e-10, prec="mixed"))
-    assert st.status == 0
-    us = exact.exact_solution(4 * math.pi * p.rho, p.h, "periodic")
+    phi, st = R.solve(rho, p.h, bc, opts=o)
+    assert st.status == 0 and st.cycles == ref.cycles
+    np.testing.assert_allclose(st.history, ref.history, rtol=1e-4)
+    us = exact.exact_solution(4 * math.pi * p.rho, p.h, bc, None)
     assert relmax(phi.cpu().numpy(), us) < 1e-9
 
 
