@@ -95,7 +95,10 @@ def kernel_symbol(R, shape, s, prec="fp64"):
     return {"ring64x8": f"rkl::k_fused_tau<{tname}, {s}, 64, 8>",
             "ring64x4": f"rkl::k_fused_tau<{tname}, {s}, 64, 4>",
             "zq64x32": f"rkl::k_tau_zq<{tname}, {s}, 64, 32, 512, 1, 0>",
-            "zq64x16": f"rkl::k_tau_zq<{tname}, {s}, 64, 16, 256, 1, 0>"}.get(v, f"rkl::k_stage<{tname}>")
+            "zq64x16": f"rkl::k_tau_zq<{tname}, {s}, 64, 16, 256, 1, 0>",
+            "strip8x4": f"rkl::k_tau_strip<{tname}, {s}, 8, 4, true, false>",
+            "strip8x1": f"rkl::k_tau_strip<{tname}, {s}, 8, 1, true, false>",
+            "strip4x4": f"rkl::k_tau_strip<{tname}, {s}, 4, 4, true, false>"}.get(v, f"rkl::k_stage<{tname}>")
 
 
 def sweep_inputs(torch, W, dev):

@@ -348,7 +348,9 @@ def kernel_info(shape, s, bc="periodic", prec="fp64"):
         words = 3.0
         v = tune_get(shape, s, bc, prec)
         name = {"zq64x32": f"k_tau_zq<{tname}, {s}, 64, 32>", "zq64x16": f"k_tau_zq<{tname}, {s}, 64, 16>",
-                "ring64x4": f"k_fused_tau<{tname}, {s}, 64, 4>"}.get(v["variant"], f"k_fused_tau<{tname}, {s}, 64, 8>")
+                "ring64x4": f"k_fused_tau<{tname}, {s}, 64, 4>", "strip8x4": f"k_tau_strip<{tname}, {s}, 8, 4>",
+                "strip8x1": f"k_tau_strip<{tname}, {s}, 8, 1>", "strip4x4": f"k_tau_strip<{tname}, {s}, 4, 4>",
+                }.get(v["variant"], f"k_fused_tau<{tname}, {s}, 64, 8>")
     else:
         words = (3.0 + 4.0 * (s - 1)) / s
         name = f"k_stage<{tname}>"

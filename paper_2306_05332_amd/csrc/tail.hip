@@ -36,18 +36,63 @@ struct TailArgs {
 
 constexpr int TNT = 512;
 
+// Cell walk of one thread over a level: q = tid, tid + TNT, ... with its
+// (i, j, k) advanced by carries (one division per level and phase, not per cell).
+struct CellWalk {
+  int q, i, j, k, di, dj, dk, n, nx, ny;
+  __device__ CellWalk(int tid, int stride, int nx_, int ny_, int nz_) : nx(nx_), ny(ny_) {
+    n = nx_ * ny_ * nz_;
+    q = tid;
+    i = tid % nx;
+    j = (tid / nx) % ny;
+    k = tid / (nx * ny);
+    di = stride % nx;
+    dj = (stride / nx) % ny;
+    dk = stride / (nx * ny);
+  }
+  __device__ bool ok() const { return q < n; }
+  __device__ void next(int stride) {
+    q += stride;
+    i += di;
+    int cj = 0;
+    if (i >= nx) {
+      i -= nx;
+      cj = 1;
+    }
+    j += dj + cj;
+    int ck = 0;
+    if (j >= ny) {
+      j -= ny;
+      ck = 1;
+    }
+    k += dk + ck;
+  }
+};
+
+// 7-point M at cell q = (i, j, k) of a level held in LDS.  Every neighbour is
+// read unconditionally: a periodic neighbour wraps, a missing Dirichlet
+// neighbour reads the centre with sign -1 (the error-equation ghost -c), so
+// the six reads can be in flight together.
 template <typename T>
-__device__ __forceinline__ T tail_lap(const TailLevel<T>& V, const T* Y, int q, int per) {
+__device__ __forceinline__ T tail_lap(const TailLevel<T>& V, const T* Y, int q, int i, int j, int k, int per) {
   const int nx = V.nx, ny = V.ny, nz = V.nz;
-  const int i = q % nx, t = q / nx, j = t % ny, k = t / ny;
   const int sy = nx, sz = nx * ny;
+  const int qxm = i > 0 ? q - 1 : (per ? q + nx - 1 : q);
+  const int qxp = i < nx - 1 ? q + 1 : (per ? q - (nx - 1) : q);
+  const int qym = j > 0 ? q - sy : (per ? q + (ny - 1) * sy : q);
+  const int qyp = j < ny - 1 ? q + sy : (per ? q - (ny - 1) * sy : q);
+  const int qzm = k > 0 ? q - sz : (per ? q + (nz - 1) * sz : q);
+  const int qzp = k < nz - 1 ? q + sz : (per ? q - (nz - 1) * sz : q);
   const T c = Y[q];
-  const T xm = i > 0 ? Y[q - 1] : (per ? Y[q + nx - 1] : -c);
-  const T xp = i < nx - 1 ? Y[q + 1] : (per ? Y[q - (nx - 1)] : -c);
-  const T ym = j > 0 ? Y[q - sy] : (per ? Y[q + (ny - 1) * sy] : -c);
-  const T yp = j < ny - 1 ? Y[q + sy] : (per ? Y[q - (ny - 1) * sy] : -c);
-  const T zm = k > 0 ? Y[q - sz] : (per ? Y[q + (nz - 1) * sz] : -c);
-  const T zp = k < nz - 1 ? Y[q + sz] : (per ? Y[q - (nz - 1) * sz] : -c);
+  T xm = Y[qxm], xp = Y[qxp], ym = Y[qym], yp = Y[qyp], zm = Y[qzm], zp = Y[qzp];
+  if (!per) {
+    xm = i > 0 ? xm : -xm;
+    xp = i < nx - 1 ? xp : -xp;
+    ym = j > 0 ? ym : -ym;
+    yp = j < ny - 1 ? yp : -yp;
+    zm = k > 0 ? zm : -zm;
+    zp = k < nz - 1 ? zp : -zp;
+  }
   return ((xm + xp) - (T)2 * c) * V.ihx2 + ((ym + yp) - (T)2 * c) * V.ihy2 + ((zm + zp) - (T)2 * c) * V.ihz2;
 }
 
@@ -113,8 +158,9 @@ __global__ __launch_bounds__(TNT) void k_tail(TailArgs<T> A, const T* __restrict
       const T* yp = (j & 1) ? cur : alt;
       T* yw = (j & 1) ? alt : cur;
       const T mu = V.mu[j - 1], nu = V.nu[j - 1], c = V.c[j - 1];
-      for (int q = tid; q < n; q += TNT) {
-        const T r = tail_lap(V, yp, q, per) - B[q];
+      for (CellWalk w(tid, TNT, V.nx, V.ny, V.nz); w.ok(); w.next(TNT)) {
+        const int q = w.q;
+        const T r = tail_lap(V, yp, q, w.i, w.j, w.k, per) - B[q];
         yw[q] = (j == 1) ? yp[q] + c * r : mu * yp[q] + nu * yw[q] + c * r;
       }
       __syncthreads();
@@ -147,21 +193,28 @@ __global__ __launch_bounds__(TNT) void k_tail(TailArgs<T> A, const T* __restrict
     const T* B = bptr(l);
     T* BC = bptr(l + 1);
     const int cn = nof(l + 1);
-    for (int q = tid; q < cn; q += TNT) {
-      const int I = q % C.nx, t = q / C.nx, J = t % C.ny, K = t / C.ny;
+    for (CellWalk w(tid, TNT, C.nx, C.ny, C.nz); w.ok(); w.next(TNT)) {
+      const int I = w.i, J = w.j, K = w.k;
       T acc = (T)0;
+#pragma unroll
       for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
         for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
           for (int dx = 0; dx < 2; ++dx) {
             const int f = ((2 * K + dz) * F.ny + (2 * J + dy)) * F.nx + (2 * I + dx);
-            acc += B[f] - tail_lap(F, U, f, per);
+            acc += B[f] - tail_lap(F, U, f, 2 * I + dx, 2 * J + dy, 2 * K + dz, per);
           }
-      BC[q] = acc * (T)0.125;
+      BC[w.q] = acc * (T)0.125;
     }
     __syncthreads();
     if (per) remove_b_mean(l + 1);
   }
-  // coarsest level: accelerated RKL on wavefront 0 (one cell per lane slot)
+  // coarsest level: accelerated RKL on wavefront 0 (up to 4 cells per lane),
+  // neighbour offsets precomputed once; ghosts: periodic wrap or -c.  Only
+  // this wavefront touches the level's arrays, and the LDS operations of one
+  // wavefront complete in issue order, so wavefront-scope fences (compiler
+  // ordering) separate the stages.
   {
     const int l = nl - 1;
     const TailLevel<T>& V = A.lv[l];
@@ -170,21 +223,64 @@ __global__ __launch_bounds__(TNT) void k_tail(TailArgs<T> A, const T* __restrict
       T* B = bptr(l);
       T* cur = curp(l);
       T* alt = altp(l);
+      int nb[4][6];   // neighbour index (the cell itself for a Dirichlet ghost)
+      unsigned gh[4]; // bit d: neighbour d is a Dirichlet ghost (-c)
+      bool has[4];
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) {
+        const int q = tid + WAVE * cc;
+        has[cc] = q < n;
+        const int qq = has[cc] ? q : 0;
+        const int i = qq % V.nx, j = (qq / V.nx) % V.ny, k = qq / (V.nx * V.ny);
+        const int sy = V.nx, sz = V.nx * V.ny;
+        nb[cc][0] = i > 0 ? qq - 1 : (per ? qq + V.nx - 1 : qq);
+        nb[cc][1] = i < V.nx - 1 ? qq + 1 : (per ? qq - (V.nx - 1) : qq);
+        nb[cc][2] = j > 0 ? qq - sy : (per ? qq + (V.ny - 1) * sy : qq);
+        nb[cc][3] = j < V.ny - 1 ? qq + sy : (per ? qq - (V.ny - 1) * sy : qq);
+        nb[cc][4] = k > 0 ? qq - sz : (per ? qq + (V.nz - 1) * sz : qq);
+        nb[cc][5] = k < V.nz - 1 ? qq + sz : (per ? qq - (V.nz - 1) * sz : qq);
+        gh[cc] = 0u;
+        if (!per) {
+          if (i == 0) gh[cc] |= 1u;
+          if (i == V.nx - 1) gh[cc] |= 2u;
+          if (j == 0) gh[cc] |= 4u;
+          if (j == V.ny - 1) gh[cc] |= 8u;
+          if (k == 0) gh[cc] |= 16u;
+          if (k == V.nz - 1) gh[cc] |= 32u;
+        }
+      }
+      auto lapc = [&](const T* Y, int cc) -> T {
+        const int q = tid + WAVE * cc;
+        const T c = Y[q];
+        T v[6];
+#pragma unroll
+        for (int d = 0; d < 6; ++d) v[d] = Y[nb[cc][d]];
+#pragma unroll
+        for (int d = 0; d < 6; ++d) v[d] = ((gh[cc] >> d) & 1u) ? -v[d] : v[d];
+        return ((v[0] + v[1]) - (T)2 * c) * V.ihx2 + ((v[2] + v[3]) - (T)2 * c) * V.ihy2 +
+               ((v[4] + v[5]) - (T)2 * c) * V.ihz2;
+      };
+      T bl[4];
       double b2 = 0.0;
-      for (int q = tid; q < n; q += WAVE) {
-        cur[q] = (T)0;
-        b2 += (double)B[q] * (double)B[q];
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) {
+        const int q = tid + WAVE * cc;
+        bl[cc] = has[cc] ? B[q] : (T)0;
+        if (has[cc]) cur[q] = (T)0;
+        b2 += (double)bl[cc] * (double)bl[cc];
       }
       const double bnorm = sqrt(wave_sum_dpp(b2));
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       int step = 0;
       if (bnorm > 0.0) {
         while (true) {
           double r2 = 0.0;
-          for (int q = tid; q < n; q += WAVE) {
-            const T r = tail_lap(V, cur, q, per) - B[q];
-            r2 += (double)r * (double)r;
-          }
+#pragma unroll
+          for (int cc = 0; cc < 4; ++cc)
+            if (has[cc]) {
+              const T r = lapc(cur, cc) - bl[cc];
+              r2 += (double)r * (double)r;
+            }
           const double res = sqrt(wave_sum_dpp(r2));
           if (res <= A.ctol * bnorm || step >= A.cmax) break;
           const int qs = step < nsched ? step : nsched - 1;
@@ -199,18 +295,18 @@ __global__ __launch_bounds__(TNT) void k_tail(TailArgs<T> A, const T* __restrict
             for (int cc = 0; cc < 4; ++cc) {
               const int q = tid + WAVE * cc;
               outv[cc] = (T)0;
-              if (q < n) {
-                const T r = tail_lap(V, yp, q, per) - B[q];
+              if (has[cc]) {
+                const T r = lapc(yp, cc) - bl[cc];
                 outv[cc] = (j == 1) ? yp[q] + c * r : mu * yp[q] + nu * yw[q] + c * r;
               }
             }
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 #pragma unroll
             for (int cc = 0; cc < 4; ++cc) {
               const int q = tid + WAVE * cc;
-              if (q < n) yw[q] = outv[cc];
+              if (has[cc]) yw[q] = outv[cc];
             }
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
           }
           if (s & 1) {
             T* t = cur;
@@ -219,10 +315,14 @@ __global__ __launch_bounds__(TNT) void k_tail(TailArgs<T> A, const T* __restrict
           }
           if (per) {
             double sm = 0.0;
-            for (int q = tid; q < n; q += WAVE) sm += (double)cur[q];
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc)
+              if (has[cc]) sm += (double)cur[tid + WAVE * cc];
             const T m = (T)(wave_sum_dpp(sm) / (double)n);
-            for (int q = tid; q < n; q += WAVE) cur[q] -= m;
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc)
+              if (has[cc]) cur[tid + WAVE * cc] -= m;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
           }
           ++step;
         }
@@ -242,8 +342,8 @@ __global__ __launch_bounds__(TNT) void k_tail(TailArgs<T> A, const T* __restrict
     const T* E = curp(l + 1);
     T* U = curp(l);
     const int fn = nof(l);
-    for (int q = tid; q < fn; q += TNT) {
-      const int i = q % F.nx, t = q / F.nx, j = t % F.ny, k = t / F.ny;
+    for (CellWalk w(tid, TNT, F.nx, F.ny, F.nz); w.ok(); w.next(TNT)) {
+      const int q = w.q, i = w.i, j = w.j, k = w.k;
       const int I = i >> 1, J = j >> 1, K = k >> 1;
       const int sx = (i & 1) ? 1 : -1, sy = (j & 1) ? 1 : -1, sz = (k & 1) ? 1 : -1;
       T acc = (T)0;
@@ -253,9 +353,9 @@ __global__ __launch_bounds__(TNT) void k_tail(TailArgs<T> A, const T* __restrict
             int a = I + dx * sx, bb = J + dy * sy, cidx = K + dz * sz;
             T sg = (T)1;
             if (per) {
-              a = (a + C.nx) % C.nx;
-              bb = (bb + C.ny) % C.ny;
-              cidx = (cidx + C.nz) % C.nz;
+              a = a < 0 ? a + C.nx : (a >= C.nx ? a - C.nx : a);
+              bb = bb < 0 ? bb + C.ny : (bb >= C.ny ? bb - C.ny : bb);
+              cidx = cidx < 0 ? cidx + C.nz : (cidx >= C.nz ? cidx - C.nz : cidx);
             } else {
               if (a < 0) { a = 0; sg = -sg; }
               if (a >= C.nx) { a = C.nx - 1; sg = -sg; }
