@@ -12,7 +12,11 @@ Paper references (Mandal, Mukherjee & Mignone 2023):
 * coarsest solver: the accelerated RKL iteration (App. A.4);
 * convergence metric: L2 norm of the residual relative to the residual of
   Phi = 0 (Sec. 4.1, caption of the error figure);
-* RKL as the relaxation (Sec. 2.2.4; App. A.2 eq. RKL_intermediate_source).
+* RKL as the relaxation (Sec. 2.2.4; App. A.2 eq. RKL_intermediate_source);
+  the paper's own smoother, red-black Gauss-Seidel (Sec. 2.2.4), is the
+  alternative ``smoother="gsrb"`` (one relaxation = one red + black pass);
+* single-level relaxation to a maximum residual (App. B): accelerated RKL,
+  GS-RB and SOR with the App. B over-relaxation parameter.
 
 Readings of silent or garbled points (listed in the design notes):
 * the coarse-level signs of the listing are made consistent by writing every
@@ -33,6 +37,7 @@ import numpy as np
 from .operators import (DIRICHLET, PERIODIC, Grid, apply_M, build_hierarchy,
                         prolong, restrict)
 from .rkl import accelerated_schedule, tau_step
+from .smoothers import gsrb_sweep, sor_omega
 
 STATUS_OK = 0
 STATUS_ENOCONV = -3
@@ -54,6 +59,8 @@ class Options:
     four_pi_G: float = 4.0 * math.pi   # G = 1 (Sec. 4.1)
     coarse_tol: float | None = None    # None: 1e-13 (float64) / 1e-6 (float32)
     coarse_max_steps: int = 200
+    smoother: str = "rkl"       # "rkl": one s-stage tau-step; "gsrb": one red-black GS pass
+    omega: float = 1.0          # GS-RB over-relaxation inside the V-cycle (1 = plain GS-RB)
 
 
 @dataclass
@@ -106,6 +113,16 @@ def rkl_accelerated(u, b, level, theta, faces=None, tol=1e-13, max_steps=200,
         steps += 1
 
 
+def relax(u, b, level, opts, faces=None):
+    """One relaxation of M u = b on ``level``: an RKL tau-step (s stages,
+    tau = theta tau_max), or one red-black Gauss-Seidel pass (Sec. 2.2.4)."""
+    if opts.smoother == "rkl":
+        return tau_step(u, b, opts.s, opts.theta, level, faces)
+    if opts.smoother == "gsrb":
+        return gsrb_sweep(u, b, level.h, level.bc, faces, opts.omega)
+    raise ValueError(f"unknown smoother {opts.smoother!r}")
+
+
 def coarsest_solve(b, level, opts, stats=None):
     """Solve M_c u = b on the coarsest level from u = 0 (homogeneous ghosts)."""
     u = np.zeros_like(b)
@@ -135,10 +152,10 @@ def vcycle(u0, f, levels, opts, faces=None, stats=None):
     if L == 1:
         # single level: the relaxation is the whole cycle
         for _ in range(opts.n_pre + opts.n_post):
-            u[0] = tau_step(u[0], b[0], opts.s, opts.theta, levels[0], faces)
+            u[0] = relax(u[0], b[0], levels[0], opts, faces)
         return u[0]
     for _ in range(opts.n_pre):
-        u[0] = tau_step(u[0], b[0], opts.s, opts.theta, levels[0], faces)
+        u[0] = relax(u[0], b[0], levels[0], opts, faces)
     for l in range(1, L):
         lv = levels[l - 1]
         r = apply_M(u[l - 1], lv.h, bc, faces if l == 1 else None) - b[l - 1]
@@ -148,14 +165,14 @@ def vcycle(u0, f, levels, opts, faces=None, stats=None):
         u[l] = np.zeros_like(b[l])
         if l < L - 1:
             for _ in range(opts.n_pre):
-                u[l] = tau_step(u[l], b[l], opts.s, opts.theta, levels[l], None)
+                u[l] = relax(u[l], b[l], levels[l], opts, None)
         else:
             u[l] = coarsest_solve(b[l], levels[l], opts, stats)
     for l in range(L - 2, -1, -1):
         u[l] = u[l] + prolong(u[l + 1], bc)
         fl = faces if l == 0 else None
         for _ in range(opts.n_post):
-            u[l] = tau_step(u[l], b[l], opts.s, opts.theta, levels[l], fl)
+            u[l] = relax(u[l], b[l], levels[l], opts, fl)
     return u[0]
 
 
@@ -223,6 +240,49 @@ def solve(rho, grid: Grid, opts: Options = None, faces=None, phi0=None):
     if grid.bc == PERIODIC:
         u = u - u.mean()
     return u, stats
+
+
+def relax_solve(f, grid: Grid, method, faces=None, tol_max=1e-10, max_iters=100000,
+                s=0, theta=0.9, omega=None, check_every=1, phi0=None):
+    """Single-level relaxation of M u = f (no multigrid), App. B.
+
+    Iterates until the maximum residual max|M u - f| <= ``tol_max`` (tested
+    before every ``check_every`` iterations) or ``max_iters`` iterations:
+    * ``"rkl"``: RKL tau-steps; s = 0 walks the accelerated schedule of
+      App. A.4 (then its last entry repeated), s > 0 keeps s fixed;
+      tau = theta tau_max(s);
+    * ``"gsrb"``: red-black Gauss-Seidel passes (omega = 1);
+    * ``"sor"``: red-black SOR with omega from App. B (``sor_omega``) unless
+      ``omega`` is given.
+    Periodic grids have the mean of u removed after every iteration.
+    Returns (u, iterations, final max residual, history of tested residuals).
+    """
+    lv = build_hierarchy(grid, 1 << 30)[0]
+    fz = faces if grid.bc == DIRICHLET else None
+    u = np.zeros(grid.shape) if phi0 is None else np.array(phi0, dtype=np.float64)
+    if method == "sor" and omega is None:
+        omega = sor_omega(grid.shape, lv.h)
+    sched = accelerated_schedule(lv, theta) if (method == "rkl" and s == 0) else None
+    it = 0
+    hist = []
+    while True:
+        res = float(np.abs(apply_M(u, lv.h, grid.bc, fz) - f).max())
+        hist.append(res)
+        if res <= tol_max or it >= max_iters:
+            return u, it, res, hist
+        for _ in range(check_every):
+            if it >= max_iters:
+                break
+            if method == "rkl":
+                sk = sched[min(it, len(sched) - 1)] if sched is not None else s
+                u = tau_step(u, f, sk, theta, lv, fz)
+            elif method in ("gsrb", "sor"):
+                u = gsrb_sweep(u, f, lv.h, grid.bc, fz, 1.0 if method == "gsrb" else omega)
+            else:
+                raise ValueError(f"unknown method {method!r}")
+            if grid.bc == PERIODIC:
+                u = u - u.mean()
+            it += 1
 
 
 def rkl_smooth(phi, f, grid: Grid, s, theta, n_steps, faces=None):

@@ -284,3 +284,90 @@ def test_fourth_order_gradient_convergence():
         errs.append(np.abs(gx - want).max())
         assert np.abs(gy).max() < 1e-12 and np.abs(gz).max() < 1e-12
     assert abs(math.log2(errs[0] / errs[1]) - 4.0) < 0.1
+
+
+# ---------------------------------------------------------------- GS-RB smoother and App. B relaxation
+
+def test_gsrb_sweep_matches_bruteforce_loops():
+    """Red-black pass written cell by cell: red cells from the old values, then
+    black cells from the new red ones; Dirichlet ghosts 2 g - u_cell refreshed
+    before each half pass (lagged), omega-weighted update."""
+    rng = np.random.default_rng(21)
+    n = 4
+    h = (0.3, 0.2, 0.25)
+    u = rng.standard_normal((n, n, n))
+    b = rng.standard_normal((n, n, n))
+    faces = tuple(rng.standard_normal(s) for s in ((n, n),) * 6)
+    om = 1.3
+    want = u.copy()
+    ih = [1 / hh ** 2 for hh in h]
+    D = 2 * sum(ih)
+    for colour in (0, 1):
+        old = want.copy()
+        for k in range(n):
+            for j in range(n):
+                for i in range(n):
+                    if (i + j + k) % 2 != colour:
+                        continue
+                    c = old[k, j, i]
+                    xm = old[k, j, i - 1] if i > 0 else 2 * faces[0][k, j] - c
+                    xp = old[k, j, i + 1] if i < n - 1 else 2 * faces[1][k, j] - c
+                    ym = old[k, j - 1, i] if j > 0 else 2 * faces[2][k, i] - c
+                    yp = old[k, j + 1, i] if j < n - 1 else 2 * faces[3][k, i] - c
+                    zm = old[k - 1, j, i] if k > 0 else 2 * faces[4][j, i] - c
+                    zp = old[k + 1, j, i] if k < n - 1 else 2 * faces[5][j, i] - c
+                    new = ((xm + xp) * ih[0] + (ym + yp) * ih[1] + (zm + zp) * ih[2] - b[k, j, i]) / D
+                    want[k, j, i] = (1 - om) * c + om * new
+    got = sm.gsrb_sweep(u, b, h, "dirichlet", faces, om)
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-13)
+
+
+def test_gsrb_asymptotic_rate_is_jacobi_radius_squared():
+    """Red-black ordering is consistent, so on a periodic box (no ghosts) the
+    Gauss-Seidel rate is rho_J^2.  The Jacobi eigenvalue of the Fourier mode
+    with wave numbers 2 pi m / n is the mean of the three cosines; the largest
+    below 1 belongs to the smoothest mode along one axis: (2 + cos(2 pi / n)) / 3."""
+    n = 16
+    g = op.Grid(n, n, n, 1 / n, 1 / n, 1 / n, "periodic")
+    rng = np.random.default_rng(3)
+    f = rng.standard_normal(g.shape)
+    f -= f.mean()
+    _, it, res, hist = mg.relax_solve(f, g, "gsrb", tol_max=1e-300, max_iters=120)
+    assert hist[-1] > 1e-9 * hist[0]   # still far above rounding
+    ratio = hist[-1] / hist[-2]
+    assert abs(ratio - ((2 + math.cos(2 * math.pi / n)) / 3) ** 2) < 2e-3
+
+
+def test_gsrb_vcycle_reduces_residual_about_tenfold():
+    """Sec. 4.1: with the GS-RB smoother (N_pre = 2, N_post = 1) and the RKL
+    coarsest solver the residual falls by about an order of magnitude per
+    cycle; the solve reaches the exact discrete solution."""
+    p = W.accuracy_problem(32)
+    g = op.Grid(32, 32, 32, *p.h, "dirichlet")
+    phi, st = mg.solve(p.rho, g, mg.Options(tol=1e-10, smoother="gsrb"), faces=p.faces)
+    assert st.status == 0
+    h = st.history
+    rates = [h[i] / h[i + 1] for i in range(1, len(h) - 1)]
+    geo = math.exp(sum(math.log(r) for r in rates) / len(rates))
+    assert 5.0 < geo < 20.0
+    us = exact.exact_solution(4 * math.pi * p.rho, p.h, "dirichlet", p.faces)
+    assert np.abs(phi - us).max() < 1e-9 * np.abs(us).max()
+
+
+def test_relax_solve_app_b_ordering():
+    """App. B: to the same maximum residual the accelerated RKL iteration needs
+    far fewer iterations than SOR, and SOR fewer than GS-RB; each stops below
+    the tolerance, and SOR at omega = 1 is GS-RB."""
+    n = 16
+    p = W.accuracy_problem(n)
+    g = op.Grid(n, n, n, *p.h, "dirichlet")
+    f = mg.prepare_source(p.rho, g, mg.Options())
+    out = {}
+    for m in ("rkl", "gsrb", "sor"):
+        u, it, res, hist = mg.relax_solve(f, g, m, faces=p.faces, tol_max=1e-10)
+        assert res <= 1e-10
+        out[m] = it
+    assert out["rkl"] < out["sor"] < out["gsrb"]
+    a = mg.relax_solve(f, g, "sor", faces=p.faces, tol_max=1e-300, max_iters=7, omega=1.0)[0]
+    b = mg.relax_solve(f, g, "gsrb", faces=p.faces, tol_max=1e-300, max_iters=7)[0]
+    np.testing.assert_array_equal(a, b)
