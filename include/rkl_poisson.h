@@ -63,6 +63,12 @@ typedef struct {
     int bc;            /* rkl_bc */
 } rkl_grid;
 
+/* V-cycle relaxation.  RKL_SMOOTH_RKL: one s-stage RKL tau-step per
+ * relaxation (App. A eq. RKL_intermediate_source).  RKL_SMOOTH_GSRB: one
+ * red-black Gauss-Seidel pass per relaxation, the paper's own smoother
+ * (Sec. 2.2.4); the coarsest level is always solved by accelerated RKL. */
+typedef enum { RKL_SMOOTH_RKL = 0, RKL_SMOOTH_GSRB = 1 } rkl_smoother;
+
 /* Solver options.  rkl_default_opts() fills the defaults noted here. */
 typedef struct {
     int s;               /* stages per smoothing tau-step (default 2; 0: the tuned stage count  */
@@ -78,6 +84,8 @@ typedef struct {
     double coarse_tol;   /* coarsest solve: stop at ||M u - b|| <= coarse_tol ||b||; 0 picks
                             1e-13 (float64) or 1e-6 (float32)                                   */
     int coarse_max_steps;/* coarsest solve: cap on tau-steps (default 200)                      */
+    int smoother;        /* rkl_smoother: relaxation of the V-cycle above the coarsest level    */
+                         /* (default RKL_SMOOTH_RKL)                                            */
 } rkl_opts;
 
 /* Solve statistics.  `history` (host, optional) receives the relative
@@ -256,6 +264,43 @@ rkl_status rkl_tune_set_s(const rkl_grid *grid, int prec, int s);
 int rkl_level_shapes(const rkl_grid *grid, int min_coarse, int *nxyz, int cap);
 /* Name of a variant ("ring64x8", ...; "heuristic" for 0 or unknown). */
 const char *rkl_variant_name(int variant);
+
+/*
+ * n_iter red-black Gauss-Seidel iterations (omega = 1) or SOR iterations
+ * (omega in (0, 2)) on M phi = f at one level (Sec. 2.2.4; App. B): red cells
+ * ((i + j + k) even) from the old values, then black cells from the new red
+ * values, each u += (omega / D)(M u - f), D = 2 sum h^-2; Dirichlet ghosts
+ * (2 g - u, or -u with bc_faces NULL) are taken from the current values.
+ * f, phi: device float64[n]; phi is updated in place.
+ */
+rkl_status rkl_gsrb_smooth(const rkl_grid *grid, double omega, int n_iter, const double *f,
+                           const double *bc_faces, double *phi, void *hip_stream);
+
+/*
+ * Single-level relaxation of M phi = f to a maximum residual (App. B: the
+ * comparison of RKL, Gauss-Seidel and SOR without multigrid).
+ */
+typedef enum { RKL_RELAX_RKL = 0, RKL_RELAX_GSRB = 1, RKL_RELAX_SOR = 2 } rkl_relax_method;
+typedef struct {
+    int method;          /* rkl_relax_method                                                  */
+    int s;               /* RKL: 0 = accelerated schedule of App. A.4, > 0 = fixed stage count */
+    double tau_frac;     /* RKL: theta = tau / tau_max (default 0.9)                          */
+    double omega;        /* SOR: over-relaxation; 0 = App. B optimum 2/(1 + sqrt(1 - rho_J^2)),
+                            rho_J = sum cos(pi/n_d) h_d^-2 / sum h_d^-2 (default 0)           */
+    double tol_max;      /* stop when max |M phi - f| <= tol_max (default 1e-10)              */
+    int max_iters;       /* cap on iterations: tau-steps or GS / SOR passes (default 100000)  */
+    int check_every;     /* iterations between residual tests (default 1)                     */
+} rkl_relax_opts;
+void rkl_default_relax_opts(rkl_relax_opts *o);
+/*
+ * phi: device float64[n], initial guess in, result out; periodic grids have
+ * the mean of phi removed after every iteration (f must be mean-free).
+ * stats (optional): cycles = iterations, res0 = first tested residual,
+ * rel_res = last tested max |M phi - f| (absolute), history = tested residuals,
+ * status = RKL_OK, RKL_ENOCONV (max_iters) or RKL_ENONFINITE.
+ */
+rkl_status rkl_relax_solve(const rkl_grid *grid, const rkl_relax_opts *opts, const double *f,
+                           const double *bc_faces, double *phi, rkl_stats *stats, void *hip_stream);
 
 /* Thread-local message describing the last failure (never NULL). */
 const char *rkl_last_error(void);

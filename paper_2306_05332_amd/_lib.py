@@ -40,7 +40,13 @@ class c_opts(ctypes.Structure):
     _fields_ = [("s", ctypes.c_int), ("tau_frac", ctypes.c_double), ("n_pre", ctypes.c_int),
                 ("n_post", ctypes.c_int), ("min_coarse", ctypes.c_int), ("tol", ctypes.c_double),
                 ("max_cycles", ctypes.c_int), ("prec", ctypes.c_int), ("four_pi_G", ctypes.c_double),
-                ("coarse_tol", ctypes.c_double), ("coarse_max_steps", ctypes.c_int)]
+                ("coarse_tol", ctypes.c_double), ("coarse_max_steps", ctypes.c_int), ("smoother", ctypes.c_int)]
+
+
+class c_relax(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int), ("s", ctypes.c_int), ("tau_frac", ctypes.c_double),
+                ("omega", ctypes.c_double), ("tol_max", ctypes.c_double), ("max_iters", ctypes.c_int),
+                ("check_every", ctypes.c_int)]
 
 
 class c_stats(ctypes.Structure):
@@ -58,7 +64,10 @@ class c_tune(ctypes.Structure):
 EXPORTS = ("rkl_default_opts", "rkl_poisson_solve", "mg_vcycle", "rkl_smooth", "rkl_residual",
            "rkl_restrict", "rkl_prolong_add", "rkl_coarse_solve", "rkl_poisson_solve_batched",
            "rkl_tau_step_launches", "rkl_tune_set", "rkl_tune_clear", "rkl_tune_get", "rkl_autotune",
-           "rkl_tune_set_s", "rkl_level_shapes", "rkl_variant_name", "rkl_last_error", "rkl_release_all")
+           "rkl_tune_set_s", "rkl_level_shapes", "rkl_variant_name", "rkl_gsrb_smooth", "rkl_default_relax_opts",
+           "rkl_relax_solve", "rkl_last_error", "rkl_release_all")
+SMOOTHERS = {"rkl": 0, "gsrb": 1}
+RELAX = {"rkl": 0, "gsrb": 1, "sor": 2}
 VARIANTS = {0: "heuristic", 1: "ring64x8", 2: "ring64x4", 3: "zq64x32", 4: "zq64x16", 5: "strip8x4",
             6: "strip8x1", 7: "strip4x4"}
 
@@ -105,6 +114,12 @@ def load_library(path: str = LIB_PATH):
         getattr(lib, name).restype = ctypes.c_int
     lib.rkl_variant_name.argtypes = [ctypes.c_int]
     lib.rkl_variant_name.restype = ctypes.c_char_p
+    lib.rkl_gsrb_smooth.argtypes = [pg, ctypes.c_double, ctypes.c_int, P, P, P, P]
+    lib.rkl_gsrb_smooth.restype = ctypes.c_int
+    lib.rkl_default_relax_opts.argtypes = [ctypes.POINTER(c_relax)]
+    lib.rkl_default_relax_opts.restype = None
+    lib.rkl_relax_solve.argtypes = [pg, ctypes.POINTER(c_relax), P, P, P, ps, P]
+    lib.rkl_relax_solve.restype = ctypes.c_int
     lib.rkl_last_error.argtypes = []
     lib.rkl_last_error.restype = ctypes.c_char_p
     lib.rkl_release_all.argtypes = []
@@ -144,11 +159,12 @@ class Options:
     four_pi_G: float = 4.0 * math.pi
     coarse_tol: float = 0.0
     coarse_max_steps: int = 200
+    smoother: str = "rkl"
 
     def c(self):
         return c_opts(self.s, self.tau_frac, self.n_pre, self.n_post, self.min_coarse, self.tol,
                       self.max_cycles, PREC[self.prec], self.four_pi_G, self.coarse_tol,
-                      self.coarse_max_steps)
+                      self.coarse_max_steps, SMOOTHERS[self.smoother])
 
 
 @dataclass
@@ -319,6 +335,37 @@ def solve_batched(rhos, hs, bcs, opts: Options | None = None, history_cap=64, ra
     stats = [Stats(s.cycles, s.levels, s.res0, s.rel_res, list(hh[:s.history_len]), s.status)
              for s, hh in zip(sts, hists)]
     return phis, stats
+
+
+def gsrb_smooth(f, phi, h, bc="periodic", omega=1.0, n_iter=1, faces=None):
+    """n_iter red-black Gauss-Seidel (omega = 1) or SOR passes on M phi = f in place (rkl_gsrb_smooth)."""
+    lib = load_library()
+    _check_faces(faces, f.shape, bc)
+    g = _grid(f.shape, h, bc)
+    _check(lib.rkl_gsrb_smooth(ctypes.byref(g), float(omega), int(n_iter), _dev(f, "f"), _dev(faces, "faces"),
+                               _dev(phi, "phi"), _stream(f)))
+    return phi
+
+
+def relax_solve(f, h, bc="dirichlet", method="rkl", faces=None, phi0=None, s=0, tau_frac=0.9, omega=0.0,
+                tol_max=1e-10, max_iters=100000, check_every=1, history_cap=4096, raise_on_error=True):
+    """Single-level relaxation to max|M phi - f| <= tol_max (rkl_relax_solve, App. B).
+    method: "rkl" (s = 0: accelerated schedule), "gsrb" or "sor" (omega = 0: App. B optimum).
+    Returns (phi, Stats) with Stats.cycles = iterations, Stats.rel_res = final max residual."""
+    lib = load_library()
+    _check_faces(faces, f.shape, bc)
+    g = _grid(f.shape, h, bc)
+    phi = torch.zeros_like(f) if phi0 is None else phi0.clone()
+    ro = c_relax(RELAX[method], int(s), float(tau_frac), float(omega), float(tol_max), int(max_iters),
+                 int(check_every))
+    hist = (ctypes.c_double * max(1, history_cap))()
+    st = c_stats(0, 0, 0.0, 0.0, hist, history_cap, 0, 0)
+    status = lib.rkl_relax_solve(ctypes.byref(g), ctypes.byref(ro), _dev(f, "f"), _dev(faces, "faces"),
+                                 _dev(phi, "phi"), ctypes.byref(st), _stream(f))
+    stats = Stats(st.cycles, st.levels, st.res0, st.rel_res, list(hist[:st.history_len]), status)
+    if status in (RKL_EINVAL, RKL_ENOMEM, RKL_EHIP) or (raise_on_error and status != RKL_OK):
+        _check(status)
+    return phi, stats
 
 
 def tau_step_launches(shape, s, bc="periodic", prec="fp64"):

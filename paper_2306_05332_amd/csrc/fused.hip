@@ -707,6 +707,27 @@ bool launch_fused_tau(const LevelView<T>& L, const T* u, const T* b, T* out, int
   return launch_fused_tau_as<T>(L, fused_choice<T>(L, s), u, b, out, s, co, part, stop, st, bt);
 }
 
+template <typename T>
+bool launch_gsrb_fused(const LevelView<T>& L, const T* u, const T* b, T* out, double omega, double* part,
+                       const int* stop, hipStream_t st, const Batch& bt) {
+  if (!fused_tau_supported<T>(L, 2)) return false;
+  const double d = 2.0 * ((double)L.ihx2 + (double)L.ihy2 + (double)L.ihz2);
+  const FusedChoice c = fused_choice<T>(L, 2);
+  // the tile shape tuned for RKL s = 2 suits the two-stage pass; other families use 4-row strips
+  if (c.variant == FV_STRIP_8x4)
+    launch_strip_gsrb<T, 8, 4>(L, c.target, u, b, out, omega / d, part, stop, bt, st);
+  else
+    launch_strip_gsrb<T, 4, 4>(L, is_strip(c.variant) ? c.target : 1024, u, b, out, omega / d, part, stop, bt, st);
+  return true;
+}
+
+template <typename T>
+size_t gsrb_blocks(const LevelView<T>& L) {
+  const FusedChoice c = fused_choice<T>(L, 2);
+  if (c.variant == FV_STRIP_8x4) return (size_t)strip_grid(2, 8, 4, L.nx, L.ny, L.nz, c.target).nblk;
+  return (size_t)strip_grid(2, 4, 4, L.nx, L.ny, L.nz, is_strip(c.variant) ? c.target : 1024).nblk;
+}
+
 const char* fused_variant_name(int variant) {
   switch (variant) {
     case FV_RING_64x8: return "ring64x8";
@@ -732,6 +753,12 @@ const char* fused_variant_name(int variant) {
                                        const StageCoef*, double*, const int*, hipStream_t, const Batch&);
 RKL_FUSED_INST(double)
 RKL_FUSED_INST(float)
+template bool launch_gsrb_fused<double>(const LevelView<double>&, const double*, const double*, double*, double,
+                                        double*, const int*, hipStream_t, const Batch&);
+template bool launch_gsrb_fused<float>(const LevelView<float>&, const float*, const float*, float*, double, double*,
+                                       const int*, hipStream_t, const Batch&);
+template size_t gsrb_blocks<double>(const LevelView<double>&);
+template size_t gsrb_blocks<float>(const LevelView<float>&);
 #undef RKL_FUSED_INST
 
 }  // namespace rkl

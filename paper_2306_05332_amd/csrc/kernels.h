@@ -129,6 +129,29 @@ StripGrid strip_grid(int s, int R, int WY, int nx, int ny, int nz, int target);
 template <typename T, int S, int R, int WY>
 void launch_strip(const LevelView<T>& L, int target, const T* u, const T* b, T* out, const FCoef<T, S>& fc,
                   double* part, const int* stop, const Batch& bt, hipStream_t st);
+template <typename T, int R, int WY>
+void launch_strip_gsrb(const LevelView<T>& L, int target, const T* u, const T* b, T* out, double omega_over_d,
+                       double* part, const int* stop, const Batch& bt, hipStream_t st);
+
+// One red-black Gauss-Seidel (omega = 1) or SOR iteration on M u = b
+// (Sec. 2.2.4; App. B): red cells ((i + j + k) even) from the old values,
+// then black cells from the new red values, u += (omega / D)(M u - b) with
+// D = 2 sum h^-2, Dirichlet ghosts from the current values.  Out of place in
+// one HBM pass when the level takes the strip kernel (returns true; u ==
+// nullptr reads a zero iterate; part as for the fused tau-step), else false.
+template <typename T>
+bool launch_gsrb_fused(const LevelView<T>& L, const T* u, const T* b, T* out, double omega, double* part,
+                       const int* stop, hipStream_t st, const Batch& bt = single_batch());
+template <typename T>
+size_t gsrb_blocks(const LevelView<T>& L);  // partial sums written by launch_gsrb_fused
+// One colour per launch, any level size: uout = uin with the cells of
+// `colour` updated from uin (two launches make one iteration).
+template <typename T>
+void launch_gsrb_half(const LevelView<T>& L, const T* uin, T* uout, const T* b, int colour, double omega,
+                      const int* stop, hipStream_t st, const Batch& bt = single_batch());
+// max |M u - b| over the level: per-block maxima in part, reduced into out[0]
+template <typename T>
+void launch_resid_absmax(const LevelView<T>& L, const T* u, const T* b, double* part, double* out, hipStream_t st);
 void tune_install(int nx, int ny, int nz, int periodic, int dbl, int s, FusedChoice c);  // FV_HEUR erases
 void tune_clear();
 int tune_generation();
@@ -153,6 +176,6 @@ void tail_prepare();
 template <typename T>
 void launch_tail(const TailShape& ts, const StageCoef* const* smooth, int s, int n_pre, int n_post, int periodic,
                  CoarseSchedule cs, double ctol, int cmax, const T* b_top, T* u_top, const int* stop,
-                 hipStream_t st, const Batch& bt = single_batch());
+                 hipStream_t st, const Batch& bt = single_batch(), int gs = 0);
 
 }  // namespace rkl

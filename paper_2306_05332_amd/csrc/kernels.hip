@@ -54,6 +54,76 @@ __global__ __launch_bounds__(NT) void k_stage(LevelView<T> L, const T* __restric
   }
 }
 
+// ---------------------------------------------------------------- red-black Gauss-Seidel, one colour
+// uout = uin, then the cells with (i + j + k) % 2 == colour get
+// u + (omega / D)(M u - b) evaluated on uin (Sec. 2.2.4).
+template <typename T>
+__global__ __launch_bounds__(256) void k_gsrb_half(LevelView<T> L, const T* __restrict__ uin, T* __restrict__ uout,
+                                                   const T* __restrict__ b, int colour, T coef, Batch bt,
+                                                   const int* __restrict__ stop) {
+  {
+    const long long mb = blockIdx.y;
+    uin += mb * bt.s0;
+    uout += mb * bt.s0;
+    b += mb * bt.s0;
+    if (stop != nullptr) stop += mb * bt.stop_stride;
+  }
+  if (stop != nullptr && *stop) return;
+  const size_t n = (size_t)L.nx * L.ny * L.nz;
+  for (size_t q = (size_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (size_t)gridDim.x * 256) {
+    const int i = (int)(q % L.nx), j = (int)((q / L.nx) % L.ny), k = (int)(q / ((size_t)L.nx * L.ny));
+    const T c = uin[q];
+    T y = c;
+    if (((i + j + k) & 1) == colour) y = c + coef * (lap7(L, load_nbrs(L, uin, i, j, k, q, c), c) - b[q]);
+    uout[q] = y;
+  }
+}
+
+// ---------------------------------------------------------------- max |M u - b|
+template <typename T>
+__global__ __launch_bounds__(256) void k_resid_absmax(LevelView<T> L, const T* __restrict__ u,
+                                                      const T* __restrict__ b, double* __restrict__ part) {
+  __shared__ double sh[256];
+  const size_t n = (size_t)L.nx * L.ny * L.nz;
+  double m = 0.0;
+  for (size_t q = (size_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (size_t)gridDim.x * 256) {
+    const int i = (int)(q % L.nx), j = (int)((q / L.nx) % L.ny), k = (int)(q / ((size_t)L.nx * L.ny));
+    const T c = u[q];
+    const double r = (double)(lap7(L, load_nbrs(L, u, i, j, k, q, c), c) - b[q]);
+    m = fmax(m, fabs(r));
+    if (r != r) m = r;  // keep a NaN visible
+  }
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      const double a = sh[threadIdx.x], c = sh[threadIdx.x + w];
+      sh[threadIdx.x] = (a != a || c != c) ? (a + c) : fmax(a, c);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(256) void k_reduce_max(const double* __restrict__ part, int nblk, double* __restrict__ out) {
+  __shared__ double sh[256];
+  double m = 0.0;
+  for (int q = threadIdx.x; q < nblk; q += 256) {
+    const double v = part[q];
+    m = (v != v || m != m) ? (v + m) : fmax(m, v);
+  }
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      const double a = sh[threadIdx.x], c = sh[threadIdx.x + w];
+      sh[threadIdx.x] = (a != a || c != c) ? (a + c) : fmax(a, c);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
 // ---------------------------------------------------------------- restriction alone
 template <typename T>
 __global__ __launch_bounds__(NT) void k_restrict(int fnx, int fny, int fnz, const T* __restrict__ fine,
@@ -251,6 +321,30 @@ size_t stencil_blocks(int nx, int ny, int nz) {
 }
 
 size_t ew_block_count(size_t n) { return ew_blocks(n); }
+
+template <typename T>
+void launch_gsrb_half(const LevelView<T>& L, const T* uin, T* uout, const T* b, int colour, double omega,
+                      const int* stop, hipStream_t st, const Batch& bt) {
+  const double d = 2.0 * ((double)L.ihx2 + (double)L.ihy2 + (double)L.ihz2);
+  const size_t n = (size_t)L.nx * L.ny * L.nz;
+  hipLaunchKernelGGL(k_gsrb_half<T>, dim3(ew_blocks(n), bt.nb), dim3(256), 0, st, L, uin, uout, b, colour,
+                     (T)(omega / d), bt, stop);
+}
+
+template <typename T>
+void launch_resid_absmax(const LevelView<T>& L, const T* u, const T* b, double* part, double* out, hipStream_t st) {
+  const size_t n = (size_t)L.nx * L.ny * L.nz;
+  const unsigned nb = ew_blocks(n);
+  hipLaunchKernelGGL(k_resid_absmax<T>, dim3(nb), dim3(256), 0, st, L, u, b, part);
+  hipLaunchKernelGGL(k_reduce_max, dim3(1), dim3(256), 0, st, part, (int)nb, out);
+}
+
+template void launch_gsrb_half<double>(const LevelView<double>&, const double*, double*, const double*, int, double,
+                                       const int*, hipStream_t, const Batch&);
+template void launch_gsrb_half<float>(const LevelView<float>&, const float*, float*, const float*, int, double,
+                                      const int*, hipStream_t, const Batch&);
+template void launch_resid_absmax<double>(const LevelView<double>&, const double*, const double*, double*, double*,
+                                          hipStream_t);
 
 template <typename T>
 void launch_stage(const LevelView<T>& L, const T* yp, const T* ypp, const T* b, T* yout, double mu,

@@ -373,10 +373,28 @@ void remove_mean(Plan& P, T* a, size_t n, const int* stop, hipStream_t st) {
 // are swapped when it lands in `alt`).  Fused single-pass kernel when the
 // level supports it, otherwise one kernel per stage with Y_j written over
 // Y_{j-2}.
+// One red-black Gauss-Seidel / SOR iteration (Sec. 2.2.4) from `cur`; the
+// result ends in `cur`.  One pass when the level takes the strip kernel,
+// else two one-colour passes.
+template <typename T>
+void gsrb_iter(const LevelView<T>& V, T*& cur, T*& alt, const T* b, double omega, const int* stop, hipStream_t st,
+               const Batch& bt = single_batch()) {
+  if (launch_gsrb_fused<T>(V, cur, b, alt, omega, nullptr, stop, st, bt)) {
+    check_launch();
+    std::swap(cur, alt);
+    return;
+  }
+  if (bt.nb > 1) fail(RKL_EINVAL, "batched solves need the fused smoother on every level above the tail");
+  launch_gsrb_half<T>(V, cur, alt, b, 0, omega, stop, st);
+  launch_gsrb_half<T>(V, alt, cur, b, 1, omega, stop, st);
+  check_launch();
+}
+
 template <typename T>
 void tau_step(Plan& P, const LevelView<T>& V, T*& cur, T*& alt, const T* b,
               const std::vector<StageCoef>& co, const int* stop, hipStream_t st,
-              const Batch& bt = single_batch()) {
+              const Batch& bt = single_batch(), bool gs = false) {
+  if (gs) return gsrb_iter<T>(V, cur, alt, b, 1.0, stop, st, bt);
   const int s = (int)co.size();
   if (launch_fused_tau<T>(V, cur, b, alt, s, co.data(), nullptr, stop, st, bt)) {
     check_launch();
@@ -401,16 +419,18 @@ void tau_step(Plan& P, const LevelView<T>& V, T*& cur, T*& alt, const T* b,
 template <typename T>
 void tau_from_zero(Plan& P, const LevelView<T>& V, T*& cur, T*& alt, const T* b,
                    const std::vector<StageCoef>& co, const int* stop, hipStream_t st,
-                   const Batch& bt = single_batch()) {
+                   const Batch& bt = single_batch(), bool gs = false) {
   const int s = (int)co.size();
-  if (launch_fused_tau<T>(V, (const T*)nullptr, b, cur, s, co.data(), nullptr, stop, st, bt)) {
+  const bool fused = gs ? launch_gsrb_fused<T>(V, (const T*)nullptr, b, cur, 1.0, nullptr, stop, st, bt)
+                        : launch_fused_tau<T>(V, (const T*)nullptr, b, cur, s, co.data(), nullptr, stop, st, bt);
+  if (fused) {
     check_launch();
     return;
   }
-  if (bt.nb > 1) fail(RKL_EINVAL, "batched solves need the fused tau-step on every level above the tail");
+  if (bt.nb > 1) fail(RKL_EINVAL, "batched solves need the fused smoother on every level above the tail");
   launch_fill<T>(cur, (size_t)V.nx * V.ny * V.nz, (T)0, stop, st);
   check_launch();
-  tau_step<T>(P, V, cur, alt, b, co, stop, st);
+  tau_step<T>(P, V, cur, alt, b, co, stop, st, single_batch(), gs);
 }
 
 // A tau-step from `a` that never writes `a`: the result lands in x or y and
@@ -418,7 +438,21 @@ void tau_from_zero(Plan& P, const LevelView<T>& V, T*& cur, T*& alt, const T* b,
 // also writes the partial sums of (M a - b)^2.
 template <typename T>
 bool tau_keep(Plan& P, const LevelView<T>& V, T* a, T* x, T* y, T*& cur, T*& alt, const T* b,
-              const std::vector<StageCoef>& co, double* part, const int* stop, hipStream_t st) {
+              const std::vector<StageCoef>& co, double* part, const int* stop, hipStream_t st, bool gs = false) {
+  if (gs) {
+    if (launch_gsrb_fused<T>(V, a, b, x, 1.0, part, stop, st)) {
+      check_launch();
+      cur = x;
+      alt = y;
+      return true;
+    }
+    launch_gsrb_half<T>(V, a, x, b, 0, 1.0, stop, st);
+    launch_gsrb_half<T>(V, x, y, b, 1, 1.0, stop, st);
+    check_launch();
+    cur = y;
+    alt = x;
+    return false;
+  }
   const int s = (int)co.size();
   if (launch_fused_tau<T>(V, a, b, x, s, co.data(), part, stop, st)) {
     check_launch();
@@ -525,10 +559,11 @@ void vcycle_from(Plan& P, Hier<T>& H, T*& cur0, T*& alt0, const T* b0, const dou
   auto B2 = [&](int l, int l2) {
     return Batch{vb.nb, (long long)P.lv[l].n, (long long)P.lv[l2].n, vb.stop_stride, vb.part_stride};
   };
+  const bool gs = o.smoother == RKL_SMOOTH_GSRB;
   if (L == 1) {
     if (vb.nb > 1) fail(RKL_EINVAL, "batched solves need at least two levels");
     for (int q = pre_done; q < o.n_pre + o.n_post; ++q)
-      tau_step<T>(P, V(0), cur0, alt0, b0, P.lv[0].smooth, stop, st);
+      tau_step<T>(P, V(0), cur0, alt0, b0, P.lv[0].smooth, stop, st, single_batch(), gs);
     return;
   }
   // levels lt.. run in the one-workgroup tail when they fit
@@ -536,7 +571,7 @@ void vcycle_from(Plan& P, Hier<T>& H, T*& cur0, T*& alt0, const T* b0, const dou
   if (vb.nb > 1 && lt <= 0) fail(RKL_EINVAL, "batched solves need the one-workgroup coarse tail");
   const int lbot = lt > 0 ? lt : L - 1;
   for (int q = pre_done; q < o.n_pre; ++q)
-    tau_step<T>(P, V(0), cur0, alt0, b0, P.lv[0].smooth, stop, st, B1(0));
+    tau_step<T>(P, V(0), cur0, alt0, b0, P.lv[0].smooth, stop, st, B1(0), gs);
   for (int l = 1; l <= lbot; ++l) {
     T* fu = (l == 1) ? cur0 : H.u[l - 1];
     const T* fb = (l == 1) ? b0 : H.b[l - 1];
@@ -548,7 +583,7 @@ void vcycle_from(Plan& P, Hier<T>& H, T*& cur0, T*& alt0, const T* b0, const dou
       const StageCoef* sm[TAIL_MAX_LEVELS];
       for (int k = 0; k < ts.nlev; ++k) sm[k] = P.lv[lt + k].smooth.data();
       launch_tail<T>(ts, sm, o.s, o.n_pre, o.n_post, P.periodic ? 1 : 0, P.cs(), coarse_tol_for<T>(o),
-                     o.coarse_max_steps, H.b[lt], H.u[lt], stop, st, B1(lt));
+                     o.coarse_max_steps, H.b[lt], H.u[lt], stop, st, B1(lt), gs ? 1 : 0);
       check_launch();
       break;
     }
@@ -562,9 +597,9 @@ void vcycle_from(Plan& P, Hier<T>& H, T*& cur0, T*& alt0, const T* b0, const dou
     }
     if (l < L - 1) {
       if (o.n_pre > 0) {
-        tau_from_zero<T>(P, V(l), H.u[l], H.t[l], H.b[l], C.smooth, stop, st, B1(l));
+        tau_from_zero<T>(P, V(l), H.u[l], H.t[l], H.b[l], C.smooth, stop, st, B1(l), gs);
         for (int q = 1; q < o.n_pre; ++q)
-          tau_step<T>(P, V(l), H.u[l], H.t[l], H.b[l], C.smooth, stop, st, B1(l));
+          tau_step<T>(P, V(l), H.u[l], H.t[l], H.b[l], C.smooth, stop, st, B1(l), gs);
       } else {
         launch_fill<T>(H.u[l], C.n, (T)0, stop, st, B1(l));
       }
@@ -580,7 +615,7 @@ void vcycle_from(Plan& P, Hier<T>& H, T*& cur0, T*& alt0, const T* b0, const dou
     const Lev& F = P.lv[l];
     launch_prolong_add<T>(F.nx, F.ny, F.nz, P.periodic ? 1 : 0, H.u[l + 1], cu, stop, st, B2(l, l + 1));
     check_launch();
-    for (int q = 0; q < o.n_post; ++q) tau_step<T>(P, V(l), cu, ca, bl, F.smooth, stop, st, B1(l));
+    for (int q = 0; q < o.n_post; ++q) tau_step<T>(P, V(l), cu, ca, bl, F.smooth, stop, st, B1(l), gs);
   }
 }
 
@@ -668,6 +703,7 @@ rkl_opts resolve_opts(const rkl_opts* in) {
   if (!std::isfinite(o.four_pi_G)) fail(RKL_EINVAL, "four_pi_G must be finite");
   if (!(o.coarse_tol >= 0.0)) fail(RKL_EINVAL, "coarse_tol must be >= 0");
   if (o.coarse_max_steps < 0) fail(RKL_EINVAL, "coarse_max_steps must be >= 0");
+  if (o.smoother != RKL_SMOOTH_RKL && o.smoother != RKL_SMOOTH_GSRB) fail(RKL_EINVAL, "unknown smoother");
   return o;
 }
 
@@ -772,7 +808,8 @@ rkl_status solve_fp64(Plan& P, const rkl_opts& o, const double* rho, const doubl
   HIPCHK(hipMemcpyAsync(P.dscal + 5, P.dscal + 4, sizeof(double), hipMemcpyDeviceToDevice, st));
   conv_reset(P, st);
   const int* stop = &P.dconv->stop;
-  const bool fused0 = fused_tau_supported<double>(V0, o.s) && o.n_pre > 0;
+  const bool gs = o.smoother == RKL_SMOOTH_GSRB;
+  const bool fused0 = fused_tau_supported<double>(V0, gs ? 2 : o.s) && o.n_pre > 0;
   int queued = 0;
   ConvState cs = conv_read(P, st);
   while (true) {
@@ -786,8 +823,8 @@ rkl_status solve_fp64(Plan& P, const rkl_opts& o, const double* rho, const doubl
       int nblk, stride;
       if (fused0) {
         // first relaxation, fused with the residual norm of the start state
-        tau_keep<double>(P, V0, a, bufs[ib], bufs[ic], cur, alt, P.f0, F.smooth, P.part, stop, st);
-        nblk = (int)fused_tau_blocks<double>(V0, o.s);
+        tau_keep<double>(P, V0, a, bufs[ib], bufs[ic], cur, alt, P.f0, F.smooth, P.part, stop, st, gs);
+        nblk = (int)(gs ? gsrb_blocks<double>(V0) : fused_tau_blocks<double>(V0, o.s));
         stride = 1;
         launch_check(P.part, nblk, stride, Res0Sqrt::ptr(P), o.tol, o.max_cycles, 1.0, P.dconv, st);
         check_launch();
@@ -799,7 +836,7 @@ rkl_status solve_fp64(Plan& P, const rkl_opts& o, const double* rho, const doubl
         launch_check(P.part, nblk, stride, Res0Sqrt::ptr(P), o.tol, o.max_cycles, 1.0, P.dconv, st);
         check_launch();
         if (o.n_pre > 0) {
-          tau_keep<double>(P, V0, a, bufs[ib], bufs[ic], cur, alt, P.f0, F.smooth, nullptr, stop, st);
+          tau_keep<double>(P, V0, a, bufs[ib], bufs[ic], cur, alt, P.f0, F.smooth, nullptr, stop, st, gs);
           pre_done = 1;
         } else {
           copy_d2d(bufs[ib], a, F.n, st);
@@ -858,7 +895,8 @@ rkl_status solve_mixed(Plan& P, const rkl_opts& o, const double* rho, const doub
       float* alt = P.h32.t[0];
       int pre_done = 0;
       if (o.n_pre > 0) {
-        tau_from_zero<float>(P, V32, cur, alt, P.h32.b[0], F.smooth, stop, st);
+        tau_from_zero<float>(P, V32, cur, alt, P.h32.b[0], F.smooth, stop, st, single_batch(),
+                             o.smoother == RKL_SMOOTH_GSRB);
         pre_done = 1;
       } else {
         launch_fill<float>(cur, F.n, 0.0f, stop, st);
@@ -1030,7 +1068,7 @@ void class_iteration(ClassPlan& C, Hier<T>& H, const rkl_opts& o, hipStream_t st
   const Batch b0{nb, (long long)F.n, 0, CONV_INTS, ps};
   int pre_done = 0;
   if (o.n_pre > 0) {
-    tau_from_zero<T>(P, VT, cur, alt, H.b[0], F.smooth, stop, st, b0);
+    tau_from_zero<T>(P, VT, cur, alt, H.b[0], F.smooth, stop, st, b0, o.smoother == RKL_SMOOTH_GSRB);
     pre_done = 1;
   } else {
     launch_fill<T>(cur, F.n, (T)0, stop, st, b0);
@@ -1112,10 +1150,11 @@ struct LoopSig {
   double tol, coarse_tol;
   int max_cycles, n_pre, n_post, coarse_max_steps;
   int tune_gen;  // kernel variants are chosen at capture time
+  int smoother;
   bool operator==(const LoopSig& o) const {
     return cls == o.cls && tol == o.tol && coarse_tol == o.coarse_tol && max_cycles == o.max_cycles &&
            n_pre == o.n_pre && n_post == o.n_post && coarse_max_steps == o.coarse_max_steps &&
-           tune_gen == o.tune_gen;
+           tune_gen == o.tune_gen && smoother == o.smoother;
   }
 };
 
@@ -1132,7 +1171,8 @@ std::unique_ptr<GraphCache> g_graph;
 
 // Capture `iters` outer iterations of every class into one graph (cached).
 hipGraphExec_t batch_graph(std::vector<ClassPlan*>& cls, const rkl_opts& o, int iters) {
-  LoopSig sig{{}, o.tol, o.coarse_tol, o.max_cycles, o.n_pre, o.n_post, o.coarse_max_steps, tune_generation()};
+  LoopSig sig{{}, o.tol, o.coarse_tol, o.max_cycles, o.n_pre, o.n_post, o.coarse_max_steps, tune_generation(),
+              o.smoother};
   for (auto* c : cls) sig.cls.push_back({c, iters});
   if (g_graph && g_graph->sig == sig) return g_graph->exec;
   tail_prepare();
@@ -1155,8 +1195,9 @@ template <typename T>
 bool class_ok(Plan& P, const rkl_opts& o) {
   const int lt = tail_level<T>(P);
   if (P.L() < 2 || lt <= 0) return false;
+  const int sf = o.smoother == RKL_SMOOTH_GSRB ? 2 : o.s;
   for (int l = 0; l < lt; ++l)
-    if (!fused_tau_supported<T>(view<T>(P.lv[l], P.periodic, nullptr), o.s)) return false;
+    if (!fused_tau_supported<T>(view<T>(P.lv[l], P.periodic, nullptr), sf)) return false;
   return true;
 }
 
@@ -1362,6 +1403,7 @@ void rkl_default_opts(rkl_opts* o) {
   o->four_pi_G = 4.0 * M_PI;
   o->coarse_tol = 0.0;
   o->coarse_max_steps = 200;
+  o->smoother = RKL_SMOOTH_RKL;
 }
 
 const char* rkl_last_error(void) { return g_err.c_str(); }
@@ -1638,5 +1680,117 @@ int rkl_level_shapes(const rkl_grid* grid, int min_coarse, int* nxyz, int cap) {
 }
 
 const char* rkl_variant_name(int variant) { return fused_variant_name(variant); }
+
+rkl_status rkl_gsrb_smooth(const rkl_grid* grid, double omega, int n_iter, const double* f, const double* bc_faces,
+                           double* phi, void* hip_stream) {
+  return guarded([&]() -> rkl_status {
+    validate_grid(grid, bc_faces);
+    if (!(omega > 0.0 && omega < 2.0)) fail(RKL_EINVAL, "omega must be in (0, 2)");
+    if (n_iter < 0) fail(RKL_EINVAL, "n_iter must be >= 0");
+    if (!f || !phi) fail(RKL_EINVAL, "f and phi must be non-NULL");
+    Plan& P = get_plan(*grid, 2, 0.9, INT_MAX, RKL_FP64);
+    std::lock_guard<std::mutex> lk(P.mu);
+    hipStream_t st = (hipStream_t)hip_stream;
+    const LevelView<double> V0 = view<double>(P.lv[0], P.periodic, bc_faces);
+    double* cur = phi;
+    double* alt = P.t0;
+    for (int q = 0; q < n_iter; ++q) gsrb_iter<double>(V0, cur, alt, f, omega, nullptr, st);
+    if (cur != phi) copy_d2d(phi, cur, P.lv[0].n, st);
+    HIPCHK(hipStreamSynchronize(st));
+    return RKL_OK;
+  });
+}
+
+void rkl_default_relax_opts(rkl_relax_opts* o) {
+  if (!o) return;
+  o->method = RKL_RELAX_RKL;
+  o->s = 0;
+  o->tau_frac = 0.9;
+  o->omega = 0.0;
+  o->tol_max = 1e-10;
+  o->max_iters = 100000;
+  o->check_every = 1;
+}
+
+rkl_status rkl_relax_solve(const rkl_grid* grid, const rkl_relax_opts* opts, const double* f, const double* bc_faces,
+                           double* phi, rkl_stats* stats, void* hip_stream) {
+  return guarded([&]() -> rkl_status {
+    validate_grid(grid, bc_faces);
+    rkl_relax_opts ro;
+    rkl_default_relax_opts(&ro);
+    if (opts) ro = *opts;
+    if (ro.method != RKL_RELAX_RKL && ro.method != RKL_RELAX_GSRB && ro.method != RKL_RELAX_SOR)
+      fail(RKL_EINVAL, "unknown relaxation method");
+    if (ro.s < 0 || ro.s > 64) fail(RKL_EINVAL, "s must be in [0, 64]");
+    if (!(ro.tau_frac > 0.0 && ro.tau_frac < 2.0)) fail(RKL_EINVAL, "tau_frac must be in (0, 2)");
+    if (!(ro.omega >= 0.0 && ro.omega < 2.0)) fail(RKL_EINVAL, "omega must be in [0, 2)");
+    if (!(ro.tol_max >= 0.0)) fail(RKL_EINVAL, "tol_max must be >= 0");
+    if (ro.max_iters < 0 || ro.check_every < 1) fail(RKL_EINVAL, "need max_iters >= 0 and check_every >= 1");
+    if (!f || !phi) fail(RKL_EINVAL, "f and phi must be non-NULL");
+    if (stats) stats->history_len = 0;
+    const bool rkl = ro.method == RKL_RELAX_RKL;
+    Plan& P = get_plan(*grid, rkl && ro.s > 0 ? ro.s : 2, ro.tau_frac, INT_MAX, RKL_FP64);
+    std::lock_guard<std::mutex> lk(P.mu);
+    hipStream_t st = (hipStream_t)hip_stream;
+    const Lev& F = P.lv[0];
+    const LevelView<double> V0 = view<double>(F, P.periodic, bc_faces);
+    double omega = 1.0;
+    if (ro.method == RKL_RELAX_SOR) {
+      omega = ro.omega;
+      if (omega == 0.0) {
+        const double ix = 1.0 / (grid->hx * grid->hx), iy = 1.0 / (grid->hy * grid->hy),
+                     iz = 1.0 / (grid->hz * grid->hz);
+        const double rj = (std::cos(M_PI / grid->nx) * ix + std::cos(M_PI / grid->ny) * iy +
+                           std::cos(M_PI / grid->nz) * iz) / (ix + iy + iz);
+        omega = 2.0 / (1.0 + std::sqrt(1.0 - rj * rj));
+      }
+    }
+    double* cur = phi;
+    double* alt = P.t0;
+    int it = 0;
+    double res = 0.0;
+    rkl_status status = RKL_OK;
+    bool first = true;
+    while (true) {
+      launch_resid_absmax<double>(V0, cur, f, P.part, P.dscal, st);
+      check_launch();
+      res = readback(P, 1, st)[0];
+      record(stats, res);
+      if (first && stats) stats->res0 = res;
+      first = false;
+      if (!std::isfinite(res)) {
+        status = RKL_ENONFINITE;
+        g_err = "non-finite residual";
+        break;
+      }
+      if (res <= ro.tol_max) break;
+      if (it >= ro.max_iters) {
+        status = RKL_ENOCONV;
+        g_err = "max_iters reached before tol_max";
+        break;
+      }
+      for (int c = 0; c < ro.check_every && it < ro.max_iters; ++c) {
+        if (rkl) {
+          const std::vector<StageCoef>& co =
+              ro.s > 0 ? F.smooth : P.sched_coef[std::min(it, (int)P.sched_coef.size() - 1)];
+          tau_step<double>(P, V0, cur, alt, f, co, nullptr, st);
+        } else {
+          gsrb_iter<double>(V0, cur, alt, f, omega, nullptr, st);
+        }
+        if (P.periodic) remove_mean<double>(P, cur, F.n, nullptr, st);
+        ++it;
+      }
+    }
+    if (cur != phi) copy_d2d(phi, cur, F.n, st);
+    HIPCHK(hipStreamSynchronize(st));
+    if (stats) {
+      stats->cycles = it;
+      stats->levels = 1;
+      stats->rel_res = res;
+      stats->status = status;
+    }
+    return status;
+  });
+}
 
 }  // extern "C"

@@ -23,6 +23,12 @@
 // -c, built from the centre value of the operand being differentiated.
 // Optionally the kernel returns float64 partial sums of (M u - b)^2 over its
 // output cells (the residual of the tau-step's input).
+//
+// With GS = true the same two-stage pass is one red-black Gauss-Seidel
+// (omega-SOR) iteration (Sec. 2.2.4): stage 1 updates the red cells
+// ((i + j + k) even) from the old values, stage 2 the black cells from the
+// new red ones, each by u += (omega / D) (M u - b), D = 2 sum h^-2, i.e. the
+// stage recurrence with mu = 1, nu = 0 applied to one colour.
 #include "kernels.h"
 
 namespace rkl {
@@ -42,7 +48,7 @@ __device__ __forceinline__ double wshift(double v) {
   return __hiloint2double(hi, lo);
 }
 
-template <typename T, int S, int R, int WY, bool PER, bool UZ>
+template <typename T, int S, int R, int WY, bool PER, bool UZ, bool GS>
 __global__ __launch_bounds__(64 * WY) void k_tau_strip(LevelView<T> L, const T* __restrict__ u,
                                                        const T* __restrict__ b, T* __restrict__ out,
                                                        FCoef<T, S> co, int zc, int gx_tiles, int gy_tiles,
@@ -82,6 +88,7 @@ __global__ __launch_bounds__(64 * WY) void k_tau_strip(LevelView<T> L, const T* 
 
   long long yoff[NU];    // row offsets in elements (wrapped or clamped), wave-uniform
   unsigned rin = 0;      // bit i: row i lies in the box
+  unsigned rodd = 0;     // bit i: row i has an odd index (GS colouring)
 #pragma unroll
   for (int i = 0; i < NU; ++i) {
     const int gyu = y0 + i;
@@ -89,7 +96,11 @@ __global__ __launch_bounds__(64 * WY) void k_tau_strip(LevelView<T> L, const T* 
     const int gy = PER ? ((gyu % ny) + ny) % ny : min(max(gyu, 0), ny - 1);
     yoff[i] = (long long)gy * nx;
     if (in) rin |= 1u << i;
+    if (gy & 1) rodd |= 1u << i;
   }
+  const int xodd = gx & 1;
+  // parity of plane p's index (wrapped for periodic boxes; |p| stays within a period of the box)
+  auto zodd = [&](int p) -> int { return (PER ? (p < 0 ? p + nz : (p >= nz ? p - nz : p)) : p) & 1; };
   // plane p -> element offset of its (wrapped or clamped) plane; advanced by one
   // plane per iteration without divisions
   auto plane0 = [&](int p) -> long long {
@@ -178,7 +189,8 @@ __global__ __launch_bounds__(64 * WY) void k_tau_strip(LevelView<T> L, const T* 
 #pragma unroll
         for (int i = 1; i < NU - 1; ++i) {
           const T res = lap(U0, U1, U2, i, p) - Bq[0][i];
-          const T y = U1[i] + co.c[0] * res;
+          T y = U1[i] + co.c[0] * res;
+          if (GS && ((xodd ^ ((rodd >> i) & 1) ^ zodd(p)) != 0)) y = U1[i];  // black cell: unchanged
           if (part != nullptr && pown && i >= S && i < S + R && xown && ((rin >> i) & 1u))
             r2 += (double)res * (double)res;
           if constexpr (S == 1) YS[i] = y;
@@ -199,7 +211,8 @@ __global__ __launch_bounds__(64 * WY) void k_tau_strip(LevelView<T> L, const T* 
           const T(&Xp)[NU] = Yq[j - 2][2];
           const T y2 = (j == 2) ? U0[i] : Yq[j >= 3 ? j - 3 : 0][0][i];
           const T res = lap(Xm, Xc, Xp, i, p) - Bq[j - 1][i];
-          const T y = co.mu[j - 1] * Xc[i] + co.nu[j - 1] * y2 + co.c[j - 1] * res;
+          T y = co.mu[j - 1] * Xc[i] + co.nu[j - 1] * y2 + co.c[j - 1] * res;
+          if (GS && ((xodd ^ ((rodd >> i) & 1) ^ zodd(p)) == 0)) y = Xc[i];  // red cell: unchanged
           if (j == S) YS[i] = y;
           else Yq[j - 1][2][i] = y;
         }
@@ -261,26 +274,46 @@ StripGrid strip_grid(int s, int R, int WY, int nx, int ny, int nz, int target) {
   return g;
 }
 
-template <typename T, int S, int R, int WY>
-void launch_strip(const LevelView<T>& L, int target, const T* u, const T* b, T* out, const FCoef<T, S>& fc,
-                  double* part, const int* stop, const Batch& bt, hipStream_t st) {
+template <typename T, int S, int R, int WY, bool GS>
+static void launch_strip_k(const LevelView<T>& L, int target, const T* u, const T* b, T* out, const FCoef<T, S>& fc,
+                           double* part, const int* stop, const Batch& bt, hipStream_t st) {
   const StripGrid g = strip_grid(S, R, WY, L.nx, L.ny, L.nz, target);
   const dim3 grid(g.nblk, bt.nb), block(64 * WY);
   if (L.periodic) {
     if (u == nullptr)
-      hipLaunchKernelGGL((k_tau_strip<T, S, R, WY, true, true>), grid, block, 0, st, L, u, b, out, fc, g.zc, g.gx,
-                         g.gy, g.nblk, part, bt, stop);
+      hipLaunchKernelGGL((k_tau_strip<T, S, R, WY, true, true, GS>), grid, block, 0, st, L, u, b, out, fc, g.zc,
+                         g.gx, g.gy, g.nblk, part, bt, stop);
     else
-      hipLaunchKernelGGL((k_tau_strip<T, S, R, WY, true, false>), grid, block, 0, st, L, u, b, out, fc, g.zc, g.gx,
-                         g.gy, g.nblk, part, bt, stop);
+      hipLaunchKernelGGL((k_tau_strip<T, S, R, WY, true, false, GS>), grid, block, 0, st, L, u, b, out, fc, g.zc,
+                         g.gx, g.gy, g.nblk, part, bt, stop);
   } else {
     if (u == nullptr)
-      hipLaunchKernelGGL((k_tau_strip<T, S, R, WY, false, true>), grid, block, 0, st, L, u, b, out, fc, g.zc, g.gx,
-                         g.gy, g.nblk, part, bt, stop);
+      hipLaunchKernelGGL((k_tau_strip<T, S, R, WY, false, true, GS>), grid, block, 0, st, L, u, b, out, fc, g.zc,
+                         g.gx, g.gy, g.nblk, part, bt, stop);
     else
-      hipLaunchKernelGGL((k_tau_strip<T, S, R, WY, false, false>), grid, block, 0, st, L, u, b, out, fc, g.zc,
+      hipLaunchKernelGGL((k_tau_strip<T, S, R, WY, false, false, GS>), grid, block, 0, st, L, u, b, out, fc, g.zc,
                          g.gx, g.gy, g.nblk, part, bt, stop);
   }
+}
+
+template <typename T, int S, int R, int WY>
+void launch_strip(const LevelView<T>& L, int target, const T* u, const T* b, T* out, const FCoef<T, S>& fc,
+                  double* part, const int* stop, const Batch& bt, hipStream_t st) {
+  launch_strip_k<T, S, R, WY, false>(L, target, u, b, out, fc, part, stop, bt, st);
+}
+
+// one red-black GS / SOR iteration in one pass: the two-stage strip kernel
+// with mu = 1, nu = 0, c = omega / D on the cells of each stage's colour
+template <typename T, int R, int WY>
+void launch_strip_gsrb(const LevelView<T>& L, int target, const T* u, const T* b, T* out, double omega_over_d,
+                       double* part, const int* stop, const Batch& bt, hipStream_t st) {
+  FCoef<T, 2> fc;
+  for (int j = 0; j < 2; ++j) {
+    fc.mu[j] = (T)1;
+    fc.nu[j] = (T)0;
+    fc.c[j] = (T)omega_over_d;
+  }
+  launch_strip_k<T, 2, R, WY, true>(L, target, u, b, out, fc, part, stop, bt, st);
 }
 
 #define RKL_STRIP_INST(T, S, R, WY)                                                                          \
@@ -302,5 +335,13 @@ RKL_STRIP_INST(float, 1, 4, 4)
 RKL_STRIP_INST(float, 2, 4, 4)
 RKL_STRIP_INST(float, 3, 4, 4)
 #undef RKL_STRIP_INST
+#define RKL_GSRB_INST(T, R, WY)                                                                             \
+  template void launch_strip_gsrb<T, R, WY>(const LevelView<T>&, int, const T*, const T*, T*, double, double*, \
+                                            const int*, const Batch&, hipStream_t);
+RKL_GSRB_INST(double, 8, 4)
+RKL_GSRB_INST(double, 4, 4)
+RKL_GSRB_INST(float, 8, 4)
+RKL_GSRB_INST(float, 4, 4)
+#undef RKL_GSRB_INST
 
 }  // namespace rkl

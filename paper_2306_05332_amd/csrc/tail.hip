@@ -24,11 +24,13 @@ struct TailLevel {
   int nx, ny, nz, off;  // off: first of this level's three LDS arrays (u, alt, b)
   T ihx2, ihy2, ihz2;
   T mu[TAIL_MAX_S], nu[TAIL_MAX_S], c[TAIL_MAX_S];
+  T gsc;                // red-black Gauss-Seidel smoother: 1 / D, D = 2 sum h^-2
 };
 
 template <typename T>
 struct TailArgs {
   int nlev, s, n_pre, n_post, periodic, cmax;
+  int gs;               // smoother: 0 RKL tau-step, 1 red-black Gauss-Seidel pass
   double ctol;
   CoarseSchedule cs;
   TailLevel<T> lv[TAIL_MAX_LEVELS];
@@ -143,7 +145,9 @@ __global__ __launch_bounds__(TNT) void k_tail(TailArgs<T> A, const T* __restrict
     for (int q = tid; q < n; q += TNT) B[q] -= m;
     __syncthreads();
   };
-  // one tau-step on level l (stage by stage, Y_j over Y_{j-2}); from_zero: Y_0 = 0
+  // one relaxation on level l: an RKL tau-step (stage by stage, Y_j over
+  // Y_{j-2}) or a red-black Gauss-Seidel pass (in place: a cell's neighbours
+  // all have the other colour on these even-sized levels); from_zero: u = 0
   auto tau = [&](int l, bool from_zero) {
     const TailLevel<T>& V = A.lv[l];
     const int n = nof(l);
@@ -153,6 +157,17 @@ __global__ __launch_bounds__(TNT) void k_tail(TailArgs<T> A, const T* __restrict
     if (from_zero) {
       for (int q = tid; q < n; q += TNT) cur[q] = (T)0;
       __syncthreads();
+    }
+    if (A.gs) {
+      for (int colour = 0; colour < 2; ++colour) {
+        for (CellWalk w(tid, TNT, V.nx, V.ny, V.nz); w.ok(); w.next(TNT)) {
+          if (((w.i + w.j + w.k) & 1) != colour) continue;
+          const int q = w.q;
+          cur[q] += V.gsc * (tail_lap(V, cur, q, w.i, w.j, w.k, per) - B[q]);
+        }
+        __syncthreads();
+      }
+      return;
     }
     for (int j = 1; j <= A.s; ++j) {
       const T* yp = (j & 1) ? cur : alt;
@@ -410,9 +425,10 @@ void tail_prepare() {
 template <typename T>
 void launch_tail(const TailShape& ts, const StageCoef* const* smooth, int s, int n_pre, int n_post, int periodic,
                  CoarseSchedule cs, double ctol, int cmax, const T* b_top, T* u_top, const int* stop,
-                 hipStream_t st, const Batch& bt) {
+                 hipStream_t st, const Batch& bt, int gs) {
   TailArgs<T> A;
   std::memset(&A, 0, sizeof(A));
+  A.gs = gs;
   A.nlev = ts.nlev;
   A.s = s;
   A.n_pre = n_pre;
@@ -432,6 +448,7 @@ void launch_tail(const TailShape& ts, const StageCoef* const* smooth, int s, int
     V.ihx2 = (T)ts.ihx2[l];
     V.ihy2 = (T)ts.ihy2[l];
     V.ihz2 = (T)ts.ihz2[l];
+    V.gsc = (T)(1.0 / (2.0 * (ts.ihx2[l] + ts.ihy2[l] + ts.ihz2[l])));
     for (int j = 0; j < s; ++j) {
       V.mu[j] = (T)smooth[l][j].mu;
       V.nu[j] = (T)smooth[l][j].nu;
@@ -446,8 +463,8 @@ void launch_tail(const TailShape& ts, const StageCoef* const* smooth, int s, int
 template bool tail_fits<double>(const TailShape&, int);
 template bool tail_fits<float>(const TailShape&, int);
 template void launch_tail<double>(const TailShape&, const StageCoef* const*, int, int, int, int, CoarseSchedule,
-                                  double, int, const double*, double*, const int*, hipStream_t, const Batch&);
+                                  double, int, const double*, double*, const int*, hipStream_t, const Batch&, int);
 template void launch_tail<float>(const TailShape&, const StageCoef* const*, int, int, int, int, CoarseSchedule,
-                                 double, int, const float*, float*, const int*, hipStream_t, const Batch&);
+                                 double, int, const float*, float*, const int*, hipStream_t, const Batch&, int);
 
 }  // namespace rkl
