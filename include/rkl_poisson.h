@@ -269,8 +269,10 @@ const char *rkl_variant_name(int variant);
  * n_iter red-black Gauss-Seidel iterations (omega = 1) or SOR iterations
  * (omega in (0, 2)) on M phi = f at one level (Sec. 2.2.4; App. B): red cells
  * ((i + j + k) even) from the old values, then black cells from the new red
- * values, each u += (omega / D)(M u - f), D = 2 sum h^-2; Dirichlet ghosts
- * (2 g - u, or -u with bc_faces NULL) are taken from the current values.
+ * values, each u += (omega / D_cell)(M u - f) with D_cell the operator's own
+ * diagonal (2 sum h^-2, plus h_d^-2 for each Dirichlet face of the cell, whose
+ * ghost is 2 g - u, or -u with bc_faces NULL), so omega = 1 solves each
+ * cell's row exactly (the Jacobi splitting behind App. B's omega).
  * f, phi: device float64[n]; phi is updated in place.
  */
 rkl_status rkl_gsrb_smooth(const rkl_grid *grid, double omega, int n_iter, const double *f,

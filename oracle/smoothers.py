@@ -13,7 +13,13 @@ Reading of App. B: its Delta_t = 2 [sum h^-2]^-1 would make rho_J exceed 1 on
 a uniform grid; the factor is taken as 1/2 (Delta_t = Delta t_par), which gives
 the textbook rho_J = cos(pi/N) for a cube.
 
-Ghost cells are refreshed before every half-sweep (lagged ghosts).
+Reading of the splitting: rho_J and the optimal omega of App. B are those of
+the Jacobi splitting of the discrete operator itself, so every relaxation
+divides the residual by the operator's own diagonal.  For a cell next to a
+Dirichlet face that diagonal includes the ghost's -u term (ghost 2 g - u,
+eq. solution_ghost, or -u, eq. error_ghost): D_cell = 2 sum h^-2 + h_d^-2 per
+such face.  The update is u <- u + omega (M u - b) / D_cell with M u built from
+the current values (ghosts refreshed before every half-sweep).
 """
 from __future__ import annotations
 
@@ -37,10 +43,29 @@ def _diag(h):
     return 2.0 * (1.0 / hx**2 + 1.0 / hy**2 + 1.0 / hz**2)
 
 
+def cell_diagonal(shape, h, bc):
+    """-(diagonal of M) per cell: 2 sum h^-2, plus h_d^-2 for each Dirichlet
+    face the cell touches (the ghost's -u term)."""
+    d = np.full(shape, _diag(h))
+    if bc == "dirichlet":
+        hx, hy, hz = h
+        d[:, :, 0] += 1.0 / hx**2
+        d[:, :, -1] += 1.0 / hx**2
+        d[:, 0, :] += 1.0 / hy**2
+        d[:, -1, :] += 1.0 / hy**2
+        d[0, :, :] += 1.0 / hz**2
+        d[-1, :, :] += 1.0 / hz**2
+    return d
+
+
+def _residual_M(u, b, h, bc, faces):
+    """M u - b with the ghosts of the current u."""
+    return _nbr_sum(u, h, bc, faces) - _diag(h) * u - b
+
+
 def jacobi_sweep(u, b, h, bc, faces=None, omega=1.0):
-    """omega-Jacobi: u <- (1-omega) u + omega (sum_nbr/h^2 - b) / (2 sum h^-2)."""
-    new = (_nbr_sum(u, h, bc, faces) - b) / _diag(h)
-    return (1.0 - omega) * u + omega * new
+    """omega-Jacobi: u <- u + omega (M u - b) / D_cell."""
+    return u + omega * _residual_M(u, b, h, bc, faces) / cell_diagonal(u.shape, h, bc)
 
 
 def colour_mask(shape, colour):
@@ -51,13 +76,15 @@ def colour_mask(shape, colour):
 
 
 def gsrb_sweep(u, b, h, bc, faces=None, omega=1.0):
-    """One red-black Gauss-Seidel iteration (red half-sweep, then black).
-    ``omega`` != 1 gives the SOR variant."""
+    """One red-black Gauss-Seidel iteration (red half-sweep, then black), each
+    colour u <- u + omega (M u - b) / D_cell from the values before that half
+    sweep.  ``omega`` != 1 gives the SOR variant."""
     u = np.array(u, copy=True)
+    dc = cell_diagonal(u.shape, h, bc)
     for colour in (0, 1):
         m = colour_mask(u.shape, colour)
-        new = (_nbr_sum(u, h, bc, faces) - b) / _diag(h)
-        u[m] = (1.0 - omega) * u[m] + omega * new[m]
+        r = _residual_M(u, b, h, bc, faces)
+        u[m] = u[m] + omega * r[m] / dc[m]
     return u
 
 

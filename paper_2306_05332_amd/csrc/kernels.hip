@@ -56,7 +56,8 @@ __global__ __launch_bounds__(NT) void k_stage(LevelView<T> L, const T* __restric
 
 // ---------------------------------------------------------------- red-black Gauss-Seidel, one colour
 // uout = uin, then the cells with (i + j + k) % 2 == colour get
-// u + (omega / D)(M u - b) evaluated on uin (Sec. 2.2.4).
+// u + (omega / D_cell)(M u - b) evaluated on uin (Sec. 2.2.4); D_cell = 2 sum
+// h^-2 plus h_d^-2 per Dirichlet face of the cell (the operator's diagonal).
 template <typename T>
 __global__ __launch_bounds__(256) void k_gsrb_half(LevelView<T> L, const T* __restrict__ uin, T* __restrict__ uout,
                                                    const T* __restrict__ b, int colour, T coef, Batch bt,
@@ -74,7 +75,21 @@ __global__ __launch_bounds__(256) void k_gsrb_half(LevelView<T> L, const T* __re
     const int i = (int)(q % L.nx), j = (int)((q / L.nx) % L.ny), k = (int)(q / ((size_t)L.nx * L.ny));
     const T c = uin[q];
     T y = c;
-    if (((i + j + k) & 1) == colour) y = c + coef * (lap7(L, load_nbrs(L, uin, i, j, k, q, c), c) - b[q]);
+    if (((i + j + k) & 1) == colour) {
+      T cf = coef;
+      if (!L.periodic) {
+        const T d = (T)2 * (L.ihx2 + L.ihy2 + L.ihz2);
+        T extra = (T)0;
+        if (i == 0) extra += L.ihx2;
+        if (i == L.nx - 1) extra += L.ihx2;
+        if (j == 0) extra += L.ihy2;
+        if (j == L.ny - 1) extra += L.ihy2;
+        if (k == 0) extra += L.ihz2;
+        if (k == L.nz - 1) extra += L.ihz2;
+        if (extra != (T)0) cf = coef * d / (d + extra);
+      }
+      y = c + cf * (lap7(L, load_nbrs(L, uin, i, j, k, q, c), c) - b[q]);
+    }
     uout[q] = y;
   }
 }

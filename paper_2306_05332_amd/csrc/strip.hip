@@ -27,8 +27,11 @@
 // With GS = true the same two-stage pass is one red-black Gauss-Seidel
 // (omega-SOR) iteration (Sec. 2.2.4): stage 1 updates the red cells
 // ((i + j + k) even) from the old values, stage 2 the black cells from the
-// new red ones, each by u += (omega / D) (M u - b), D = 2 sum h^-2, i.e. the
-// stage recurrence with mu = 1, nu = 0 applied to one colour.
+// new red ones, each by u += (omega / D_cell) (M u - b), i.e. the stage
+// recurrence with mu = 1, nu = 0 applied to one colour.  D_cell is the
+// operator's own diagonal: 2 sum h^-2, plus h_d^-2 for each Dirichlet face
+// the cell touches (the ghost's -u term), so that omega = 1 solves each
+// cell's row exactly.
 #include "kernels.h"
 
 namespace rkl {
@@ -118,6 +121,20 @@ __global__ __launch_bounds__(64 * WY) void k_tau_strip(LevelView<T> L, const T* 
     return *(const T*)(base + xb);
   };
   auto pin = [&](int p) { return PER || (p >= 0 && p < nz); };
+  // GS coefficient of row i, plane p: c * D / D_cell (Dirichlet faces add h_d^-2)
+  const T dgs = (T)2 * (L.ihx2 + L.ihy2 + L.ihz2);
+  auto gscoef = [&](T c, int i, int p) -> T {
+    if (PER) return c;
+    const int gyu = y0 + i;
+    T extra = (T)0;
+    if (xlo) extra += L.ihx2;
+    if (xhi) extra += L.ihx2;
+    if (gyu == 0) extra += L.ihy2;
+    if (gyu == ny - 1) extra += L.ihy2;
+    if (p == 0) extra += L.ihz2;
+    if (p == nz - 1) extra += L.ihz2;
+    return extra == (T)0 ? c : c * dgs / (dgs + extra);
+  };
 
   // Dirichlet ghost of face f at face index fi for centre value c
   auto ghost = [&](int f, long long fi, T c) -> T {
@@ -189,8 +206,13 @@ __global__ __launch_bounds__(64 * WY) void k_tau_strip(LevelView<T> L, const T* 
 #pragma unroll
         for (int i = 1; i < NU - 1; ++i) {
           const T res = lap(U0, U1, U2, i, p) - Bq[0][i];
-          T y = U1[i] + co.c[0] * res;
-          if (GS && ((xodd ^ ((rodd >> i) & 1) ^ zodd(p)) != 0)) y = U1[i];  // black cell: unchanged
+          T y;
+          if (GS) {
+            y = U1[i] + gscoef(co.c[0], i, p) * res;
+            if ((xodd ^ ((rodd >> i) & 1) ^ zodd(p)) != 0) y = U1[i];  // black cell: unchanged
+          } else {
+            y = U1[i] + co.c[0] * res;
+          }
           if (part != nullptr && pown && i >= S && i < S + R && xown && ((rin >> i) & 1u))
             r2 += (double)res * (double)res;
           if constexpr (S == 1) YS[i] = y;
@@ -211,8 +233,13 @@ __global__ __launch_bounds__(64 * WY) void k_tau_strip(LevelView<T> L, const T* 
           const T(&Xp)[NU] = Yq[j - 2][2];
           const T y2 = (j == 2) ? U0[i] : Yq[j >= 3 ? j - 3 : 0][0][i];
           const T res = lap(Xm, Xc, Xp, i, p) - Bq[j - 1][i];
-          T y = co.mu[j - 1] * Xc[i] + co.nu[j - 1] * y2 + co.c[j - 1] * res;
-          if (GS && ((xodd ^ ((rodd >> i) & 1) ^ zodd(p)) == 0)) y = Xc[i];  // red cell: unchanged
+          T y;
+          if (GS) {
+            y = Xc[i] + gscoef(co.c[j - 1], i, p) * res;
+            if ((xodd ^ ((rodd >> i) & 1) ^ zodd(p)) == 0) y = Xc[i];  // red cell: unchanged
+          } else {
+            y = co.mu[j - 1] * Xc[i] + co.nu[j - 1] * y2 + co.c[j - 1] * res;
+          }
           if (j == S) YS[i] = y;
           else Yq[j - 1][2][i] = y;
         }

@@ -24,7 +24,7 @@ struct TailLevel {
   int nx, ny, nz, off;  // off: first of this level's three LDS arrays (u, alt, b)
   T ihx2, ihy2, ihz2;
   T mu[TAIL_MAX_S], nu[TAIL_MAX_S], c[TAIL_MAX_S];
-  T gsc;                // red-black Gauss-Seidel smoother: 1 / D, D = 2 sum h^-2
+  T gsc;                // red-black Gauss-Seidel smoother: 1 / D, D = 2 sum h^-2 (interior cells)
 };
 
 template <typename T>
@@ -163,7 +163,18 @@ __global__ __launch_bounds__(TNT) void k_tail(TailArgs<T> A, const T* __restrict
         for (CellWalk w(tid, TNT, V.nx, V.ny, V.nz); w.ok(); w.next(TNT)) {
           if (((w.i + w.j + w.k) & 1) != colour) continue;
           const int q = w.q;
-          cur[q] += V.gsc * (tail_lap(V, cur, q, w.i, w.j, w.k, per) - B[q]);
+          T cf = V.gsc;
+          if (!per) {  // the operator's diagonal: + h_d^-2 per Dirichlet face of the cell
+            T extra = (T)0;
+            if (w.i == 0) extra += V.ihx2;
+            if (w.i == V.nx - 1) extra += V.ihx2;
+            if (w.j == 0) extra += V.ihy2;
+            if (w.j == V.ny - 1) extra += V.ihy2;
+            if (w.k == 0) extra += V.ihz2;
+            if (w.k == V.nz - 1) extra += V.ihz2;
+            if (extra != (T)0) cf = (T)1 / ((T)1 / V.gsc + extra);
+          }
+          cur[q] += cf * (tail_lap(V, cur, q, w.i, w.j, w.k, per) - B[q]);
         }
         __syncthreads();
       }

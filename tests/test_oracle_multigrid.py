@@ -267,10 +267,19 @@ def test_gsrb_and_jacobi_converge_to_exact(bc):
         if bc == "periodic":
             u -= u.mean()
     assert np.abs(u - us).max() < 1e-8 * np.abs(us).max()
-    # red-black: the first half-sweep updates exactly the red cells
+    # red-black: the first half-sweep updates exactly the red cells, each by
+    # its own row of the system (diagonal 6/h^2, +1/h^2 per Dirichlet face)
     u1 = sm.gsrb_sweep(np.zeros_like(f), f, h, bc)
     red = sm.colour_mask(f.shape, 0)
-    np.testing.assert_allclose(u1[red], (-f / (6 * n * n))[red], atol=1e-15)
+    nface = np.zeros(f.shape)
+    if bc == "dirichlet":
+        for ax in range(3):
+            idx = [slice(None)] * 3
+            idx[ax] = 0
+            nface[tuple(idx)] += 1
+            idx[ax] = -1
+            nface[tuple(idx)] += 1
+    np.testing.assert_allclose(u1[red], (-f / ((6 + nface) * n * n))[red], atol=1e-15)
 
 
 def test_fourth_order_gradient_convergence():
@@ -290,8 +299,9 @@ def test_fourth_order_gradient_convergence():
 
 def test_gsrb_sweep_matches_bruteforce_loops():
     """Red-black pass written cell by cell: red cells from the old values, then
-    black cells from the new red ones; Dirichlet ghosts 2 g - u_cell refreshed
-    before each half pass (lagged), omega-weighted update."""
+    black cells from the new red ones, each solving its own row of the
+    discrete system exactly (omega = 1) and over-relaxed by omega: a
+    Dirichlet face contributes 2 g to the right side and -u to the diagonal."""
     rng = np.random.default_rng(21)
     n = 4
     h = (0.3, 0.2, 0.25)
@@ -310,14 +320,24 @@ def test_gsrb_sweep_matches_bruteforce_loops():
                     if (i + j + k) % 2 != colour:
                         continue
                     c = old[k, j, i]
-                    xm = old[k, j, i - 1] if i > 0 else 2 * faces[0][k, j] - c
-                    xp = old[k, j, i + 1] if i < n - 1 else 2 * faces[1][k, j] - c
-                    ym = old[k, j - 1, i] if j > 0 else 2 * faces[2][k, i] - c
-                    yp = old[k, j + 1, i] if j < n - 1 else 2 * faces[3][k, i] - c
-                    zm = old[k - 1, j, i] if k > 0 else 2 * faces[4][j, i] - c
-                    zp = old[k + 1, j, i] if k < n - 1 else 2 * faces[5][j, i] - c
-                    new = ((xm + xp) * ih[0] + (ym + yp) * ih[1] + (zm + zp) * ih[2] - b[k, j, i]) / D
-                    want[k, j, i] = (1 - om) * c + om * new
+                    # row of the discrete system: sum_nb a_nb u_nb - diag u = b - boundary terms
+                    rhs = b[k, j, i]
+                    diag = D
+                    acc = 0.0
+                    for (cond, val, face, w) in (
+                            (i > 0, lambda: old[k, j, i - 1], lambda: faces[0][k, j], ih[0]),
+                            (i < n - 1, lambda: old[k, j, i + 1], lambda: faces[1][k, j], ih[0]),
+                            (j > 0, lambda: old[k, j - 1, i], lambda: faces[2][k, i], ih[1]),
+                            (j < n - 1, lambda: old[k, j + 1, i], lambda: faces[3][k, i], ih[1]),
+                            (k > 0, lambda: old[k - 1, j, i], lambda: faces[4][j, i], ih[2]),
+                            (k < n - 1, lambda: old[k + 1, j, i], lambda: faces[5][j, i], ih[2])):
+                        if cond:
+                            acc += w * val()
+                        else:
+                            rhs -= 2 * w * face()
+                            diag += w
+                    exact_row = (acc - rhs) / diag
+                    want[k, j, i] = (1 - om) * c + om * exact_row
     got = sm.gsrb_sweep(u, b, h, "dirichlet", faces, om)
     np.testing.assert_allclose(got, want, rtol=0, atol=1e-13)
 
