@@ -304,6 +304,19 @@ void rkl_default_relax_opts(rkl_relax_opts *o);
 rkl_status rkl_relax_solve(const rkl_grid *grid, const rkl_relax_opts *opts, const double *f,
                            const double *bc_faces, double *phi, rkl_stats *stats, void *hip_stream);
 
+/*
+ * Gravitational acceleration g = -grad(phi) by the 4th-order differences of
+ * Sec. 3 (eq. 4thorder_acceleration), e.g.
+ *   g_x = -(4/3)(phi_{i+1} - phi_{i-1})/(2 dx) + (1/3)(phi_{i+2} - phi_{i-2})/(4 dx).
+ * Two ghost layers: periodic wrap; Dirichlet odd reflection about the face
+ * values of phi (phi_{-m} = 2 g - phi_{m-1}, m = 1, 2; bc_faces NULL: g = 0),
+ * which needs every Dirichlet extent >= 2.
+ *   phi        device float64[n]
+ *   gx, gy, gz device float64[n] outputs (caller-owned)
+ */
+rkl_status rkl_gradient(const rkl_grid *grid, const double *phi, const double *bc_faces, double *gx,
+                        double *gy, double *gz, void *hip_stream);
+
 /* Thread-local message describing the last failure (never NULL). */
 const char *rkl_last_error(void);
 

@@ -65,7 +65,7 @@ EXPORTS = ("rkl_default_opts", "rkl_poisson_solve", "mg_vcycle", "rkl_smooth", "
            "rkl_restrict", "rkl_prolong_add", "rkl_coarse_solve", "rkl_poisson_solve_batched",
            "rkl_tau_step_launches", "rkl_tune_set", "rkl_tune_clear", "rkl_tune_get", "rkl_autotune",
            "rkl_tune_set_s", "rkl_level_shapes", "rkl_variant_name", "rkl_gsrb_smooth", "rkl_default_relax_opts",
-           "rkl_relax_solve", "rkl_last_error", "rkl_release_all")
+           "rkl_relax_solve", "rkl_gradient", "rkl_last_error", "rkl_release_all")
 SMOOTHERS = {"rkl": 0, "gsrb": 1}
 RELAX = {"rkl": 0, "gsrb": 1, "sor": 2}
 VARIANTS = {0: "heuristic", 1: "ring64x8", 2: "ring64x4", 3: "zq64x32", 4: "zq64x16", 5: "strip8x4",
@@ -120,6 +120,8 @@ def load_library(path: str = LIB_PATH):
     lib.rkl_default_relax_opts.restype = None
     lib.rkl_relax_solve.argtypes = [pg, ctypes.POINTER(c_relax), P, P, P, ps, P]
     lib.rkl_relax_solve.restype = ctypes.c_int
+    lib.rkl_gradient.argtypes = [pg, P, P, P, P, P, P]
+    lib.rkl_gradient.restype = ctypes.c_int
     lib.rkl_last_error.argtypes = []
     lib.rkl_last_error.restype = ctypes.c_char_p
     lib.rkl_release_all.argtypes = []
@@ -366,6 +368,17 @@ def relax_solve(f, h, bc="dirichlet", method="rkl", faces=None, phi0=None, s=0, 
     if status in (RKL_EINVAL, RKL_ENOMEM, RKL_EHIP) or (raise_on_error and status != RKL_OK):
         _check(status)
     return phi, stats
+
+
+def gradient(phi, h, bc="periodic", faces=None):
+    """(g_x, g_y, g_z) = -grad(phi) by 4th-order differences (rkl_gradient)."""
+    lib = load_library()
+    _check_faces(faces, phi.shape, bc)
+    g = _grid(phi.shape, h, bc)
+    gx, gy, gz = (torch.empty_like(phi) for _ in range(3))
+    _check(lib.rkl_gradient(ctypes.byref(g), _dev(phi, "phi"), _dev(faces, "faces"), _dev(gx, "gx"), _dev(gy, "gy"),
+                            _dev(gz, "gz"), _stream(phi)))
+    return gx, gy, gz
 
 
 def tau_step_launches(shape, s, bc="periodic", prec="fp64"):

@@ -149,6 +149,10 @@ size_t gsrb_blocks(const LevelView<T>& L);  // partial sums written by launch_gs
 template <typename T>
 void launch_gsrb_half(const LevelView<T>& L, const T* uin, T* uout, const T* b, int colour, double omega,
                       const int* stop, hipStream_t st, const Batch& bt = single_batch());
+// g = -grad(phi) by 4th-order differences (Sec. 3, eq. 4thorder_acceleration);
+// Dirichlet second ghost layer by odd reflection about the face value.
+void launch_gradient(int nx, int ny, int nz, double hx, double hy, double hz, int periodic, const double* faces,
+                     const double* phi, double* gx, double* gy, double* gz, hipStream_t st);
 // max |M u - b| over the level: per-block maxima in part, reduced into out[0]
 template <typename T>
 void launch_resid_absmax(const LevelView<T>& L, const T* u, const T* b, double* part, double* out, hipStream_t st);

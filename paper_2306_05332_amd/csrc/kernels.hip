@@ -94,6 +94,53 @@ __global__ __launch_bounds__(256) void k_gsrb_half(LevelView<T> L, const T* __re
   }
 }
 
+// ---------------------------------------------------------------- acceleration g = -grad(phi)
+// 4th-order differences (Sec. 3, eq. 4thorder_acceleration) with two ghost
+// layers: periodic wrap, or odd reflection about the Dirichlet face value g
+// (phi_{-m} = 2 g - phi_{m-1}, m = 1, 2; g = 0 without face data).
+__global__ __launch_bounds__(NT) void k_gradient(int nx, int ny, int nz, double ihx, double ihy, double ihz,
+                                                 int periodic, const double* __restrict__ faces,
+                                                 const double* __restrict__ phi, double* __restrict__ gx,
+                                                 double* __restrict__ gy, double* __restrict__ gz, int kz) {
+  const int i = blockIdx.x * TX + threadIdx.x;
+  const int j = blockIdx.y * TY + threadIdx.y;
+  const int k0 = blockIdx.z * kz;
+  if (i >= nx || j >= ny) return;
+  const int k1 = min(k0 + kz, nz);
+  const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
+  auto fv = [&](int face, size_t idx) -> double {
+    return faces != nullptr ? faces[face_off(face, nx, ny, nz) + idx] : 0.0;
+  };
+  for (int k = k0; k < k1; ++k) {
+    const size_t c = (size_t)k * sz + (size_t)j * sy + i;
+    // value at offset d in {-2,-1,1,2} along an axis of length n at position p
+    auto along = [&](int p, int n, int d, size_t stride, int flo, int fhi, size_t fidx) -> double {
+      const int q = p + d;
+      if (q >= 0 && q < n) return phi[c + (ptrdiff_t)d * (ptrdiff_t)stride];
+      if (periodic) {
+        const int w = ((q % n) + n) % n;  // also for axes shorter than the stencil
+        return phi[c + (ptrdiff_t)(w - p) * (ptrdiff_t)stride];
+      }
+      if (q < 0) {
+        const int m = -q;  // ghost layer m: mirror cell m - 1
+        return 2.0 * fv(flo, fidx) - phi[c + (ptrdiff_t)(m - 1 - p) * (ptrdiff_t)stride];
+      }
+      const int m = q - (n - 1);  // mirror cell n - m
+      return 2.0 * fv(fhi, fidx) - phi[c + (ptrdiff_t)(n - m - p) * (ptrdiff_t)stride];
+    };
+    auto deriv = [&](double m2, double m1, double p1, double p2, double ih) {
+      return -(4.0 / 3.0) * (p1 - m1) * (0.5 * ih) + (1.0 / 3.0) * (p2 - m2) * (0.25 * ih);
+    };
+    const size_t fx = (size_t)k * ny + j, fy = (size_t)k * nx + i, fz = (size_t)j * nx + i;
+    gx[c] = deriv(along(i, nx, -2, 1, 0, 1, fx), along(i, nx, -1, 1, 0, 1, fx), along(i, nx, 1, 1, 0, 1, fx),
+                  along(i, nx, 2, 1, 0, 1, fx), ihx);
+    gy[c] = deriv(along(j, ny, -2, sy, 2, 3, fy), along(j, ny, -1, sy, 2, 3, fy), along(j, ny, 1, sy, 2, 3, fy),
+                  along(j, ny, 2, sy, 2, 3, fy), ihy);
+    gz[c] = deriv(along(k, nz, -2, sz, 4, 5, fz), along(k, nz, -1, sz, 4, 5, fz), along(k, nz, 1, sz, 4, 5, fz),
+                  along(k, nz, 2, sz, 4, 5, fz), ihz);
+  }
+}
+
 // ---------------------------------------------------------------- max |M u - b|
 template <typename T>
 __global__ __launch_bounds__(256) void k_resid_absmax(LevelView<T> L, const T* __restrict__ u,
@@ -336,6 +383,13 @@ size_t stencil_blocks(int nx, int ny, int nz) {
 }
 
 size_t ew_block_count(size_t n) { return ew_blocks(n); }
+
+void launch_gradient(int nx, int ny, int nz, double hx, double hy, double hz, int periodic, const double* faces,
+                     const double* phi, double* gx, double* gy, double* gz, hipStream_t st) {
+  const int kz = ((size_t)nx * ny * nz < ((size_t)1 << 21)) ? 1 : KZ;
+  hipLaunchKernelGGL(k_gradient, grid3(nx, ny, nz, kz), dim3(TX, TY), 0, st, nx, ny, nz, 1.0 / hx, 1.0 / hy,
+                     1.0 / hz, periodic, faces, phi, gx, gy, gz, kz);
+}
 
 template <typename T>
 void launch_gsrb_half(const LevelView<T>& L, const T* uin, T* uout, const T* b, int colour, double omega,

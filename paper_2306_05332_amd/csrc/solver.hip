@@ -1701,6 +1701,20 @@ rkl_status rkl_gsrb_smooth(const rkl_grid* grid, double omega, int n_iter, const
   });
 }
 
+rkl_status rkl_gradient(const rkl_grid* grid, const double* phi, const double* bc_faces, double* gx, double* gy,
+                        double* gz, void* hip_stream) {
+  return guarded([&]() -> rkl_status {
+    validate_grid(grid, bc_faces);
+    if (!phi || !gx || !gy || !gz) fail(RKL_EINVAL, "phi, gx, gy and gz must be non-NULL");
+    if (grid->bc == RKL_BC_DIRICHLET && (grid->nx < 2 || grid->ny < 2 || grid->nz < 2))
+      fail(RKL_EINVAL, "Dirichlet gradients need at least 2 cells along every axis");
+    launch_gradient(grid->nx, grid->ny, grid->nz, grid->hx, grid->hy, grid->hz, grid->bc == RKL_BC_PERIODIC ? 1 : 0,
+                    bc_faces, phi, gx, gy, gz, (hipStream_t)hip_stream);
+    check_launch();
+    return RKL_OK;
+  });
+}
+
 void rkl_default_relax_opts(rkl_relax_opts* o) {
   if (!o) return;
   o->method = RKL_RELAX_RKL;

@@ -391,3 +391,42 @@ def test_relax_solve_app_b_ordering():
     a = mg.relax_solve(f, g, "sor", faces=p.faces, tol_max=1e-300, max_iters=7, omega=1.0)[0]
     b = mg.relax_solve(f, g, "gsrb", faces=p.faces, tol_max=1e-300, max_iters=7)[0]
     np.testing.assert_array_equal(a, b)
+
+
+# ---------------------------------------------------------------- 4th-order acceleration, both boundaries
+
+def test_acceleration_matches_periodic_routine_and_linear_fields():
+    rng = np.random.default_rng(8)
+    n = (8, 10, 12)
+    h = (0.1, 0.2, 0.3)
+    phi = rng.standard_normal(n)
+    a = gradient.acceleration(phi, h, "periodic")
+    b = gradient.acceleration_periodic(phi, h)
+    for x, y in zip(a, b):
+        np.testing.assert_allclose(x, y, rtol=0, atol=1e-12)
+    # Dirichlet: a linear field with its exact face values has g = -grad exactly,
+    # up to the boundary (the odd reflection continues it linearly)
+    nz, ny, nx = n
+    X, Y, Z = W.cell_centres(n, (0.0, 0.0, 0.0), h)
+    c = (1.5, -2.0, 0.75)
+    lin = lambda x, y, z: c[0] * x + c[1] * y + c[2] * z + 0.3  # noqa: E731
+    phi = lin(X, Y, Z)
+    faces = tuple(lin(fx, fy, fz) for (fx, fy, fz) in W.face_centres(n, (0.0, 0.0, 0.0), h))
+    gx, gy, gz = gradient.acceleration(phi, h, "dirichlet", faces)
+    np.testing.assert_allclose(gx, -c[0], atol=1e-12)
+    np.testing.assert_allclose(gy, -c[1], atol=1e-12)
+    np.testing.assert_allclose(gz, -c[2], atol=1e-12)
+
+
+def test_acceleration_of_paper_model_converges():
+    """Sec. 4.1: g_x from the exact discrete solution approaches the analytic
+    acceleration (eq. acceleration_3D) at second order (the potential's error
+    dominates the 4th-order stencil)."""
+    errs = []
+    for n in (16, 32):
+        p = W.accuracy_problem(n)
+        us = exact.exact_solution(4 * math.pi * p.rho, p.h, "dirichlet", p.faces)
+        gx, _, _ = gradient.acceleration(us, p.h, "dirichlet", p.faces)
+        want = W.accuracy_acceleration_x(n)
+        errs.append(math.sqrt(np.mean((gx - want) ** 2)) / math.sqrt(np.mean(want ** 2)))
+    assert 1.6 < math.log2(errs[0] / errs[1]) < 2.6

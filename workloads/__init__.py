@@ -167,6 +167,31 @@ def accuracy_problem(n, rho0=1.0, r0=0.25):
                    phi_exact=_accuracy_phi(r, rho0, r0), name=f"accuracy_{n}")
 
 
+def accuracy_fields_device(n, device, rho0=1.0, r0=0.25):
+    """The accuracy model built directly in device memory (torch), for grids
+    too large to build on the host: (rho, phi_exact, g_x exact, faces) with
+    faces as numpy arrays (x-, x+, y-, y+, z-, z+)."""
+    import torch
+    h = 1.0 / n
+    c = -0.5 + (torch.arange(n, dtype=torch.float64, device=device) + 0.5) * h
+    Z = c.view(n, 1, 1)
+    Y = c.view(1, n, 1)
+    X = c.view(1, 1, n)
+    r = torch.sqrt(X * X + Y * Y + Z * Z)
+    rho = torch.where(r <= r0, rho0 * (1.0 - r * r / (r0 * r0)) ** 2, torch.zeros_like(r))
+    mass = 32.0 * math.pi * rho0 * r0**3 / 105.0
+    inside = (-2.0 / 3.0 * math.pi * rho0 * r0 * r0
+              + 4.0 * math.pi * rho0 * (r * r / 6.0 - r**4 / (10.0 * r0 * r0) + r**6 / (42.0 * r0**4)))
+    phi = torch.where(r <= r0, inside, -mass / r)
+    gin = -4.0 * math.pi * rho0 * (r / 3.0 - 0.4 * r**3 / r0**2 + r**5 / (7.0 * r0**4))
+    gr = torch.where(r <= r0, gin, -mass / (r * r))
+    gx = gr * X / r
+    del inside, gin, gr
+    faces = tuple(_accuracy_phi(np.sqrt(fx * fx + fy * fy + fz * fz), rho0, r0)
+                  for (fx, fy, fz) in face_centres((n, n, n), (-0.5,) * 3, (h,) * 3))
+    return rho, phi, gx, faces
+
+
 def accuracy_acceleration_x(n, rho0=1.0, r0=0.25):
     """x-component of the analytic acceleration of the accuracy model (eq. acceleration_3D)."""
     X, Y, Z = cell_centres((n, n, n), (-0.5,) * 3, (1.0 / n,) * 3)
