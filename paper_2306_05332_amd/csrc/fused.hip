@@ -635,6 +635,7 @@ template <typename T, int S>
 void launch_fused_S(const LevelView<T>& L, FusedChoice c, const T* u, const T* b, T* out, const StageCoef* co,
                     double* part, const int* stop, const Batch& bt, hipStream_t st) {
   const FCoef<T, S> fc = make_fcoef<T, S>(co);
+  if (is_strip(c.variant) && L.faces != nullptr) c = FusedChoice{FV_RING_64x8, 1024};  // strips take no face data
   if (is_strip(c.variant)) {
     if constexpr (strip_instantiated<T, S>()) {
       if (c.variant == FV_STRIP_8x4) return launch_strip<T, S, 8, 4>(L, c.target, u, b, out, fc, part, stop, bt, st);
@@ -668,6 +669,7 @@ void launch_fused_S(const LevelView<T>& L, FusedChoice c, const T* u, const T* b
 
 template <typename T>
 size_t fused_tau_blocks_as(const LevelView<T>& L, FusedChoice c, int s) {
+  if (is_strip(c.variant) && L.faces != nullptr) c = FusedChoice{FV_RING_64x8, 1024};
   if (is_strip(c.variant)) {
     int R, WY;
     strip_shape(c.variant, R, WY);
@@ -710,7 +712,7 @@ bool launch_fused_tau(const LevelView<T>& L, const T* u, const T* b, T* out, int
 template <typename T>
 bool launch_gsrb_fused(const LevelView<T>& L, const T* u, const T* b, T* out, double omega, double* part,
                        const int* stop, hipStream_t st, const Batch& bt) {
-  if (!fused_tau_supported<T>(L, 2)) return false;
+  if (!fused_tau_supported<T>(L, 2) || L.faces != nullptr) return false;
   const double d = 2.0 * ((double)L.ihx2 + (double)L.ihy2 + (double)L.ihz2);
   const FusedChoice c = fused_choice<T>(L, 2);
   // the tile shape tuned for RKL s = 2 suits the two-stage pass; other families use 4-row strips

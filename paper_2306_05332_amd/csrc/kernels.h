@@ -149,6 +149,10 @@ size_t gsrb_blocks(const LevelView<T>& L);  // partial sums written by launch_gs
 template <typename T>
 void launch_gsrb_half(const LevelView<T>& L, const T* uin, T* uout, const T* b, int colour, double omega,
                       const int* stop, hipStream_t st, const Batch& bt = single_batch());
+// dst = src - sum over the Dirichlet faces of a cell of 2 g h_d^-2: after this
+// the finest level needs only the homogeneous ghost -u (dst may be src).
+void launch_fold_faces(int nx, int ny, int nz, double hx, double hy, double hz, const double* faces,
+                       const double* src, double* dst, hipStream_t st);
 // g = -grad(phi) by 4th-order differences (Sec. 3, eq. 4thorder_acceleration);
 // Dirichlet second ghost layer by odd reflection about the face value.
 void launch_gradient(int nx, int ny, int nz, double hx, double hy, double hz, int periodic, const double* faces,

@@ -94,6 +94,32 @@ __global__ __launch_bounds__(256) void k_gsrb_half(LevelView<T> L, const T* __re
   }
 }
 
+// ---------------------------------------------------------------- Dirichlet data into the right-hand side
+// The finest-level ghost 2 g - u (Sec. 2.3, eq. solution_ghost) contributes
+// 2 g h_d^-2 to (M u) at a face cell plus the homogeneous part -u h_d^-2, so
+// M u - f = M_0 u - (f - sum 2 g h_d^-2) with M_0 the operator with ghost -u.
+// dst = src minus those terms (dst may be src).
+__global__ __launch_bounds__(NT) void k_fold_faces(int nx, int ny, int nz, double ihx2, double ihy2, double ihz2,
+                                                   const double* __restrict__ faces, const double* src, double* dst,
+                                                   int kz) {
+  const int i = blockIdx.x * TX + threadIdx.x;
+  const int j = blockIdx.y * TY + threadIdx.y;
+  const int k0 = blockIdx.z * kz;
+  if (i >= nx || j >= ny) return;
+  const int k1 = min(k0 + kz, nz);
+  for (int k = k0; k < k1; ++k) {
+    const size_t c = ((size_t)k * ny + j) * nx + i;
+    double t = 0.0;
+    if (i == 0) t += faces[face_off(0, nx, ny, nz) + (size_t)k * ny + j] * ihx2;
+    if (i == nx - 1) t += faces[face_off(1, nx, ny, nz) + (size_t)k * ny + j] * ihx2;
+    if (j == 0) t += faces[face_off(2, nx, ny, nz) + (size_t)k * nx + i] * ihy2;
+    if (j == ny - 1) t += faces[face_off(3, nx, ny, nz) + (size_t)k * nx + i] * ihy2;
+    if (k == 0) t += faces[face_off(4, nx, ny, nz) + (size_t)j * nx + i] * ihz2;
+    if (k == nz - 1) t += faces[face_off(5, nx, ny, nz) + (size_t)j * nx + i] * ihz2;
+    if (t != 0.0 || src != dst) dst[c] = src[c] - 2.0 * t;
+  }
+}
+
 // ---------------------------------------------------------------- acceleration g = -grad(phi)
 // 4th-order differences (Sec. 3, eq. 4thorder_acceleration) with two ghost
 // layers: periodic wrap, or odd reflection about the Dirichlet face value g
@@ -383,6 +409,13 @@ size_t stencil_blocks(int nx, int ny, int nz) {
 }
 
 size_t ew_block_count(size_t n) { return ew_blocks(n); }
+
+void launch_fold_faces(int nx, int ny, int nz, double hx, double hy, double hz, const double* faces,
+                       const double* src, double* dst, hipStream_t st) {
+  const int kz = ((size_t)nx * ny * nz < ((size_t)1 << 21)) ? 1 : KZ;
+  hipLaunchKernelGGL(k_fold_faces, grid3(nx, ny, nz, kz), dim3(TX, TY), 0, st, nx, ny, nz, 1.0 / (hx * hx),
+                     1.0 / (hy * hy), 1.0 / (hz * hz), faces, src, dst, kz);
+}
 
 void launch_gradient(int nx, int ny, int nz, double hx, double hy, double hz, int periodic, const double* faces,
                      const double* phi, double* gx, double* gy, double* gz, hipStream_t st) {

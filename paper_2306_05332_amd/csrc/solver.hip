@@ -619,6 +619,18 @@ void vcycle_from(Plan& P, Hier<T>& H, T*& cur0, T*& alt0, const T* b0, const dou
   }
 }
 
+// dst = src with the Dirichlet face data moved into the right-hand side
+// (every kernel then applies the homogeneous ghost -u on every level)
+void fold_faces(Plan& P, const double* faces, const double* src, double* dst, hipStream_t st) {
+  const Lev& F = P.lv[0];
+  if (faces != nullptr) {
+    launch_fold_faces(F.nx, F.ny, F.nz, F.hx, F.hy, F.hz, faces, src, dst, st);
+    check_launch();
+  } else if (src != dst) {
+    HIPCHK(hipMemcpyAsync(dst, src, F.n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  }
+}
+
 // f0 = four_pi_G * rho, mean removed when periodic
 void prepare_source(Plan& P, const double* rho, double c, hipStream_t st) {
   const size_t n = P.lv[0].n;
@@ -713,8 +725,9 @@ rkl_opts resolve_opts(const rkl_opts* in) {
 bool solve_start(Plan& P, const rkl_opts& o, const double* rho, const double* faces, double* phi,
                  rkl_stats* stats, hipStream_t st, double& res0, rkl_status& status) {
   const Lev& F = P.lv[0];
-  const LevelView<double> V0 = view<double>(F, P.periodic, faces);
+  const LevelView<double> V0 = view<double>(F, P.periodic, nullptr);
   prepare_source(P, rho, o.four_pi_G, st);
+  fold_faces(P, faces, P.f0, P.f0, st);
   resid_norm2_async<double>(P, V0, nullptr, P.f0, st);
   HIPCHK(hipMemcpyAsync(P.dscal + 4, P.dscal, sizeof(double), hipMemcpyDeviceToDevice, st));  // res0^2
   res0 = std::sqrt(readback(P, 1, st)[0]);
@@ -757,7 +770,7 @@ rkl_status finish_status(const ConvState& cs) {
 rkl_status solve_fp64(Plan& P, const rkl_opts& o, const double* rho, const double* faces, double* phi,
                       rkl_stats* stats, hipStream_t st) {
   const Lev& F = P.lv[0];
-  const LevelView<double> V0 = view<double>(F, P.periodic, faces);
+  const LevelView<double> V0 = view<double>(F, P.periodic, nullptr);  // face data folded into f0
   double res0;
   rkl_status status;
   if (!solve_start(P, o, rho, faces, phi, stats, st, res0, status)) return status;
@@ -845,7 +858,7 @@ rkl_status solve_fp64(Plan& P, const rkl_opts& o, const double* rho, const doubl
           pre_done = 0;
         }
       }
-      vcycle_from<double>(P, P.h64, cur, alt, P.f0, faces, pre_done, o, stop, st, VBatch{1, 0, 0, P.dscal});
+      vcycle_from<double>(P, P.h64, cur, alt, P.f0, nullptr, pre_done, o, stop, st, VBatch{1, 0, 0, P.dscal});
       int ie = 0;
       for (int k = 0; k < 3; ++k)
         if (bufs[k] == cur) ie = k;
@@ -868,7 +881,7 @@ rkl_status solve_fp64(Plan& P, const rkl_opts& o, const double* rho, const doubl
 rkl_status solve_mixed(Plan& P, const rkl_opts& o, const double* rho, const double* faces, double* phi,
                        rkl_stats* stats, hipStream_t st) {
   const Lev& F = P.lv[0];
-  const LevelView<double> V0 = view<double>(F, P.periodic, faces);
+  const LevelView<double> V0 = view<double>(F, P.periodic, nullptr);  // face data folded into f0
   const LevelView<float> V32 = view<float>(F, P.periodic, nullptr);
   double res0;
   rkl_status status;
@@ -1439,12 +1452,13 @@ rkl_status mg_vcycle(const rkl_grid* grid, const rkl_opts* opts, const double* f
     hipStream_t st = (hipStream_t)hip_stream;
     double* cur = phi;
     double* alt = P.t0;
-    vcycle_from<double>(P, P.h64, cur, alt, f, bc_faces, 0, o, nullptr, st, VBatch{1, 0, 0, P.dscal});
+    fold_faces(P, bc_faces, f, P.f0, st);
+    vcycle_from<double>(P, P.h64, cur, alt, P.f0, nullptr, 0, o, nullptr, st, VBatch{1, 0, 0, P.dscal});
     if (cur != phi) copy_d2d(phi, cur, P.lv[0].n, st);
     if (rel_res_out) {
-      const LevelView<double> V0 = view<double>(P.lv[0], P.periodic, bc_faces);
-      const double r0 = resid_norm<double>(P, V0, nullptr, f, st);
-      const double r = resid_norm<double>(P, V0, phi, f, st);
+      const LevelView<double> V0 = view<double>(P.lv[0], P.periodic, nullptr);
+      const double r0 = resid_norm<double>(P, V0, nullptr, P.f0, st);
+      const double r = resid_norm<double>(P, V0, phi, P.f0, st);
       *rel_res_out = r0 > 0.0 ? r / r0 : r;
     }
     HIPCHK(hipStreamSynchronize(st));
@@ -1466,10 +1480,11 @@ rkl_status rkl_smooth(const rkl_grid* grid, int s, double tau_frac, int n_steps,
     Plan& P = get_plan(*grid, s, tau_frac, INT_MAX, RKL_FP64);
     std::lock_guard<std::mutex> lk(P.mu);
     hipStream_t st = (hipStream_t)hip_stream;
-    const LevelView<double> V0 = view<double>(P.lv[0], P.periodic, bc_faces);
+    const LevelView<double> V0 = view<double>(P.lv[0], P.periodic, nullptr);
+    fold_faces(P, bc_faces, f, P.f0, st);
     double* cur = phi;
     double* alt = P.t0;
-    for (int q = 0; q < n_steps; ++q) tau_step<double>(P, V0, cur, alt, f, P.lv[0].smooth, nullptr, st);
+    for (int q = 0; q < n_steps; ++q) tau_step<double>(P, V0, cur, alt, P.f0, P.lv[0].smooth, nullptr, st);
     if (cur != phi) copy_d2d(phi, cur, P.lv[0].n, st);
     HIPCHK(hipStreamSynchronize(st));
     return RKL_OK;
@@ -1484,8 +1499,9 @@ rkl_status rkl_residual(const rkl_grid* grid, const double* f, const double* bc_
     Plan& P = get_plan(*grid, 2, 0.9, INT_MAX, RKL_FP64);
     std::lock_guard<std::mutex> lk(P.mu);
     hipStream_t st = (hipStream_t)hip_stream;
-    const LevelView<double> V0 = view<double>(P.lv[0], P.periodic, bc_faces);
-    launch_residual<double, double>(V0, phi, f, r_out, P.part, nullptr, st);
+    const LevelView<double> V0 = view<double>(P.lv[0], P.periodic, nullptr);
+    fold_faces(P, bc_faces, f, P.f0, st);
+    launch_residual<double, double>(V0, phi, P.f0, r_out, P.part, nullptr, st);
     launch_reduce(P.part, (int)resid_blocks(V0.nx, V0.ny, V0.nz), 2, 1, P.dscal, nullptr, st);
     check_launch();
     const double r2 = readback(P, 1, st)[0];
@@ -1691,10 +1707,11 @@ rkl_status rkl_gsrb_smooth(const rkl_grid* grid, double omega, int n_iter, const
     Plan& P = get_plan(*grid, 2, 0.9, INT_MAX, RKL_FP64);
     std::lock_guard<std::mutex> lk(P.mu);
     hipStream_t st = (hipStream_t)hip_stream;
-    const LevelView<double> V0 = view<double>(P.lv[0], P.periodic, bc_faces);
+    const LevelView<double> V0 = view<double>(P.lv[0], P.periodic, nullptr);
+    fold_faces(P, bc_faces, f, P.f0, st);
     double* cur = phi;
     double* alt = P.t0;
-    for (int q = 0; q < n_iter; ++q) gsrb_iter<double>(V0, cur, alt, f, omega, nullptr, st);
+    for (int q = 0; q < n_iter; ++q) gsrb_iter<double>(V0, cur, alt, P.f0, omega, nullptr, st);
     if (cur != phi) copy_d2d(phi, cur, P.lv[0].n, st);
     HIPCHK(hipStreamSynchronize(st));
     return RKL_OK;
@@ -1747,7 +1764,9 @@ rkl_status rkl_relax_solve(const rkl_grid* grid, const rkl_relax_opts* opts, con
     std::lock_guard<std::mutex> lk(P.mu);
     hipStream_t st = (hipStream_t)hip_stream;
     const Lev& F = P.lv[0];
-    const LevelView<double> V0 = view<double>(F, P.periodic, bc_faces);
+    const LevelView<double> V0 = view<double>(F, P.periodic, nullptr);
+    fold_faces(P, bc_faces, f, P.f0, st);
+    f = P.f0;
     double omega = 1.0;
     if (ro.method == RKL_RELAX_SOR) {
       omega = ro.omega;

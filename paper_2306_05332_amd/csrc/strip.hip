@@ -19,8 +19,9 @@
 //
 // Boundaries (Sec. 2.3): periodic boxes wrap rows, planes and columns
 // (a wavefront may hold several periods of a short axis); Dirichlet stencils
-// that leave the box take the ghost 2 g - c (finest level with face data) or
-// -c, built from the centre value of the operand being differentiated.
+// that leave the box take the homogeneous ghost -c of the operand being
+// differentiated (finest-level face data is folded into the right-hand side
+// before any relaxation, so no face array is read here).
 // Optionally the kernel returns float64 partial sums of (M u - b)^2 over its
 // output cells (the residual of the tau-step's input).
 //
@@ -136,11 +137,6 @@ __global__ __launch_bounds__(64 * WY) void k_tau_strip(LevelView<T> L, const T* 
     return extra == (T)0 ? c : c * dgs / (dgs + extra);
   };
 
-  // Dirichlet ghost of face f at face index fi for centre value c
-  auto ghost = [&](int f, long long fi, T c) -> T {
-    if (L.faces != nullptr) return (T)(2.0 * L.faces[face_off(f, nx, ny, nz) + fi]) - c;
-    return -c;
-  };
   // 7-point M applied to the centre row i of plane p: X = centre plane,
   // Zm / Zp = planes below and above
   auto lap = [&](const T(&Zm)[NU], const T(&X)[NU], const T(&Zp)[NU], int i, int p) -> T {
@@ -149,13 +145,12 @@ __global__ __launch_bounds__(64 * WY) void k_tau_strip(LevelView<T> L, const T* 
     T ym = X[i - 1], yp = X[i + 1], zm = Zm[i], zp = Zp[i];
     if (!PER) {
       const int gyu = y0 + i;
-      const int gy = min(max(gyu, 0), ny - 1);
-      if (xlo) xm = ghost(0, (long long)p * ny + gy, c);
-      if (xhi) xp = ghost(1, (long long)p * ny + gy, c);
-      if (gyu == 0) ym = ghost(2, (long long)p * nx + gx, c);
-      if (gyu == ny - 1) yp = ghost(3, (long long)p * nx + gx, c);
-      if (p == 0) zm = ghost(4, (long long)gy * nx + gx, c);
-      if (p == nz - 1) zp = ghost(5, (long long)gy * nx + gx, c);
+      if (xlo) xm = -c;
+      if (xhi) xp = -c;
+      if (gyu == 0) ym = -c;
+      if (gyu == ny - 1) yp = -c;
+      if (p == 0) zm = -c;
+      if (p == nz - 1) zp = -c;
     }
     return ((xm + xp) - (T)2 * c) * L.ihx2 + ((ym + yp) - (T)2 * c) * L.ihy2 + ((zm + zp) - (T)2 * c) * L.ihz2;
   };
