@@ -51,8 +51,9 @@ TOL = 1e-10
 SWEEP_STEPS = 40
 COPY_BYTES = 256 * 1024 * 1024  # plain copy used to scale the HBM counters
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "fused_tau_256_fp64_pmc.txt")
-KERNEL_SOURCES = ["paper_2306_05332_amd/csrc/fused.hip", "paper_2306_05332_amd/csrc/kernels.h",
-                  "paper_2306_05332_amd/csrc/rkl_device.h", "paper_2306_05332_amd/tuning/gfx950.json"]
+KERNEL_SOURCES = ["paper_2306_05332_amd/csrc/fused.hip", "paper_2306_05332_amd/csrc/strip.hip",
+                  "paper_2306_05332_amd/csrc/kernels.h", "paper_2306_05332_amd/csrc/rkl_device.h",
+                  "paper_2306_05332_amd/tuning/gfx950.json"]
 
 
 def parse():
@@ -96,9 +97,9 @@ def kernel_symbol(R, shape, s, prec="fp64"):
             "ring64x4": f"rkl::k_fused_tau<{tname}, {s}, 64, 4>",
             "zq64x32": f"rkl::k_tau_zq<{tname}, {s}, 64, 32, 512, 1, 0>",
             "zq64x16": f"rkl::k_tau_zq<{tname}, {s}, 64, 16, 256, 1, 0>",
-            "strip8x4": f"rkl::k_tau_strip<{tname}, {s}, 8, 4, true, false>",
-            "strip8x1": f"rkl::k_tau_strip<{tname}, {s}, 8, 1, true, false>",
-            "strip4x4": f"rkl::k_tau_strip<{tname}, {s}, 4, 4, true, false>"}.get(v, f"rkl::k_stage<{tname}>")
+            "strip8x4": f"rkl::k_tau_strip<{tname}, {s}, 8, 4, true, false, false>",
+            "strip8x1": f"rkl::k_tau_strip<{tname}, {s}, 8, 1, true, false, false>",
+            "strip4x4": f"rkl::k_tau_strip<{tname}, {s}, 4, 4, true, false, false>"}.get(v, f"rkl::k_stage<{tname}>")
 
 
 def sweep_inputs(torch, W, dev):
@@ -225,7 +226,7 @@ def summarize_trace(d):
     sw = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in best]
     span = (int(best[-1]["End_Timestamp"]) - int(best[0]["Start_Timestamp"])) / 1e3 / len(best)
     out += ["", f"finest-level tau-step kernel: {ksym}",
-            f"  all launches (levels 256^3 and 128^3 share this kernel): {len(dur)}, mean {sum(dur) / len(dur):.2f} us",
+            f"  all launches of this kernel (any level): {len(dur)}, mean {sum(dur) / len(dur):.2f} us",
             f"  timed sweep at 256^3: {len(sw)} launches, mean duration {sum(sw) / len(sw):.2f} us "
             f"(min {min(sw):.2f}, max {max(sw):.2f}); first start to last end / launches {span:.2f} us",
             f"  algorithmic bytes per launch: {3 * 8 * N ** 3} -> "
