@@ -159,7 +159,7 @@ def vcycle(u0, f, levels, opts, faces=None, stats=None):
     for l in range(1, L):
         lv = levels[l - 1]
         r = apply_M(u[l - 1], lv.h, bc, faces if l == 1 else None) - b[l - 1]
-        b[l] = -restrict(r)
+        b[l] = -restrict(r, lv.flat)
         if bc == PERIODIC:
             b[l] = b[l] - b[l].mean()
         u[l] = np.zeros_like(b[l])
@@ -169,7 +169,7 @@ def vcycle(u0, f, levels, opts, faces=None, stats=None):
         else:
             u[l] = coarsest_solve(b[l], levels[l], opts, stats)
     for l in range(L - 2, -1, -1):
-        u[l] = u[l] + prolong(u[l + 1], bc)
+        u[l] = u[l] + prolong(u[l + 1], bc, levels[l].flat)
         fl = faces if l == 0 else None
         for _ in range(opts.n_post):
             u[l] = relax(u[l], b[l], levels[l], opts, fl)

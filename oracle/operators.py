@@ -16,6 +16,12 @@ Paper references (Mandal, Mukherjee & Mignone 2023):
 Arrays are float64 numpy arrays of shape (nz, ny, nx) (x fastest).  Boundary
 face arrays (Dirichlet, finest level only) are ordered x-, x+, y-, y+, z-, z+
 with shapes (nz,ny), (nz,ny), (nz,nx), (nz,nx), (ny,nx), (ny,nx).
+
+Two dimensions (eqs. discrete_laplace_2D, restriction_example_2D,
+prolongation_example_2D) use the same arrays with nz = 1 and hz = inf: every
+z term of the operator then carries the factor 1/hz^2 = 0, so the 7-point
+operator is the 5-point one; the hierarchy coarsens x and y only, restriction
+averages 4 children and prolongation weighs (9, 3, 3, 1)/16.
 """
 from __future__ import annotations
 
@@ -43,6 +49,16 @@ class Grid:
     def shape(self):
         return (self.nz, self.ny, self.nx)
 
+    @property
+    def flat(self):
+        """A 2-D problem: nz = 1 and hz = inf."""
+        return self.nz == 1 and not np.isfinite(self.hz)
+
+
+def grid2d(nx, ny, hx, hy, bc):
+    """A 2-D grid in the (nz = 1, hz = inf) representation."""
+    return Grid(nx, ny, 1, hx, hy, float("inf"), bc)
+
 
 @dataclass
 class Level:
@@ -52,6 +68,10 @@ class Level:
     shape: tuple  # (nz, ny, nx)
     h: tuple  # (hx, hy, hz)
     bc: str
+
+    @property
+    def flat(self):
+        return self.shape[0] == 1 and not np.isfinite(self.h[2])
 
     @property
     def lam(self):
@@ -79,9 +99,12 @@ def build_hierarchy(grid: Grid, min_coarse: int = 4):
     h = (grid.hx, grid.hy, grid.hz)
     l = 0
     levels.append(Level(0, shape, h, grid.bc))
-    while all((n % 2 == 0) and ((n // 2) % 2 == 0) and (n // 2 >= min_coarse) for n in shape):
-        shape = tuple(n // 2 for n in shape)
-        h = tuple(2.0 * x for x in h)
+    flat = grid.flat
+    def ok(n):
+        return (n % 2 == 0) and ((n // 2) % 2 == 0) and (n // 2 >= min_coarse)
+    while all(ok(n) for n in (shape[1:] if flat else shape)):
+        shape = ((1,) if flat else (shape[0] // 2,)) + tuple(n // 2 for n in shape[1:])
+        h = (2.0 * h[0], 2.0 * h[1], h[2] if flat else 2.0 * h[2])
         l += 1
         levels.append(Level(l, shape, h, grid.bc))
     return levels
@@ -143,22 +166,29 @@ def residual(u, b, h, bc, faces=None):
     return apply_M(u, h, bc, faces) - b
 
 
-def restrict(r):
-    """8-point average onto the coarse grid (eq. restriction_example_3D)."""
+def restrict(r, flat=False):
+    """8-point average onto the coarse grid (eq. restriction_example_3D); in
+    2-D (``flat``, nz = 1) the 4-point average of eq. restriction_example_2D."""
     nz, ny, nx = r.shape
+    if flat:
+        v = r.reshape(1, ny // 2, 2, nx // 2, 2)
+        return v.sum(axis=(2, 4)) / 4.0
     v = r.reshape(nz // 2, 2, ny // 2, 2, nx // 2, 2)
     return v.sum(axis=(1, 3, 5)) / 8.0
 
 
-def prolong(e, bc):
+def prolong(e, bc, flat=False):
     """Cell-centred trilinear prolongation (eq. prolongation_example_3D).
 
     Each fine cell takes 27/64 of its parent A, 9/64 of each of the three
     face-adjacent coarse cells on its side (B, D, E), 3/64 of the three
     edge-adjacent ones (C, F, H) and 1/64 of the corner one (G).  Coarse ghosts
     are those of the error equation: homogeneous Dirichlet (-e_adj) or
-    periodic wrap (Sec. 2.3).
+    periodic wrap (Sec. 2.3).  In 2-D (``flat``, nz = 1) the weights are
+    (9, 3, 3, 1)/16 in x and y (eq. prolongation_example_2D).
     """
+    if flat:
+        return _prolong_2d(e, bc)
     p = padded(e, bc, None)
     # corner ghosts are needed by the corner weight G: fill them consistently
     # (periodic: wrap; Dirichlet: odd reflection through each face)
@@ -183,6 +213,24 @@ def prolong(e, bc):
                                           1 + dy * sy: 1 + dy * sy + ny,
                                           1 + dx * sx: 1 + dx * sx + nx]
                 out[oz::2, oy::2, ox::2] = acc
+    return out
+
+
+def _prolong_2d(e, bc):
+    """Bilinear cell-centred prolongation of a (1, ny, nx) array."""
+    q = _fill_edges_corners(padded(e, bc, None), bc)[1]  # (ny + 2, nx + 2) plane with ghosts
+    _, ny, nx = e.shape
+    out = np.zeros((1, 2 * ny, 2 * nx), dtype=e.dtype)
+    w = {0: 3.0, 1: 1.0}
+    for oy in (0, 1):
+        for ox in (0, 1):
+            sy = -1 if oy == 0 else 1
+            sx = -1 if ox == 0 else 1
+            acc = np.zeros((ny, nx), dtype=e.dtype)
+            for dy in (0, 1):
+                for dx in (0, 1):
+                    acc += (w[dy] * w[dx] / 16.0) * q[1 + dy * sy: 1 + dy * sy + ny, 1 + dx * sx: 1 + dx * sx + nx]
+            out[0, oy::2, ox::2] = acc
     return out
 
 

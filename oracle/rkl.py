@@ -151,8 +151,10 @@ def mode_eigenvalue(level, k: int) -> float:
     """
     nz, ny, nx = level.shape
     hx, hy, hz = level.h
-    ns = (nx, ny, nz)
-    hs = (hx, hy, hz)
+    # a 2-D level (nz = 1, hz = inf: eq. discrete_laplace_2D) has no z modes
+    ax = [(n, hh) for n, hh in zip((nx, ny, nz), (hx, hy, hz)) if math.isfinite(hh)]
+    ns = tuple(a[0] for a in ax)
+    hs = tuple(a[1] for a in ax)
     if level.bc == "periodic":
         return min(4.0 * math.sin(k * math.pi / n) ** 2 / (hh * hh) for n, hh in zip(ns, hs))
     return sum(4.0 * math.sin(k * math.pi / (2.0 * n)) ** 2 / (hh * hh) for n, hh in zip(ns, hs))
@@ -167,7 +169,7 @@ def accelerated_schedule(level, theta: float):
     one is skipped.  After the list ends the iteration repeats its last entry
     (s for k = 1).
     """
-    n = min(level.shape)
+    n = min(nn for nn, hh in zip(level.shape[::-1], level.h) if math.isfinite(hh))
     k = max(1, n // 2)
     out = []
     s_old = 0

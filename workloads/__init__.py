@@ -139,6 +139,73 @@ def uniform_sphere(n=32, radius=0.3, rho0=1.0, box=(-1.0, 1.0)):
                    phi_exact=pot(r), name=f"uniform_sphere_{n}")
 
 
+def uniform_disc(nx=64, ny=None, radius=0.3, rho0=1.0, box=(-1.0, 1.0)):
+    """Two-dimensional analogue of ``uniform_sphere``: a constant-density disc
+    of ``radius`` at the origin on a Dirichlet rectangle (nz = 1, hz = inf).
+
+    ``box`` gives the x extent; y spans ny cells of the same width (square
+    cells).  With G = 1 the continuous potential is pi rho0 r^2 inside and
+    2 pi rho0 R^2 ln(r/R) + pi rho0 R^2 outside; the faces carry its values
+    (z faces are zero and carry no weight in 2-D).
+    """
+    ny = nx if ny is None else ny
+    hx = (box[1] - box[0]) / nx
+    h = (hx, hx, float("inf"))
+    lo = (box[0], -0.5 * ny * hx, 0.0)
+    xs = lo[0] + (np.arange(nx) + 0.5) * hx
+    ys = lo[1] + (np.arange(ny) + 0.5) * hx
+    X = np.broadcast_to(xs[None, :], (ny, nx))
+    Y = np.broadcast_to(ys[:, None], (ny, nx))
+    r = np.sqrt(X * X + Y * Y)
+    rho = np.where(r <= radius, rho0, 0.0)[None].astype(np.float64)
+
+    def pot(rr):
+        rr = np.asarray(rr, dtype=np.float64)
+        inside = math.pi * rho0 * rr * rr
+        with np.errstate(divide="ignore"):
+            outside = 2.0 * math.pi * rho0 * radius * radius * np.log(rr / radius) + math.pi * rho0 * radius ** 2
+        return np.where(rr <= radius, inside, outside)
+
+    x0, x1 = lo[0], lo[0] + nx * hx
+    y0, y1 = lo[1], lo[1] + ny * hx
+    faces = (pot(np.hypot(x0, ys))[None, :], pot(np.hypot(x1, ys))[None, :],
+             pot(np.hypot(xs, y0))[None, :], pot(np.hypot(xs, y1))[None, :],
+             np.zeros((ny, nx)), np.zeros((ny, nx)))
+    return Problem(rho=rho, h=h, lo=lo, bc="dirichlet", faces=faces,
+                   phi_exact=pot(r)[None], name=f"uniform_disc_{nx}x{ny}")
+
+
+def gaussian_blobs_2d(nx, ny=None, nblobs=8, rng=None, seed=None, sigma_range=(0.02, 0.08)):
+    """Periodic Gaussian blobs on the unit square (nz = 1, hz = inf), the 2-D
+    analogue of ``gaussian_blobs``; the mean is subtracted."""
+    if rng is None:
+        rng = np.random.default_rng(seed)
+    ny = nx if ny is None else ny
+    centres = rng.uniform(0.0, 1.0, size=(nblobs, 2))
+    sigmas = rng.uniform(sigma_range[0], sigma_range[1], size=nblobs)
+    amps = np.exp(rng.normal(0.0, 1.0, size=nblobs))
+    xs = (np.arange(nx) + 0.5) / nx
+    ys = (np.arange(ny) + 0.5) / ny
+    rho = np.zeros((1, ny, nx), dtype=np.float64)
+    for (cx, cy), sg, a in zip(centres, sigmas, amps):
+        dx = xs - cx
+        dx -= np.round(dx)
+        dy = ys - cy
+        dy -= np.round(dy)
+        c = -0.5 / (sg * sg)
+        rho[0] += a * (np.exp(c * dy * dy)[:, None] * np.exp(c * dx * dx)[None, :])
+    rho -= rho.mean()
+    return Problem(rho=rho, h=(1.0 / nx, 1.0 / ny, float("inf")), lo=(0.0, 0.0, 0.0), bc="periodic",
+                   name=f"blobs2d_{nx}x{ny}_{nblobs}")
+
+
+def problem_2d(nx, ny, bc, seed=0):
+    """A 2-D test problem: blobs (periodic) or the uniform disc (Dirichlet)."""
+    if bc == "periodic":
+        return gaussian_blobs_2d(nx, ny, nblobs=8, seed=seed)
+    return uniform_disc(nx, ny)
+
+
 def _accuracy_phi(r, rho0, r0):
     mass = 32.0 * math.pi * rho0 * r0**3 / 105.0
     inside = (-2.0 / 3.0 * math.pi * rho0 * r0 * r0
