@@ -56,7 +56,14 @@ typedef enum {
     RKL_MIXED = 1   /* float32 V-cycles inside a float64 defect-correction loop     */
 } rkl_precision;
 
-/* Finest-level geometry: active cell counts and spacings (Sec. 2.2.1). */
+/* Finest-level geometry: active cell counts and spacings (Sec. 2.2.1).
+ * Two dimensions: nz = 1 with hz = +infinity (HUGE_VAL).  Every z term of the
+ * operator then carries 1/hz^2 = 0, which leaves the 5-point Laplacian of
+ * eq. discrete_laplace_2D; the hierarchy halves x and y only, restriction
+ * averages 4 children (eq. restriction_example_2D) and prolongation weighs
+ * (9,3,3,1)/16 (eq. prolongation_example_2D).  Dirichlet face arrays keep
+ * the six-face layout; the two z faces (ny*nx values each) carry no weight.
+ * hz = inf with nz != 1 is RKL_EINVAL. */
 typedef struct {
     int nx, ny, nz;
     double hx, hy, hz;
@@ -162,6 +169,9 @@ rkl_status rkl_residual(const rkl_grid *grid, const double *f, const double *bc_
  * rkl_prolong_add: fine += P(coarse) with the (27,9,9,9,3,3,3,1)/64 weights of
  *   eq. prolongation_example_3D and error-equation ghosts on the coarse grid
  *   (homogeneous Dirichlet or periodic, Sec. 2.3); `grid` describes the FINE grid.
+ * On a two-dimensional grid (nz = 1, hz = inf) they are the 4-point average and
+ * the (9,3,3,1)/16 weights of eqs. restriction_example_2D and
+ * prolongation_example_2D, and the coarse grid has nz = 1 as well.
  */
 rkl_status rkl_restrict(const rkl_grid *grid, const double *fine, double *coarse,
                         void *hip_stream);
@@ -310,7 +320,8 @@ rkl_status rkl_relax_solve(const rkl_grid *grid, const rkl_relax_opts *opts, con
  *   g_x = -(4/3)(phi_{i+1} - phi_{i-1})/(2 dx) + (1/3)(phi_{i+2} - phi_{i-2})/(4 dx).
  * Two ghost layers: periodic wrap; Dirichlet odd reflection about the face
  * values of phi (phi_{-m} = 2 g - phi_{m-1}, m = 1, 2; bc_faces NULL: g = 0),
- * which needs every Dirichlet extent >= 2.
+ * which needs every Dirichlet extent >= 2.  A two-dimensional grid (nz = 1,
+ * hz = inf) gets gz = 0.
  *   phi        device float64[n]
  *   gx, gy, gz device float64[n] outputs (caller-owned)
  */

@@ -10,6 +10,8 @@ layer is filled) reflect oddly about the face value g, phi_{-m} = 2 g -
 phi_{m-1} for m = 1, 2 (the first layer is the solution ghost of eq.
 solution_ghost; without face data g = 0), which reproduces linear fields
 exactly.
+
+Two dimensions (nz = 1, hz = inf) have no z derivative: g_z is zero.
 """
 from __future__ import annotations
 
@@ -21,6 +23,9 @@ def acceleration_periodic(phi, h):
     out = []
     # numpy axis 2 = x, 1 = y, 0 = z
     for axis, hh in ((2, h[0]), (1, h[1]), (0, h[2])):
+        if axis == 0 and _flat(phi, h):
+            out.append(np.zeros_like(phi))
+            continue
         p1 = np.roll(phi, -1, axis=axis)
         m1 = np.roll(phi, 1, axis=axis)
         p2 = np.roll(phi, -2, axis=axis)
@@ -29,7 +34,11 @@ def acceleration_periodic(phi, h):
     return tuple(out)
 
 
-def _pad2(phi, bc, faces):
+def _flat(phi, h):
+    return phi.shape[0] == 1 and not np.isfinite(h[2])
+
+
+def _pad2(phi, bc, faces, flat=False):
     """Copy of phi with two ghost layers per face (edges and corners unused)."""
     nz, ny, nx = phi.shape
     p = np.zeros((nz + 4, ny + 4, nx + 4))
@@ -45,8 +54,9 @@ def _pad2(phi, bc, faces):
         p[2:-2, 2:-2, nx + 1 + m] = 2.0 * np.asarray(g[1]) - phi[:, :, nx - m]
         p[2:-2, 2 - m, 2:-2] = 2.0 * np.asarray(g[2]) - phi[:, m - 1, :]
         p[2:-2, ny + 1 + m, 2:-2] = 2.0 * np.asarray(g[3]) - phi[:, ny - m, :]
-        p[2 - m, 2:-2, 2:-2] = 2.0 * np.asarray(g[4]) - phi[m - 1, :, :]
-        p[nz + 1 + m, 2:-2, 2:-2] = 2.0 * np.asarray(g[5]) - phi[nz - m, :, :]
+        if not flat:
+            p[2 - m, 2:-2, 2:-2] = 2.0 * np.asarray(g[4]) - phi[m - 1, :, :]
+            p[nz + 1 + m, 2:-2, 2:-2] = 2.0 * np.asarray(g[5]) - phi[nz - m, :, :]
     return p
 
 
@@ -55,10 +65,15 @@ def acceleration(phi, h, bc="periodic", faces=None):
     described in the module docstring; ``faces`` = (x-, x+, y-, y+, z-, z+)
     face values of phi for Dirichlet boxes (None: homogeneous)."""
     phi = np.asarray(phi, dtype=np.float64)
-    p = _pad2(phi, bc, faces)
+    flat = _flat(phi, h)
+    p = _pad2(phi, bc, faces, flat)
     c = p[2:-2, 2:-2, 2:-2]
     out = []
     for axis, hh in ((2, h[0]), (1, h[1]), (0, h[2])):
+        if axis == 0 and flat:
+            out.append(np.zeros_like(phi))
+            continue
+
         def sh(d):
             sl = [slice(2, -2)] * 3
             n = p.shape[axis] - 4

@@ -180,10 +180,23 @@ class Stats:
 
 
 def _grid(shape, h, bc):
+    """rkl_grid of a (nz, ny, nx) or two-dimensional (ny, nx) array.  A 2-D
+    problem is the single layer nz = 1 with hz = inf (no z coupling); h may
+    then be (hx, hy) or one number."""
+    flat = len(shape) == 2
+    if flat:
+        shape = (1,) + tuple(shape)
     nz, ny, nx = shape
     if isinstance(h, (int, float)):
-        h = (float(h),) * 3
+        h = (float(h), float(h), math.inf if flat else float(h))
+    elif len(h) == 2:
+        h = (h[0], h[1], math.inf)
     return c_grid(nx, ny, nz, float(h[0]), float(h[1]), float(h[2]), BC[bc])
+
+
+def _flat_shape(t):
+    """A fine array of one z plane is two-dimensional for the transfer operators."""
+    return t.dim() == 2 or t.shape[0] == 1
 
 
 def _dev(t, name, dtype=torch.float64):
@@ -207,8 +220,13 @@ def _current_stream():
 
 
 def pack_faces(faces, device=None):
-    """Six face arrays (x-, x+, y-, y+, z-, z+) -> one flat float64 CUDA tensor."""
+    """Six face arrays (x-, x+, y-, y+, z-, z+) -> one flat float64 CUDA tensor.
+    Four arrays (x-, x+ of ny values; y-, y+ of nx values) describe a 2-D grid:
+    its two z faces carry no weight and are packed as zeros."""
     parts = [torch.as_tensor(f, dtype=torch.float64).reshape(-1) for f in faces]
+    if len(parts) == 4:
+        nxy = parts[0].numel() * parts[2].numel()
+        parts += [torch.zeros(nxy, dtype=torch.float64), torch.zeros(nxy, dtype=torch.float64)]
     out = torch.cat(parts)
     return out.to(device or "cuda").contiguous()
 
@@ -218,7 +236,7 @@ def _check_faces(faces, shape, bc):
         return
     if bc != "dirichlet":
         raise ValueError("faces are only valid for Dirichlet grids")
-    nz, ny, nx = shape
+    nz, ny, nx = (1,) + tuple(shape) if len(shape) == 2 else shape
     want = 2 * (ny * nz + nx * nz + nx * ny)
     if faces.numel() != want:
         raise ValueError(f"packed faces must hold {want} values for shape {tuple(shape)}, got {faces.numel()}")
@@ -280,17 +298,22 @@ def residual(f, phi, h, bc="periodic", faces=None):
 
 
 def restrict(fine):
+    """coarse = R(fine): 8-point average, or the 4-point one of a 2-D (ny, nx)
+    or (1, ny, nx) array (rkl_restrict)."""
     lib = load_library()
-    nz, ny, nx = fine.shape
-    coarse = torch.empty((nz // 2, ny // 2, nx // 2), dtype=fine.dtype, device=fine.device)
-    g = _grid(fine.shape, 1.0, "periodic")
+    flat = _flat_shape(fine)
+    ny, nx = fine.shape[-2:]
+    cshape = (ny // 2, nx // 2) if fine.dim() == 2 else (1 if flat else fine.shape[0] // 2, ny // 2, nx // 2)
+    coarse = torch.empty(cshape, dtype=fine.dtype, device=fine.device)
+    g = _grid(fine.shape, (1.0, 1.0) if flat else 1.0, "periodic")
     _check(lib.rkl_restrict(ctypes.byref(g), _dev(fine, "fine"), _dev(coarse, "coarse"), _stream(fine)))
     return coarse
 
 
 def prolong_add(coarse, fine, bc="periodic"):
+    """fine += P(coarse): trilinear, or bilinear for a 2-D fine array (rkl_prolong_add)."""
     lib = load_library()
-    g = _grid(fine.shape, 1.0, bc)
+    g = _grid(fine.shape, (1.0, 1.0) if _flat_shape(fine) else 1.0, bc)
     _check(lib.rkl_prolong_add(ctypes.byref(g), _dev(coarse, "coarse"), _dev(fine, "fine"), _stream(fine)))
     return fine
 
@@ -473,11 +496,12 @@ def tune_set_s(shape, s, bc="periodic", prec="fp64"):
     _check(lib.rkl_tune_set_s(ctypes.byref(_grid(shape, 1.0, bc)), PREC[prec], int(s)))
 
 
-def level_shapes(shape, min_coarse=4, bc="periodic"):
-    """Multigrid level shapes (nz, ny, nx), finest first."""
+def level_shapes(shape, min_coarse=4, bc="periodic", h=1.0):
+    """Multigrid level shapes (nz, ny, nx), finest first.  A (ny, nx) shape, or
+    h = (hx, hy), describes a two-dimensional grid."""
     lib = load_library()
     buf = (ctypes.c_int * (3 * 64))()
-    L = lib.rkl_level_shapes(ctypes.byref(_grid(shape, 1.0, bc)), int(min_coarse), buf, 64)
+    L = lib.rkl_level_shapes(ctypes.byref(_grid(shape, h, bc)), int(min_coarse), buf, 64)
     if L < 0:
         _check(L)
     return [(buf[3 * q + 2], buf[3 * q + 1], buf[3 * q]) for q in range(min(L, 64))]

@@ -3,7 +3,8 @@
 //
 //   k_stage          one RKL stage (App. A eq. RKL_intermediate_source), used
 //                    on levels too small for the fused tau-step
-//   k_restrict       8-point average (eq. restriction_example_3D)
+//   k_restrict       8-point average (eq. restriction_example_3D); 4-point
+//                    (eq. restriction_example_2D) for a one-plane fine grid
 //   k_reduce         fixed-order sum of per-block partials
 //   k_check          convergence test of the V-cycle loop on the device
 //   k_scale / k_sub_mean / k_fill / k_sum / k_add_cast: elementwise helpers
@@ -123,7 +124,8 @@ __global__ __launch_bounds__(NT) void k_fold_faces(int nx, int ny, int nz, doubl
 // ---------------------------------------------------------------- acceleration g = -grad(phi)
 // 4th-order differences (Sec. 3, eq. 4thorder_acceleration) with two ghost
 // layers: periodic wrap, or odd reflection about the Dirichlet face value g
-// (phi_{-m} = 2 g - phi_{m-1}, m = 1, 2; g = 0 without face data).
+// (phi_{-m} = 2 g - phi_{m-1}, m = 1, 2; g = 0 without face data).  ihz = 0
+// (hz = inf, a two-dimensional grid) gives g_z = 0 without z reads.
 __global__ __launch_bounds__(NT) void k_gradient(int nx, int ny, int nz, double ihx, double ihy, double ihz,
                                                  int periodic, const double* __restrict__ faces,
                                                  const double* __restrict__ phi, double* __restrict__ gx,
@@ -162,8 +164,11 @@ __global__ __launch_bounds__(NT) void k_gradient(int nx, int ny, int nz, double 
                   along(i, nx, 2, 1, 0, 1, fx), ihx);
     gy[c] = deriv(along(j, ny, -2, sy, 2, 3, fy), along(j, ny, -1, sy, 2, 3, fy), along(j, ny, 1, sy, 2, 3, fy),
                   along(j, ny, 2, sy, 2, 3, fy), ihy);
-    gz[c] = deriv(along(k, nz, -2, sz, 4, 5, fz), along(k, nz, -1, sz, 4, 5, fz), along(k, nz, 1, sz, 4, 5, fz),
-                  along(k, nz, 2, sz, 4, 5, fz), ihz);
+    if (ihz == 0.0)
+      gz[c] = 0.0;
+    else
+      gz[c] = deriv(along(k, nz, -2, sz, 4, 5, fz), along(k, nz, -1, sz, 4, 5, fz), along(k, nz, 1, sz, 4, 5, fz),
+                    along(k, nz, 2, sz, 4, 5, fz), ihz);
   }
 }
 
@@ -216,7 +221,8 @@ __global__ __launch_bounds__(256) void k_reduce_max(const double* __restrict__ p
 template <typename T>
 __global__ __launch_bounds__(NT) void k_restrict(int fnx, int fny, int fnz, const T* __restrict__ fine,
                                                  T* __restrict__ coarse) {
-  const int cnx = fnx / 2, cny = fny / 2, cnz = fnz / 2;
+  const bool flat = fnz == 1;
+  const int cnx = fnx / 2, cny = fny / 2, cnz = flat ? 1 : fnz / 2;
   const int ic = blockIdx.x * TX + threadIdx.x;
   const int jc = blockIdx.y * TY + threadIdx.y;
   const int kc0 = blockIdx.z * KZ;
@@ -224,11 +230,11 @@ __global__ __launch_bounds__(NT) void k_restrict(int fnx, int fny, int fnz, cons
   const int kc1 = min(kc0 + KZ, cnz);
   for (int kc = kc0; kc < kc1; ++kc) {
     T acc = (T)0;
-    for (int dz = 0; dz < 2; ++dz)
+    for (int dz = 0; dz < (flat ? 1 : 2); ++dz)
       for (int dy = 0; dy < 2; ++dy)
         for (int dx = 0; dx < 2; ++dx)
           acc += fine[((size_t)(2 * kc + dz) * fny + (2 * jc + dy)) * fnx + (2 * ic + dx)];
-    coarse[((size_t)kc * cny + jc) * cnx + ic] = acc * (T)0.125;
+    coarse[((size_t)kc * cny + jc) * cnx + ic] = acc * (flat ? (T)0.25 : (T)0.125);
   }
 }
 
@@ -459,8 +465,9 @@ void launch_stage(const LevelView<T>& L, const T* yp, const T* ypp, const T* b, 
 
 template <typename T>
 void launch_restrict(int fnx, int fny, int fnz, const T* fine, T* coarse, hipStream_t st) {
-  hipLaunchKernelGGL(k_restrict<T>, grid3(fnx / 2, fny / 2, fnz / 2), dim3(TX, TY), 0, st, fnx, fny,
-                     fnz, fine, coarse);
+  const int cnz = fnz == 1 ? 1 : fnz / 2;  // one fine plane: two-dimensional
+  hipLaunchKernelGGL(k_restrict<T>, grid3(fnx / 2, fny / 2, cnz), dim3(TX, TY), 0, st, fnx, fny, fnz, fine,
+                     coarse);
 }
 
 void launch_reduce(const double* part, int nblk, int stride, int nq, double* out, const int* stop,

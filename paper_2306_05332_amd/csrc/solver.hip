@@ -58,6 +58,7 @@ inline void check_launch() {
 struct Lev {
   int nx, ny, nz;
   double hx, hy, hz;
+  bool flat;                       // two-dimensional: nz = 1, hz = inf (no z coupling)
   size_t n;
   double lam, dtpar;               // Lambda_l = 4 sum h^-2, Delta t_par = 2 / Lambda_l
   std::vector<StageCoef> smooth;   // coefficients of the smoothing tau-step
@@ -81,16 +82,18 @@ std::vector<StageCoef> stage_coefs(int s, double theta, double dtpar) {
 // count), s_k = Round(2.4048 / arccos(x_k) - 1/2), x_k = 1 - theta dt_par
 // |lambda_k|, repeats skipped.  |lambda_k|: Dirichlet diagonal mode
 // sum_d 4 sin^2(k pi / 2 n_d) / h_d^2; periodic axis mode min_d 4 sin^2(k pi / n_d) / h_d^2.
+// A two-dimensional level has no z modes: d runs over x and y only.
 std::vector<int> accel_schedule(const Lev& L, bool periodic, double theta) {
   const int ns[3] = {L.nx, L.ny, L.nz};
   const double hs[3] = {L.hx, L.hy, L.hz};
-  const int n = std::min(L.nx, std::min(L.ny, L.nz));
+  const int nd = L.flat ? 2 : 3;
+  const int n = L.flat ? std::min(L.nx, L.ny) : std::min(L.nx, std::min(L.ny, L.nz));
   int k = std::max(1, n / 2);
   int s_old = 0;
   std::vector<int> out;
   while (true) {
     double lk = periodic ? 1e300 : 0.0;
-    for (int d = 0; d < 3; ++d) {
+    for (int d = 0; d < nd; ++d) {
       if (periodic) {
         const double sv = std::sin(k * M_PI / ns[d]);
         lk = std::min(lk, 4.0 * sv * sv / (hs[d] * hs[d]));
@@ -186,10 +189,16 @@ struct Plan {
 std::mutex g_plans_mu;
 std::map<PlanKey, std::unique_ptr<Plan>> g_plans;
 
+bool flat_grid(const rkl_grid& g) { return g.nz == 1 && std::isinf(g.hz) && g.hz > 0.0; }
+
+// Levels from finest to coarsest: halve every axis (x and y only for a
+// two-dimensional grid) while each halved count is even and >= min_coarse.
 std::vector<Lev> build_levels(const rkl_grid& g, int min_coarse, int s, double theta) {
   std::vector<Lev> lv;
   int n[3] = {g.nx, g.ny, g.nz};
   double h[3] = {g.hx, g.hy, g.hz};
+  const bool flat = flat_grid(g);
+  const int nd = flat ? 2 : 3;
   while (true) {
     Lev L;
     L.nx = n[0];
@@ -198,16 +207,17 @@ std::vector<Lev> build_levels(const rkl_grid& g, int min_coarse, int s, double t
     L.hx = h[0];
     L.hy = h[1];
     L.hz = h[2];
+    L.flat = flat;
     L.n = (size_t)n[0] * n[1] * n[2];
     L.lam = 4.0 * (1.0 / (h[0] * h[0]) + 1.0 / (h[1] * h[1]) + 1.0 / (h[2] * h[2]));
     L.dtpar = 2.0 / L.lam;
     L.smooth = stage_coefs(s, theta, L.dtpar);
     lv.push_back(L);
     bool ok = true;
-    for (int d = 0; d < 3; ++d)
+    for (int d = 0; d < nd; ++d)
       ok = ok && (n[d] % 2 == 0) && ((n[d] / 2) % 2 == 0) && (n[d] / 2 >= min_coarse);
     if (!ok) break;
-    for (int d = 0; d < 3; ++d) {
+    for (int d = 0; d < nd; ++d) {
       n[d] /= 2;
       h[d] *= 2.0;
     }
@@ -303,7 +313,8 @@ Plan& get_plan(const rkl_grid& g, int s, double theta, int min_coarse, int prec)
   HIPCHK(hipMemcpy(P->d_sched, P->sched.data(), P->sched.size() * sizeof(int), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(P->d_coff, coff.data(), coff.size() * sizeof(int), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(P->d_coef, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice));
-  if (coarse_in_lds(*P, C) && L >= 3) {
+  // the one-workgroup tail carries the 3-D transfer operators only
+  if (coarse_in_lds(*P, C) && L >= 3 && !P->lv[0].flat) {
     for (int lt = 1; lt < L - 1; ++lt) {
       const TailShape ts = tail_shape(*P, lt);
       if (P->tail64 < 0 && tail_fits<double>(ts, s)) P->tail64 = lt;
@@ -694,9 +705,10 @@ void validate_grid(const rkl_grid* g, const double* bc_faces) {
   if (!g) fail(RKL_EINVAL, "grid is NULL");
   if (g->nx < 1 || g->ny < 1 || g->nz < 1) fail(RKL_EINVAL, "cell counts must be >= 1");
   if ((double)g->nx * g->ny * g->nz > 4.0e10) fail(RKL_EINVAL, "grid too large");
-  if (!(g->hx > 0.0 && g->hy > 0.0 && g->hz > 0.0) || !std::isfinite(g->hx) || !std::isfinite(g->hy) ||
-      !std::isfinite(g->hz))
+  if (!(g->hx > 0.0 && g->hy > 0.0 && g->hz > 0.0) || !std::isfinite(g->hx) || !std::isfinite(g->hy))
     fail(RKL_EINVAL, "spacings must be positive and finite");
+  if (!std::isfinite(g->hz) && g->nz != 1)
+    fail(RKL_EINVAL, "hz = inf (a two-dimensional grid) needs nz = 1");
   if (g->bc != RKL_BC_DIRICHLET && g->bc != RKL_BC_PERIODIC) fail(RKL_EINVAL, "unknown boundary type");
   if (g->bc == RKL_BC_PERIODIC && bc_faces) fail(RKL_EINVAL, "bc_faces must be NULL for periodic grids");
 }
@@ -1513,7 +1525,8 @@ rkl_status rkl_residual(const rkl_grid* grid, const double* f, const double* bc_
 rkl_status rkl_restrict(const rkl_grid* grid, const double* fine, double* coarse, void* hip_stream) {
   return guarded([&]() -> rkl_status {
     validate_grid(grid, nullptr);
-    if (grid->nx % 2 || grid->ny % 2 || grid->nz % 2) fail(RKL_EINVAL, "fine sizes must be even");
+    if (grid->nx % 2 || grid->ny % 2 || (grid->nz % 2 && !flat_grid(*grid)))
+      fail(RKL_EINVAL, "fine sizes must be even (nz = 1 only for a two-dimensional grid)");
     if (!fine || !coarse) fail(RKL_EINVAL, "NULL array");
     hipStream_t st = (hipStream_t)hip_stream;
     launch_restrict<double>(grid->nx, grid->ny, grid->nz, fine, coarse, st);
@@ -1526,7 +1539,8 @@ rkl_status rkl_restrict(const rkl_grid* grid, const double* fine, double* coarse
 rkl_status rkl_prolong_add(const rkl_grid* grid, const double* coarse, double* fine, void* hip_stream) {
   return guarded([&]() -> rkl_status {
     validate_grid(grid, nullptr);
-    if (grid->nx % 2 || grid->ny % 2 || grid->nz % 2) fail(RKL_EINVAL, "fine sizes must be even");
+    if (grid->nx % 2 || grid->ny % 2 || (grid->nz % 2 && !flat_grid(*grid)))
+      fail(RKL_EINVAL, "fine sizes must be even (nz = 1 only for a two-dimensional grid)");
     if (!fine || !coarse) fail(RKL_EINVAL, "NULL array");
     hipStream_t st = (hipStream_t)hip_stream;
     launch_prolong_add<double>(grid->nx, grid->ny, grid->nz, grid->bc == RKL_BC_PERIODIC ? 1 : 0, coarse,
@@ -1723,7 +1737,7 @@ rkl_status rkl_gradient(const rkl_grid* grid, const double* phi, const double* b
   return guarded([&]() -> rkl_status {
     validate_grid(grid, bc_faces);
     if (!phi || !gx || !gy || !gz) fail(RKL_EINVAL, "phi, gx, gy and gz must be non-NULL");
-    if (grid->bc == RKL_BC_DIRICHLET && (grid->nx < 2 || grid->ny < 2 || grid->nz < 2))
+    if (grid->bc == RKL_BC_DIRICHLET && (grid->nx < 2 || grid->ny < 2 || (grid->nz < 2 && !flat_grid(*grid))))
       fail(RKL_EINVAL, "Dirichlet gradients need at least 2 cells along every axis");
     launch_gradient(grid->nx, grid->ny, grid->nz, grid->hx, grid->hy, grid->hz, grid->bc == RKL_BC_PERIODIC ? 1 : 0,
                     bc_faces, phi, gx, gy, gz, (hipStream_t)hip_stream);

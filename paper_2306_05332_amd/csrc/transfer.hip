@@ -11,6 +11,13 @@
 //                            weights of eq. prolongation_example_3D and the
 //                            error-equation ghosts of the coarse grid
 //
+// A fine level with a single z plane is two-dimensional (levels of a 3-D
+// hierarchy always have an even number of planes): restriction then averages
+// the 4 children of eq. restriction_example_2D, and prolongation takes the
+// z-neighbour plane equal to the parent plane, which turns the trilinear
+// weights into the (9, 3, 3, 1)/16 of eq. prolongation_example_2D
+// (27 + 9 = 36, 9 + 3 = 12, 3 + 1 = 4 sixty-fourths).
+//
 // Both march upward in z.  The residual kernels keep four fine u planes of a
 // 64 x 16 tile (plus a one-cell halo) in an LDS ring and handle one coarse
 // plane (two fine planes) per step; the prolongation keeps three coarse
@@ -194,7 +201,7 @@ __global__ __launch_bounds__(RNT) void k_resid_tile(LevelView<TU> F, const TU* _
         const int gcx = tx * (RBX / 2) + cx, gcy = ty * (RBY / 2) + cy;
         if (gcx < cnx && gcy < cny) {
           const TU v = ((zs[2 * cy][2 * cx] + zs[2 * cy][2 * cx + 1]) +
-                        (zs[2 * cy + 1][2 * cx] + zs[2 * cy + 1][2 * cx + 1])) * (TU)0.125;
+                        (zs[2 * cy + 1][2 * cx] + zs[2 * cy + 1][2 * cx + 1])) * (nz == 1 ? (TU)0.25 : (TU)0.125);
           out[((size_t)K * cny + gcy) * cnx + gcx] = (TR)v;
           s1 += (double)v;
         }
@@ -231,7 +238,8 @@ __global__ __launch_bounds__(PNT) void k_prolong_tile(int fnx, int fny, int fnz,
   __shared__ T cr[3][PCL];
   if (stop != nullptr && *stop) return;
   const int tid = threadIdx.x;
-  const int cnx = fnx / 2, cny = fny / 2, cnz = fnz / 2;
+  const bool flat = fnz == 1;  // two-dimensional: one coarse plane, its own z neighbour
+  const int cnx = fnx / 2, cny = fny / 2, cnz = flat ? 1 : fnz / 2;
   const int bid = xcd_remap(blockIdx.x, nblk);
   const int tx = bid % gx_tiles, ty = (bid / gx_tiles) % gy_tiles, tz = bid / (gx_tiles * gy_tiles);
   const int k0 = tz * kc, k1 = min(k0 + kc, fnz);  // kc is even
@@ -264,7 +272,8 @@ __global__ __launch_bounds__(PNT) void k_prolong_tile(int fnx, int fny, int fnz,
   auto load_c = [&](int K, T (&dst)[PNC]) {
     T zs = (T)1;
     int Kw = K;
-    if (periodic) Kw = (K % cnz + cnz) % cnz;
+    if (flat) Kw = 0;
+    else if (periodic) Kw = (K % cnz + cnz) % cnz;
     else {
       if (K < 0) { Kw = 0; zs = -zs; }
       if (K >= cnz) { Kw = cnz - 1; zs = -zs; }

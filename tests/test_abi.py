@@ -52,6 +52,7 @@ def test_default_options(lib):
 
 @pytest.mark.parametrize("bad", [
     dict(nx=0), dict(hx=0.0), dict(hy=-1.0), dict(hz=float("nan")), dict(bc=7),
+    dict(hz=float("inf")), dict(hx=float("inf"), nz=1), dict(hz=-float("inf"), nz=1),
 ])
 def test_invalid_grid_rejected_without_gpu(lib, bad):
     from paper_2306_05332_amd._lib import c_grid
@@ -117,6 +118,19 @@ def test_level_shapes_follow_the_coarsening_rule(lib):
         assert _lib.level_shapes(shape, 4) == want, shape
     assert _lib.level_shapes((256, 256, 256))[-1] == (4, 4, 4)
     assert len(_lib.level_shapes((256, 256, 256))) == 7
+
+
+def test_level_shapes_two_dimensional(lib):
+    """nz = 1 with hz = inf halves x and y only, like the oracle's 2-D
+    hierarchy; with a finite hz the single plane stops the coarsening."""
+    from oracle import operators as oop
+    from paper_2306_05332_amd import _lib
+    for ny, nx in [(48, 64), (4096, 4096), (80, 96), (6, 10), (768, 1024)]:
+        want = [lv.shape for lv in oop.build_hierarchy(oop.grid2d(nx, ny, 1.0, 1.0, "periodic"), 4)]
+        assert _lib.level_shapes((ny, nx)) == want
+        assert _lib.level_shapes((1, ny, nx), h=(1.0, 1.0)) == want
+        assert _lib.level_shapes((1, ny, nx)) == [(1, ny, nx)]
+    assert _lib.level_shapes((48, 64))[-1] == (1, 6, 8)
 
 
 def test_tuning_table_install_query_erase(lib):

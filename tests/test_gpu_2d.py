@@ -1,0 +1,238 @@
+"""Two-dimensional problems on the GPU (eqs. discrete_laplace_2D,
+restriction_example_2D, prolongation_example_2D) against the oracle and the
+exact discrete solutions.
+
+A 2-D grid is the single layer nz = 1 with hz = inf.  Operators, transfers
+and tau-steps are compared cell by cell (1e-12 relative, float64); V-cycles
+against the oracle's V-cycles (1e-11); solves against the exact solution
+(1e-9) and the oracle's cycle counts.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import exact
+from oracle import gradient as ograd
+from oracle import multigrid as omg
+from oracle import operators as oop
+from oracle import smoothers as osm
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+FOURPI = 4.0 * math.pi
+INF = float("inf")
+
+
+def _lib():
+    import paper_2306_05332_amd as R
+    return R
+
+
+def cu(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def relmax(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def rand_faces2(rng, ny, nx):
+    return (rng.standard_normal((1, ny)), rng.standard_normal((1, ny)), rng.standard_normal((1, nx)),
+            rng.standard_normal((1, nx)), np.zeros((ny, nx)), np.zeros((ny, nx)))
+
+
+# ragged against every tile shape (64 x 16 residual tiles, 64 x 8 prolongation
+# tiles), small and several tiles wide
+SHAPES = [(1, 16, 16), (1, 24, 40), (1, 70, 130), (1, 130, 200)]
+H2 = (0.11, 0.07, INF)
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("bc", ["periodic", "dirichlet"])
+def test_residual_2d(shape, bc):
+    R = _lib()
+    rng = np.random.default_rng(3)
+    _, ny, nx = shape
+    u = rng.standard_normal(shape)
+    f = rng.standard_normal(shape)
+    faces = rand_faces2(rng, ny, nx) if bc == "dirichlet" else None
+    want = f - oop.apply_M(u, H2, bc, faces)
+    r, nrm = R.residual(cu(f), cu(u), H2, bc, faces=R.pack_faces(faces) if faces else None)
+    assert relmax(r.cpu().numpy(), want) < 1e-12
+    assert abs(nrm - np.linalg.norm(want)) <= 1e-12 * np.linalg.norm(want)
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("bc", ["periodic", "dirichlet"])
+def test_transfers_2d(shape, bc):
+    R = _lib()
+    rng = np.random.default_rng(5)
+    fine = rng.standard_normal(shape)
+    c = R.restrict(cu(fine))
+    assert tuple(c.shape) == (1, shape[1] // 2, shape[2] // 2)
+    assert relmax(c.cpu().numpy(), oop.restrict(fine, flat=True)) < 1e-14
+    # (ny, nx) arrays are two-dimensional as well
+    c2 = R.restrict(cu(fine[0]))
+    assert torch.equal(c2, c[0])
+    e = rng.standard_normal((1, shape[1] // 2, shape[2] // 2))
+    u = rng.standard_normal(shape)
+    got = R.prolong_add(cu(e), cu(u), bc)
+    want = u + oop.prolong(e, bc, flat=True)
+    assert relmax(got.cpu().numpy(), want) < 1e-13
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("bc", ["periodic", "dirichlet"])
+@pytest.mark.parametrize("s", [1, 2, 3])
+def test_tau_steps_2d(shape, bc, s):
+    R = _lib()
+    rng = np.random.default_rng(7 + s)
+    _, ny, nx = shape
+    u0 = rng.standard_normal(shape)
+    f = rng.standard_normal(shape) * 50
+    faces = rand_faces2(rng, ny, nx) if bc == "dirichlet" else None
+    g = oop.Grid(nx, ny, 1, *H2, bc)
+    want = omg.rkl_smooth(u0, f, g, s, 0.9, 2, faces)
+    print(f"2-D tau-steps shape={shape} bc={bc} s={s}", flush=True)
+    phi = cu(u0)
+    R.smooth(cu(f), phi, H2, bc, s=s, tau_frac=0.9, n_steps=2, faces=R.pack_faces(faces) if faces else None)
+    assert relmax(phi.cpu().numpy(), want) < 1e-12
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("bc", ["periodic", "dirichlet"])
+def test_gsrb_passes_2d(shape, bc):
+    R = _lib()
+    rng = np.random.default_rng(9)
+    _, ny, nx = shape
+    u0 = rng.standard_normal(shape)
+    f = rng.standard_normal(shape) * 50
+    faces = rand_faces2(rng, ny, nx) if bc == "dirichlet" else None
+    want = u0
+    for _ in range(2):
+        want = osm.gsrb_sweep(want, f, H2, bc, faces, 1.4)
+    phi = cu(u0)
+    R.gsrb_smooth(cu(f), phi, H2, bc, omega=1.4, n_iter=2, faces=R.pack_faces(faces) if faces else None)
+    assert relmax(phi.cpu().numpy(), want) < 1e-12
+
+
+PROBLEMS = [(64, 48, "periodic"), (64, 48, "dirichlet"), (96, 80, "dirichlet"), (256, 256, "periodic"),
+            (256, 128, "dirichlet")]
+
+
+def _p(nx, ny, bc):
+    return W.problem_2d(nx, ny, bc, seed=4)
+
+
+@pytest.mark.parametrize("nx,ny,bc", PROBLEMS[:3])
+@pytest.mark.parametrize("smoother", ["rkl", "gsrb"])
+def test_vcycle_2d_matches_oracle(nx, ny, bc, smoother):
+    R = _lib()
+    p = _p(nx, ny, bc)
+    g = oop.grid2d(nx, ny, p.h[0], p.h[1], bc)
+    f = omg.prepare_source(p.rho, g, omg.Options())
+    lv = oop.build_hierarchy(g)
+    oo = omg.Options(smoother=smoother)
+    rng = np.random.default_rng(1)
+    u0 = rng.standard_normal(p.shape) * 0.01
+    want = omg.vcycle(u0, f, lv, oo, p.faces)
+    want2 = omg.vcycle(want, f, lv, oo, p.faces)
+    faces = R.pack_faces(p.faces) if p.faces else None
+    o = R.Options(smoother=smoother)
+    phi = cu(u0)
+    print(f"2-D V-cycle {nx}x{ny} {bc} {smoother}", flush=True)
+    R.vcycle(cu(f), phi, p.h, bc, faces=faces, opts=o)
+    assert relmax(phi.cpu().numpy(), want) < 1e-11
+    R.vcycle(cu(f), phi, p.h, bc, faces=faces, opts=o)
+    assert relmax(phi.cpu().numpy(), want2) < 1e-11
+
+
+@pytest.mark.parametrize("nx,ny,bc", PROBLEMS)
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_solve_2d_reaches_exact(nx, ny, bc, prec):
+    R = _lib()
+    p = _p(nx, ny, bc)
+    faces = R.pack_faces(p.faces) if p.faces else None
+    print(f"2-D solve {nx}x{ny} {bc} {prec}", flush=True)
+    phi, st = R.solve(cu(p.rho), p.h, bc, faces=faces, opts=R.Options(tol=1e-10, prec=prec))
+    assert st.status == 0 and st.rel_res <= 1e-10
+    us = exact.exact_solution(FOURPI * p.rho, p.h, bc, p.faces)
+    assert relmax(phi.cpu().numpy(), us) < 1e-9
+    if prec == "fp64" and nx * ny <= 96 * 80:
+        g = oop.grid2d(nx, ny, p.h[0], p.h[1], bc)
+        _, ost = omg.solve(p.rho, g, omg.Options(tol=1e-10), faces=p.faces)
+        assert abs(ost.cycles - st.cycles) <= 1
+        np.testing.assert_allclose(st.history[:4], ost.history[:4], rtol=1e-8)
+
+
+def test_solve_2d_plain_arrays_and_four_faces():
+    """(ny, nx) tensors with h = (hx, hy) and four face arrays are the same
+    problem as the (1, ny, nx) layer."""
+    R = _lib()
+    p = W.uniform_disc(64, 48)
+    f4 = [a[0] for a in p.faces[:4]]
+    phi2, st2 = R.solve(cu(p.rho[0]), p.h[:2], "dirichlet", faces=R.pack_faces(f4), opts=R.Options(tol=1e-10))
+    phi3, st3 = R.solve(cu(p.rho), p.h, "dirichlet", faces=R.pack_faces(p.faces), opts=R.Options(tol=1e-10))
+    assert tuple(phi2.shape) == (48, 64)
+    assert st2.history == st3.history and torch.equal(phi2, phi3[0])
+
+
+def test_large_2d_periodic_solve():
+    """4096^2 (the cell count of a 256^3 box) reaches u* of the FFT solver."""
+    R = _lib()
+    p = W.gaussian_blobs_2d(4096, 4096, nblobs=32, seed=6)
+    us = exact.exact_solution(FOURPI * p.rho, p.h, "periodic")
+    for prec in ("fp64", "mixed"):
+        print(f"2-D 4096^2 {prec}", flush=True)
+        phi, st = R.solve(cu(p.rho), p.h, "periodic", opts=R.Options(tol=1e-10, prec=prec))
+        assert st.status == 0 and st.rel_res <= 1e-10 and st.cycles <= 14
+        assert relmax(phi.cpu().numpy(), us) < 1e-9
+
+
+def test_smooth_disc_second_order():
+    """The smooth compact 2-D density against its continuous potential:
+    second-order convergence of the GPU solutions (ratio 4 per halving)."""
+    R = _lib()
+    errs = []
+    for n in (128, 256, 512, 1024):
+        p = W.smooth_disc(n)
+        phi, st = R.solve(cu(p.rho), p.h, "dirichlet", faces=R.pack_faces(p.faces), opts=R.Options(tol=1e-11))
+        assert st.status == 0
+        errs.append(np.sqrt(np.mean((phi.cpu().numpy() - p.phi_exact) ** 2)))
+    print("2-D smooth disc L2 errors", errs, flush=True)
+    for a, b in zip(errs, errs[1:]):
+        assert 3.6 < a / b < 4.4
+
+
+@pytest.mark.parametrize("bc", ["periodic", "dirichlet"])
+def test_gradient_2d(bc):
+    R = _lib()
+    rng = np.random.default_rng(2)
+    shape = (1, 40, 70)
+    phi = rng.standard_normal(shape)
+    faces = rand_faces2(rng, 40, 70) if bc == "dirichlet" else None
+    want = ograd.acceleration(phi, H2, bc, faces)
+    got = R.gradient(cu(phi), H2, bc, faces=R.pack_faces(faces) if faces else None)
+    for a, b in zip(got[:2], want[:2]):
+        assert relmax(a.cpu().numpy(), b) < 1e-12
+    assert not got[2].any()
+
+
+def test_batched_2d():
+    R = _lib()
+    probs = [W.gaussian_blobs_2d(n, n, nblobs=6, seed=s) for s, n in enumerate((64, 64, 128, 64, 128))]
+    phis, stats = R.solve_batched([cu(p.rho) for p in probs], [p.h for p in probs], "periodic",
+                                  opts=R.Options(tol=1e-10))
+    for p, phi, st in zip(probs, phis, stats):
+        assert st.status == 0
+        us = exact.exact_solution(FOURPI * p.rho, p.h, "periodic")
+        assert relmax(phi.cpu().numpy(), us) < 1e-9
+
+
+def test_2d_invalid_grids():
+    R = _lib()
+    x = torch.zeros((2, 8, 8), dtype=torch.float64, device="cuda")
+    _, st = R.solve(x, (0.1, 0.1, INF), "periodic", raise_on_error=False)
+    assert st.status == R.RKL_EINVAL

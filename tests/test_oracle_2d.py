@@ -245,3 +245,43 @@ def test_2d_multigrid_solve_reaches_exact(bc, smoother):
     assert max(rates[1:]) < 0.2
     us = exact.exact_solution(4 * math.pi * p.rho, p.h, bc, p.faces)
     assert np.abs(u - us).max() / np.abs(us).max() < 1e-8
+
+
+def test_acceleration_2d():
+    """Eq. 4thorder_acceleration in 2-D: exact on a linear field with its face
+    values (Dirichlet), fourth order on a periodic sine, g_z = 0."""
+    from oracle import gradient
+    nx, ny = 12, 10
+    hx, hy = 0.1, 0.2
+    x = (np.arange(nx) + 0.5) * hx
+    y = (np.arange(ny) + 0.5) * hy
+    phi = (1.0 + 2.0 * x[None, :] - 3.0 * y[:, None])[None]
+    X1 = nx * hx
+    Y1 = ny * hy
+    faces = ((1.0 - 3.0 * y)[None, :], (1.0 + 2.0 * X1 - 3.0 * y)[None, :],
+             (1.0 + 2.0 * x)[None, :], (1.0 + 2.0 * x - 3.0 * Y1)[None, :], np.zeros((ny, nx)), np.zeros((ny, nx)))
+    gx, gy, gz = gradient.acceleration(phi, (hx, hy, INF), "dirichlet", faces)
+    np.testing.assert_allclose(gx, -2.0, atol=1e-12)
+    np.testing.assert_allclose(gy, 3.0, atol=1e-12)
+    assert gz.shape == phi.shape and not gz.any()
+    errs = []
+    for n in (16, 32):
+        xs = (np.arange(n) + 0.5) / n
+        ph = (np.sin(2 * math.pi * xs)[None, :] * np.cos(2 * math.pi * xs)[:, None])[None]
+        gx, gy, gz = gradient.acceleration(ph, (1 / n, 1 / n, INF), "periodic")
+        want = -2 * math.pi * np.cos(2 * math.pi * xs)[None, :] * np.cos(2 * math.pi * xs)[:, None]
+        errs.append(np.abs(gx[0] - want).max())
+        assert not gz.any()
+    assert 14.0 < errs[0] / errs[1] < 18.0
+
+
+def test_smooth_disc_workload_second_order():
+    """The smooth 2-D density's closed-form potential solves the continuous
+    problem: the exact discrete solutions approach it at second order."""
+    errs = []
+    for n in (32, 64, 128):
+        p = W.smooth_disc(n)
+        us = exact.exact_solution(4 * math.pi * p.rho, p.h, "dirichlet", p.faces)
+        errs.append(np.sqrt(np.mean((us - p.phi_exact) ** 2)))
+    for a, b in zip(errs, errs[1:]):
+        assert 3.6 < a / b < 4.4

@@ -175,6 +175,29 @@ def uniform_disc(nx=64, ny=None, radius=0.3, rho0=1.0, box=(-1.0, 1.0)):
                    phi_exact=pot(r)[None], name=f"uniform_disc_{nx}x{ny}")
 
 
+def _smooth_disc_phi(r, rho0, r0):
+    # (1/r)(r phi')' = 4 pi rho with rho = rho0 (1 - r^2/r0^2)^2 inside r0:
+    # r phi' = 4 pi rho0 (r^2/2 - r^4/(2 r0^2) + r^6/(6 r0^4)); mass pi rho0 r0^2 / 3
+    inside = 4.0 * math.pi * rho0 * (r * r / 4.0 - r**4 / (8.0 * r0 * r0) + r**6 / (36.0 * r0**4))
+    with np.errstate(divide="ignore"):
+        outside = (2.0 / 3.0) * math.pi * rho0 * r0 * r0 * np.log(r / r0) + 11.0 * math.pi * rho0 * r0 * r0 / 18.0
+    return np.where(r <= r0, inside, outside)
+
+
+def smooth_disc(n, rho0=1.0, r0=0.25):
+    """Two-dimensional analogue of the accuracy model: rho = rho0 (1 -
+    r^2/r0^2)^2 inside r0 on [-0.5, 0.5]^2 (nz = 1, hz = inf), Dirichlet data
+    from the continuous potential (G = 1), which is returned as phi_exact."""
+    h = 1.0 / n
+    xs = -0.5 + (np.arange(n) + 0.5) * h
+    r = np.sqrt(xs[None, :] ** 2 + xs[:, None] ** 2)
+    rho = np.where(r <= r0, rho0 * (1.0 - r * r / (r0 * r0)) ** 2, 0.0)[None]
+    edge = lambda a, b: _smooth_disc_phi(np.hypot(a, b), rho0, r0)[None, :]
+    faces = (edge(-0.5, xs), edge(0.5, xs), edge(xs, -0.5), edge(xs, 0.5), np.zeros((n, n)), np.zeros((n, n)))
+    return Problem(rho=rho, h=(h, h, float("inf")), lo=(-0.5, -0.5, 0.0), bc="dirichlet", faces=faces,
+                   phi_exact=_smooth_disc_phi(r, rho0, r0)[None], name=f"smooth_disc_{n}")
+
+
 def gaussian_blobs_2d(nx, ny=None, nblobs=8, rng=None, seed=None, sigma_range=(0.02, 0.08)):
     """Periodic Gaussian blobs on the unit square (nz = 1, hz = inf), the 2-D
     analogue of ``gaussian_blobs``; the mean is subtracted."""
