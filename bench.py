@@ -97,9 +97,12 @@ def kernel_symbol(R, shape, s, prec="fp64"):
             "ring64x4": f"rkl::k_fused_tau<{tname}, {s}, 64, 4>",
             "zq64x32": f"rkl::k_tau_zq<{tname}, {s}, 64, 32, 512, 1, 0>",
             "zq64x16": f"rkl::k_tau_zq<{tname}, {s}, 64, 16, 256, 1, 0>",
-            "strip8x4": f"rkl::k_tau_strip<{tname}, {s}, 8, 4, true, false, false>",
-            "strip8x1": f"rkl::k_tau_strip<{tname}, {s}, 8, 1, true, false, false>",
-            "strip4x4": f"rkl::k_tau_strip<{tname}, {s}, 4, 4, true, false, false>"}.get(v, f"rkl::k_stage<{tname}>")
+            "strip8x4": f"rkl::k_tau_strip<{tname}, {s}, 8, 4, true, false, false, false>",
+            "strip8x1": f"rkl::k_tau_strip<{tname}, {s}, 8, 1, true, false, false, false>",
+            "strip4x4": f"rkl::k_tau_strip<{tname}, {s}, 4, 4, true, false, false, false>",
+            "strip2d8": f"rkl::k_tau_strip<{tname}, {s}, 8, 1, true, false, false, true>",
+            "strip2d4": f"rkl::k_tau_strip<{tname}, {s}, 4, 1, true, false, false, true>"}.get(
+                v, f"rkl::k_stage<{tname}>")
 
 
 def sweep_inputs(torch, W, dev):

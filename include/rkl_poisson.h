@@ -235,7 +235,12 @@ int rkl_tau_step_launches(const rkl_grid *grid, int s, int prec);
  *           5  strip, 4 wavefronts of 64 columns x 8 rows per workgroup
  *           6  strip, 1 wavefront of 64 columns x 8 rows per workgroup
  *           7  strip, 4 wavefronts of 64 columns x 4 rows per workgroup
- *              (strip: s <= 2 in float64, s <= 3 in float32)
+ *           8  2-D strip, 1 wavefront per workgroup, 8 segments of 64 columns
+ *              per lane, marching in y
+ *           9  2-D strip, as 8 with 4 segments per lane
+ *              (strip: s <= 2 in float64, s <= 3 in float32; variants 8 and 9
+ *              are for two-dimensional levels, nz = 1 with hz = inf, and
+ *              those levels take no other variant)
  * Entries are keyed by (nx, ny, nz, bc, prec, s) of one multigrid LEVEL
  * (prec RKL_FP64: float64 sweeps; RKL_MIXED: the float32 sweeps of the
  * mixed path) and take effect at the next solve.  The table is per process.
@@ -250,8 +255,9 @@ typedef struct {
     double us;           /* rkl_autotune: mean launch time in microseconds   */
 } rkl_tune_entry;
 
-/* Install n entries (host array).  RKL_EINVAL for a malformed entry or a
- * variant not built for that (s, prec); then nothing is installed. */
+/* Install n entries (host array).  RKL_EINVAL for a malformed entry, a
+ * variant not built for that (s, prec), or a 2-D variant on an entry with
+ * nz != 1 (or a 3-D one with nz = 1); then nothing is installed. */
 rkl_status rkl_tune_set(const rkl_tune_entry *entries, int n);
 /* Drop every tile entry and every stage-count entry. */
 rkl_status rkl_tune_clear(void);

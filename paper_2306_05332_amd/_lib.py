@@ -69,7 +69,7 @@ EXPORTS = ("rkl_default_opts", "rkl_poisson_solve", "mg_vcycle", "rkl_smooth", "
 SMOOTHERS = {"rkl": 0, "gsrb": 1}
 RELAX = {"rkl": 0, "gsrb": 1, "sor": 2}
 VARIANTS = {0: "heuristic", 1: "ring64x8", 2: "ring64x4", 3: "zq64x32", 4: "zq64x16", 5: "strip8x4",
-            6: "strip8x1", 7: "strip4x4"}
+            6: "strip8x1", 7: "strip4x4", 8: "strip2d8", 9: "strip2d4"}
 
 _lib = None
 
@@ -404,17 +404,18 @@ def gradient(phi, h, bc="periodic", faces=None):
     return gx, gy, gz
 
 
-def tau_step_launches(shape, s, bc="periodic", prec="fp64"):
-    """Kernel launches per finest-level tau-step (1 = fused single pass)."""
+def tau_step_launches(shape, s, bc="periodic", prec="fp64", h=1.0):
+    """Kernel launches per finest-level tau-step (1 = fused single pass).  A
+    (ny, nx) shape, or h = (hx, hy) / hz = inf, is a two-dimensional level."""
     lib = load_library()
-    g = _grid(shape, 1.0, bc)
+    g = _grid(shape, h, bc)
     r = lib.rkl_tau_step_launches(ctypes.byref(g), int(s), PREC[prec])
     if r < 0:
         _check(r)
     return r
 
 
-def kernel_info(shape, s, bc="periodic", prec="fp64"):
+def kernel_info(shape, s, bc="periodic", prec="fp64", h=1.0):
     """Algorithmic HBM bytes of the finest-level sweep kernel, per launch.
 
     Fused tau-step: u and b read once, Y_s written once: 3 words per cell.
@@ -422,17 +423,17 @@ def kernel_info(shape, s, bc="periodic", prec="fp64"):
     stages j >= 2 move 4 (Y_{j-1}, Y_{j-2}, b in; Y_j out); the per-launch
     figure is their mean over the s launches of one tau-step.
     """
-    nz, ny, nx = shape
-    cells = nx * ny * nz
+    cells = math.prod(shape)
     word = 8 if prec == "fp64" else 4
-    launches = tau_step_launches(shape, s, bc, prec)
+    launches = tau_step_launches(shape, s, bc, prec, h)
     tname = "double" if prec == "fp64" else "float"
     if launches == 1:
         words = 3.0
-        v = tune_get(shape, s, bc, prec)
+        v = tune_get(shape, s, bc, prec, h)
         name = {"zq64x32": f"k_tau_zq<{tname}, {s}, 64, 32>", "zq64x16": f"k_tau_zq<{tname}, {s}, 64, 16>",
                 "ring64x4": f"k_fused_tau<{tname}, {s}, 64, 4>", "strip8x4": f"k_tau_strip<{tname}, {s}, 8, 4>",
                 "strip8x1": f"k_tau_strip<{tname}, {s}, 8, 1>", "strip4x4": f"k_tau_strip<{tname}, {s}, 4, 4>",
+                "strip2d8": f"k_tau_strip<{tname}, {s}, 8, 1>", "strip2d4": f"k_tau_strip<{tname}, {s}, 4, 1>",
                 }.get(v["variant"], f"k_fused_tau<{tname}, {s}, 64, 8>")
     else:
         words = (3.0 + 4.0 * (s - 1)) / s
@@ -470,11 +471,12 @@ def tune_clear():
     _check(load_library().rkl_tune_clear())
 
 
-def tune_get(shape, s, bc="periodic", prec="fp64"):
-    """The tile choice in effect for a level of shape (nz, ny, nx)."""
+def tune_get(shape, s, bc="periodic", prec="fp64", h=1.0):
+    """The tile choice in effect for a level of shape (nz, ny, nx) (or a 2-D
+    (ny, nx) level; h = (hx, hy) marks a (1, ny, nx) shape as 2-D too)."""
     lib = load_library()
     out = c_tune()
-    _check(lib.rkl_tune_get(ctypes.byref(_grid(shape, 1.0, bc)), int(s), PREC[prec], ctypes.byref(out)))
+    _check(lib.rkl_tune_get(ctypes.byref(_grid(shape, h, bc)), int(s), PREC[prec], ctypes.byref(out)))
     return _entry_dict(out)
 
 

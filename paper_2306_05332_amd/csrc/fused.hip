@@ -493,8 +493,16 @@ constexpr int fused_max_s() {
   return sizeof(T) == 8 ? 3 : 4;
 }
 
+template <typename T, int S>
+constexpr bool strip_instantiated() {
+  return sizeof(T) == 8 ? S <= 2 : S <= 3;
+}
+
+// 2-D levels: the FLAT strip kernel only (face data folded beforehand)
 template <typename T>
 bool fused_tau_supported(const LevelView<T>& L, int s) {
+  if (level_is_2d(L))
+    return s >= 1 && s <= (sizeof(T) == 8 ? 2 : 3) && L.nx >= 16 && L.ny >= 8 && L.faces == nullptr;
   return s >= 1 && s <= fused_max_s<T>() && L.nx >= 16 && L.ny >= 8 && L.nz >= 8;
 }
 
@@ -509,14 +517,16 @@ bool fused_variant_ok(int variant, int s) {
     case FV_ZQ_64x16: return s == 2 || s == 3;
     case FV_STRIP_8x4:
     case FV_STRIP_8x1:
-    case FV_STRIP_4x4: return dbl ? s <= 2 : s <= 3;
+    case FV_STRIP_4x4:
+    case FV_STRIP2D_8:
+    case FV_STRIP2D_4: return dbl ? s <= 2 : s <= 3;
     default: return false;
   }
 }
 
-template <typename T, int S>
-constexpr bool strip_instantiated() {
-  return sizeof(T) == 8 ? S <= 2 : S <= 3;
+template <typename T>
+static bool variant_fits(const LevelView<T>& L, int variant) {
+  return variant_is_2d(variant) == level_is_2d(L);
 }
 
 static bool is_strip(int variant) {
@@ -601,6 +611,7 @@ int tune_generation() {
 // z-queue kernel on large levels and the LDS-ring kernel on small ones.
 template <typename T>
 FusedChoice fused_heuristic(const LevelView<T>& L, int s) {
+  if (level_is_2d(L)) return FusedChoice{FV_STRIP2D_8, 1024};
   if (fused_variant_ok<T>(FV_STRIP_4x4, s)) {
     const bool big = (size_t)L.nx * L.ny * L.nz >= ((size_t)192 * 192 * 192);
     if (sizeof(T) == 8 && L.periodic && big) return FusedChoice{FV_STRIP_8x4, 1024};
@@ -615,7 +626,8 @@ FusedChoice fused_choice(const LevelView<T>& L, int s) {
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find(TuneKey{L.nx, L.ny, L.nz, L.periodic ? 1 : 0, sizeof(T) == 8 ? 1 : 0, s});
-    if (it != g_tune.end() && fused_variant_ok<T>(it->second.variant, s)) return it->second;
+    if (it != g_tune.end() && fused_variant_ok<T>(it->second.variant, s) && variant_fits(L, it->second.variant))
+      return it->second;
   }
   return fused_heuristic<T>(L, s);
 }
@@ -635,6 +647,13 @@ template <typename T, int S>
 void launch_fused_S(const LevelView<T>& L, FusedChoice c, const T* u, const T* b, T* out, const StageCoef* co,
                     double* part, const int* stop, const Batch& bt, hipStream_t st) {
   const FCoef<T, S> fc = make_fcoef<T, S>(co);
+  if (variant_is_2d(c.variant)) {
+    if constexpr (strip_instantiated<T, S>()) {
+      if (c.variant == FV_STRIP2D_4) return launch_strip2d<T, S, 4, 1>(L, c.target, u, b, out, fc, part, stop, bt, st);
+      return launch_strip2d<T, S, 8, 1>(L, c.target, u, b, out, fc, part, stop, bt, st);
+    }
+    return;  // not reached: fused_tau_supported bounds s on 2-D levels
+  }
   if (is_strip(c.variant) && L.faces != nullptr) c = FusedChoice{FV_RING_64x8, 1024};  // strips take no face data
   if (is_strip(c.variant)) {
     if constexpr (strip_instantiated<T, S>()) {
@@ -669,6 +688,8 @@ void launch_fused_S(const LevelView<T>& L, FusedChoice c, const T* u, const T* b
 
 template <typename T>
 size_t fused_tau_blocks_as(const LevelView<T>& L, FusedChoice c, int s) {
+  if (variant_is_2d(c.variant))
+    return (size_t)strip_grid(s, c.variant == FV_STRIP2D_4 ? 4 : 8, 1, L.nx, 1, L.ny, c.target, true).nblk;
   if (is_strip(c.variant) && L.faces != nullptr) c = FusedChoice{FV_RING_64x8, 1024};
   if (is_strip(c.variant)) {
     int R, WY;
@@ -688,7 +709,9 @@ size_t fused_tau_blocks(const LevelView<T>& L, int s) {
 template <typename T>
 bool launch_fused_tau_as(const LevelView<T>& L, FusedChoice c, const T* u, const T* b, T* out, int s,
                          const StageCoef* co, double* part, const int* stop, hipStream_t st, const Batch& bt) {
-  if (!fused_tau_supported<T>(L, s) || !fused_variant_ok<T>(c.variant, s) || c.target < 1) return false;
+  if (!fused_tau_supported<T>(L, s) || !fused_variant_ok<T>(c.variant, s) || !variant_fits(L, c.variant) ||
+      c.target < 1)
+    return false;
   switch (s) {
     case 1: launch_fused_S<T, 1>(L, c, u, b, out, co, part, stop, bt, st); return true;
     case 2: launch_fused_S<T, 2>(L, c, u, b, out, co, part, stop, bt, st); return true;
@@ -716,16 +739,23 @@ bool launch_gsrb_fused(const LevelView<T>& L, const T* u, const T* b, T* out, do
   const double d = 2.0 * ((double)L.ihx2 + (double)L.ihy2 + (double)L.ihz2);
   const FusedChoice c = fused_choice<T>(L, 2);
   // the tile shape tuned for RKL s = 2 suits the two-stage pass; other families use 4-row strips
-  if (c.variant == FV_STRIP_8x4)
-    launch_strip_gsrb<T, 8, 4>(L, c.target, u, b, out, omega / d, part, stop, bt, st);
+  if (c.variant == FV_STRIP2D_4)
+    launch_strip_gsrb<T, 4, 1, true>(L, c.target, u, b, out, omega / d, part, stop, bt, st);
+  else if (c.variant == FV_STRIP2D_8)
+    launch_strip_gsrb<T, 8, 1, true>(L, c.target, u, b, out, omega / d, part, stop, bt, st);
+  else if (c.variant == FV_STRIP_8x4)
+    launch_strip_gsrb<T, 8, 4, false>(L, c.target, u, b, out, omega / d, part, stop, bt, st);
   else
-    launch_strip_gsrb<T, 4, 4>(L, is_strip(c.variant) ? c.target : 1024, u, b, out, omega / d, part, stop, bt, st);
+    launch_strip_gsrb<T, 4, 4, false>(L, is_strip(c.variant) ? c.target : 1024, u, b, out, omega / d, part, stop,
+                                      bt, st);
   return true;
 }
 
 template <typename T>
 size_t gsrb_blocks(const LevelView<T>& L) {
   const FusedChoice c = fused_choice<T>(L, 2);
+  if (variant_is_2d(c.variant))
+    return (size_t)strip_grid(2, c.variant == FV_STRIP2D_4 ? 4 : 8, 1, L.nx, 1, L.ny, c.target, true).nblk;
   if (c.variant == FV_STRIP_8x4) return (size_t)strip_grid(2, 8, 4, L.nx, L.ny, L.nz, c.target).nblk;
   return (size_t)strip_grid(2, 4, 4, L.nx, L.ny, L.nz, is_strip(c.variant) ? c.target : 1024).nblk;
 }
@@ -739,6 +769,8 @@ const char* fused_variant_name(int variant) {
     case FV_STRIP_8x4: return "strip8x4";
     case FV_STRIP_8x1: return "strip8x1";
     case FV_STRIP_4x4: return "strip4x4";
+    case FV_STRIP2D_8: return "strip2d8";
+    case FV_STRIP2D_4: return "strip2d4";
     default: return "heuristic";
   }
 }

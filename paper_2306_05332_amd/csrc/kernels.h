@@ -102,8 +102,15 @@ enum : int {
   FV_STRIP_8x4 = 5,   // strip kernel: R = 8 rows per lane, 4 wavefronts per workgroup
   FV_STRIP_8x1 = 6,   // R = 8, one wavefront per workgroup
   FV_STRIP_4x4 = 7,   // R = 4, 4 wavefronts per workgroup
-  FV_COUNT = 8
+  FV_STRIP2D_8 = 8,   // two-dimensional levels only: 8 x segments per lane, one wavefront per workgroup
+  FV_STRIP2D_4 = 9,   // two-dimensional levels only: 4 x segments per lane
+  FV_COUNT = 10
 };
+// A two-dimensional level (nz = 1, ihz2 = 0) takes the FV_STRIP2D_* variants
+// and no others; a 3-D level takes every variant but those.
+inline bool variant_is_2d(int variant) { return variant == FV_STRIP2D_8 || variant == FV_STRIP2D_4; }
+template <typename T>
+inline bool level_is_2d(const LevelView<T>& L) { return L.nz == 1 && L.ihz2 == (T)0; }
 struct FusedChoice {
   int variant;
   int target;
@@ -122,14 +129,19 @@ size_t fused_tau_blocks_max(int nx, int ny, int nz);  // over every variant and 
 
 // Strip form of the fused tau-step (strip.hip): one wavefront per 64-column x
 // strip of R = 8 or 4 rows, 4 or 1 wavefronts per workgroup stacked in y.
+// The 2-D form marches y with R x segments per lane (flat = true: nx, ny, nz
+// describe the transposed view, ny = 1 and nz = the 2-D row count).
 struct StripGrid {
   int ox, gx, gy, zc, gz, nblk;
 };
-StripGrid strip_grid(int s, int R, int WY, int nx, int ny, int nz, int target);
+StripGrid strip_grid(int s, int R, int WY, int nx, int ny, int nz, int target, bool flat = false);
 template <typename T, int S, int R, int WY>
 void launch_strip(const LevelView<T>& L, int target, const T* u, const T* b, T* out, const FCoef<T, S>& fc,
                   double* part, const int* stop, const Batch& bt, hipStream_t st);
-template <typename T, int R, int WY>
+template <typename T, int S, int R, int WY>
+void launch_strip2d(const LevelView<T>& L, int target, const T* u, const T* b, T* out, const FCoef<T, S>& fc,
+                    double* part, const int* stop, const Batch& bt, hipStream_t st);
+template <typename T, int R, int WY, bool FLAT>
 void launch_strip_gsrb(const LevelView<T>& L, int target, const T* u, const T* b, T* out, double omega_over_d,
                        double* part, const int* stop, const Batch& bt, hipStream_t st);
 

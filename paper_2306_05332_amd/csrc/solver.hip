@@ -1344,7 +1344,8 @@ int autotune_level(const rkl_grid& g, int s, int prec, int reps, rkl_tune_entry*
   const LevelView<T> V = view<T>(Lv, per, nullptr);
   if (!fused_tau_supported<T>(V, s))
     fail(RKL_EINVAL, "no fused tau-step for this shape and s (needs nx >= 16, ny >= 8, nz >= 8, s <= " +
-                         std::to_string(sizeof(T) == 8 ? 3 : 4) + ")");
+                         std::to_string(sizeof(T) == 8 ? 3 : 4) + "; two-dimensional: nz = 1, s <= " +
+                         std::to_string(sizeof(T) == 8 ? 2 : 3) + ")");
   DevScratch mem;
   T* u = (T*)mem.get(Lv.n * sizeof(T));
   T* o = (T*)mem.get(Lv.n * sizeof(T));
@@ -1357,7 +1358,7 @@ int autotune_level(const rkl_grid& g, int s, int prec, int reps, rkl_tune_entry*
   std::vector<rkl_tune_entry> all;
   const int targets[] = {128, 256, 512, 1024, 2048};
   for (int v = 1; v < FV_COUNT; ++v) {
-    if (!fused_variant_ok<T>(v, s)) continue;
+    if (!fused_variant_ok<T>(v, s) || variant_is_2d(v) != level_is_2d(V)) continue;
     for (int tg : targets) {
       const FusedChoice c{v, tg};
       for (int w = 0; w < 2; ++w) {
@@ -1626,6 +1627,8 @@ rkl_status rkl_tune_set(const rkl_tune_entry* entries, int n) {
         fail(RKL_EINVAL, "malformed tuning entry " + std::to_string(q));
       const bool ok = e.prec == RKL_FP64 ? fused_variant_ok<double>(e.variant, e.s) : fused_variant_ok<float>(e.variant, e.s);
       if (e.variant != FV_HEUR && !ok) fail(RKL_EINVAL, "variant not available for this s and precision in entry " + std::to_string(q));
+      if (e.variant != FV_HEUR && variant_is_2d(e.variant) != (e.nz == 1))
+        fail(RKL_EINVAL, "entry " + std::to_string(q) + ": strip2d variants are for two-dimensional levels (nz = 1) only");
     }
     for (int q = 0; q < n; ++q) {
       const rkl_tune_entry& e = entries[q];

@@ -33,6 +33,15 @@
 // operator's own diagonal: 2 sum h^-2, plus h_d^-2 for each Dirichlet face
 // the cell touches (the ghost's -u term), so that omega = 1 solves each
 // cell's row exactly.
+//
+// FLAT = true is the two-dimensional form (eq. discrete_laplace_2D).  The
+// launcher hands the kernel a transposed view: the 2-D y axis becomes the
+// marching axis (nz' = ny, ihz2' = ihy2) and the view has one row (ny' = 1,
+// ihy2' = 0).  A lane's R "rows" are then R separate 64-column x segments of
+// the same grid row, side by side (segment i starts OX columns after
+// segment i - 1), so a wavefront still loads R values of u and of b per
+// plane; there are no y-halo rows, and each segment keeps its own column,
+// boundary flags and colour parity.
 #include "kernels.h"
 
 namespace rkl {
@@ -52,7 +61,7 @@ __device__ __forceinline__ double wshift(double v) {
   return __hiloint2double(hi, lo);
 }
 
-template <typename T, int S, int R, int WY, bool PER, bool UZ, bool GS>
+template <typename T, int S, int R, int WY, bool PER, bool UZ, bool GS, bool FLAT>
 __global__ __launch_bounds__(64 * WY) void k_tau_strip(LevelView<T> L, const T* __restrict__ u,
                                                        const T* __restrict__ b, T* __restrict__ out,
                                                        FCoef<T, S> co, int zc, int gx_tiles, int gy_tiles,
@@ -66,9 +75,11 @@ __global__ __launch_bounds__(64 * WY) void k_tau_strip(LevelView<T> L, const T* 
     if (part != nullptr) part += mb * bt.part_stride;
     if (stop != nullptr) stop += mb * bt.stop_stride;
   }
-  constexpr int NU = R + 2 * S;   // rows held per lane
-  constexpr int OX = 64 - 2 * S;  // output columns per wavefront
+  constexpr int HY = FLAT ? 0 : S;  // halo rows on either side of the R output rows
+  constexpr int NU = R + 2 * HY;    // rows held per lane
+  constexpr int OX = 64 - 2 * S;    // output columns per wavefront (per segment when FLAT)
   constexpr int NY = S > 1 ? S - 1 : 1;
+  constexpr int A1 = FLAT ? 0 : 1;  // first row of stage 1 (stage j starts at row A1 * j)
   __shared__ double red[WY];
   if (stop != nullptr && *stop) return;
 
@@ -81,28 +92,47 @@ __global__ __launch_bounds__(64 * WY) void k_tau_strip(LevelView<T> L, const T* 
   const int tx = bid % gx_tiles;
   const int ty = (bid / gx_tiles) % gy_tiles;
   const int tz = bid / (gx_tiles * gy_tiles);
-  const int gxu = tx * OX - S + lane;        // column of this lane (unwrapped)
-  const int y0 = (ty * WY + w) * R - S;      // row of strip index 0 (unwrapped, wave-uniform)
+  const int gxu = tx * OX - S + lane;        // column of this lane (unwrapped; 3-D form)
+  const int y0 = FLAT ? 0 : (ty * WY + w) * R - S;  // row of strip index 0 (unwrapped, wave-uniform)
   const int z0 = tz * zc, z1 = min(z0 + zc, nz);
   const bool xin = gxu >= 0 && gxu < nx;
   const int gx = PER ? ((gxu % nx) + nx) % nx : min(max(gxu, 0), nx - 1);
   const unsigned xb = (unsigned)gx * (unsigned)sizeof(T);  // byte offset of this lane's column
   const bool xown = lane >= S && lane < 64 - S && xin;
   const bool xlo = !PER && gxu == 0, xhi = !PER && gxu == nx - 1;
+  // FLAT: per-segment column byte offsets and bit masks (bit i: segment i)
+  unsigned sxb[FLAT ? R : 1];
+  unsigned sown = 0, slo = 0, shi = 0, sodd = 0;
+  if constexpr (FLAT) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int cu = ((tx * WY + w) * R + i) * OX - S + lane;
+      const int c = PER ? ((cu % nx) + nx) % nx : min(max(cu, 0), nx - 1);
+      sxb[i] = (unsigned)c * (unsigned)sizeof(T);
+      if (lane >= S && lane < 64 - S && cu >= 0 && cu < nx) sown |= 1u << i;
+      if (!PER && cu == 0) slo |= 1u << i;
+      if (!PER && cu == nx - 1) shi |= 1u << i;
+      if (c & 1) sodd |= 1u << i;
+    }
+  }
+  auto colb = [&](int i) -> unsigned { if constexpr (FLAT) return sxb[i]; else return xb; };
+  auto own = [&](int i) -> bool { if constexpr (FLAT) return (sown >> i) & 1u; else return xown; };
+  auto atlo = [&](int i) -> bool { if constexpr (FLAT) return (slo >> i) & 1u; else return xlo; };
+  auto athi = [&](int i) -> bool { if constexpr (FLAT) return (shi >> i) & 1u; else return xhi; };
+  auto xpar = [&](int i) -> int { if constexpr (FLAT) return (sodd >> i) & 1u; else return gx & 1; };
 
   long long yoff[NU];    // row offsets in elements (wrapped or clamped), wave-uniform
   unsigned rin = 0;      // bit i: row i lies in the box
   unsigned rodd = 0;     // bit i: row i has an odd index (GS colouring)
 #pragma unroll
   for (int i = 0; i < NU; ++i) {
-    const int gyu = y0 + i;
+    const int gyu = FLAT ? 0 : y0 + i;  // FLAT: every segment lies in the view's single row
     const bool in = gyu >= 0 && gyu < ny;
     const int gy = PER ? ((gyu % ny) + ny) % ny : min(max(gyu, 0), ny - 1);
     yoff[i] = (long long)gy * nx;
     if (in) rin |= 1u << i;
     if (gy & 1) rodd |= 1u << i;
   }
-  const int xodd = gx & 1;
   // parity of plane p's index (wrapped for periodic boxes; |p| stays within a period of the box)
   auto zodd = [&](int p) -> int { return (PER ? (p < 0 ? p + nz : (p >= nz ? p - nz : p)) : p) & 1; };
   // plane p -> element offset of its (wrapped or clamped) plane; advanced by one
@@ -119,7 +149,7 @@ __global__ __launch_bounds__(64 * WY) void k_tau_strip(LevelView<T> L, const T* 
   };
   auto row = [&](const T* __restrict__ a, long long poff, int i) -> T {
     const char* base = (const char*)(a + poff + yoff[i]);
-    return *(const T*)(base + xb);
+    return *(const T*)(base + colb(i));
   };
   auto pin = [&](int p) { return PER || (p >= 0 && p < nz); };
   // GS coefficient of row i, plane p: c * D / D_cell (Dirichlet faces add h_d^-2)
@@ -128,10 +158,10 @@ __global__ __launch_bounds__(64 * WY) void k_tau_strip(LevelView<T> L, const T* 
     if (PER) return c;
     const int gyu = y0 + i;
     T extra = (T)0;
-    if (xlo) extra += L.ihx2;
-    if (xhi) extra += L.ihx2;
-    if (gyu == 0) extra += L.ihy2;
-    if (gyu == ny - 1) extra += L.ihy2;
+    if (atlo(i)) extra += L.ihx2;
+    if (athi(i)) extra += L.ihx2;
+    if (!FLAT && gyu == 0) extra += L.ihy2;
+    if (!FLAT && gyu == ny - 1) extra += L.ihy2;
     if (p == 0) extra += L.ihz2;
     if (p == nz - 1) extra += L.ihz2;
     return extra == (T)0 ? c : c * dgs / (dgs + extra);
@@ -142,17 +172,29 @@ __global__ __launch_bounds__(64 * WY) void k_tau_strip(LevelView<T> L, const T* 
   auto lap = [&](const T(&Zm)[NU], const T(&X)[NU], const T(&Zp)[NU], int i, int p) -> T {
     const T c = X[i];
     T xm = wshift<DPP_WAVE_SHR1>(c), xp = wshift<DPP_WAVE_SHL1>(c);
-    T ym = X[i - 1], yp = X[i + 1], zm = Zm[i], zp = Zp[i];
-    if (!PER) {
-      const int gyu = y0 + i;
-      if (xlo) xm = -c;
-      if (xhi) xp = -c;
-      if (gyu == 0) ym = -c;
-      if (gyu == ny - 1) yp = -c;
-      if (p == 0) zm = -c;
-      if (p == nz - 1) zp = -c;
+    T zm = Zm[i], zp = Zp[i];
+    if constexpr (FLAT) {  // 5-point: x within the segment, 2-D y along the march
+      if (!PER) {
+        if (atlo(i)) xm = -c;
+        if (athi(i)) xp = -c;
+        if (p == 0) zm = -c;
+        if (p == nz - 1) zp = -c;
+      }
+      return ((xm + xp) - (T)2 * c) * L.ihx2 + ((zm + zp) - (T)2 * c) * L.ihz2;
+    } else {
+      T ym = X[i - 1], yp = X[i + 1];
+      if (!PER) {
+        const int gyu = y0 + i;
+        if (xlo) xm = -c;
+        if (xhi) xp = -c;
+        if (gyu == 0) ym = -c;
+        if (gyu == ny - 1) yp = -c;
+        if (p == 0) zm = -c;
+        if (p == nz - 1) zp = -c;
+      }
+      return ((xm + xp) - (T)2 * c) * L.ihx2 + ((ym + yp) - (T)2 * c) * L.ihy2 +
+             ((zm + zp) - (T)2 * c) * L.ihz2;
     }
-    return ((xm + xp) - (T)2 * c) * L.ihx2 + ((ym + yp) - (T)2 * c) * L.ihy2 + ((zm + zp) - (T)2 * c) * L.ihz2;
   };
 
   T U0[NU], U1[NU], U2[NU], UN[NU];  // u at planes zl-1, zl, zl+1; zl+2 in flight
@@ -177,7 +219,7 @@ __global__ __launch_bounds__(64 * WY) void k_tau_strip(LevelView<T> L, const T* 
 #pragma unroll
   for (int i = 0; i < NU; ++i) U2[i] = (UZ || !pin(zs + 1) || !(PER || ((rin >> i) & 1u))) ? (T)0 : row(u, ou, i);
 #pragma unroll
-  for (int i = 1; i < NU - 1; ++i) Bq[0][i] = (!pin(zs) || !(PER || ((rin >> i) & 1u))) ? (T)0 : row(b, ob, i);
+  for (int i = A1; i < NU - A1; ++i) Bq[0][i] = (!pin(zs) || !(PER || ((rin >> i) & 1u))) ? (T)0 : row(b, ob, i);
   double r2 = 0.0;
   T YS[NU];  // Y_S of the iteration's output plane, stored after the queues advance
 
@@ -191,38 +233,38 @@ __global__ __launch_bounds__(64 * WY) void k_tau_strip(LevelView<T> L, const T* 
       for (int i = 0; i < NU; ++i) UN[i] = row(u, ou, i);
     }
 #pragma unroll
-    for (int i = 1; i < NU - 1; ++i) BN[i] = row(b, ob, i);
-    // stage 1 at plane zl, rows 1 .. NU-2
+    for (int i = A1; i < NU - A1; ++i) BN[i] = row(b, ob, i);
+    // stage 1 at plane zl, rows A1 .. NU-1-A1
     {
       const int p = zl;
       const bool on = pin(p) && p >= z0 - (S - 1) && p <= z1 - 1 + (S - 1);
       const bool pown = p >= z0 && p < z1;
       if (on) {
 #pragma unroll
-        for (int i = 1; i < NU - 1; ++i) {
+        for (int i = A1; i < NU - A1; ++i) {
           const T res = lap(U0, U1, U2, i, p) - Bq[0][i];
           T y;
           if (GS) {
             y = U1[i] + gscoef(co.c[0], i, p) * res;
-            if ((xodd ^ ((rodd >> i) & 1) ^ zodd(p)) != 0) y = U1[i];  // black cell: unchanged
+            if ((xpar(i) ^ ((rodd >> i) & 1) ^ zodd(p)) != 0) y = U1[i];  // black cell: unchanged
           } else {
             y = U1[i] + co.c[0] * res;
           }
-          if (part != nullptr && pown && i >= S && i < S + R && xown && ((rin >> i) & 1u))
+          if (part != nullptr && pown && i >= HY && i < HY + R && own(i) && ((rin >> i) & 1u))
             r2 += (double)res * (double)res;
           if constexpr (S == 1) YS[i] = y;
           else Yq[0][2][i] = y;
         }
       }
     }
-    // stages 2 .. S at planes zl - j + 1, rows j .. NU-1-j
+    // stages 2 .. S at planes zl - j + 1, rows A1 j .. NU-1-A1 j
 #pragma unroll
     for (int j = 2; j <= S; ++j) {
       const int p = zl - j + 1;
       const bool on = pin(p) && p >= z0 - (S - j) && p <= z1 - 1 + (S - j);
       if (on) {
 #pragma unroll
-        for (int i = j; i < NU - j; ++i) {
+        for (int i = A1 * j; i < NU - A1 * j; ++i) {
           const T(&Xm)[NU] = Yq[j - 2][0];
           const T(&Xc)[NU] = Yq[j - 2][1];
           const T(&Xp)[NU] = Yq[j - 2][2];
@@ -231,7 +273,7 @@ __global__ __launch_bounds__(64 * WY) void k_tau_strip(LevelView<T> L, const T* 
           T y;
           if (GS) {
             y = Xc[i] + gscoef(co.c[j - 1], i, p) * res;
-            if ((xodd ^ ((rodd >> i) & 1) ^ zodd(p)) == 0) y = Xc[i];  // red cell: unchanged
+            if ((xpar(i) ^ ((rodd >> i) & 1) ^ zodd(p)) == 0) y = Xc[i];  // red cell: unchanged
           } else {
             y = co.mu[j - 1] * Xc[i] + co.nu[j - 1] * y2 + co.c[j - 1] * res;
           }
@@ -264,8 +306,8 @@ __global__ __launch_bounds__(64 * WY) void k_tau_strip(LevelView<T> L, const T* 
       const int p = zl - S + 1;
       if (p >= z0 && p < z1) {
 #pragma unroll
-        for (int i = S; i < S + R; ++i)
-          if (xown && ((rin >> i) & 1u)) *(T*)((char*)(out + oo + yoff[i]) + xb) = YS[i];
+        for (int i = HY; i < HY + R; ++i)
+          if (own(i) && ((rin >> i) & 1u)) *(T*)((char*)(out + oo + yoff[i]) + colb(i)) = YS[i];
       }
     }
     oo = next_plane(oo, zl - S + 2);
@@ -283,11 +325,18 @@ __global__ __launch_bounds__(64 * WY) void k_tau_strip(LevelView<T> L, const T* 
   }
 }
 
-StripGrid strip_grid(int s, int R, int WY, int nx, int ny, int nz, int target) {
+// flat: (nx, ny, nz) is the transposed view of a 2-D level (ny = 1, nz = the
+// 2-D row count); a workgroup then spans WY * R segments of ox columns in x
+StripGrid strip_grid(int s, int R, int WY, int nx, int ny, int nz, int target, bool flat) {
   StripGrid g;
   g.ox = 64 - 2 * s;
-  g.gx = (nx + g.ox - 1) / g.ox;
-  g.gy = (ny + R * WY - 1) / (R * WY);
+  if (flat) {
+    g.gx = (nx + g.ox * R * WY - 1) / (g.ox * R * WY);
+    g.gy = 1;
+  } else {
+    g.gx = (nx + g.ox - 1) / g.ox;
+    g.gy = (ny + R * WY - 1) / (R * WY);
+  }
   const int xy = g.gx * g.gy;
   const int chunks = std::max(1, (target + xy - 1) / xy);
   g.zc = std::max(4, std::min(64, (nz + chunks - 1) / chunks));
@@ -296,37 +345,56 @@ StripGrid strip_grid(int s, int R, int WY, int nx, int ny, int nz, int target) {
   return g;
 }
 
-template <typename T, int S, int R, int WY, bool GS>
-static void launch_strip_k(const LevelView<T>& L, int target, const T* u, const T* b, T* out, const FCoef<T, S>& fc,
+// The view the FLAT kernel marches: the 2-D level (nz = 1, ihz2 = 0) with y
+// moved to the marching axis; the memory layout is unchanged.
+template <typename T>
+static LevelView<T> flat_view(const LevelView<T>& L) {
+  LevelView<T> V = L;
+  V.ny = 1;
+  V.nz = L.ny;
+  V.ihy2 = (T)0;
+  V.ihz2 = L.ihy2;
+  return V;
+}
+
+template <typename T, int S, int R, int WY, bool GS, bool FLAT>
+static void launch_strip_k(const LevelView<T>& L0, int target, const T* u, const T* b, T* out, const FCoef<T, S>& fc,
                            double* part, const int* stop, const Batch& bt, hipStream_t st) {
-  const StripGrid g = strip_grid(S, R, WY, L.nx, L.ny, L.nz, target);
+  const LevelView<T> L = FLAT ? flat_view(L0) : L0;
+  const StripGrid g = strip_grid(S, R, WY, L.nx, L.ny, L.nz, target, FLAT);
   const dim3 grid(g.nblk, bt.nb), block(64 * WY);
   if (L.periodic) {
     if (u == nullptr)
-      hipLaunchKernelGGL((k_tau_strip<T, S, R, WY, true, true, GS>), grid, block, 0, st, L, u, b, out, fc, g.zc,
-                         g.gx, g.gy, g.nblk, part, bt, stop);
+      hipLaunchKernelGGL((k_tau_strip<T, S, R, WY, true, true, GS, FLAT>), grid, block, 0, st, L, u, b, out, fc,
+                         g.zc, g.gx, g.gy, g.nblk, part, bt, stop);
     else
-      hipLaunchKernelGGL((k_tau_strip<T, S, R, WY, true, false, GS>), grid, block, 0, st, L, u, b, out, fc, g.zc,
-                         g.gx, g.gy, g.nblk, part, bt, stop);
+      hipLaunchKernelGGL((k_tau_strip<T, S, R, WY, true, false, GS, FLAT>), grid, block, 0, st, L, u, b, out, fc,
+                         g.zc, g.gx, g.gy, g.nblk, part, bt, stop);
   } else {
     if (u == nullptr)
-      hipLaunchKernelGGL((k_tau_strip<T, S, R, WY, false, true, GS>), grid, block, 0, st, L, u, b, out, fc, g.zc,
-                         g.gx, g.gy, g.nblk, part, bt, stop);
+      hipLaunchKernelGGL((k_tau_strip<T, S, R, WY, false, true, GS, FLAT>), grid, block, 0, st, L, u, b, out, fc,
+                         g.zc, g.gx, g.gy, g.nblk, part, bt, stop);
     else
-      hipLaunchKernelGGL((k_tau_strip<T, S, R, WY, false, false, GS>), grid, block, 0, st, L, u, b, out, fc, g.zc,
-                         g.gx, g.gy, g.nblk, part, bt, stop);
+      hipLaunchKernelGGL((k_tau_strip<T, S, R, WY, false, false, GS, FLAT>), grid, block, 0, st, L, u, b, out, fc,
+                         g.zc, g.gx, g.gy, g.nblk, part, bt, stop);
   }
 }
 
 template <typename T, int S, int R, int WY>
 void launch_strip(const LevelView<T>& L, int target, const T* u, const T* b, T* out, const FCoef<T, S>& fc,
                   double* part, const int* stop, const Batch& bt, hipStream_t st) {
-  launch_strip_k<T, S, R, WY, false>(L, target, u, b, out, fc, part, stop, bt, st);
+  launch_strip_k<T, S, R, WY, false, false>(L, target, u, b, out, fc, part, stop, bt, st);
+}
+
+template <typename T, int S, int R, int WY>
+void launch_strip2d(const LevelView<T>& L, int target, const T* u, const T* b, T* out, const FCoef<T, S>& fc,
+                    double* part, const int* stop, const Batch& bt, hipStream_t st) {
+  launch_strip_k<T, S, R, WY, false, true>(L, target, u, b, out, fc, part, stop, bt, st);
 }
 
 // one red-black GS / SOR iteration in one pass: the two-stage strip kernel
 // with mu = 1, nu = 0, c = omega / D on the cells of each stage's colour
-template <typename T, int R, int WY>
+template <typename T, int R, int WY, bool FLAT>
 void launch_strip_gsrb(const LevelView<T>& L, int target, const T* u, const T* b, T* out, double omega_over_d,
                        double* part, const int* stop, const Batch& bt, hipStream_t st) {
   FCoef<T, 2> fc;
@@ -335,7 +403,7 @@ void launch_strip_gsrb(const LevelView<T>& L, int target, const T* u, const T* b
     fc.nu[j] = (T)0;
     fc.c[j] = (T)omega_over_d;
   }
-  launch_strip_k<T, 2, R, WY, true>(L, target, u, b, out, fc, part, stop, bt, st);
+  launch_strip_k<T, 2, R, WY, true, FLAT>(L, target, u, b, out, fc, part, stop, bt, st);
 }
 
 #define RKL_STRIP_INST(T, S, R, WY)                                                                          \
@@ -357,13 +425,31 @@ RKL_STRIP_INST(float, 1, 4, 4)
 RKL_STRIP_INST(float, 2, 4, 4)
 RKL_STRIP_INST(float, 3, 4, 4)
 #undef RKL_STRIP_INST
-#define RKL_GSRB_INST(T, R, WY)                                                                             \
-  template void launch_strip_gsrb<T, R, WY>(const LevelView<T>&, int, const T*, const T*, T*, double, double*, \
-                                            const int*, const Batch&, hipStream_t);
-RKL_GSRB_INST(double, 8, 4)
-RKL_GSRB_INST(double, 4, 4)
-RKL_GSRB_INST(float, 8, 4)
-RKL_GSRB_INST(float, 4, 4)
+#define RKL_STRIP2D_INST(T, S, R, WY)                                                                          \
+  template void launch_strip2d<T, S, R, WY>(const LevelView<T>&, int, const T*, const T*, T*, const FCoef<T, S>&, \
+                                            double*, const int*, const Batch&, hipStream_t);
+RKL_STRIP2D_INST(double, 1, 8, 1)
+RKL_STRIP2D_INST(double, 2, 8, 1)
+RKL_STRIP2D_INST(double, 1, 4, 1)
+RKL_STRIP2D_INST(double, 2, 4, 1)
+RKL_STRIP2D_INST(float, 1, 8, 1)
+RKL_STRIP2D_INST(float, 2, 8, 1)
+RKL_STRIP2D_INST(float, 3, 8, 1)
+RKL_STRIP2D_INST(float, 1, 4, 1)
+RKL_STRIP2D_INST(float, 2, 4, 1)
+RKL_STRIP2D_INST(float, 3, 4, 1)
+#undef RKL_STRIP2D_INST
+#define RKL_GSRB_INST(T, R, WY, FLAT)                                                                          \
+  template void launch_strip_gsrb<T, R, WY, FLAT>(const LevelView<T>&, int, const T*, const T*, T*, double,     \
+                                                  double*, const int*, const Batch&, hipStream_t);
+RKL_GSRB_INST(double, 8, 4, false)
+RKL_GSRB_INST(double, 4, 4, false)
+RKL_GSRB_INST(float, 8, 4, false)
+RKL_GSRB_INST(float, 4, 4, false)
+RKL_GSRB_INST(double, 8, 1, true)
+RKL_GSRB_INST(double, 4, 1, true)
+RKL_GSRB_INST(float, 8, 1, true)
+RKL_GSRB_INST(float, 4, 1, true)
 #undef RKL_GSRB_INST
 
 }  // namespace rkl

@@ -185,3 +185,28 @@ def test_stored_table_is_valid(lib):
     if not os.path.exists(autotune.DEFAULT_TABLE):
         pytest.skip("no stored tuning table")
     assert autotune.load() > 0
+
+
+def test_strip2d_variants_only_on_two_dimensional_levels(lib):
+    from paper_2306_05332_amd import _lib
+    try:
+        _lib.tune_set([{"nx": 64, "ny": 32, "nz": 1, "bc": "periodic", "prec": "fp64", "s": 2,
+                        "variant": "strip2d4", "target": 256}])
+        got = _lib.tune_get((32, 64), 2, "periodic", "fp64")
+        assert (got["variant"], got["target"]) == ("strip2d4", 256)
+        for bad in ({"nz": 8, "variant": "strip2d8"}, {"nz": 1, "variant": "strip8x4"},
+                    {"nz": 1, "variant": "strip2d8", "s": 3}):
+            e = {"nx": 64, "ny": 32, "bc": "periodic", "prec": "fp64", "s": 2, "target": 256}
+            e.update(bad)
+            with pytest.raises(_lib.RKLError):
+                _lib.tune_set([e])
+        # float32 sweeps take s = 3 on 2-D levels
+        _lib.tune_set([{"nx": 64, "ny": 32, "nz": 1, "bc": "dirichlet", "prec": "mixed", "s": 3,
+                        "variant": "strip2d8", "target": 128}])
+        assert _lib.tune_get((32, 64), 3, "dirichlet", "mixed")["variant"] == "strip2d8"
+        assert _lib.tau_step_launches((32, 64), 2, "periodic") == 1
+        assert _lib.tau_step_launches((32, 64), 3, "periodic") == 3
+        assert _lib.tau_step_launches((1, 32, 64), 2, "periodic") == 2  # finite hz: a 3-D single plane
+    finally:
+        _lib.tune_clear()
+        _lib.install_default_tuning()

@@ -236,3 +236,65 @@ def test_2d_invalid_grids():
     x = torch.zeros((2, 8, 8), dtype=torch.float64, device="cuda")
     _, st = R.solve(x, (0.1, 0.1, INF), "periodic", raise_on_error=False)
     assert st.status == R.RKL_EINVAL
+
+
+# the 2-D strip kernel: one or several waves across x (8 or 4 segments of 60
+# or 62 columns per lane), ragged in x and y, short and long y chunks
+FSHAPES = [(1, 9, 17), (1, 70, 130), (1, 40, 1000), (1, 257, 300)]
+
+
+@pytest.mark.parametrize("variant", ["strip2d8", "strip2d4"])
+@pytest.mark.parametrize("shape", FSHAPES)
+@pytest.mark.parametrize("bc", ["periodic", "dirichlet"])
+@pytest.mark.parametrize("s", [1, 2])
+def test_forced_strip2d_matches_oracle(variant, shape, bc, s):
+    R = _lib()
+    R.load_library()
+    _, ny, nx = shape
+    target = 128 if (nx + ny) % 2 else 2048
+    try:
+        R.tune_set([{"nx": nx, "ny": ny, "nz": 1, "bc": bc, "prec": "fp64", "s": s, "variant": variant,
+                     "target": target}])
+        assert R.tune_get(shape, s, bc, "fp64", h=H2)["variant"] == variant
+        assert R.tau_step_launches(shape, s, bc, "fp64", h=H2) == 1
+        rng = np.random.default_rng(17 + s)
+        u0 = rng.standard_normal(shape)
+        f = rng.standard_normal(shape) * 50
+        faces = rand_faces2(rng, ny, nx) if bc == "dirichlet" else None
+        g = oop.Grid(nx, ny, 1, *H2, bc)
+        want = omg.rkl_smooth(u0, f, g, s, 0.9, 3, faces)
+        print(f"strip2d variant={variant} target={target} shape={shape} bc={bc} s={s}", flush=True)
+        phi = cu(u0)
+        R.smooth(cu(f), phi, H2, bc, s=s, tau_frac=0.9, n_steps=3, faces=R.pack_faces(faces) if faces else None)
+        assert relmax(phi.cpu().numpy(), want) < 1e-12
+        if s == 2:
+            wg = u0
+            for _ in range(2):
+                wg = osm.gsrb_sweep(wg, f, H2, bc, faces, 1.3)
+            phi = cu(u0)
+            R.gsrb_smooth(cu(f), phi, H2, bc, omega=1.3, n_iter=2, faces=R.pack_faces(faces) if faces else None)
+            assert relmax(phi.cpu().numpy(), wg) < 1e-12
+    finally:
+        R.tune_clear()
+        R.install_default_tuning()
+
+
+@pytest.mark.parametrize("variant", ["strip2d8", "strip2d4"])
+@pytest.mark.parametrize("bc", ["periodic", "dirichlet"])
+def test_forced_strip2d_mixed_solve(variant, bc):
+    """The float32 sweeps of the mixed path (s = 3 included) on every 2-D
+    level with the forced variant reach u*."""
+    R = _lib()
+    p = _p(256, 128, bc)
+    try:
+        R.tune_set([{"nx": 256 >> l, "ny": 128 >> l, "nz": 1, "bc": bc, "prec": pr, "s": s, "variant": variant,
+                     "target": 512} for l in range(4) for pr in ("mixed", "fp64") for s in (2, 3)
+                    if not (pr == "fp64" and s == 3)])
+        us = exact.exact_solution(FOURPI * p.rho, p.h, bc, p.faces)
+        faces = R.pack_faces(p.faces) if p.faces else None
+        for prec, s in (("mixed", 3), ("mixed", 2), ("fp64", 2)):
+            phi, st = R.solve(cu(p.rho), p.h, bc, faces=faces, opts=R.Options(tol=1e-10, prec=prec, s=s))
+            assert st.status == 0 and relmax(phi.cpu().numpy(), us) < 1e-9
+    finally:
+        R.tune_clear()
+        R.install_default_tuning()
