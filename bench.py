@@ -401,8 +401,9 @@ def main():
 
 
 def run_extras(R, W, torch, args):
-    """The batched workload (96 periodic grids of 32^3..128^3, mixed, tol 1e-8)
-    and the adjoint workload (8 x 128^3, forward + backward, float64)."""
+    """The batched workload (96 periodic grids of 32^3..128^3, mixed, tol 1e-8),
+    the adjoint workload (8 x 128^3, forward + backward, float64) and the
+    two-dimensional workload (periodic 4096^2)."""
     out = {}
     probs = W.batch_blob_problems(seed=4)
     rhos = [torch.from_numpy(p.rho).cuda() for p in probs]
@@ -449,7 +450,55 @@ def run_extras(R, W, torch, args):
     out["adjoint"] = {"grids": 8, "n": 128, "prec": "fp64", "tol": 1e-10, "forward_ms": (t1 - t0) * 1e3,
                       "backward_ms": (t2 - t1) * 1e3}
     print(f"# adjoint 8x128^3: forward {(t1 - t0) * 1e3:.2f} ms, backward {(t2 - t1) * 1e3:.2f} ms", flush=True)
+    del rho, wt, phi
+
+    out["two_d"] = run_two_d(R, W, torch)
     return out
+
+
+def run_two_d(R, W, torch, n=4096):
+    """Two-dimensional workload: periodic 4096^2 (the cell count of 256^3),
+    32 seeded Gaussian blobs, float64 and mixed solves to 1e-10, and the
+    finest-level 2-D strip tau-step timed with HIP events on the solver's
+    stream (3 words of algorithmic HBM traffic per cell)."""
+    import numpy as np
+    from oracle import exact
+    p = W.gaussian_blobs_2d(n, n, nblobs=32, seed=6)
+    rho = torch.from_numpy(p.rho).cuda()
+    res = {"n": n, "bc": "periodic", "tol": TOL}
+    us = exact.exact_solution(4.0 * math.pi * p.rho, p.h, "periodic")
+    for prec in ("fp64", "mixed"):
+        o = R.Options(tol=TOL, prec=prec)
+        R.solve(rho, p.h, "periodic", opts=o)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = 5
+        for _ in range(reps):
+            phi, st = R.solve(rho, p.h, "periodic", opts=o)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / reps
+        err = float(np.abs(phi.cpu().numpy() - us).max() / np.abs(us).max())
+        res[prec] = {"ms": t * 1e3, "cycles": st.cycles, "rel_res": st.rel_res, "max_rel_err_vs_exact": err}
+        print(f"# 2-D {n}^2 {prec}: {t * 1e3:.3f} ms, cycles={st.cycles}", flush=True)
+    f = rho * (4.0 * math.pi)
+    u = torch.zeros_like(rho)
+    stream = torch.cuda.current_stream()
+    R.smooth(f, u, p.h, "periodic", s=2, n_steps=2)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    R.smooth(f, u, p.h, "periodic", s=2, n_steps=SWEEP_STEPS)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    info = R.kernel_info((n, n), 2)
+    t_launch = ev0.elapsed_time(ev1) * 1e-3 / (SWEEP_STEPS * info["launches_per_tau"])
+    ach = info["bytes_per_launch"] / t_launch / 1e9
+    rows = {"strip2d8": 8, "strip2d4": 4}.get(R.tune_get((n, n), 2)["variant"])
+    res["tau_step"] = {"kernel": f"rkl::k_tau_strip<double, 2, {rows}, 1, true, false, false, true>",
+                       "mean_launch_us": t_launch * 1e6, "bytes_per_launch": info["bytes_per_launch"],
+                       "achieved_GBs": ach, "frac_of_hbm_peak": ach / HBM_PEAK_GBS}
+    print(f"# 2-D tau-step: {t_launch * 1e6:.2f} us, {ach:.0f} GB/s", flush=True)
+    return res
 
 
 if __name__ == "__main__":

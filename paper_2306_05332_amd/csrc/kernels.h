@@ -178,10 +178,10 @@ int tune_generation();
 const char* fused_variant_name(int variant);
 
 // Coarse tail of the V-cycle in one workgroup (tail.hip).
-constexpr int TAIL_MAX_LEVELS = 4;
+constexpr int TAIL_MAX_LEVELS = 6;
 constexpr int TAIL_MAX_S = 8;
 constexpr int TAIL_MAX_CELLS = 4096;          // cells of the top tail level
-constexpr size_t TAIL_MAX_LDS = 120 * 1024;   // dynamic LDS for the tail arrays
+constexpr size_t TAIL_MAX_LDS = 144 * 1024;   // dynamic LDS for the tail arrays (static LDS: ~13 KB)
 struct TailShape {
   int nlev;
   int nx[TAIL_MAX_LEVELS], ny[TAIL_MAX_LEVELS], nz[TAIL_MAX_LEVELS];

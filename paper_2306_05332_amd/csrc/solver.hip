@@ -313,8 +313,7 @@ Plan& get_plan(const rkl_grid& g, int s, double theta, int min_coarse, int prec)
   HIPCHK(hipMemcpy(P->d_sched, P->sched.data(), P->sched.size() * sizeof(int), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(P->d_coff, coff.data(), coff.size() * sizeof(int), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(P->d_coef, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice));
-  // the one-workgroup tail carries the 3-D transfer operators only
-  if (coarse_in_lds(*P, C) && L >= 3 && !P->lv[0].flat) {
+  if (coarse_in_lds(*P, C) && L >= 3) {
     for (int lt = 1; lt < L - 1; ++lt) {
       const TailShape ts = tail_shape(*P, lt);
       if (P->tail64 < 0 && tail_fits<double>(ts, s)) P->tail64 = lt;

@@ -12,7 +12,10 @@
 //   the top level's correction u, written back to HBM.
 // The arithmetic is that of the per-level kernels (stage recurrence of App. A
 // eq. RKL_intermediate_source; ghosts of Sec. 2.3 for the error equation:
-// homogeneous Dirichlet -c or periodic wrap).
+// homogeneous Dirichlet -c or periodic wrap).  Two-dimensional hierarchies
+// (nz = 1 and ihz2 = 0 on every level) restrict with the 4-child average of
+// eq. restriction_example_2D and prolong with the parent plane as its own z
+// neighbour, i.e. the (9, 3, 3, 1)/16 weights of eq. prolongation_example_2D.
 #include <cstring>
 
 #include "kernels.h"
@@ -31,6 +34,7 @@ template <typename T>
 struct TailArgs {
   int nlev, s, n_pre, n_post, periodic, cmax;
   int gs;               // smoother: 0 RKL tau-step, 1 red-black Gauss-Seidel pass
+  int flat;             // 1: two-dimensional levels
   double ctol;
   CoarseSchedule cs;
   TailLevel<T> lv[TAIL_MAX_LEVELS];
@@ -219,11 +223,12 @@ __global__ __launch_bounds__(TNT) void k_tail(TailArgs<T> A, const T* __restrict
     const T* B = bptr(l);
     T* BC = bptr(l + 1);
     const int cn = nof(l + 1);
+    const int ndz = A.flat ? 1 : 2;
+    const T rw = A.flat ? (T)0.25 : (T)0.125;
     for (CellWalk w(tid, TNT, C.nx, C.ny, C.nz); w.ok(); w.next(TNT)) {
       const int I = w.i, J = w.j, K = w.k;
       T acc = (T)0;
-#pragma unroll
-      for (int dz = 0; dz < 2; ++dz)
+      for (int dz = 0; dz < ndz; ++dz)
 #pragma unroll
         for (int dy = 0; dy < 2; ++dy)
 #pragma unroll
@@ -231,7 +236,7 @@ __global__ __launch_bounds__(TNT) void k_tail(TailArgs<T> A, const T* __restrict
             const int f = ((2 * K + dz) * F.ny + (2 * J + dy)) * F.nx + (2 * I + dx);
             acc += B[f] - tail_lap(F, U, f, 2 * I + dx, 2 * J + dy, 2 * K + dz, per);
           }
-      BC[w.q] = acc * (T)0.125;
+      BC[w.q] = acc * rw;
     }
     __syncthreads();
     if (per) remove_b_mean(l + 1);
@@ -387,9 +392,12 @@ __global__ __launch_bounds__(TNT) void k_tail(TailArgs<T> A, const T* __restrict
               if (a >= C.nx) { a = C.nx - 1; sg = -sg; }
               if (bb < 0) { bb = 0; sg = -sg; }
               if (bb >= C.ny) { bb = C.ny - 1; sg = -sg; }
-              if (cidx < 0) { cidx = 0; sg = -sg; }
-              if (cidx >= C.nz) { cidx = C.nz - 1; sg = -sg; }
+              if (!A.flat) {
+                if (cidx < 0) { cidx = 0; sg = -sg; }
+                if (cidx >= C.nz) { cidx = C.nz - 1; sg = -sg; }
+              }
             }
+            if (A.flat) cidx = 0;  // 2-D: the parent plane is its own z neighbour
             const T w = (T)((dz ? 1 : 3) * (dy ? 1 : 3) * (dx ? 1 : 3));
             acc += w * sg * E[(cidx * C.ny + bb) * C.nx + a];
           }
@@ -440,6 +448,7 @@ void launch_tail(const TailShape& ts, const StageCoef* const* smooth, int s, int
   TailArgs<T> A;
   std::memset(&A, 0, sizeof(A));
   A.gs = gs;
+  A.flat = ts.nz[0] == 1 && ts.ihz2[0] == 0.0 ? 1 : 0;
   A.nlev = ts.nlev;
   A.s = s;
   A.n_pre = n_pre;

@@ -90,7 +90,10 @@ __global__ __launch_bounds__(RNT) void k_resid_tile(LevelView<TU> F, const TU* _
     igy[q] = ty * RBY + idx / RBX;
     iin[q] = igx[q] < nx && igy[q] < ny;
   }
-  auto plane_ok = [&](int p) { return per ? true : (p >= 0 && p < nz); };
+  // a two-dimensional level (one plane, ihz2 = 0) reads only its own plane:
+  // the z terms carry no weight
+  const bool flat = nz == 1 && F.ihz2 == (TU)0;
+  auto plane_ok = [&](int p) { return flat ? p == 0 : (per ? true : (p >= 0 && p < nz)); };
   auto zw = [&](int p) { return per ? (p % nz + nz) % nz : p; };
   auto rslot = [](int p) { return (p + 8) & 3; };
 
