@@ -127,6 +127,23 @@ __device__ __forceinline__ double dpp_mov_f64(double v) {
   return __hiloint2double(h2, l2);
 }
 
+// Whole-wavefront shift by one lane (GFX9 DPP wave_shl:1 / wave_shr:1); the
+// end lanes receive 0.
+constexpr int DPP_WAVE_SHL1 = 0x130;  // dst[i] = src[i + 1]
+constexpr int DPP_WAVE_SHR1 = 0x138;  // dst[i] = src[i - 1]
+
+template <int CTRL>
+__device__ __forceinline__ float wshift(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, true));
+}
+
+template <int CTRL>
+__device__ __forceinline__ double wshift(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+
 __device__ __forceinline__ double wave_sum_dpp(double v) {
   v += dpp_mov_f64<0x111, 0xf>(v);  // row_shr:1
   v += dpp_mov_f64<0x112, 0xf>(v);  // row_shr:2

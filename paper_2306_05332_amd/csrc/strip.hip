@@ -46,21 +46,6 @@
 
 namespace rkl {
 
-constexpr int DPP_WAVE_SHL1 = 0x130;  // dst[i] = src[i + 1]
-constexpr int DPP_WAVE_SHR1 = 0x138;  // dst[i] = src[i - 1]
-
-template <int CTRL>
-__device__ __forceinline__ float wshift(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, true));
-}
-
-template <int CTRL>
-__device__ __forceinline__ double wshift(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, true);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, true);
-  return __hiloint2double(hi, lo);
-}
-
 template <typename T, int S, int R, int WY, bool PER, bool UZ, bool GS, bool FLAT>
 __global__ __launch_bounds__(64 * WY) void k_tau_strip(LevelView<T> L, const T* __restrict__ u,
                                                        const T* __restrict__ b, T* __restrict__ out,

@@ -353,6 +353,252 @@ __global__ __launch_bounds__(PNT) void k_prolong_tile(int fnx, int fny, int fnz,
   }
 }
 
+// ---------------------------------------------------------------- single-plane levels
+// A level with one z plane (a two-dimensional level, or a 3-D grid of one
+// plane) takes row-marching kernels instead of the tiles above, whose blocks
+// would each see a single plane pair.  A lane owns one column pair (2I, 2I+1)
+// -- one coarse column I -- and lanes 0 and 63 of a wavefront are halo: their
+// pairs only feed the x neighbours of lanes 1 and 62 through wavefront DPP
+// shifts, so a wavefront covers 62 coarse columns.  Each wavefront marches a
+// chunk of row pairs (2J, 2J+1); the u rows 2J-1 .. 2J+2 stay in registers
+// and the next rows are loaded one step ahead, so every row is read once.
+// The z term of the single plane is the periodic self-neighbour (0) or the
+// Dirichlet ghost pair (2 g - c on both sides; 0 for hz = inf); face data,
+// where given, enters every Dirichlet ghost as 2 g - c.
+constexpr int P2W = 4;    // wavefronts per workgroup, stacked in row chunks
+constexpr int P2OX = 62;  // coarse columns (column pairs) per wavefront
+
+struct Grid2D {
+  int gx, gy, jc, nblk;
+};
+
+// npx column pairs, npy row pairs; chunks sized for ~4096 wavefronts
+static Grid2D grid_2d(int npx, int npy) {
+  Grid2D g;
+  g.gx = (npx + P2OX - 1) / P2OX;
+  const int chunks = std::max(1, (4096 + g.gx - 1) / g.gx);
+  g.jc = std::max(4, (npy + chunks - 1) / chunks);
+  const int nch = (npy + g.jc - 1) / g.jc;
+  g.gy = (nch + P2W - 1) / P2W;
+  g.nblk = g.gx * g.gy;
+  return g;
+}
+
+template <typename TU, typename TR, bool RESTRICT>
+__global__ __launch_bounds__(64 * P2W) void k_resid_2d(LevelView<TU> F, const TU* __restrict__ u,
+                                                       const TU* __restrict__ b, TR* __restrict__ out, int jc,
+                                                       int gx, double* __restrict__ part, Batch bt,
+                                                       const int* __restrict__ stop) {
+  {
+    const long long mb = blockIdx.y;
+    if (u != nullptr) u += mb * bt.s0;
+    b += mb * bt.s0;
+    if (out != nullptr) out += mb * (RESTRICT ? bt.s1 : bt.s0);
+    part += mb * bt.part_stride;
+    if (stop != nullptr) stop += mb * bt.stop_stride;
+  }
+  __shared__ double red[2][P2W];
+  if (stop != nullptr && *stop) return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int nx = F.nx, ny = F.ny;
+  const bool per = F.periodic != 0;
+  const int tx = blockIdx.x % gx, ty = blockIdx.x / gx;
+  const int npy = (ny + 1) / 2;
+  const int J0 = (ty * P2W + w) * jc, J1 = min(J0 + jc, npy);  // wave-uniform
+  const int I = tx * P2OX - 1 + lane;  // coarse column (unwrapped)
+  const int c0u = 2 * I, c1u = 2 * I + 1;
+  auto wrapx = [&](int c) { return per ? ((c % nx) + nx) % nx : min(max(c, 0), nx - 1); };
+  auto wrapy = [&](int r) { return per ? ((r % ny) + ny) % ny : min(max(r, 0), ny - 1); };
+  const int c0 = wrapx(c0u), c1 = wrapx(c1u);
+  const bool own = lane >= 1 && lane <= 62;
+  const bool in0 = own && c0u >= 0 && c0u < nx, in1 = own && c1u >= 0 && c1u < nx;
+  const bool lo0 = !per && c0u == 0, hi0 = !per && c0u == nx - 1, hi1 = !per && c1u == nx - 1;
+  const int cnx = nx / 2;
+
+  auto ldrow = [&](const TU* a, int r, TU& v0, TU& v1) {
+    const size_t ro = (size_t)wrapy(r) * nx;
+    v0 = a[ro + c0];
+    v1 = a[ro + c1];
+  };
+  // b - M u at row r, columns c0 / c1; (m0, m1) row r - 1, (p0, p1) row r + 1
+  auto res = [&](TU m0, TU m1, TU x0, TU x1, TU p0, TU p1, int r, TU bv0, TU bv1, TU& r0, TU& r1) {
+    TU xl = wshift<DPP_WAVE_SHR1>(x1), xr = wshift<DPP_WAVE_SHL1>(x0);  // columns 2I-1 and 2I+2
+    TU xm0 = xl, xp0 = x1, xm1 = x0, xp1 = xr;
+    TU z0 = (TU)0, z1 = (TU)0;  // z terms (periodic: the plane is its own neighbour)
+    if (!per) {
+      const int rc = min(max(r, 0), ny - 1);  // face index row (rows outside the box are not stored)
+      if (lo0) xm0 = dir_ghost(F, 0, (size_t)rc, x0);
+      if (hi0) xp0 = dir_ghost(F, 1, (size_t)rc, x0);
+      if (hi1) xp1 = dir_ghost(F, 1, (size_t)rc, x1);
+      if (r == 0) {
+        m0 = dir_ghost(F, 2, (size_t)c0, x0);
+        m1 = dir_ghost(F, 2, (size_t)c1, x1);
+      }
+      if (r == ny - 1) {
+        p0 = dir_ghost(F, 3, (size_t)c0, x0);
+        p1 = dir_ghost(F, 3, (size_t)c1, x1);
+      }
+      const size_t f0 = (size_t)rc * nx + c0, f1 = (size_t)rc * nx + c1;
+      z0 = ((dir_ghost(F, 4, f0, x0) + dir_ghost(F, 5, f0, x0)) - (TU)2 * x0) * F.ihz2;
+      z1 = ((dir_ghost(F, 4, f1, x1) + dir_ghost(F, 5, f1, x1)) - (TU)2 * x1) * F.ihz2;
+    }
+    r0 = bv0 - (((xm0 + xp0) - (TU)2 * x0) * F.ihx2 + ((m0 + p0) - (TU)2 * x0) * F.ihy2 + z0);
+    r1 = bv1 - (((xm1 + xp1) - (TU)2 * x1) * F.ihx2 + ((m1 + p1) - (TU)2 * x1) * F.ihy2 + z1);
+  };
+
+  double s2 = 0.0, s1 = 0.0;
+  if (J0 < J1) {
+    TU w0a = 0, w0b = 0, w1a = 0, w1b = 0, w2a = 0, w2b = 0, w3a = 0, w3b = 0;  // u rows 2J-1 .. 2J+2
+    TU b0a, b0b, b1a, b1b;                                                        // b rows 2J, 2J+1
+    if (u != nullptr) {
+      ldrow(u, 2 * J0 - 1, w0a, w0b);
+      ldrow(u, 2 * J0, w1a, w1b);
+      ldrow(u, 2 * J0 + 1, w2a, w2b);
+      ldrow(u, 2 * J0 + 2, w3a, w3b);
+    }
+    ldrow(b, 2 * J0, b0a, b0b);
+    ldrow(b, 2 * J0 + 1, b1a, b1b);
+    for (int J = J0; J < J1; ++J) {
+      TU n3a = 0, n3b = 0, n4a = 0, n4b = 0, nb0a = 0, nb0b = 0, nb1a = 0, nb1b = 0;
+      if (J + 1 < J1) {
+        if (u != nullptr) {
+          ldrow(u, 2 * J + 3, n3a, n3b);
+          ldrow(u, 2 * J + 4, n4a, n4b);
+        }
+        ldrow(b, 2 * J + 2, nb0a, nb0b);
+        ldrow(b, 2 * J + 3, nb1a, nb1b);
+      }
+      const int ra = 2 * J, rb = 2 * J + 1;
+      TU r00, r01, r10, r11;
+      res(w0a, w0b, w1a, w1b, w2a, w2b, ra, b0a, b0b, r00, r01);
+      res(w1a, w1b, w2a, w2b, w3a, w3b, rb, b1a, b1b, r10, r11);
+      const bool rowb = rb < ny;
+      if (in0) s2 += (double)r00 * (double)r00 + (rowb ? (double)r10 * (double)r10 : 0.0);
+      if (in1) s2 += (double)r01 * (double)r01 + (rowb ? (double)r11 * (double)r11 : 0.0);
+      if (RESTRICT) {
+        if (own && I >= 0 && I < cnx) {
+          const TU v = ((r00 + r01) + (r10 + r11)) * (TU)0.25;
+          out[(size_t)J * cnx + I] = (TR)v;
+          s1 += (double)v;
+        }
+      } else {
+        if (in0) {
+          s1 += (double)r00 + (rowb ? (double)r10 : 0.0);
+          if (out != nullptr) {
+            out[(size_t)ra * nx + c0u] = (TR)r00;
+            if (rowb) out[(size_t)rb * nx + c0u] = (TR)r10;
+          }
+        }
+        if (in1) {
+          s1 += (double)r01 + (rowb ? (double)r11 : 0.0);
+          if (out != nullptr) {
+            out[(size_t)ra * nx + c1u] = (TR)r01;
+            if (rowb) out[(size_t)rb * nx + c1u] = (TR)r11;
+          }
+        }
+      }
+      w0a = w2a; w0b = w2b;
+      w1a = w3a; w1b = w3b;
+      w2a = n3a; w2b = n3b;
+      w3a = n4a; w3b = n4b;
+      b0a = nb0a; b0b = nb0b;
+      b1a = nb1a; b1b = nb1b;
+    }
+  }
+  const double t2 = wave_sum_dpp(s2), t1 = wave_sum_dpp(s1);
+  if (lane == 0) {
+    red[0][w] = t2;
+    red[1][w] = t1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, c = 0.0;
+#pragma unroll
+    for (int q = 0; q < P2W; ++q) {
+      a += red[0][q];
+      c += red[1][q];
+    }
+    part[2 * (size_t)blockIdx.x] = a;
+    part[2 * (size_t)blockIdx.x + 1] = c;
+  }
+}
+
+// fine += P(e) on a single-plane level: (9, 3, 3, 1)/16 weights of eq.
+// prolongation_example_2D; coarse ghosts wrap (periodic) or take -e
+// (homogeneous Dirichlet, a corner ghost the product of both signs)
+template <typename T>
+__global__ __launch_bounds__(64 * P2W) void k_prolong_2d(int fnx, int fny, int periodic, const T* __restrict__ e,
+                                                         T* __restrict__ fine, int jc, int gx, Batch bt,
+                                                         const int* __restrict__ stop) {
+  {
+    const long long mb = blockIdx.y;
+    e += mb * bt.s1;
+    fine += mb * bt.s0;
+    if (stop != nullptr) stop += mb * bt.stop_stride;
+  }
+  if (stop != nullptr && *stop) return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int cnx = fnx / 2, cny = fny / 2;
+  const bool per = periodic != 0;
+  const int tx = blockIdx.x % gx, ty = blockIdx.x / gx;
+  const int J0 = (ty * P2W + w) * jc, J1 = min(J0 + jc, cny);
+  const int I = tx * P2OX - 1 + lane;
+  int Iw = I;
+  T sx = (T)1;
+  if (per) Iw = ((I % cnx) + cnx) % cnx;
+  else if (I < 0 || I >= cnx) { Iw = min(max(I, 0), cnx - 1); sx = (T)-1; }
+  const bool own = lane >= 1 && lane <= 62 && I >= 0 && I < cnx;
+  // coarse row J (unwrapped) at this lane's column, and its x neighbours by DPP
+  auto ldc = [&](int J, T& c, T& cm, T& cp) {
+    int Jw = J;
+    T sy = (T)1;
+    if (per) Jw = ((J % cny) + cny) % cny;
+    else if (J < 0 || J >= cny) { Jw = min(max(J, 0), cny - 1); sy = (T)-1; }
+    c = sx * sy * e[(size_t)Jw * cnx + Iw];
+    cm = wshift<DPP_WAVE_SHR1>(c);
+    cp = wshift<DPP_WAVE_SHL1>(c);
+  };
+  if (J0 >= J1) return;
+  T am, amm, amp, ac, acm, acp, ap, apm, app;  // rows J-1, J, J+1: value, x-1, x+1
+  ldc(J0 - 1, am, amm, amp);
+  ldc(J0, ac, acm, acp);
+  const size_t f0 = (size_t)(2 * I);
+  auto ldf = [&](int r, T& v0, T& v1) {
+    v0 = (T)0;
+    v1 = (T)0;
+    if (own && r < fny) {
+      v0 = fine[(size_t)r * fnx + f0];
+      v1 = fine[(size_t)r * fnx + f0 + 1];
+    }
+  };
+  T u0a, u0b, u1a, u1b;
+  ldf(2 * J0, u0a, u0b);
+  ldf(2 * J0 + 1, u1a, u1b);
+  for (int J = J0; J < J1; ++J) {
+    ldc(J + 1, ap, apm, app);
+    T n0a = 0, n0b = 0, n1a = 0, n1b = 0;
+    if (J + 1 < J1) {
+      ldf(2 * J + 2, n0a, n0b);
+      ldf(2 * J + 3, n1a, n1b);
+    }
+    const T k = (T)(1.0 / 16.0);
+    // fine (2I, 2J): neighbours I-1, J-1; (2I+1, 2J): I+1, J-1; (2I, 2J+1): I-1, J+1; (2I+1, 2J+1): I+1, J+1
+    const T p00 = ((T)9 * ac + (T)3 * (acm + am) + amm) * k;
+    const T p01 = ((T)9 * ac + (T)3 * (acp + am) + amp) * k;
+    const T p10 = ((T)9 * ac + (T)3 * (acm + ap) + apm) * k;
+    const T p11 = ((T)9 * ac + (T)3 * (acp + ap) + app) * k;
+    if (own) {
+      fine[(size_t)(2 * J) * fnx + f0] = u0a + p00;
+      fine[(size_t)(2 * J) * fnx + f0 + 1] = u0b + p01;
+      fine[(size_t)(2 * J + 1) * fnx + f0] = u1a + p10;
+      fine[(size_t)(2 * J + 1) * fnx + f0 + 1] = u1b + p11;
+    }
+    am = ac; amm = acm; amp = acp;
+    ac = ap; acm = apm; acp = app;
+    u0a = n0a; u0b = n0b; u1a = n1a; u1b = n1b;
+  }
+}
+
 // ---------------------------------------------------------------- launchers
 struct TileGrid {
   int gx, gy, gz, kc, nblk;
@@ -372,11 +618,20 @@ static TileGrid resid_grid(int nx, int ny, int nz) {
   return g;
 }
 
-size_t resid_blocks(int nx, int ny, int nz) { return (size_t)resid_grid(nx, ny, nz).nblk; }
+size_t resid_blocks(int nx, int ny, int nz) {
+  if (nz == 1) return (size_t)grid_2d((nx + 1) / 2, (ny + 1) / 2).nblk;
+  return (size_t)resid_grid(nx, ny, nz).nblk;
+}
 
 template <typename TU, typename TR>
 void launch_residual(const LevelView<TU>& L, const TU* u, const TU* b, TR* r_out, double* part,
                      const int* stop, hipStream_t st, const Batch& bt) {
+  if (L.nz == 1) {
+    const Grid2D g = grid_2d((L.nx + 1) / 2, (L.ny + 1) / 2);
+    hipLaunchKernelGGL((k_resid_2d<TU, TR, false>), dim3(g.nblk, bt.nb), dim3(64 * P2W), 0, st, L, u, b, r_out,
+                       g.jc, g.gx, part, bt, stop);
+    return;
+  }
   const TileGrid g = resid_grid(L.nx, L.ny, L.nz);
   hipLaunchKernelGGL((k_resid_tile<TU, TR, false>), dim3(g.nblk, bt.nb), dim3(RNT), 0, st, L, u, b, r_out,
                      g.kc, g.gx, g.gy, g.nblk, part, bt, stop);
@@ -385,6 +640,12 @@ void launch_residual(const LevelView<TU>& L, const TU* u, const TU* b, TR* r_out
 template <typename T>
 void launch_resid_restrict(const LevelView<T>& F, const T* u, const T* b, T* bc, double* part,
                            const int* stop, hipStream_t st, const Batch& bt) {
+  if (F.nz == 1) {  // restriction happens below the finest level only: no face data
+    const Grid2D g = grid_2d(F.nx / 2, F.ny / 2);
+    hipLaunchKernelGGL((k_resid_2d<T, T, true>), dim3(g.nblk, bt.nb), dim3(64 * P2W), 0, st, F, u, b, bc, g.jc,
+                       g.gx, part, bt, stop);
+    return;
+  }
   const TileGrid g = resid_grid(F.nx, F.ny, F.nz);
   hipLaunchKernelGGL((k_resid_tile<T, T, true>), dim3(g.nblk, bt.nb), dim3(RNT), 0, st, F, u, b, bc, g.kc,
                      g.gx, g.gy, g.nblk, part, bt, stop);
@@ -393,6 +654,12 @@ void launch_resid_restrict(const LevelView<T>& F, const T* u, const T* b, T* bc,
 template <typename T>
 void launch_prolong_add(int fnx, int fny, int fnz, int periodic, const T* e, T* fine, const int* stop,
                         hipStream_t st, const Batch& bt) {
+  if (fnz == 1) {
+    const Grid2D g2 = grid_2d(fnx / 2, fny / 2);
+    hipLaunchKernelGGL(k_prolong_2d<T>, dim3(g2.nblk, bt.nb), dim3(64 * P2W), 0, st, fnx, fny, periodic, e, fine,
+                       g2.jc, g2.gx, bt, stop);
+    return;
+  }
   TileGrid g;
   g.gx = (fnx + PBX - 1) / PBX;
   g.gy = (fny + PBY - 1) / PBY;

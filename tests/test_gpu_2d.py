@@ -49,7 +49,7 @@ SHAPES = [(1, 16, 16), (1, 24, 40), (1, 70, 130), (1, 130, 200)]
 H2 = (0.11, 0.07, INF)
 
 
-@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("shape", SHAPES + [(1, 35, 129), (1, 1, 17), (1, 300, 2)])
 @pytest.mark.parametrize("bc", ["periodic", "dirichlet"])
 def test_residual_2d(shape, bc):
     R = _lib()
@@ -64,7 +64,28 @@ def test_residual_2d(shape, bc):
     assert abs(nrm - np.linalg.norm(want)) <= 1e-12 * np.linalg.norm(want)
 
 
-@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("shape", [(1, 35, 129), (1, 24, 40), (1, 33, 64)])
+@pytest.mark.parametrize("bc", ["periodic", "dirichlet"])
+def test_residual_single_plane_3d(shape, bc):
+    """A 3-D grid of one plane (finite hz): the z terms are the periodic
+    self-neighbour (0) or the Dirichlet ghosts 2g - u of both z faces."""
+    R = _lib()
+    rng = np.random.default_rng(13)
+    _, ny, nx = shape
+    h = (0.11, 0.07, 0.13)
+    u = rng.standard_normal(shape)
+    f = rng.standard_normal(shape)
+    faces = None
+    if bc == "dirichlet":
+        faces = (rng.standard_normal((1, ny)), rng.standard_normal((1, ny)), rng.standard_normal((1, nx)),
+                 rng.standard_normal((1, nx)), rng.standard_normal((ny, nx)), rng.standard_normal((ny, nx)))
+    want = f - oop.apply_M(u, h, bc, faces)
+    r, nrm = R.residual(cu(f), cu(u), h, bc, faces=R.pack_faces(faces) if faces else None)
+    assert relmax(r.cpu().numpy(), want) < 1e-12
+    assert abs(nrm - np.linalg.norm(want)) <= 1e-12 * np.linalg.norm(want)
+
+
+@pytest.mark.parametrize("shape", SHAPES + [(1, 130, 1000)])
 @pytest.mark.parametrize("bc", ["periodic", "dirichlet"])
 def test_transfers_2d(shape, bc):
     R = _lib()
