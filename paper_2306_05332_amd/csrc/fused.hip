@@ -498,17 +498,27 @@ constexpr bool strip_instantiated() {
   return sizeof(T) == 8 ? S <= 2 : S <= 3;
 }
 
+// The 2-D strip kernel takes up to 4 stages in one pass (two s = 2 tau-steps
+// of a pre-smoothing pair included): without y-halo rows its registers allow
+// it, 8 x segments per lane up to s = 2 (float64) / 4 (float32), 4 beyond.
+constexpr int STRIP2D_MAX_S = 4;
+template <typename T, int S>
+constexpr int strip2d_rows(bool want8) {
+  return (want8 && (sizeof(T) == 4 || S <= 2)) ? 8 : 4;
+}
+
 // 2-D levels: the FLAT strip kernel only (face data folded beforehand)
 template <typename T>
 bool fused_tau_supported(const LevelView<T>& L, int s) {
-  if (level_is_2d(L))
-    return s >= 1 && s <= (sizeof(T) == 8 ? 2 : 3) && L.nx >= 16 && L.ny >= 8 && L.faces == nullptr;
+  if (level_is_2d(L)) return s >= 1 && s <= STRIP2D_MAX_S && L.nx >= 16 && L.ny >= 8 && L.faces == nullptr;
   return s >= 1 && s <= fused_max_s<T>() && L.nx >= 16 && L.ny >= 8 && L.nz >= 8;
 }
 
 template <typename T>
 bool fused_variant_ok(int variant, int s) {
-  if (s < 1 || s > fused_max_s<T>()) return false;
+  if (s < 1) return false;
+  if (variant_is_2d(variant)) return s <= STRIP2D_MAX_S;
+  if (s > fused_max_s<T>()) return false;
   const bool dbl = sizeof(T) == 8;
   switch (variant) {
     case FV_RING_64x8:
@@ -517,9 +527,7 @@ bool fused_variant_ok(int variant, int s) {
     case FV_ZQ_64x16: return s == 2 || s == 3;
     case FV_STRIP_8x4:
     case FV_STRIP_8x1:
-    case FV_STRIP_4x4:
-    case FV_STRIP2D_8:
-    case FV_STRIP2D_4: return dbl ? s <= 2 : s <= 3;
+    case FV_STRIP_4x4: return dbl ? s <= 2 : s <= 3;
     default: return false;
   }
 }
@@ -611,7 +619,7 @@ int tune_generation() {
 // z-queue kernel on large levels and the LDS-ring kernel on small ones.
 template <typename T>
 FusedChoice fused_heuristic(const LevelView<T>& L, int s) {
-  if (level_is_2d(L)) return FusedChoice{FV_STRIP2D_8, 1024};
+  if (level_is_2d(L)) return FusedChoice{FV_STRIP2D_8, s >= 3 ? 2048 : 1024};
   if (fused_variant_ok<T>(FV_STRIP_4x4, s)) {
     const bool big = (size_t)L.nx * L.ny * L.nz >= ((size_t)192 * 192 * 192);
     if (sizeof(T) == 8 && L.periodic && big) return FusedChoice{FV_STRIP_8x4, 1024};
@@ -648,12 +656,16 @@ void launch_fused_S(const LevelView<T>& L, FusedChoice c, const T* u, const T* b
                     double* part, const int* stop, const Batch& bt, hipStream_t st) {
   const FCoef<T, S> fc = make_fcoef<T, S>(co);
   if (variant_is_2d(c.variant)) {
-    if constexpr (strip_instantiated<T, S>()) {
-      if (c.variant == FV_STRIP2D_4) return launch_strip2d<T, S, 4, 1>(L, c.target, u, b, out, fc, part, stop, bt, st);
-      return launch_strip2d<T, S, 8, 1>(L, c.target, u, b, out, fc, part, stop, bt, st);
+    if constexpr (S <= STRIP2D_MAX_S) {
+      if (strip2d_rows<T, S>(c.variant == FV_STRIP2D_8) == 8)
+        return launch_strip2d<T, S, strip2d_rows<T, S>(true), 1>(L, c.target, u, b, out, fc, part, stop, bt, st);
+      return launch_strip2d<T, S, 4, 1>(L, c.target, u, b, out, fc, part, stop, bt, st);
     }
     return;  // not reached: fused_tau_supported bounds s on 2-D levels
   }
+  if constexpr (S > fused_max_s<T>()) {
+    return;  // not reached: 3-D levels take at most fused_max_s stages
+  } else {
   if (is_strip(c.variant) && L.faces != nullptr) c = FusedChoice{FV_RING_64x8, 1024};  // strips take no face data
   if (is_strip(c.variant)) {
     if constexpr (strip_instantiated<T, S>()) {
@@ -684,12 +696,15 @@ void launch_fused_S(const LevelView<T>& L, FusedChoice c, const T* u, const T* b
   }
   hipLaunchKernelGGL((k_fused_tau<T, S, 64, 8>), dim3(g.nblk, bt.nb), dim3(FNT), 0, st, L, u, b, out, fc, g.zc,
                      g.gx, g.gy, g.nblk, part, bt, stop);
+  }
 }
 
 template <typename T>
 size_t fused_tau_blocks_as(const LevelView<T>& L, FusedChoice c, int s) {
-  if (variant_is_2d(c.variant))
-    return (size_t)strip_grid(s, c.variant == FV_STRIP2D_4 ? 4 : 8, 1, L.nx, 1, L.ny, c.target, true).nblk;
+  if (variant_is_2d(c.variant)) {
+    const bool r8 = c.variant == FV_STRIP2D_8 && (sizeof(T) == 4 || s <= 2);
+    return (size_t)strip_grid(s, r8 ? 8 : 4, 1, L.nx, 1, L.ny, c.target, true).nblk;
+  }
   if (is_strip(c.variant) && L.faces != nullptr) c = FusedChoice{FV_RING_64x8, 1024};
   if (is_strip(c.variant)) {
     int R, WY;
@@ -716,12 +731,8 @@ bool launch_fused_tau_as(const LevelView<T>& L, FusedChoice c, const T* u, const
     case 1: launch_fused_S<T, 1>(L, c, u, b, out, co, part, stop, bt, st); return true;
     case 2: launch_fused_S<T, 2>(L, c, u, b, out, co, part, stop, bt, st); return true;
     case 3: launch_fused_S<T, 3>(L, c, u, b, out, co, part, stop, bt, st); return true;
-    default:
-      if constexpr (sizeof(T) == 4) {
-        launch_fused_S<T, 4>(L, c, u, b, out, co, part, stop, bt, st);
-        return true;
-      }
-      return false;
+    case 4: launch_fused_S<T, 4>(L, c, u, b, out, co, part, stop, bt, st); return true;
+    default: return false;
   }
 }
 

@@ -62,6 +62,7 @@ struct Lev {
   size_t n;
   double lam, dtpar;               // Lambda_l = 4 sum h^-2, Delta t_par = 2 / Lambda_l
   std::vector<StageCoef> smooth;   // coefficients of the smoothing tau-step
+  std::vector<StageCoef> smooth2;  // two smoothing tau-steps as one 2s-stage recurrence
 };
 
 // Stage coefficients of one s-stage tau-step: mu_j = (2j-1)/j, nu_j = (1-j)/j,
@@ -212,6 +213,11 @@ std::vector<Lev> build_levels(const rkl_grid& g, int min_coarse, int s, double t
     L.lam = 4.0 * (1.0 / (h[0] * h[0]) + 1.0 / (h[1] * h[1]) + 1.0 / (h[2] * h[2]));
     L.dtpar = 2.0 / L.lam;
     L.smooth = stage_coefs(s, theta, L.dtpar);
+    // the second tau-step's first stage is the recurrence with mu = 1, nu = 0,
+    // and its second stage's Y_{j-2} is the first step's result: two steps
+    // are the 2s-stage recurrence with the coefficient list repeated
+    L.smooth2 = L.smooth;
+    L.smooth2.insert(L.smooth2.end(), L.smooth.begin(), L.smooth.end());
     lv.push_back(L);
     bool ok = true;
     for (int d = 0; d < nd; ++d)
@@ -424,6 +430,20 @@ void tau_step(Plan& P, const LevelView<T>& V, T*& cur, T*& alt, const T* b,
   if (s & 1) std::swap(cur, alt);
 }
 
+// Two relaxations in one pass: on a two-dimensional level the strip kernel
+// runs the 2s-stage recurrence of two tau-steps reading u and b once (there
+// are no y-halo rows, so the extra stages cost little); 3-D levels keep one
+// pass per tau-step, where the 2s-stage pass's halo rows make it slower.
+template <typename T>
+bool pair_ok(const LevelView<T>& V, int s, bool gs) {
+  return !gs && level_is_2d(V) && fused_tau_supported<T>(V, 2 * s);
+}
+
+// n relaxations, paired where pair_ok allows
+template <typename T>
+void relax_n(Plan& P, const LevelView<T>& V, const Lev& Lv, int n, T*& cur, T*& alt, const T* b, const int* stop,
+             hipStream_t st, const Batch& bt, bool gs);
+
 // A tau-step whose input is the zero iterate (first relaxation of a coarse
 // correction); the result lands in `cur` (its previous contents are ignored).
 template <typename T>
@@ -441,6 +461,31 @@ void tau_from_zero(Plan& P, const LevelView<T>& V, T*& cur, T*& alt, const T* b,
   launch_fill<T>(cur, (size_t)V.nx * V.ny * V.nz, (T)0, stop, st);
   check_launch();
   tau_step<T>(P, V, cur, alt, b, co, stop, st, single_batch(), gs);
+}
+
+template <typename T>
+void relax_n(Plan& P, const LevelView<T>& V, const Lev& Lv, int n, T*& cur, T*& alt, const T* b, const int* stop,
+             hipStream_t st, const Batch& bt, bool gs) {
+  const int s = (int)Lv.smooth.size();
+  for (int q = 0; q < n;) {
+    if (n - q >= 2 && pair_ok<T>(V, s, gs)) {
+      tau_step<T>(P, V, cur, alt, b, Lv.smooth2, stop, st, bt, gs);
+      q += 2;
+    } else {
+      tau_step<T>(P, V, cur, alt, b, Lv.smooth, stop, st, bt, gs);
+      ++q;
+    }
+  }
+}
+
+// The first n_pre >= 1 relaxations of a coarse correction from the zero
+// iterate (one or two of them fused into the first pass); returns how many ran
+template <typename T>
+int relax_from_zero(Plan& P, const LevelView<T>& V, const Lev& Lv, int n_pre, T*& cur, T*& alt, const T* b,
+                    const int* stop, hipStream_t st, const Batch& bt, bool gs) {
+  const bool pair = n_pre >= 2 && pair_ok<T>(V, (int)Lv.smooth.size(), gs);
+  tau_from_zero<T>(P, V, cur, alt, b, pair ? Lv.smooth2 : Lv.smooth, stop, st, bt, gs);
+  return pair ? 2 : 1;
 }
 
 // A tau-step from `a` that never writes `a`: the result lands in x or y and
@@ -580,8 +625,7 @@ void vcycle_from(Plan& P, Hier<T>& H, T*& cur0, T*& alt0, const T* b0, const dou
   const int lt = tail_level<T>(P);
   if (vb.nb > 1 && lt <= 0) fail(RKL_EINVAL, "batched solves need the one-workgroup coarse tail");
   const int lbot = lt > 0 ? lt : L - 1;
-  for (int q = pre_done; q < o.n_pre; ++q)
-    tau_step<T>(P, V(0), cur0, alt0, b0, P.lv[0].smooth, stop, st, B1(0), gs);
+  if (pre_done < o.n_pre) relax_n<T>(P, V(0), P.lv[0], o.n_pre - pre_done, cur0, alt0, b0, stop, st, B1(0), gs);
   for (int l = 1; l <= lbot; ++l) {
     T* fu = (l == 1) ? cur0 : H.u[l - 1];
     const T* fb = (l == 1) ? b0 : H.b[l - 1];
@@ -607,9 +651,8 @@ void vcycle_from(Plan& P, Hier<T>& H, T*& cur0, T*& alt0, const T* b0, const dou
     }
     if (l < L - 1) {
       if (o.n_pre > 0) {
-        tau_from_zero<T>(P, V(l), H.u[l], H.t[l], H.b[l], C.smooth, stop, st, B1(l), gs);
-        for (int q = 1; q < o.n_pre; ++q)
-          tau_step<T>(P, V(l), H.u[l], H.t[l], H.b[l], C.smooth, stop, st, B1(l), gs);
+        const int done = relax_from_zero<T>(P, V(l), C, o.n_pre, H.u[l], H.t[l], H.b[l], stop, st, B1(l), gs);
+        if (done < o.n_pre) relax_n<T>(P, V(l), C, o.n_pre - done, H.u[l], H.t[l], H.b[l], stop, st, B1(l), gs);
       } else {
         launch_fill<T>(H.u[l], C.n, (T)0, stop, st, B1(l));
       }
@@ -625,7 +668,7 @@ void vcycle_from(Plan& P, Hier<T>& H, T*& cur0, T*& alt0, const T* b0, const dou
     const Lev& F = P.lv[l];
     launch_prolong_add<T>(F.nx, F.ny, F.nz, P.periodic ? 1 : 0, H.u[l + 1], cu, stop, st, B2(l, l + 1));
     check_launch();
-    for (int q = 0; q < o.n_post; ++q) tau_step<T>(P, V(l), cu, ca, bl, F.smooth, stop, st, B1(l), gs);
+    if (o.n_post > 0) relax_n<T>(P, V(l), F, o.n_post, cu, ca, bl, stop, st, B1(l), gs);
   }
 }
 
@@ -834,6 +877,7 @@ rkl_status solve_fp64(Plan& P, const rkl_opts& o, const double* rho, const doubl
   const int* stop = &P.dconv->stop;
   const bool gs = o.smoother == RKL_SMOOTH_GSRB;
   const bool fused0 = fused_tau_supported<double>(V0, gs ? 2 : o.s) && o.n_pre > 0;
+  const bool pair0 = fused0 && o.n_pre >= 2 && pair_ok<double>(V0, o.s, gs);
   int queued = 0;
   ConvState cs = conv_read(P, st);
   while (true) {
@@ -847,12 +891,13 @@ rkl_status solve_fp64(Plan& P, const rkl_opts& o, const double* rho, const doubl
       int nblk, stride;
       if (fused0) {
         // first relaxation, fused with the residual norm of the start state
-        tau_keep<double>(P, V0, a, bufs[ib], bufs[ic], cur, alt, P.f0, F.smooth, P.part, stop, st, gs);
-        nblk = (int)(gs ? gsrb_blocks<double>(V0) : fused_tau_blocks<double>(V0, o.s));
+        tau_keep<double>(P, V0, a, bufs[ib], bufs[ic], cur, alt, P.f0, pair0 ? F.smooth2 : F.smooth, P.part, stop,
+                         st, gs);
+        nblk = (int)(gs ? gsrb_blocks<double>(V0) : fused_tau_blocks<double>(V0, pair0 ? 2 * o.s : o.s));
         stride = 1;
         launch_check(P.part, nblk, stride, Res0Sqrt::ptr(P), o.tol, o.max_cycles, 1.0, P.dconv, st);
         check_launch();
-        pre_done = 1;
+        pre_done = pair0 ? 2 : 1;
       } else {
         launch_residual<double, double>(V0, a, P.f0, (double*)nullptr, P.part, stop, st);
         nblk = (int)resid_blocks(F.nx, F.ny, F.nz);
@@ -919,9 +964,8 @@ rkl_status solve_mixed(Plan& P, const rkl_opts& o, const double* rho, const doub
       float* alt = P.h32.t[0];
       int pre_done = 0;
       if (o.n_pre > 0) {
-        tau_from_zero<float>(P, V32, cur, alt, P.h32.b[0], F.smooth, stop, st, single_batch(),
-                             o.smoother == RKL_SMOOTH_GSRB);
-        pre_done = 1;
+        pre_done = relax_from_zero<float>(P, V32, F, o.n_pre, cur, alt, P.h32.b[0], stop, st, single_batch(),
+                                          o.smoother == RKL_SMOOTH_GSRB);
       } else {
         launch_fill<float>(cur, F.n, 0.0f, stop, st);
       }
@@ -1092,8 +1136,7 @@ void class_iteration(ClassPlan& C, Hier<T>& H, const rkl_opts& o, hipStream_t st
   const Batch b0{nb, (long long)F.n, 0, CONV_INTS, ps};
   int pre_done = 0;
   if (o.n_pre > 0) {
-    tau_from_zero<T>(P, VT, cur, alt, H.b[0], F.smooth, stop, st, b0, o.smoother == RKL_SMOOTH_GSRB);
-    pre_done = 1;
+    pre_done = relax_from_zero<T>(P, VT, F, o.n_pre, cur, alt, H.b[0], stop, st, b0, o.smoother == RKL_SMOOTH_GSRB);
   } else {
     launch_fill<T>(cur, F.n, (T)0, stop, st, b0);
   }
@@ -1493,10 +1536,14 @@ rkl_status rkl_smooth(const rkl_grid* grid, int s, double tau_frac, int n_steps,
     std::lock_guard<std::mutex> lk(P.mu);
     hipStream_t st = (hipStream_t)hip_stream;
     const LevelView<double> V0 = view<double>(P.lv[0], P.periodic, nullptr);
-    fold_faces(P, bc_faces, f, P.f0, st);
+    const double* b = f;  // f is used as given; face data, if any, is folded into a copy
+    if (bc_faces != nullptr) {
+      fold_faces(P, bc_faces, f, P.f0, st);
+      b = P.f0;
+    }
     double* cur = phi;
     double* alt = P.t0;
-    for (int q = 0; q < n_steps; ++q) tau_step<double>(P, V0, cur, alt, P.f0, P.lv[0].smooth, nullptr, st);
+    relax_n<double>(P, V0, P.lv[0], n_steps, cur, alt, b, nullptr, st, single_batch(), false);
     if (cur != phi) copy_d2d(phi, cur, P.lv[0].n, st);
     HIPCHK(hipStreamSynchronize(st));
     return RKL_OK;

@@ -423,6 +423,10 @@ RKL_STRIP2D_INST(float, 3, 8, 1)
 RKL_STRIP2D_INST(float, 1, 4, 1)
 RKL_STRIP2D_INST(float, 2, 4, 1)
 RKL_STRIP2D_INST(float, 3, 4, 1)
+RKL_STRIP2D_INST(double, 3, 4, 1)
+RKL_STRIP2D_INST(double, 4, 4, 1)
+RKL_STRIP2D_INST(float, 4, 8, 1)
+RKL_STRIP2D_INST(float, 4, 4, 1)
 #undef RKL_STRIP2D_INST
 #define RKL_GSRB_INST(T, R, WY, FLAT)                                                                          \
   template void launch_strip_gsrb<T, R, WY, FLAT>(const LevelView<T>&, int, const T*, const T*, T*, double,     \

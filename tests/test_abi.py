@@ -195,7 +195,7 @@ def test_strip2d_variants_only_on_two_dimensional_levels(lib):
         got = _lib.tune_get((32, 64), 2, "periodic", "fp64")
         assert (got["variant"], got["target"]) == ("strip2d4", 256)
         for bad in ({"nz": 8, "variant": "strip2d8"}, {"nz": 1, "variant": "strip8x4"},
-                    {"nz": 1, "variant": "strip2d8", "s": 3}):
+                    {"nz": 1, "variant": "strip2d8", "s": 5}):
             e = {"nx": 64, "ny": 32, "bc": "periodic", "prec": "fp64", "s": 2, "target": 256}
             e.update(bad)
             with pytest.raises(_lib.RKLError):
@@ -205,7 +205,8 @@ def test_strip2d_variants_only_on_two_dimensional_levels(lib):
                         "variant": "strip2d8", "target": 128}])
         assert _lib.tune_get((32, 64), 3, "dirichlet", "mixed")["variant"] == "strip2d8"
         assert _lib.tau_step_launches((32, 64), 2, "periodic") == 1
-        assert _lib.tau_step_launches((32, 64), 3, "periodic") == 3
+        assert _lib.tau_step_launches((32, 64), 4, "periodic") == 1  # 2-D levels fuse up to 4 stages
+        assert _lib.tau_step_launches((32, 64), 5, "periodic") == 5
         assert _lib.tau_step_launches((1, 32, 64), 2, "periodic") == 2  # finite hz: a 3-D single plane
     finally:
         _lib.tune_clear()

@@ -106,8 +106,11 @@ def test_transfers_2d(shape, bc):
 
 @pytest.mark.parametrize("shape", SHAPES)
 @pytest.mark.parametrize("bc", ["periodic", "dirichlet"])
-@pytest.mark.parametrize("s", [1, 2, 3])
-def test_tau_steps_2d(shape, bc, s):
+@pytest.mark.parametrize("s", [1, 2, 3, 4])
+@pytest.mark.parametrize("n_steps", [2, 3])
+def test_tau_steps_2d(shape, bc, s, n_steps):
+    """n_steps tau-steps; on 2-D levels two steps of s <= 2 run as one fused
+    2s-stage pass (a pair), s = 3, 4 as single fused passes."""
     R = _lib()
     rng = np.random.default_rng(7 + s)
     _, ny, nx = shape
@@ -115,10 +118,10 @@ def test_tau_steps_2d(shape, bc, s):
     f = rng.standard_normal(shape) * 50
     faces = rand_faces2(rng, ny, nx) if bc == "dirichlet" else None
     g = oop.Grid(nx, ny, 1, *H2, bc)
-    want = omg.rkl_smooth(u0, f, g, s, 0.9, 2, faces)
-    print(f"2-D tau-steps shape={shape} bc={bc} s={s}", flush=True)
+    want = omg.rkl_smooth(u0, f, g, s, 0.9, n_steps, faces)
+    print(f"2-D tau-steps shape={shape} bc={bc} s={s} n_steps={n_steps}", flush=True)
     phi = cu(u0)
-    R.smooth(cu(f), phi, H2, bc, s=s, tau_frac=0.9, n_steps=2, faces=R.pack_faces(faces) if faces else None)
+    R.smooth(cu(f), phi, H2, bc, s=s, tau_frac=0.9, n_steps=n_steps, faces=R.pack_faces(faces) if faces else None)
     assert relmax(phi.cpu().numpy(), want) < 1e-12
 
 
@@ -267,15 +270,15 @@ FSHAPES = [(1, 9, 17), (1, 70, 130), (1, 40, 1000), (1, 257, 300)]
 @pytest.mark.parametrize("variant", ["strip2d8", "strip2d4"])
 @pytest.mark.parametrize("shape", FSHAPES)
 @pytest.mark.parametrize("bc", ["periodic", "dirichlet"])
-@pytest.mark.parametrize("s", [1, 2])
+@pytest.mark.parametrize("s", [1, 2, 3, 4])
 def test_forced_strip2d_matches_oracle(variant, shape, bc, s):
     R = _lib()
     R.load_library()
     _, ny, nx = shape
     target = 128 if (nx + ny) % 2 else 2048
     try:
-        R.tune_set([{"nx": nx, "ny": ny, "nz": 1, "bc": bc, "prec": "fp64", "s": s, "variant": variant,
-                     "target": target}])
+        R.tune_set([{"nx": nx, "ny": ny, "nz": 1, "bc": bc, "prec": "fp64", "s": ss, "variant": variant,
+                     "target": target} for ss in {s, min(2 * s, 4)}])
         assert R.tune_get(shape, s, bc, "fp64", h=H2)["variant"] == variant
         assert R.tau_step_launches(shape, s, bc, "fp64", h=H2) == 1
         rng = np.random.default_rng(17 + s)
