@@ -100,6 +100,7 @@ def kernel_symbol(R, shape, s, prec="fp64"):
             "strip8x4": f"rkl::k_tau_strip<{tname}, {s}, 8, 4, true, false, false, false>",
             "strip8x1": f"rkl::k_tau_strip<{tname}, {s}, 8, 1, true, false, false, false>",
             "strip4x4": f"rkl::k_tau_strip<{tname}, {s}, 4, 4, true, false, false, false>",
+            "strip5x1": f"rkl::k_tau_strip<{tname}, {s}, 5, 1, true, false, false, false>",
             "strip2d8": f"rkl::k_tau_strip<{tname}, {s}, 8, 1, true, false, false, true>",
             "strip2d4": f"rkl::k_tau_strip<{tname}, {s}, 4, 1, true, false, false, true>"}.get(
                 v, f"rkl::k_stage<{tname}>")

@@ -238,6 +238,7 @@ int rkl_tau_step_launches(const rkl_grid *grid, int s, int prec);
  *           8  2-D strip, 1 wavefront per workgroup, 8 segments of 64 columns
  *              per lane, marching in y
  *           9  2-D strip, as 8 with 4 segments per lane
+ *          10  strip, 1 wavefront of 64 columns x 5 rows per workgroup
  *              (strip: s <= 2 in float64, s <= 3 in float32; variants 8 and 9
  *              are for two-dimensional levels, nz = 1 with hz = inf, and
  *              those levels take no other variant)

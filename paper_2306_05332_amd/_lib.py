@@ -69,7 +69,7 @@ EXPORTS = ("rkl_default_opts", "rkl_poisson_solve", "mg_vcycle", "rkl_smooth", "
 SMOOTHERS = {"rkl": 0, "gsrb": 1}
 RELAX = {"rkl": 0, "gsrb": 1, "sor": 2}
 VARIANTS = {0: "heuristic", 1: "ring64x8", 2: "ring64x4", 3: "zq64x32", 4: "zq64x16", 5: "strip8x4",
-            6: "strip8x1", 7: "strip4x4", 8: "strip2d8", 9: "strip2d4"}
+            6: "strip8x1", 7: "strip4x4", 8: "strip2d8", 9: "strip2d4", 10: "strip5x1"}
 
 _lib = None
 
@@ -434,6 +434,7 @@ def kernel_info(shape, s, bc="periodic", prec="fp64", h=1.0):
                 "ring64x4": f"k_fused_tau<{tname}, {s}, 64, 4>", "strip8x4": f"k_tau_strip<{tname}, {s}, 8, 4>",
                 "strip8x1": f"k_tau_strip<{tname}, {s}, 8, 1>", "strip4x4": f"k_tau_strip<{tname}, {s}, 4, 4>",
                 "strip2d8": f"k_tau_strip<{tname}, {s}, 8, 1>", "strip2d4": f"k_tau_strip<{tname}, {s}, 4, 1>",
+                "strip5x1": f"k_tau_strip<{tname}, {s}, 5, 1>",
                 }.get(v["variant"], f"k_fused_tau<{tname}, {s}, 64, 8>")
     else:
         words = (3.0 + 4.0 * (s - 1)) / s

@@ -25,9 +25,12 @@ DEFAULT_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning
 def tune_levels(shapes, s_list=(2,), bcs=("periodic",), precs=("fp64", "mixed"), reps=20, min_coarse=4,
                 min_cells=16 ** 3, log=None):
     """Tune every distinct level shape of the given grids; returns the winning
-    entries, each with the built-in choice's time beside it."""
+    entries, each with the built-in choice's time beside it.  A shape
+    (ny, nx) is a two-dimensional grid (its levels (1, ny_l, nx_l) with
+    hz = inf; s = 4 there also covers a fused pair of s = 2 tau-steps)."""
     out, seen = [], set()
     for shape in shapes:
+        h = (1.0, 1.0) if len(shape) == 2 else 1.0
         for bc in bcs:
             for lv in _lib.level_shapes(shape, min_coarse, bc):
                 if lv[0] * lv[1] * lv[2] < min_cells:
@@ -35,13 +38,13 @@ def tune_levels(shapes, s_list=(2,), bcs=("periodic",), precs=("fp64", "mixed"),
                 for prec in precs:
                     for s in s_list:
                         key = (lv, bc, prec, s)
-                        if key in seen or _lib.tau_step_launches(lv, s, bc, prec) != 1:
+                        if key in seen or _lib.tau_step_launches(lv, s, bc, prec, h) != 1:
                             continue
                         seen.add(key)
                         _lib.tune_set([{"nx": lv[2], "ny": lv[1], "nz": lv[0], "bc": bc, "prec": prec, "s": s,
                                         "variant": 0, "target": 0}])
-                        heur = _lib.tune_get(lv, s, bc, prec)
-                        res = _lib.autotune_level(lv, s, bc, prec, reps)
+                        heur = _lib.tune_get(lv, s, bc, prec, h)
+                        res = _lib.autotune_level(lv, s, bc, prec, reps, h)
                         best = dict(res[0])
                         hv = [r["us"] for r in res if r["variant"] == heur["variant"] and r["target"] == heur["target"]]
                         best["heuristic"] = f'{heur["variant"]}/{heur["target"]}'
@@ -107,6 +110,9 @@ def main(argv=None):
     ap.add_argument("--bcs", nargs="+", default=["periodic", "dirichlet"])
     ap.add_argument("--precs", nargs="+", default=["fp64", "mixed"])
     ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--sizes2d", type=int, nargs="*", default=[4096, 2048],
+                    help="square two-dimensional grids (levels down to 64^2)")
+    ap.add_argument("--s2d", type=int, nargs="+", default=[2, 4], help="stage counts for 2-D levels (4: pairs)")
     ap.add_argument("--stage-count-sizes", type=int, nargs="*", default=[256, 128])
     ap.add_argument("--out", default=DEFAULT_TABLE)
     a = ap.parse_args(argv)
@@ -115,6 +121,8 @@ def main(argv=None):
     _lib.tune_clear()
     log = lambda m: print(m, flush=True)  # noqa: E731
     tiles = tune_levels([(n, n, n) for n in a.sizes], tuple(a.s), tuple(a.bcs), tuple(a.precs), a.reps, log=log)
+    tiles += tune_levels([(n, n) for n in a.sizes2d], tuple(a.s2d), tuple(a.bcs), tuple(a.precs), a.reps,
+                         log=log)
     stage = []
     for n in a.stage_count_sizes:
         for prec in a.precs:

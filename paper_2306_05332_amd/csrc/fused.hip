@@ -527,7 +527,8 @@ bool fused_variant_ok(int variant, int s) {
     case FV_ZQ_64x16: return s == 2 || s == 3;
     case FV_STRIP_8x4:
     case FV_STRIP_8x1:
-    case FV_STRIP_4x4: return dbl ? s <= 2 : s <= 3;
+    case FV_STRIP_4x4:
+    case FV_STRIP_5x1: return dbl ? s <= 2 : s <= 3;
     default: return false;
   }
 }
@@ -538,11 +539,11 @@ static bool variant_fits(const LevelView<T>& L, int variant) {
 }
 
 static bool is_strip(int variant) {
-  return variant == FV_STRIP_8x4 || variant == FV_STRIP_8x1 || variant == FV_STRIP_4x4;
+  return variant == FV_STRIP_8x4 || variant == FV_STRIP_8x1 || variant == FV_STRIP_4x4 || variant == FV_STRIP_5x1;
 }
 static void strip_shape(int variant, int& R, int& WY) {
-  R = variant == FV_STRIP_4x4 ? 4 : 8;
-  WY = variant == FV_STRIP_8x1 ? 1 : 4;
+  R = variant == FV_STRIP_4x4 ? 4 : (variant == FV_STRIP_5x1 ? 5 : 8);
+  WY = (variant == FV_STRIP_8x1 || variant == FV_STRIP_5x1) ? 1 : 4;
 }
 
 static void variant_tile(int variant, int& bx, int& by) {
@@ -619,7 +620,7 @@ int tune_generation() {
 // z-queue kernel on large levels and the LDS-ring kernel on small ones.
 template <typename T>
 FusedChoice fused_heuristic(const LevelView<T>& L, int s) {
-  if (level_is_2d(L)) return FusedChoice{FV_STRIP2D_8, s >= 3 ? 2048 : 1024};
+  if (level_is_2d(L)) return FusedChoice{(sizeof(T) == 8 && s <= 2) ? FV_STRIP2D_8 : FV_STRIP2D_4, 2048};
   if (fused_variant_ok<T>(FV_STRIP_4x4, s)) {
     const bool big = (size_t)L.nx * L.ny * L.nz >= ((size_t)192 * 192 * 192);
     if (sizeof(T) == 8 && L.periodic && big) return FusedChoice{FV_STRIP_8x4, 1024};
@@ -672,6 +673,7 @@ void launch_fused_S(const LevelView<T>& L, FusedChoice c, const T* u, const T* b
       if (c.variant == FV_STRIP_8x4) return launch_strip<T, S, 8, 4>(L, c.target, u, b, out, fc, part, stop, bt, st);
       if (c.variant == FV_STRIP_8x1) return launch_strip<T, S, 8, 1>(L, c.target, u, b, out, fc, part, stop, bt, st);
       if (c.variant == FV_STRIP_4x4) return launch_strip<T, S, 4, 4>(L, c.target, u, b, out, fc, part, stop, bt, st);
+      if (c.variant == FV_STRIP_5x1) return launch_strip<T, S, 5, 1>(L, c.target, u, b, out, fc, part, stop, bt, st);
     }
   }
   int bx, by;
@@ -782,6 +784,7 @@ const char* fused_variant_name(int variant) {
     case FV_STRIP_4x4: return "strip4x4";
     case FV_STRIP2D_8: return "strip2d8";
     case FV_STRIP2D_4: return "strip2d4";
+    case FV_STRIP_5x1: return "strip5x1";
     default: return "heuristic";
   }
 }

@@ -50,6 +50,9 @@ template <typename T>
 void launch_fill(T* a, size_t n, T v, const int* stop, hipStream_t st, const Batch& bt = single_batch());
 void launch_scale(const double* in, double* out, size_t n, double c, double* part, hipStream_t st);
 template <typename T>
+void launch_sub_mean_part(T* a, size_t n, const double* part, int nblk, int stride, int q, double count,
+                          const int* stop, hipStream_t st, const Batch& bt = single_batch());
+template <typename T>
 void launch_sub_mean(T* a, size_t n, const double* sum, double count, const int* stop, hipStream_t st,
                      const Batch& bt = single_batch());
 template <typename T>
@@ -104,7 +107,8 @@ enum : int {
   FV_STRIP_4x4 = 7,   // R = 4, 4 wavefronts per workgroup
   FV_STRIP2D_8 = 8,   // two-dimensional levels only: 8 x segments per lane, one wavefront per workgroup
   FV_STRIP2D_4 = 9,   // two-dimensional levels only: 4 x segments per lane
-  FV_COUNT = 10
+  FV_STRIP_5x1 = 10,  // strip kernel: R = 5 rows per lane (3 waves per SIMD in float64), one wavefront per workgroup
+  FV_COUNT = 11
 };
 // A two-dimensional level (nz = 1, ihz2 = 0) takes the FV_STRIP2D_* variants
 // and no others; a 3-D level takes every variant but those.

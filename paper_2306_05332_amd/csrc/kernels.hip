@@ -362,6 +362,28 @@ __global__ __launch_bounds__(EW_NT) void k_copy_tab(double* const* __restrict__ 
 }
 
 // a -= sum[0] / count
+// a -= (sum of part[b * stride + q] over b < nblk) / count: every workgroup
+// sums the partials itself in the same fixed order (so all of them subtract
+// the same value), which saves the separate reduction launch
+template <typename T>
+__global__ __launch_bounds__(EW_NT) void k_sub_mean_part(T* __restrict__ a, size_t n, const double* __restrict__ part,
+                                                         int nblk, int stride, int q, double count, Batch bt,
+                                                         const int* __restrict__ stop) {
+  __shared__ double sh[EW_NT / WAVE];
+  __shared__ double mean;
+  a += (long long)blockIdx.y * bt.s0;
+  part += (long long)blockIdx.y * bt.part_stride;
+  if (stop != nullptr) stop += (long long)blockIdx.y * bt.stop_stride;
+  if (stop != nullptr && *stop) return;
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += EW_NT) v += part[(size_t)b * stride + q];
+  const double t = block_sum<EW_NT>(v, sh);
+  if (threadIdx.x == 0) mean = t / count;
+  __syncthreads();
+  const T m = (T)mean;
+  for (size_t i = (size_t)blockIdx.x * EW_NT + threadIdx.x; i < n; i += (size_t)gridDim.x * EW_NT) a[i] -= m;
+}
+
 template <typename T>
 __global__ __launch_bounds__(EW_NT) void k_sub_mean(T* __restrict__ a, size_t n,
                                                     const double* __restrict__ sum, double count, Batch bt,
@@ -506,6 +528,13 @@ void launch_sub_mean(T* a, size_t n, const double* sum, double count, const int*
 }
 
 template <typename T>
+void launch_sub_mean_part(T* a, size_t n, const double* part, int nblk, int stride, int q, double count,
+                          const int* stop, hipStream_t st, const Batch& bt) {
+  hipLaunchKernelGGL(k_sub_mean_part<T>, dim3(ew_blocks(n), bt.nb), dim3(EW_NT), 0, st, a, n, part, nblk, stride, q,
+                     count, bt, stop);
+}
+
+template <typename T>
 void launch_sum(const T* a, size_t n, double* part, hipStream_t st, const Batch& bt) {
   hipLaunchKernelGGL(k_sum<T>, dim3(ew_blocks(n), bt.nb), dim3(EW_NT), 0, st, a, n, part, bt);
 }
@@ -526,6 +555,10 @@ template void launch_fill<float>(float*, size_t, float, const int*, hipStream_t,
 template void launch_sub_mean<double>(double*, size_t, const double*, double, const int*, hipStream_t,
                                       const Batch&);
 template void launch_sub_mean<float>(float*, size_t, const double*, double, const int*, hipStream_t, const Batch&);
+template void launch_sub_mean_part<double>(double*, size_t, const double*, int, int, int, double, const int*,
+                                           hipStream_t, const Batch&);
+template void launch_sub_mean_part<float>(float*, size_t, const double*, int, int, int, double, const int*,
+                                          hipStream_t, const Batch&);
 template void launch_sum<double>(const double*, size_t, double*, hipStream_t, const Batch&);
 template void launch_sum<float>(const float*, size_t, double*, hipStream_t, const Batch&);
 template void launch_add_cast<float>(double*, const float*, size_t, const int*, hipStream_t, const Batch&);

@@ -641,12 +641,11 @@ void vcycle_from(Plan& P, Hier<T>& H, T*& cur0, T*& alt0, const T* b0, const dou
       check_launch();
       break;
     }
-    if (P.periodic) {
+    if (P.periodic) {  // coarse right-hand side made mean-free (its sum: the restriction's partials)
       const Lev& Fl = P.lv[l - 1];
-      Batch br{vb.nb, 2, 0, vb.stop_stride, vb.part_stride};  // two sums per member
-      launch_reduce(part, (int)resid_blocks(Fl.nx, Fl.ny, Fl.nz), 2, 2, vb.dsum, stop, st, br);
-      Batch bs{vb.nb, (long long)C.n, 2, vb.stop_stride, 0};
-      launch_sub_mean<T>(H.b[l], C.n, vb.dsum + 1, (double)C.n, stop, st, bs);
+      Batch bs{vb.nb, (long long)C.n, 0, vb.stop_stride, vb.part_stride};
+      launch_sub_mean_part<T>(H.b[l], C.n, part, (int)resid_blocks(Fl.nx, Fl.ny, Fl.nz), 2, 1, (double)C.n, stop, st,
+                              bs);
       check_launch();
     }
     if (l < L - 1) {

@@ -409,6 +409,11 @@ RKL_STRIP_INST(double, 2, 4, 4)
 RKL_STRIP_INST(float, 1, 4, 4)
 RKL_STRIP_INST(float, 2, 4, 4)
 RKL_STRIP_INST(float, 3, 4, 4)
+RKL_STRIP_INST(double, 1, 5, 1)
+RKL_STRIP_INST(double, 2, 5, 1)
+RKL_STRIP_INST(float, 1, 5, 1)
+RKL_STRIP_INST(float, 2, 5, 1)
+RKL_STRIP_INST(float, 3, 5, 1)
 #undef RKL_STRIP_INST
 #define RKL_STRIP2D_INST(T, S, R, WY)                                                                          \
   template void launch_strip2d<T, S, R, WY>(const LevelView<T>&, int, const T*, const T*, T*, const FCoef<T, S>&, \

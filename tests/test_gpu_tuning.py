@@ -45,11 +45,12 @@ def _restore_table():
 # ragged in x, y and z for every tile shape; the last one spans several
 # z-queue tiles in x and y
 VSHAPES = [(20, 11, 130), (16, 16, 16), (40, 24, 64), (72, 130, 160)]
-VARIANTS = ["ring64x8", "ring64x4", "zq64x32", "zq64x16", "strip8x4", "strip8x1", "strip4x4"]
+VARIANTS = ["ring64x8", "ring64x4", "zq64x32", "zq64x16", "strip8x4", "strip8x1", "strip4x4", "strip5x1"]
 # stage counts each variant is built for: (float64, float32)
 SUPPORT = {"ring64x8": ((1, 2, 3), (1, 2, 3, 4)), "ring64x4": ((1, 2, 3), (1, 2, 3, 4)),
            "zq64x32": ((2, 3), (2, 3)), "zq64x16": ((2, 3), (2, 3)),
-           "strip8x4": ((1, 2), (1, 2, 3)), "strip8x1": ((1, 2), (1, 2, 3)), "strip4x4": ((1, 2), (1, 2, 3))}
+           "strip8x4": ((1, 2), (1, 2, 3)), "strip8x1": ((1, 2), (1, 2, 3)), "strip4x4": ((1, 2), (1, 2, 3)),
+           "strip5x1": ((1, 2), (1, 2, 3))}
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
