@@ -67,6 +67,8 @@ def parse():
     ap.add_argument("--pmc-probe", action="store_true")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--summarize-trace", metavar="TRACE_DIR")
+    ap.add_argument("--only-two-d", action="store_true", help="run only the 2-D workload; print its JSON")
+    ap.add_argument("--summarize-trace-2d", metavar="TRACE_DIR")
     return ap.parse_args()
 
 
@@ -238,6 +240,45 @@ def summarize_trace(d):
     print("\n".join(out))
 
 
+TWO_D_KERNEL = "rkl::k_tau_strip<double, 4, 4, 1, true, false, false, true>"
+
+
+def summarize_trace_2d(d):
+    """rocprofv3 --kernel-trace --stats of the 2-D workload: the top kernels,
+    and the 4096^2 pair pass's mean duration over the timed sweep."""
+    stats = _rows(_find(d, "kernel_stats.csv"))
+    trace = _rows(_find(d, "kernel_trace.csv"))
+    out = ["Kernel trace of the two-dimensional workload (periodic 4096^2, float64 and mixed solves, pair-pass sweep)",
+           "command (from /tmp, TMPDIR=/tmp):",
+           "  rocprofv3 --kernel-trace --stats --output-format csv -d <DIR> -o two_d -- "
+           "python3 <repo>/bench.py --only-two-d",
+           "  python3 <repo>/bench.py --summarize-trace-2d <DIR>",
+           "", "top kernels (rocprofv3 kernel_stats):",
+           f"  {'calls':>6} {'total_ms':>9} {'avg_us':>8} {'pct':>6}  name"]
+    for r in stats[:14]:
+        name = r["Name"].split("(")[0].replace("void ", "")
+        out.append(f"  {int(r['Calls']):>6} {float(r['TotalDurationNs']) / 1e6:>9.3f} "
+                   f"{float(r['AverageNs']) / 1e3:>8.2f} {float(r['Percentage']):>6.2f}  {name}")
+    order = sorted(trace, key=lambda r: int(r["Start_Timestamp"]))
+    gsize = lambda r: int(r.get("Grid_Size_X", r.get("Grid_Size", "0")) or 0)  # noqa: E731
+    top = max(gsize(r) for r in order if TWO_D_KERNEL in r["Kernel_Name"])  # the 4096^2 launches
+    best, cur = [], []
+    for r in order:
+        if TWO_D_KERNEL in r["Kernel_Name"] and gsize(r) == top:
+            cur.append(r)
+            if len(cur) > len(best):
+                best = list(cur)
+        else:
+            cur = []
+    sw = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in best[-(SWEEP_STEPS // 2):]]
+    n = 4096
+    out += ["", f"2-D pair pass (two s = 2 tau-steps in one 4-stage pass): {TWO_D_KERNEL}",
+            f"  timed sweep at 4096^2: {len(sw)} launches, mean duration {sum(sw) / len(sw):.2f} us "
+            f"(min {min(sw):.2f}, max {max(sw):.2f})",
+            f"  algorithmic bytes per launch: {3 * 8 * n * n} -> {3 * 8 * n * n / (sum(sw) / len(sw)) / 1e3:.1f} GB/s"]
+    print("\n".join(out))
+
+
 # ---------------------------------------------------------------- probes
 def pmc_probe():
     """A plain copy of COPY_BYTES (three times) and ten finest-level tau-steps."""
@@ -264,12 +305,25 @@ def main():
         return summarize_pmc(*args.summarize_pmc)
     if args.summarize_trace:
         return summarize_trace(args.summarize_trace)
+    if args.summarize_trace_2d:
+        return summarize_trace_2d(args.summarize_trace_2d)
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (this solver's path is single-GPU); got --gpus {args.gpus}",
               file=sys.stderr)
         sys.exit(2)
     if args.pmc_probe:
         return pmc_probe()
+    if args.only_two_d:
+        import torch
+
+        import paper_2306_05332_amd as R
+        import workloads as W
+        if not torch.cuda.is_available():
+            print("bench.py needs a GPU", file=sys.stderr)
+            sys.exit(2)
+        R.load_library()
+        print(json.dumps(run_two_d(R, W, torch)), flush=True)
+        return
     import numpy as np
     import torch
 
@@ -498,7 +552,7 @@ def run_two_d(R, W, torch, n=4096):
     t_launch = ev0.elapsed_time(ev1) * 1e-3 / launches
     nbytes = 3 * 8 * n * n
     ach = nbytes / t_launch / 1e9
-    res["tau_pair_pass"] = {"kernel": "rkl::k_tau_strip<double, 4, 4, 1, true, false, false, true>",
+    res["tau_pair_pass"] = {"kernel": TWO_D_KERNEL,
                             "tau_steps_per_launch": 2, "mean_launch_us": t_launch * 1e6,
                             "us_per_tau_step": t_launch * 1e6 / 2, "bytes_per_launch": nbytes,
                             "achieved_GBs": ach, "frac_of_hbm_peak": ach / HBM_PEAK_GBS}

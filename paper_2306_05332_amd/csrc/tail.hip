@@ -102,6 +102,90 @@ __device__ __forceinline__ T tail_lap(const TailLevel<T>& V, const T* Y, int q, 
   return ((xm + xp) - (T)2 * c) * V.ihx2 + ((ym + yp) - (T)2 * c) * V.ihy2 + ((zm + zp) - (T)2 * c) * V.ihz2;
 }
 
+// Value of `v` in lane `src` (ds_bpermute: the LDS crossbar, no LDS memory).
+__device__ __forceinline__ double lane_get(double v, int src) {
+  const int a = src << 2;
+  const int lo = __builtin_amdgcn_ds_bpermute(a, __double2loint(v));
+  const int hi = __builtin_amdgcn_ds_bpermute(a, __double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float lane_get(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
+}
+
+// Accelerated RKL on a coarsest level of at most 64 cells held one cell per
+// lane of wavefront 0, in registers: the six neighbours come from their
+// lanes by lane exchanges (a Dirichlet ghost reads the lane itself and flips
+// the sign), so a stage touches no LDS memory.  Same schedule, stop test
+// (before every tau-step) and periodic mean removal as the LDS form.
+template <typename T>
+__device__ void coarse_regs(const TailLevel<T>& V, const int* ssched, const int* scoff, const double* scoef,
+                            int nsched, int per, double ctol, int cmax, T* B, T* U) {
+  const int lane = threadIdx.x;
+  const int nx = V.nx, ny = V.ny, nz = V.nz, n = nx * ny * nz;
+  const bool has = lane < n;
+  const int q = has ? lane : 0;
+  const int i = q % nx, j = (q / nx) % ny, k = q / (nx * ny);
+  const int sy = nx, sz = nx * ny;
+  int nb[6];
+  nb[0] = i > 0 ? q - 1 : (per ? q + nx - 1 : q);
+  nb[1] = i < nx - 1 ? q + 1 : (per ? q - (nx - 1) : q);
+  nb[2] = j > 0 ? q - sy : (per ? q + (ny - 1) * sy : q);
+  nb[3] = j < ny - 1 ? q + sy : (per ? q - (ny - 1) * sy : q);
+  nb[4] = k > 0 ? q - sz : (per ? q + (nz - 1) * sz : q);
+  nb[5] = k < nz - 1 ? q + sz : (per ? q - (nz - 1) * sz : q);
+  T sg[6];
+#pragma unroll
+  for (int d = 0; d < 6; ++d) sg[d] = (T)1;
+  if (!per) {
+    if (i == 0) sg[0] = (T)-1;
+    if (i == nx - 1) sg[1] = (T)-1;
+    if (j == 0) sg[2] = (T)-1;
+    if (j == ny - 1) sg[3] = (T)-1;
+    if (k == 0) sg[4] = (T)-1;
+    if (k == nz - 1) sg[5] = (T)-1;
+  }
+  if (!has) {
+#pragma unroll
+    for (int d = 0; d < 6; ++d) nb[d] = lane;  // idle lanes hold 0 and read themselves
+  }
+  const T bl = has ? B[q] : (T)0;
+  auto mres = [&](T y) -> T {  // (M y - b) at this lane's cell; every lane takes part in the exchanges
+    T v[6];
+#pragma unroll
+    for (int d = 0; d < 6; ++d) v[d] = sg[d] * lane_get(y, nb[d]);
+    return ((v[0] + v[1]) - (T)2 * y) * V.ihx2 + ((v[2] + v[3]) - (T)2 * y) * V.ihy2 +
+           ((v[4] + v[5]) - (T)2 * y) * V.ihz2 - bl;
+  };
+  const double bnorm = sqrt(wave_sum_dpp((double)bl * (double)bl));
+  T u = (T)0;
+  int step = 0;
+  if (bnorm > 0.0) {
+    while (true) {
+      const T r = mres(u);
+      const double res = sqrt(wave_sum_dpp(has ? (double)r * (double)r : 0.0));
+      if (res <= ctol * bnorm || step >= cmax) break;
+      const int qs = step < nsched ? step : nsched - 1;
+      const int s = ssched[qs];
+      const double* co = scoef + 3 * scoff[qs];
+      T y1 = u, y2 = u;  // Y_{j-1}, Y_{j-2}
+      for (int jj = 1; jj <= s; ++jj) {
+        const T mu = (T)co[3 * (jj - 1)], nu = (T)co[3 * (jj - 1) + 1], c = (T)co[3 * (jj - 1) + 2];
+        const T rr = mres(y1);
+        T y = (jj == 1) ? y1 + c * rr : mu * y1 + nu * y2 + c * rr;
+        if (!has) y = (T)0;
+        y2 = y1;
+        y1 = y;
+      }
+      u = y1;
+      if (per) u -= (T)(wave_sum_dpp(has ? (double)u : 0.0) / (double)n);
+      if (!has) u = (T)0;
+      ++step;
+    }
+  }
+  if (has) U[q] = u;
+}
+
 template <typename T>
 __global__ __launch_bounds__(TNT) void k_tail(TailArgs<T> A, const T* __restrict__ b_top, T* __restrict__ u_top,
                                               Batch bt, const int* __restrict__ stop) {
@@ -149,6 +233,42 @@ __global__ __launch_bounds__(TNT) void k_tail(TailArgs<T> A, const T* __restrict
     for (int q = tid; q < n; q += TNT) B[q] -= m;
     __syncthreads();
   };
+  // One sweep over level l calling fn(q, (M Y)[q], Y[q]) for every cell.  When
+  // the walk stride TNT is a multiple of nx * ny, a thread's cells share
+  // (i, j): its x and y neighbour offsets are computed once and it walks k;
+  // other levels take the generic cell walk.  Ghosts as in tail_lap.
+  auto lap_sweep = [&](int l, const T* Y, auto&& fn) {
+    const TailLevel<T>& V = A.lv[l];
+    const int nx = V.nx, ny = V.ny, nz = V.nz, nxy = nx * ny, n = nxy * nz;
+    if (TNT % nxy == 0) {
+      const int i = tid % nx, j = (tid / nx) % ny, kstep = TNT / nxy;
+      const int dxm = i > 0 ? -1 : (per ? nx - 1 : 0);
+      const int dxp = i < nx - 1 ? 1 : (per ? -(nx - 1) : 0);
+      const int dym = j > 0 ? -nx : (per ? (ny - 1) * nx : 0);
+      const int dyp = j < ny - 1 ? nx : (per ? -(ny - 1) * nx : 0);
+      const bool gxm = !per && i == 0, gxp = !per && i == nx - 1;
+      const bool gym = !per && j == 0, gyp = !per && j == ny - 1;
+      for (int q = tid, k = tid / nxy; q < n; q += TNT, k += kstep) {
+        const int dzm = k > 0 ? -nxy : (per ? (nz - 1) * nxy : 0);
+        const int dzp = k < nz - 1 ? nxy : (per ? -(nz - 1) * nxy : 0);
+        const T c = Y[q];
+        T xm = Y[q + dxm], xp = Y[q + dxp], ym = Y[q + dym], yp = Y[q + dyp], zm = Y[q + dzm], zp = Y[q + dzp];
+        if (!per) {
+          xm = gxm ? -xm : xm;
+          xp = gxp ? -xp : xp;
+          ym = gym ? -ym : ym;
+          yp = gyp ? -yp : yp;
+          zm = k > 0 ? zm : -zm;
+          zp = k < nz - 1 ? zp : -zp;
+        }
+        fn(q, ((xm + xp) - (T)2 * c) * V.ihx2 + ((ym + yp) - (T)2 * c) * V.ihy2 + ((zm + zp) - (T)2 * c) * V.ihz2,
+           c);
+      }
+    } else {
+      for (CellWalk w(tid, TNT, nx, ny, nz); w.ok(); w.next(TNT))
+        fn(w.q, tail_lap(V, Y, w.q, w.i, w.j, w.k, per), Y[w.q]);
+    }
+  };
   // one relaxation on level l: an RKL tau-step (stage by stage, Y_j over
   // Y_{j-2}) or a red-black Gauss-Seidel pass (in place: a cell's neighbours
   // all have the other colour on these even-sized levels); from_zero: u = 0
@@ -188,11 +308,10 @@ __global__ __launch_bounds__(TNT) void k_tail(TailArgs<T> A, const T* __restrict
       const T* yp = (j & 1) ? cur : alt;
       T* yw = (j & 1) ? alt : cur;
       const T mu = V.mu[j - 1], nu = V.nu[j - 1], c = V.c[j - 1];
-      for (CellWalk w(tid, TNT, V.nx, V.ny, V.nz); w.ok(); w.next(TNT)) {
-        const int q = w.q;
-        const T r = tail_lap(V, yp, q, w.i, w.j, w.k, per) - B[q];
-        yw[q] = (j == 1) ? yp[q] + c * r : mu * yp[q] + nu * yw[q] + c * r;
-      }
+      if (j == 1)
+        lap_sweep(l, yp, [&](int q, T mv, T cv) { yw[q] = cv + c * (mv - B[q]); });
+      else
+        lap_sweep(l, yp, [&](int q, T mv, T cv) { yw[q] = mu * cv + nu * yw[q] + c * (mv - B[q]); });
       __syncthreads();
     }
     if (A.s & 1) swapped ^= 1u << l;
@@ -216,37 +335,48 @@ __global__ __launch_bounds__(TNT) void k_tail(TailArgs<T> A, const T* __restrict
       for (int q = tid; q < nof(l); q += TNT) cur[q] = (T)0;
       __syncthreads();
     }
-    // b_{l+1} = R(b_l - M u_l)
+    // b_{l+1} = R(b_l - M u_l): the fine residual into the level's free
+    // second array, then the average of each coarse cell's children (periodic:
+    // the coarse sum taken on the way, its mean removed after)
     const TailLevel<T>& F = A.lv[l];
     const TailLevel<T>& C = A.lv[l + 1];
     const T* U = curp(l);
     const T* B = bptr(l);
+    T* RF = altp(l);
     T* BC = bptr(l + 1);
-    const int cn = nof(l + 1);
+    lap_sweep(l, U, [&](int q, T mv, T) { RF[q] = B[q] - mv; });
+    __syncthreads();
     const int ndz = A.flat ? 1 : 2;
     const T rw = A.flat ? (T)0.25 : (T)0.125;
+    const int fnxy = F.nx * F.ny;
+    double csum = 0.0;
     for (CellWalk w(tid, TNT, C.nx, C.ny, C.nz); w.ok(); w.next(TNT)) {
-      const int I = w.i, J = w.j, K = w.k;
-      T acc = (T)0;
-      for (int dz = 0; dz < ndz; ++dz)
-#pragma unroll
-        for (int dy = 0; dy < 2; ++dy)
-#pragma unroll
-          for (int dx = 0; dx < 2; ++dx) {
-            const int f = ((2 * K + dz) * F.ny + (2 * J + dy)) * F.nx + (2 * I + dx);
-            acc += B[f] - tail_lap(F, U, f, 2 * I + dx, 2 * J + dy, 2 * K + dz, per);
-          }
-      BC[w.q] = acc * rw;
+      const int f0 = ((2 * w.k) * F.ny + 2 * w.j) * F.nx + 2 * w.i;
+      T acc = (RF[f0] + RF[f0 + 1]) + (RF[f0 + F.nx] + RF[f0 + F.nx + 1]);
+      if (ndz == 2) acc += (RF[f0 + fnxy] + RF[f0 + fnxy + 1]) + (RF[f0 + fnxy + F.nx] + RF[f0 + fnxy + F.nx + 1]);
+      const T v = acc * rw;
+      BC[w.q] = v;
+      csum += (double)v;
+    }
+    if (per) {
+      const double t = block_sum<TNT>(csum, red);
+      if (tid == 0) bc = t;
+      __syncthreads();
+      const T m = (T)(bc / (double)nof(l + 1));
+      for (int q = tid; q < nof(l + 1); q += TNT) BC[q] -= m;
     }
     __syncthreads();
-    if (per) remove_b_mean(l + 1);
   }
   // coarsest level: accelerated RKL on wavefront 0 (up to 4 cells per lane),
   // neighbour offsets precomputed once; ghosts: periodic wrap or -c.  Only
   // this wavefront touches the level's arrays, and the LDS operations of one
   // wavefront complete in issue order, so wavefront-scope fences (compiler
   // ordering) separate the stages.
-  {
+  if (nof(nl - 1) <= WAVE) {
+    if (tid < WAVE)
+      coarse_regs<T>(A.lv[nl - 1], ssched, scoff, scoef, nsched, per, A.ctol, A.cmax, bptr(nl - 1), curp(nl - 1));
+    __syncthreads();
+  } else {
     const int l = nl - 1;
     const TailLevel<T>& V = A.lv[l];
     const int n = nof(l);
@@ -372,36 +502,50 @@ __global__ __launch_bounds__(TNT) void k_tail(TailArgs<T> A, const T* __restrict
     const TailLevel<T>& C = A.lv[l + 1];
     const T* E = curp(l + 1);
     T* U = curp(l);
-    const int fn = nof(l);
+    // per axis: the parent and the neighbour on the fine cell's side
+    // (wrapped, or clamped with sign -1 for a homogeneous Dirichlet ghost);
+    // the eight coarse values then weigh (3,1) x (3,1) x (3,1) / 64.  A 2-D
+    // hierarchy takes the parent plane as its own z neighbour.
+    const int cnxy = C.nx * C.ny;
     for (CellWalk w(tid, TNT, F.nx, F.ny, F.nz); w.ok(); w.next(TNT)) {
-      const int q = w.q, i = w.i, j = w.j, k = w.k;
-      const int I = i >> 1, J = j >> 1, K = k >> 1;
-      const int sx = (i & 1) ? 1 : -1, sy = (j & 1) ? 1 : -1, sz = (k & 1) ? 1 : -1;
-      T acc = (T)0;
-      for (int dz = 0; dz < 2; ++dz)
-        for (int dy = 0; dy < 2; ++dy)
-          for (int dx = 0; dx < 2; ++dx) {
-            int a = I + dx * sx, bb = J + dy * sy, cidx = K + dz * sz;
-            T sg = (T)1;
-            if (per) {
-              a = a < 0 ? a + C.nx : (a >= C.nx ? a - C.nx : a);
-              bb = bb < 0 ? bb + C.ny : (bb >= C.ny ? bb - C.ny : bb);
-              cidx = cidx < 0 ? cidx + C.nz : (cidx >= C.nz ? cidx - C.nz : cidx);
-            } else {
-              if (a < 0) { a = 0; sg = -sg; }
-              if (a >= C.nx) { a = C.nx - 1; sg = -sg; }
-              if (bb < 0) { bb = 0; sg = -sg; }
-              if (bb >= C.ny) { bb = C.ny - 1; sg = -sg; }
-              if (!A.flat) {
-                if (cidx < 0) { cidx = 0; sg = -sg; }
-                if (cidx >= C.nz) { cidx = C.nz - 1; sg = -sg; }
-              }
-            }
-            if (A.flat) cidx = 0;  // 2-D: the parent plane is its own z neighbour
-            const T w = (T)((dz ? 1 : 3) * (dy ? 1 : 3) * (dx ? 1 : 3));
-            acc += w * sg * E[(cidx * C.ny + bb) * C.nx + a];
-          }
-      U[q] += acc * (T)(1.0 / 64.0);
+      const int q = w.q;
+      int ox[2], oy[2], oz[2];
+      T gx = (T)1, gy = (T)1, gz = (T)1;
+      {
+        const int I = w.i >> 1, n1 = I + ((w.i & 1) ? 1 : -1);
+        ox[0] = I;
+        if (per) ox[1] = n1 < 0 ? n1 + C.nx : (n1 >= C.nx ? n1 - C.nx : n1);
+        else if (n1 < 0 || n1 >= C.nx) { ox[1] = I; gx = (T)-1; }
+        else ox[1] = n1;
+      }
+      {
+        const int J = w.j >> 1, n1 = J + ((w.j & 1) ? 1 : -1);
+        oy[0] = J * C.nx;
+        int jn;
+        if (per) jn = n1 < 0 ? n1 + C.ny : (n1 >= C.ny ? n1 - C.ny : n1);
+        else if (n1 < 0 || n1 >= C.ny) { jn = J; gy = (T)-1; }
+        else jn = n1;
+        oy[1] = jn * C.nx;
+      }
+      {
+        const int K = w.k >> 1, n1 = K + ((w.k & 1) ? 1 : -1);
+        oz[0] = K * cnxy;
+        int kn;
+        if (A.flat) kn = K;
+        else if (per) kn = n1 < 0 ? n1 + C.nz : (n1 >= C.nz ? n1 - C.nz : n1);
+        else if (n1 < 0 || n1 >= C.nz) { kn = K; gz = (T)-1; }
+        else kn = n1;
+        oz[1] = kn * cnxy;
+      }
+      const T e000 = E[oz[0] + oy[0] + ox[0]], e001 = E[oz[0] + oy[0] + ox[1]];
+      const T e010 = E[oz[0] + oy[1] + ox[0]], e011 = E[oz[0] + oy[1] + ox[1]];
+      const T e100 = E[oz[1] + oy[0] + ox[0]], e101 = E[oz[1] + oy[0] + ox[1]];
+      const T e110 = E[oz[1] + oy[1] + ox[0]], e111 = E[oz[1] + oy[1] + ox[1]];
+      // x first (3 e0 + gx e1), then y, then z
+      const T p00 = (T)3 * e000 + gx * e001, p01 = (T)3 * e010 + gx * e011;
+      const T p10 = (T)3 * e100 + gx * e101, p11 = (T)3 * e110 + gx * e111;
+      const T p0 = (T)3 * p00 + gy * p01, p1 = (T)3 * p10 + gy * p11;
+      U[q] += ((T)3 * p0 + gz * p1) * (T)(1.0 / 64.0);
     }
     __syncthreads();
     for (int q = 0; q < A.n_post; ++q) tau(l, false);
