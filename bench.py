@@ -68,6 +68,8 @@ def parse():
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--summarize-trace", metavar="TRACE_DIR")
     ap.add_argument("--only-two-d", action="store_true", help="run only the 2-D workload; print its JSON")
+    ap.add_argument("--cfg3", action="store_true",
+                    help="run only the 512^3 k^-3 random-field comparison (float64 vs mixed); print its JSON")
     ap.add_argument("--summarize-trace-2d", metavar="TRACE_DIR")
     return ap.parse_args()
 
@@ -313,6 +315,17 @@ def main():
         sys.exit(2)
     if args.pmc_probe:
         return pmc_probe()
+    if args.cfg3:
+        import torch
+
+        import paper_2306_05332_amd as R
+        import workloads as W
+        if not torch.cuda.is_available():
+            print("bench.py needs a GPU", file=sys.stderr)
+            sys.exit(2)
+        R.load_library()
+        print(json.dumps(run_cfg3(R, W, torch)), flush=True)
+        return
     if args.only_two_d:
         import torch
 
@@ -387,6 +400,20 @@ def main():
     traffic, traffic_note = read_traffic()
     print(f"# sweep: {t_launch_s * 1e6:.2f} us per launch, {achieved:.0f} GB/s", flush=True)
 
+    # achievable ceiling of this HBM: a plain device-to-device copy (read + write)
+    ca = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device=dev)
+    cb = torch.empty_like(ca)
+    for _ in range(3):
+        cb.copy_(ca)
+    ev0.record(stream)
+    for _ in range(20):
+        cb.copy_(ca)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * COPY_BYTES * 20 / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
+    del ca, cb
+    print(f"# device copy: {copy_gbs:.0f} GB/s", flush=True)
+
     # ---------------- accuracy vs the exact discrete solution (CPU FFT)
     from oracle import exact
     us = exact.exact_solution(4.0 * math.pi * prob.rho, h, "periodic")
@@ -445,6 +472,9 @@ def main():
         "rel_res": {"fp64": st.rel_res, "mixed": stm.rel_res},
         "max_rel_err_vs_exact": {"fp64": err64, "mixed": errm},
         "vcycle_cell_updates_per_s": n3 * st.cycles / t_fp64,
+        "sweep_cell_updates_per_s": n3 * opts.s / t_launch_s,
+        "achievable_ceiling": {"kernel": "device-to-device copy of 256 MiB (read + write)", "GB/s": copy_gbs,
+                               "sweep_frac_of_ceiling": achieved / copy_gbs},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_note": traffic_note,
                      "kernel": kernel_symbol(R, (N, N, N), opts.s), "bytes_per_launch": info["bytes_per_launch"],
@@ -508,6 +538,61 @@ def run_extras(R, W, torch, args):
     del rho, wt, phi
 
     out["two_d"] = run_two_d(R, W, torch)
+    out["sphere32"] = run_sphere32(R, W, torch)
+    return out
+
+
+def run_sphere32(R, W, torch):
+    """The 32^3 uniform sphere (Dirichlet faces from -M/r), float64 to 1e-10:
+    a latency-bound solve, reported as wall time; its L2 error against the
+    continuous potential (the density is point-sampled at cell centres)."""
+    import numpy as np
+    p = W.uniform_sphere(32)
+    rho = torch.from_numpy(p.rho).cuda()
+    faces = R.pack_faces(p.faces)
+    o = R.Options(tol=TOL)
+    R.solve(rho, p.h, "dirichlet", faces=faces, opts=o)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 20
+    for _ in range(reps):
+        phi, st = R.solve(rho, p.h, "dirichlet", faces=faces, opts=o)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / reps
+    e = phi.cpu().numpy() - p.phi_exact
+    l2 = float(np.sqrt(np.mean(e * e)) / np.sqrt(np.mean(p.phi_exact ** 2)))
+    print(f"# sphere 32^3: {t * 1e3:.3f} ms, cycles={st.cycles}, L2 error vs analytic {l2:.3e}", flush=True)
+    return {"n": 32, "bc": "dirichlet", "tol": TOL, "ms": t * 1e3, "cycles": st.cycles,
+            "rel_l2_error_vs_analytic": l2}
+
+
+def run_cfg3(R, W, torch, n=512):
+    """512^3 periodic k^-3 random field (seed 3): mixed precision against
+    float64, time to 1e-10 and max error against the FFT solution; and the
+    256^3 blob field (seed 2) for the same pair."""
+    import numpy as np
+    from oracle import exact
+    out = {}
+    for label, prob in (("grf512", W.gaussian_random_field(n, seed=3)), ("blobs256", W.gaussian_blobs(N, 16, seed=2))):
+        rho = torch.from_numpy(prob.rho).cuda()
+        us = exact.exact_solution(4.0 * math.pi * prob.rho, prob.h, "periodic")
+        res = {"n": prob.rho.shape[0]}
+        for prec in ("fp64", "mixed"):
+            o = R.Options(tol=TOL, prec=prec)
+            R.solve(rho, prob.h, "periodic", opts=o)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            reps = 3
+            for _ in range(reps):
+                phi, st = R.solve(rho, prob.h, "periodic", opts=o)
+            torch.cuda.synchronize()
+            t = (time.perf_counter() - t0) / reps
+            err = float(np.abs(phi.cpu().numpy() - us).max() / np.abs(us).max())
+            res[prec] = {"ms": t * 1e3, "cycles": st.cycles, "rel_res": st.rel_res, "max_rel_err_vs_fft": err}
+            print(f"# {label} {prec}: {t * 1e3:.2f} ms, cycles={st.cycles}, err {err:.2e}", flush=True)
+        res["mixed_speedup"] = res["fp64"]["ms"] / res["mixed"]["ms"]
+        out[label] = res
+        del rho
     return out
 
 
