@@ -575,11 +575,14 @@ static FusedGrid fused_grid(int bx, int by, int nx, int ny, int nz, int target, 
 }
 
 size_t fused_tau_blocks_max(int nx, int ny, int nz) {
-  // shortest chunk (4 planes) with the smallest tile of each family: 64 x 4
-  // (ring), 56 output columns x 4 rows (strip, s <= 4)
+  // shortest chunk of each family (ring / z-queue: 4 planes; strip: 1 plane)
+  // with its smallest tile: 64 x 4 (ring), 56 output columns x 4 rows (strip,
+  // s <= 4; the 2-D form's segments are wider)
   const size_t ring = (size_t)((nx + 63) / 64) * ((ny + 3) / 4) * ((nz + 3) / 4);
-  const size_t strip = (size_t)((nx + 55) / 56) * ((ny + 3) / 4) * ((nz + 3) / 4);
-  return std::max(ring, strip);
+  const size_t strip = (size_t)((nx + 55) / 56) * ((ny + 3) / 4) * (size_t)nz;
+  // 2-D form: segments of >= 4 x 56 columns per wavefront, chunks of one row
+  const size_t strip2d = nz == 1 ? (size_t)((nx + 223) / 224) * (size_t)ny : 0;
+  return std::max(ring, std::max(strip, strip2d));
 }
 
 // ---- tuning table

@@ -19,7 +19,7 @@ struct ConvState {
   int m;          // index of the next cycle-start state to test
   int result_m;   // cycle-start state the decision refers to (the answer)
   double rel;     // last relative residual
-  double mean;    // mean of the last tested residual (periodic float32 rhs)
+  double mean;    // mean of the last tested residual (diagnostic)
   double last[4]; // last four relative residuals (divergence test)
   double hist[CONV_HIST];
 };

@@ -13,6 +13,8 @@
 // more cycles than were needed).
 #include "kernels.h"
 
+#include <algorithm>
+
 namespace rkl {
 
 // 3-D launch shape for z-marching stencil kernels: a 64 x 4 thread tile in
@@ -527,11 +529,20 @@ void launch_sub_mean(T* a, size_t n, const double* sum, double count, const int*
   hipLaunchKernelGGL(k_sub_mean<T>, dim3(ew_blocks(n), bt.nb), dim3(EW_NT), 0, st, a, n, sum, count, bt, stop);
 }
 
+// Every workgroup of k_sub_mean_part re-reads all nblk partials, so it gets
+// about eight elements per thread (at most 2048 workgroups, at least 512 or
+// one per 256 elements) rather than one: the partial sums then cost a few MB
+// of L2 reads instead of one reduction per 256 elements.
+static inline unsigned sub_mean_part_blocks(size_t n) {
+  const size_t lo = std::min<size_t>(ew_blocks(n), 512);
+  return (unsigned)std::max(lo, std::min<size_t>(n / ((size_t)EW_NT * 8), 2048));
+}
+
 template <typename T>
 void launch_sub_mean_part(T* a, size_t n, const double* part, int nblk, int stride, int q, double count,
                           const int* stop, hipStream_t st, const Batch& bt) {
-  hipLaunchKernelGGL(k_sub_mean_part<T>, dim3(ew_blocks(n), bt.nb), dim3(EW_NT), 0, st, a, n, part, nblk, stride, q,
-                     count, bt, stop);
+  hipLaunchKernelGGL(k_sub_mean_part<T>, dim3(sub_mean_part_blocks(n), bt.nb), dim3(EW_NT), 0, st, a, n, part, nblk,
+                     stride, q, count, bt, stop);
 }
 
 template <typename T>

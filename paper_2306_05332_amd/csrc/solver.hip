@@ -954,10 +954,9 @@ rkl_status solve_mixed(Plan& P, const rkl_opts& o, const double* rho, const doub
       launch_residual<double, float>(V0, phi, P.f0, P.h32.b[0], P.part, stop, st);
       launch_check(P.part, nblk, 2, Res0Sqrt::ptr(P), o.tol, o.max_cycles, (double)F.n, P.dconv, st);
       check_launch();
-      if (P.periodic) {
-        launch_sub_mean<float>(P.h32.b[0], F.n, &P.dconv->mean, 1.0, stop, st);
-        check_launch();
-      }
+      // periodic: the defect of the mean-free f sums to zero up to rounding
+      // (the periodic M sums to zero); the rounding-level mean that the
+      // restriction carries is dropped on level 1, so level 0 needs no pass
       // one float32 V-cycle on M e = r from e = 0 (homogeneous level-0 ghosts)
       float* cur = P.h32.u[0];
       float* alt = P.h32.t[0];
@@ -1110,7 +1109,6 @@ ClassPlan& get_class(const rkl_grid& g, const rkl_opts& o, int nb) {
 }
 
 constexpr int CONV_INTS = (int)(sizeof(ConvState) / sizeof(int));
-constexpr int CONV_DOUBLES = (int)(sizeof(ConvState) / sizeof(double));
 
 // one outer iteration for every member of the class (stream-ordered, no sync)
 template <typename T>
@@ -1124,12 +1122,7 @@ void class_iteration(ClassPlan& C, Hier<T>& H, const rkl_opts& o, hipStream_t st
   launch_residual<double, T>(V0, C.phi, C.f0, H.b[0], C.part, stop, st, Batch{nb, (long long)F.n, 0, CONV_INTS, ps});
   launch_check(C.part, (int)resid_blocks(F.nx, F.ny, F.nz), 2, C.res0sq, o.tol, o.max_cycles, (double)F.n, C.conv,
                st, Batch{nb, 0, 0, 0, ps});
-  check_launch();
-  if (P.periodic) {
-    launch_sub_mean<T>(H.b[0], F.n, &C.conv->mean, 1.0, stop, st,
-                       Batch{nb, (long long)F.n, CONV_DOUBLES, CONV_INTS, 0});
-    check_launch();
-  }
+  check_launch();  // periodic: no level-0 mean pass (the defect is mean-free up to rounding; see solve_mixed)
   T* cur = H.u[0];
   T* alt = H.t[0];
   const Batch b0{nb, (long long)F.n, 0, CONV_INTS, ps};
@@ -1397,7 +1390,7 @@ int autotune_level(const rkl_grid& g, int s, int prec, int reps, rkl_tune_entry*
   check_launch();
   EventPair ev;
   std::vector<rkl_tune_entry> all;
-  const int targets[] = {128, 256, 512, 1024, 2048};
+  const int targets[] = {64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048, 3072, 4096};
   for (int v = 1; v < FV_COUNT; ++v) {
     if (!fused_variant_ok<T>(v, s) || variant_is_2d(v) != level_is_2d(V)) continue;
     for (int tg : targets) {

@@ -324,7 +324,9 @@ StripGrid strip_grid(int s, int R, int WY, int nx, int ny, int nz, int target, b
   }
   const int xy = g.gx * g.gy;
   const int chunks = std::max(1, (target + xy - 1) / xy);
-  g.zc = std::max(4, std::min(64, (nz + chunks - 1) / chunks));
+  // chunks down to one plane: on small (cache-resident, latency-bound) levels
+  // a shorter serial march beats the re-read of the chunk's boundary planes
+  g.zc = std::max(1, std::min(64, (nz + chunks - 1) / chunks));
   g.gz = (nz + g.zc - 1) / g.zc;
   g.nblk = g.gx * g.gy * g.gz;
   return g;
