@@ -43,12 +43,22 @@ void launch_reduce(const double* part, int nblk, int stride, int nq, double* out
                    hipStream_t st, const Batch& bt = single_batch());
 void launch_check(const double* part, int nblk, int stride, const double* res0sq, double tol, int max_cycles,
                   double count, ConvState* cs, hipStream_t st, const Batch& bt = single_batch());
-void launch_scale_tab(const double* const* tab, double* out, size_t n, double c, double* part, hipStream_t st,
-                      const Batch& bt);
+// member m (bt.nb members): out + m * s0 = c * (tab[m] - sum[m * s1] / count)
+// (sum nullptr: c * tab[m]); partials as launch_scale's at part + m * part_stride
+void launch_scale_tab(const double* const* tab, double* out, size_t n, double c, const double* sum, double count,
+                      double* part, hipStream_t st, const Batch& bt);
+// launch_sum over the members tab[m] (partials at part + m * part_stride)
+void launch_sum_tab(const double* const* tab, size_t n, double* part, hipStream_t st, const Batch& bt);
 void launch_copy_tab(double* const* tab, const double* src, size_t n, hipStream_t st, const Batch& bt);
 template <typename T>
 void launch_fill(T* a, size_t n, T v, const int* stop, hipStream_t st, const Batch& bt = single_batch());
-void launch_scale(const double* in, double* out, size_t n, double c, double* part, hipStream_t st);
+// out = c * (in - sum[0] / count) (sum nullptr: c * in); partials of out and
+// out^2 into part[2 blk], part[2 blk + 1] for ew_block_count(n) blocks
+void launch_scale(const double* in, double* out, size_t n, double c, const double* sum, double count, double* part,
+                  hipStream_t st);
+// dst = src - sum[0] / count, dst and src distinct
+void launch_copy_sub_mean(double* dst, const double* src, size_t n, const double* sum, double count,
+                          hipStream_t st);
 template <typename T>
 void launch_sub_mean_part(T* a, size_t n, const double* part, int nblk, int stride, int q, double count,
                           const int* stop, hipStream_t st, const Batch& bt = single_batch());

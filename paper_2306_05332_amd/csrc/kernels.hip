@@ -7,7 +7,8 @@
 //                    (eq. restriction_example_2D) for a one-plane fine grid
 //   k_reduce         fixed-order sum of per-block partials
 //   k_check          convergence test of the V-cycle loop on the device
-//   k_scale / k_sub_mean / k_fill / k_sum / k_add_cast: elementwise helpers
+//   k_scale / k_sub_mean / k_copy_sub_mean / k_fill / k_sum / k_add_cast:
+//                    elementwise helpers
 // Kernels launched inside a V-cycle take `stop`: once the device-side
 // convergence test has set it, they return at once (the host may have queued
 // more cycles than were needed).
@@ -267,8 +268,7 @@ __global__ __launch_bounds__(RED_NT) void k_reduce(const double* __restrict__ pa
 // start of cycle cs->m; records it and decides, in the host loop's order:
 // non-finite -> RKL_ENONFINITE; rel <= tol -> done; three consecutive
 // increases -> RKL_EDIVERGED; m >= max_cycles -> RKL_ENOCONV.  Also stores
-// the mean of the residual (part[b * stride + 1] / count) for the periodic
-// float32 right-hand side of the mixed-precision loop.
+// the mean of the residual (part[b * stride + 1] / count) as a diagnostic.
 __global__ __launch_bounds__(RED_NT) void k_check(const double* __restrict__ part, int nblk, int stride,
                                                   const double* __restrict__ res0sq, double tol,
                                                   int max_cycles, double count, ConvState* __restrict__ cs,
@@ -324,35 +324,43 @@ __global__ __launch_bounds__(EW_NT) void k_fill(T* __restrict__ a, size_t n, T v
     a[q] = v;
 }
 
-// out = c * in, with float64 block partial sums of out into part[blk]
-__global__ __launch_bounds__(EW_NT) void k_scale(const double* __restrict__ in, double* __restrict__ out,
-                                                 size_t n, double c, double* __restrict__ part) {
-  __shared__ double sh[EW_NT / WAVE];
-  double s = 0.0;
+// One workgroup's share of out = c * (in - m), with float64 partial sums of
+// out and of out^2 into part[2 blk], part[2 blk + 1].  The single and the
+// batched source preparation share it, so both compute the same bits.
+__device__ __forceinline__ void scale_shift_share(const double* __restrict__ in, double* __restrict__ out, size_t n,
+                                                  double c, double m, double* __restrict__ part, double* sh) {
+  double s = 0.0, s2 = 0.0;
   for (size_t q = (size_t)blockIdx.x * EW_NT + threadIdx.x; q < n; q += (size_t)gridDim.x * EW_NT) {
-    const double v = c * in[q];
+    const double v = c * (in[q] - m);
     out[q] = v;
     s += v;
+    s2 += v * v;
   }
   const double t = block_sum<EW_NT>(s, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = t;
+  const double t2 = block_sum<EW_NT>(s2, sh);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = t;
+    part[2 * blockIdx.x + 1] = t2;
+  }
 }
 
-// out (member m at out + m * s0) = c * tab[m], float64 block partials per member
-__global__ __launch_bounds__(EW_NT) void k_scale_tab(const double* const* __restrict__ tab, double* __restrict__ out,
-                                                     size_t n, double c, double* __restrict__ part, Batch bt) {
+// out = c * (in - sum[0] / count), or c * in when sum is nullptr
+__global__ __launch_bounds__(EW_NT) void k_scale(const double* __restrict__ in, double* __restrict__ out,
+                                                 size_t n, double c, const double* __restrict__ sum, double count,
+                                                 double* __restrict__ part) {
   __shared__ double sh[EW_NT / WAVE];
-  const double* in = tab[blockIdx.y];
-  out += (long long)blockIdx.y * bt.s0;
-  part += (long long)blockIdx.y * bt.part_stride;
-  double s = 0.0;
-  for (size_t q = (size_t)blockIdx.x * EW_NT + threadIdx.x; q < n; q += (size_t)gridDim.x * EW_NT) {
-    const double v = c * in[q];
-    out[q] = v;
-    s += v;
-  }
-  const double t = block_sum<EW_NT>(s, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = t;
+  scale_shift_share(in, out, n, c, sum != nullptr ? sum[0] / count : 0.0, part, sh);
+}
+
+// member m: out + m * s0 = c * (tab[m] - sum[m * s1] / count) (sum nullptr:
+// c * tab[m]), partials at part + m * part_stride
+__global__ __launch_bounds__(EW_NT) void k_scale_tab(const double* const* __restrict__ tab, double* __restrict__ out,
+                                                     size_t n, double c, const double* __restrict__ sum, double count,
+                                                     double* __restrict__ part, Batch bt) {
+  __shared__ double sh[EW_NT / WAVE];
+  const long long mb = blockIdx.y;
+  scale_shift_share(tab[mb], out + mb * bt.s0, n, c, sum != nullptr ? sum[mb * bt.s1] / count : 0.0,
+                    part + mb * bt.part_stride, sh);
 }
 
 // tab[m] = src (member m at src + m * s0)
@@ -363,7 +371,6 @@ __global__ __launch_bounds__(EW_NT) void k_copy_tab(double* const* __restrict__ 
   for (size_t q = (size_t)blockIdx.x * EW_NT + threadIdx.x; q < n; q += (size_t)gridDim.x * EW_NT) dst[q] = src[q];
 }
 
-// a -= sum[0] / count
 // a -= (sum of part[b * stride + q] over b < nblk) / count: every workgroup
 // sums the partials itself in the same fixed order (so all of them subtract
 // the same value), which saves the separate reduction launch
@@ -399,18 +406,37 @@ __global__ __launch_bounds__(EW_NT) void k_sub_mean(T* __restrict__ a, size_t n,
     a[q] -= m;
 }
 
-// part[blk] = float64 sum of a over the block's share
+// dst = src - sum[0] / count (dst and src distinct)
+__global__ __launch_bounds__(EW_NT) void k_copy_sub_mean(double* __restrict__ dst, const double* __restrict__ src,
+                                                         size_t n, const double* __restrict__ sum, double count) {
+  const double m = sum[0] / count;
+  for (size_t q = (size_t)blockIdx.x * EW_NT + threadIdx.x; q < n; q += (size_t)gridDim.x * EW_NT)
+    dst[q] = src[q] - m;
+}
+
+// part[blk] = float64 sum of a over the workgroup's share (shared by k_sum
+// and k_sum_tab so that both compute the same bits)
 template <typename T>
-__global__ __launch_bounds__(EW_NT) void k_sum(const T* __restrict__ a, size_t n, double* __restrict__ part,
-                                               Batch bt) {
-  __shared__ double sh[EW_NT / WAVE];
-  a += (long long)blockIdx.y * bt.s0;
-  part += (long long)blockIdx.y * bt.part_stride;
+__device__ __forceinline__ void sum_share(const T* __restrict__ a, size_t n, double* __restrict__ part, double* sh) {
   double s = 0.0;
   for (size_t q = (size_t)blockIdx.x * EW_NT + threadIdx.x; q < n; q += (size_t)gridDim.x * EW_NT)
     s += (double)a[q];
   const double t = block_sum<EW_NT>(s, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+template <typename T>
+__global__ __launch_bounds__(EW_NT) void k_sum(const T* __restrict__ a, size_t n, double* __restrict__ part,
+                                               Batch bt) {
+  __shared__ double sh[EW_NT / WAVE];
+  sum_share<T>(a + (long long)blockIdx.y * bt.s0, n, part + (long long)blockIdx.y * bt.part_stride, sh);
+}
+
+// the same over member m = tab[m]
+__global__ __launch_bounds__(EW_NT) void k_sum_tab(const double* const* __restrict__ tab, size_t n,
+                                                   double* __restrict__ part, Batch bt) {
+  __shared__ double sh[EW_NT / WAVE];
+  sum_share<double>(tab[blockIdx.y], n, part + (long long)blockIdx.y * bt.part_stride, sh);
 }
 
 // u64 += (double) e
@@ -505,9 +531,14 @@ void launch_check(const double* part, int nblk, int stride, const double* res0sq
                      count, cs, bt);
 }
 
-void launch_scale_tab(const double* const* tab, double* out, size_t n, double c, double* part, hipStream_t st,
-                      const Batch& bt) {
-  hipLaunchKernelGGL(k_scale_tab, dim3(ew_blocks(n), bt.nb), dim3(EW_NT), 0, st, tab, out, n, c, part, bt);
+void launch_scale_tab(const double* const* tab, double* out, size_t n, double c, const double* sum, double count,
+                      double* part, hipStream_t st, const Batch& bt) {
+  hipLaunchKernelGGL(k_scale_tab, dim3(ew_blocks(n), bt.nb), dim3(EW_NT), 0, st, tab, out, n, c, sum, count, part,
+                     bt);
+}
+
+void launch_sum_tab(const double* const* tab, size_t n, double* part, hipStream_t st, const Batch& bt) {
+  hipLaunchKernelGGL(k_sum_tab, dim3(ew_blocks(n), bt.nb), dim3(EW_NT), 0, st, tab, n, part, bt);
 }
 
 void launch_copy_tab(double* const* tab, const double* src, size_t n, hipStream_t st, const Batch& bt) {
@@ -519,8 +550,14 @@ void launch_fill(T* a, size_t n, T v, const int* stop, hipStream_t st, const Bat
   hipLaunchKernelGGL(k_fill<T>, dim3(ew_blocks(n), bt.nb), dim3(EW_NT), 0, st, a, n, v, bt, stop);
 }
 
-void launch_scale(const double* in, double* out, size_t n, double c, double* part, hipStream_t st) {
-  hipLaunchKernelGGL(k_scale, dim3(ew_blocks(n)), dim3(EW_NT), 0, st, in, out, n, c, part);
+void launch_scale(const double* in, double* out, size_t n, double c, const double* sum, double count, double* part,
+                  hipStream_t st) {
+  hipLaunchKernelGGL(k_scale, dim3(ew_blocks(n)), dim3(EW_NT), 0, st, in, out, n, c, sum, count, part);
+}
+
+void launch_copy_sub_mean(double* dst, const double* src, size_t n, const double* sum, double count,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_copy_sub_mean, dim3(ew_blocks(n)), dim3(EW_NT), 0, st, dst, src, n, sum, count);
 }
 
 template <typename T>

@@ -286,9 +286,10 @@ Plan& get_plan(const rkl_grid& g, int s, double theta, int min_coarse, int prec)
       P->h32.t[l] = P->alloc<float>(P->lv[l].n);
     }
   }
-  // partial sums: residual kernels (pairs), fused tau-step (one per block), elementwise sums
+  // partial sums: residual kernels (pairs), fused tau-step (one per block), elementwise
+  // sums (pairs for the source scaling)
   size_t cap = 2 * resid_blocks(g.nx, g.ny, g.nz);
-  cap = std::max(cap, ew_block_count(P->lv[0].n));
+  cap = std::max(cap, 2 * ew_block_count(P->lv[0].n));
   cap = std::max(cap, fused_tau_blocks_max(P->lv[0].nx, P->lv[0].ny, P->lv[0].nz));
   cap = std::max(cap, (size_t)1024);
   P->part = P->alloc<double>(cap);
@@ -683,16 +684,20 @@ void fold_faces(Plan& P, const double* faces, const double* src, double* dst, hi
   }
 }
 
-// f0 = four_pi_G * rho, mean removed when periodic
+// f0 = four_pi_G * rho, mean removed when periodic (f0 = c (rho - mean rho):
+// one read-only pass for the sum, one pass writing f0); the scaling pass
+// leaves the block partials of f0^2 in P.part (stride 2, offset 1)
 void prepare_source(Plan& P, const double* rho, double c, hipStream_t st) {
   const size_t n = P.lv[0].n;
-  launch_scale(rho, P.f0, n, c, P.part, st);
-  check_launch();
+  const double* sum = nullptr;
   if (P.periodic) {
+    launch_sum<double>(rho, n, P.part, st);
     launch_reduce(P.part, (int)ew_block_count(n), 1, 1, P.dscal + 8, nullptr, st);
-    launch_sub_mean<double>(P.f0, n, P.dscal + 8, (double)n, nullptr, st);
     check_launch();
+    sum = P.dscal + 8;
   }
+  launch_scale(rho, P.f0, n, c, sum, (double)n, P.part, st);
+  check_launch();
 }
 
 void copy_d2d(double* dst, const double* src, size_t n, hipStream_t st) {
@@ -780,8 +785,13 @@ bool solve_start(Plan& P, const rkl_opts& o, const double* rho, const double* fa
   const Lev& F = P.lv[0];
   const LevelView<double> V0 = view<double>(F, P.periodic, nullptr);
   prepare_source(P, rho, o.four_pi_G, st);
-  fold_faces(P, faces, P.f0, P.f0, st);
-  resid_norm2_async<double>(P, V0, nullptr, P.f0, st);
+  if (faces != nullptr) {
+    fold_faces(P, faces, P.f0, P.f0, st);
+    resid_norm2_async<double>(P, V0, nullptr, P.f0, st);
+  } else {  // ||M 0 - f0||^2 is the sum of f0^2: the scaling pass's partials
+    launch_reduce(P.part + 1, (int)ew_block_count(F.n), 2, 1, P.dscal, nullptr, st);
+    check_launch();
+  }
   HIPCHK(hipMemcpyAsync(P.dscal + 4, P.dscal, sizeof(double), hipMemcpyDeviceToDevice, st));  // res0^2
   res0 = std::sqrt(readback(P, 1, st)[0]);
   if (stats) {
@@ -926,8 +936,15 @@ rkl_status solve_fp64(Plan& P, const rkl_opts& o, const double* rho, const doubl
   }
   const int rm = cs.result_m;
   double* res = bufs[start[rm]];
-  if (res != phi) copy_d2d(phi, res, F.n, st);
-  if (P.periodic) remove_mean<double>(P, phi, F.n, nullptr, st);
+  if (P.periodic && res != phi) {  // phi = res - mean(res): the copy carries the mean removal
+    launch_sum<double>(res, F.n, P.part, st);
+    launch_reduce(P.part, (int)ew_block_count(F.n), 1, 1, P.dscal + 8, nullptr, st);
+    launch_copy_sub_mean(phi, res, F.n, P.dscal + 8, (double)F.n, st);
+    check_launch();
+  } else {
+    if (res != phi) copy_d2d(phi, res, F.n, st);
+    if (P.periodic) remove_mean<double>(P, phi, F.n, nullptr, st);
+  }
   HIPCHK(hipStreamSynchronize(st));
   fill_stats(stats, cs, rm);
   return finish_status(cs);
@@ -1077,7 +1094,7 @@ ClassPlan& get_class(const rkl_grid& g, const rkl_opts& o, int nb) {
   const Lev& F = base.lv[0];
   const int L = base.L();
   size_t ps = 2 * resid_blocks(F.nx, F.ny, F.nz);
-  ps = std::max(ps, ew_block_count(F.n));
+  ps = std::max(ps, 2 * ew_block_count(F.n));
   ps = std::max(ps, fused_tau_blocks_max(F.nx, F.ny, F.nz));
   C->part_stride = (int)ps;
   C->f0 = C->alloc<double>((size_t)nb * F.n);
@@ -1156,16 +1173,19 @@ std::vector<double> class_start(ClassPlan& C, const rkl_opts& o, const double* c
   const int nb = C.nb, ps = C.part_stride;
   HIPCHK(hipMemcpyAsync(C.tab_in, rho, nb * sizeof(double*), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(C.tab_out, phi, nb * sizeof(double*), hipMemcpyHostToDevice, st));
-  launch_scale_tab(C.tab_in, C.f0, F.n, o.four_pi_G, C.part, st, Batch{nb, (long long)F.n, 0, 0, ps});
-  check_launch();
+  // the single solve's arithmetic (prepare_source, solve_start), member by member
+  const int nblk = (int)ew_block_count(F.n);
+  const double* sum = nullptr;
   if (P.periodic) {
-    launch_reduce(C.part, (int)ew_block_count(F.n), 1, 1, C.dsum, nullptr, st, Batch{nb, 2, 0, 0, ps});
-    launch_sub_mean<double>(C.f0, F.n, C.dsum, (double)F.n, nullptr, st, Batch{nb, (long long)F.n, 2, 0, 0});
+    launch_sum_tab(C.tab_in, F.n, C.part, st, Batch{nb, 0, 0, 0, ps});
+    launch_reduce(C.part, nblk, 1, 1, C.dsum, nullptr, st, Batch{nb, 2, 0, 0, ps});
+    sum = C.dsum;
   }
-  const LevelView<double> V0 = view<double>(F, P.periodic, nullptr);
-  launch_residual<double, double>(V0, nullptr, C.f0, (double*)nullptr, C.part, nullptr, st,
-                                  Batch{nb, (long long)F.n, 0, 0, ps});
-  launch_reduce(C.part, (int)resid_blocks(F.nx, F.ny, F.nz), 2, 1, C.res0sq, nullptr, st, Batch{nb, 1, 0, 0, ps});
+  launch_scale_tab(C.tab_in, C.f0, F.n, o.four_pi_G, sum, (double)F.n, C.part, st,
+                   Batch{nb, (long long)F.n, 2, 0, ps});
+  check_launch();
+  // ||M 0 - f0||^2 = sum of f0^2 (no face data in batched solves)
+  launch_reduce(C.part + 1, nblk, 2, 1, C.res0sq, nullptr, st, Batch{nb, 1, 0, 0, ps});
   launch_fill<double>(C.phi, F.n, 0.0, nullptr, st, Batch{nb, (long long)F.n, 0, 0, 0});
   check_launch();
   // zero right-hand sides: relative residual 0 at once (phi stays 0)
