@@ -722,6 +722,18 @@ size_t fused_tau_blocks_as(const LevelView<T>& L, FusedChoice c, int s) {
 }
 
 template <typename T>
+int fused_chunk_blocks(const LevelView<T>& L, int variant, int s) {
+  if (variant_is_2d(variant)) {
+    const bool r8 = variant == FV_STRIP2D_8 && (sizeof(T) == 4 || s <= 2);
+    return strip_grid(s, r8 ? 8 : 4, 1, L.nx, 1, L.ny, 1, true).per;
+  }
+  if (!is_strip(variant)) return 0;
+  int R, WY;
+  strip_shape(variant, R, WY);
+  return strip_grid(s, R, WY, L.nx, L.ny, L.nz, 1).per;
+}
+
+template <typename T>
 size_t fused_tau_blocks(const LevelView<T>& L, int s) {
   return fused_tau_blocks_as<T>(L, fused_choice<T>(L, s), s);
 }
@@ -798,6 +810,7 @@ const char* fused_variant_name(int variant) {
   template FusedChoice fused_choice<T>(const LevelView<T>&, int);                                                 \
   template size_t fused_tau_blocks<T>(const LevelView<T>&, int);                                                  \
   template size_t fused_tau_blocks_as<T>(const LevelView<T>&, FusedChoice, int);                                  \
+  template int fused_chunk_blocks<T>(const LevelView<T>&, int, int);                                              \
   template bool launch_fused_tau<T>(const LevelView<T>&, const T*, const T*, T*, int, const StageCoef*, double*,  \
                                     const int*, hipStream_t, const Batch&);                                       \
   template bool launch_fused_tau_as<T>(const LevelView<T>&, FusedChoice, const T*, const T*, T*, int,             \

@@ -135,6 +135,10 @@ template <typename T>
 FusedChoice fused_choice(const LevelView<T>& L, int s);
 template <typename T>
 size_t fused_tau_blocks_as(const LevelView<T>& L, FusedChoice c, int s);
+// workgroups per z chunk of a strip variant on this level (0: not a strip
+// variant); a target of per * c gives c chunks
+template <typename T>
+int fused_chunk_blocks(const LevelView<T>& L, int variant, int s);
 template <typename T>
 bool launch_fused_tau_as(const LevelView<T>& L, FusedChoice c, const T* u, const T* b, T* out, int s,
                          const StageCoef* co, double* part, const int* stop, hipStream_t st,
@@ -145,8 +149,21 @@ size_t fused_tau_blocks_max(int nx, int ny, int nz);  // over every variant and 
 // strip of R = 8 or 4 rows, 4 or 1 wavefronts per workgroup stacked in y.
 // The 2-D form marches y with R x segments per lane (flat = true: nx, ny, nz
 // describe the transposed view, ny = 1 and nz = the 2-D row count).
+// Workgroup layout of the strip kernel.  Three-dimensional one-wavefront
+// variants pack the x remainder: when nx = txf * ox + rem, the remainder
+// column block of pk interior strips (no row of them wraps or leaves the box)
+// shares one wavefront, pk segments of rem + 2 s lanes side by side.  Per z
+// chunk the workgroups are then: txf * gy full tiles, npk packed wavefronts
+// (strips fi + k pk .. fi + k pk + pk - 1), and one remainder wavefront for each
+// strip left over (strips below fi and from fi + npk pk on).  pk = 0: no packing
+// (tiles tx = 0 .. gx - 1 over every strip).
+struct StripMap {
+  int txf, pk, npk, fi, per;
+};
 struct StripGrid {
   int ox, gx, gy, zc, gz, nblk;
+  int per;  // workgroups per z chunk (nblk = per * gz)
+  StripMap map;
 };
 StripGrid strip_grid(int s, int R, int WY, int nx, int ny, int nz, int target, bool flat = false);
 template <typename T, int S, int R, int WY>

@@ -1413,7 +1413,22 @@ int autotune_level(const rkl_grid& g, int s, int prec, int reps, rkl_tune_entry*
   const int targets[] = {64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048, 3072, 4096};
   for (int v = 1; v < FV_COUNT; ++v) {
     if (!fused_variant_ok<T>(v, s) || variant_is_2d(v) != level_is_2d(V)) continue;
-    for (int tg : targets) {
+    std::vector<int> tgs(std::begin(targets), std::end(targets));
+    // strip variants: every distinct chunk length (1 .. 64 planes), since the
+    // time depends on how evenly the workgroups fill the chip's SIMDs
+    const int per = fused_chunk_blocks<T>(V, v, s);
+    if (per > 0) {  // (the fixed targets stay, for the built-in choice's time)
+      const int nmarch = level_is_2d(V) ? V.ny : V.nz;  // planes (2-D: rows) a chunk splits
+      int last = -1;
+      for (int zc = std::min(64, nmarch); zc >= 1; --zc) {
+        const int chunks = (nmarch + zc - 1) / zc;
+        if (chunks == last) continue;
+        last = chunks;
+        if ((long long)per * chunks > (1 << 22)) break;
+        tgs.push_back(per * chunks);
+      }
+    }
+    for (int tg : tgs) {
       const FusedChoice c{v, tg};
       for (int w = 0; w < 2; ++w) {
         launch_fused_tau_as<T>(V, c, u, b, o, s, Lv.smooth.data(), part, nullptr, st);

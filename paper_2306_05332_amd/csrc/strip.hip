@@ -25,6 +25,15 @@
 // Optionally the kernel returns float64 partial sums of (M u - b)^2 over its
 // output cells (the residual of the tau-step's input).
 //
+// x tiles hold 64 - 2S output columns, so nx is rarely a multiple of them;
+// the last tile of a row of strips would then run mostly idle lanes (at
+// nx = 256, S = 2: 16 of its 60 output lanes).  One-wavefront 3-D variants
+// instead give that remainder of several interior strips to one wavefront,
+// each strip in its own segment of rem + 2S lanes (StripMap).  A segment's
+// rows are the base strip's shifted by a whole number of strips, which the
+// lane folds into its column byte offset; the wavefront shifts then carry
+// halo garbage across a segment boundary only into halo lanes.
+//
 // With GS = true the same two-stage pass is one red-black Gauss-Seidel
 // (omega-SOR) iteration (Sec. 2.2.4): stage 1 updates the red cells
 // ((i + j + k) even) from the old values, stage 2 the black cells from the
@@ -50,7 +59,7 @@ template <typename T, int S, int R, int WY, bool PER, bool UZ, bool GS, bool FLA
 __global__ __launch_bounds__(64 * WY) void k_tau_strip(LevelView<T> L, const T* __restrict__ u,
                                                        const T* __restrict__ b, T* __restrict__ out,
                                                        FCoef<T, S> co, int zc, int gx_tiles, int gy_tiles,
-                                                       int nblk, double* __restrict__ part, Batch bt,
+                                                       int nblk, StripMap sm, double* __restrict__ part, Batch bt,
                                                        const int* __restrict__ stop) {
   {
     const long long mb = blockIdx.y;
@@ -74,16 +83,42 @@ __global__ __launch_bounds__(64 * WY) void k_tau_strip(LevelView<T> L, const T* 
   const long long sxy = (long long)nx * ny;
   int bid = blockIdx.x;
   if ((nblk & 7) == 0) bid = (bid & 7) * (nblk >> 3) + (bid >> 3);  // neighbouring tiles on one XCD
-  const int tx = bid % gx_tiles;
-  const int ty = (bid / gx_tiles) % gy_tiles;
-  const int tz = bid / (gx_tiles * gy_tiles);
-  const int gxu = tx * OX - S + lane;        // column of this lane (unwrapped; 3-D form)
+  int tx, ty, tz;
+  int xl = lane, xw = 64;  // lane within its x segment, segment width (halo lanes included)
+  int yshift = 0;          // rows from the wavefront's base strip to this lane's strip
+  if (!FLAT && WY == 1 && sm.pk > 0) {
+    tz = bid / sm.per;
+    const int r = bid - tz * sm.per, nfull = sm.txf * gy_tiles;
+    if (r < nfull) {
+      tx = r % sm.txf;
+      ty = r / sm.txf;
+    } else {
+      tx = sm.txf;
+      const int k = r - nfull;
+      if (k < sm.npk) {  // packed remainder: pk interior strips side by side
+        ty = sm.fi + k * sm.pk;
+        xw = nx - sm.txf * OX + 2 * S;
+        const int q = min(lane / xw, sm.pk - 1);  // lanes past the last segment: idle (never own)
+        xl = lane - q * xw;
+        yshift = q * R;
+      } else {
+        const int m = k - sm.npk;
+        ty = m < sm.fi ? m : m + sm.npk * sm.pk;
+      }
+    }
+  } else {
+    tx = bid % gx_tiles;
+    ty = (bid / gx_tiles) % gy_tiles;
+    tz = bid / (gx_tiles * gy_tiles);
+  }
+  const int gxu = tx * OX - S + xl;          // column of this lane (unwrapped; 3-D form)
   const int y0 = FLAT ? 0 : (ty * WY + w) * R - S;  // row of strip index 0 (unwrapped, wave-uniform)
   const int z0 = tz * zc, z1 = min(z0 + zc, nz);
   const bool xin = gxu >= 0 && gxu < nx;
   const int gx = PER ? ((gxu % nx) + nx) % nx : min(max(gxu, 0), nx - 1);
-  const unsigned xb = (unsigned)gx * (unsigned)sizeof(T);  // byte offset of this lane's column
-  const bool xown = lane >= S && lane < 64 - S && xin;
+  // byte offset of this lane's column (and, in a packed wavefront, of its strip's rows)
+  const unsigned xb = ((unsigned)gx + (unsigned)yshift * (unsigned)nx) * (unsigned)sizeof(T);
+  const bool xown = xl >= S && xl < xw - S && xin;
   const bool xlo = !PER && gxu == 0, xhi = !PER && gxu == nx - 1;
   // FLAT: per-segment column byte offsets and bit masks (bit i: segment i)
   unsigned sxb[FLAT ? R : 1];
@@ -315,6 +350,7 @@ __global__ __launch_bounds__(64 * WY) void k_tau_strip(LevelView<T> L, const T* 
 StripGrid strip_grid(int s, int R, int WY, int nx, int ny, int nz, int target, bool flat) {
   StripGrid g;
   g.ox = 64 - 2 * s;
+  g.map = StripMap{0, 0, 0, 0, 0};
   if (flat) {
     g.gx = (nx + g.ox * R * WY - 1) / (g.ox * R * WY);
     g.gy = 1;
@@ -322,13 +358,26 @@ StripGrid strip_grid(int s, int R, int WY, int nx, int ny, int nz, int target, b
     g.gx = (nx + g.ox - 1) / g.ox;
     g.gy = (ny + R * WY - 1) / (R * WY);
   }
-  const int xy = g.gx * g.gy;
-  const int chunks = std::max(1, (target + xy - 1) / xy);
+  int per = g.gx * g.gy;  // workgroups per z chunk
+  if (!flat && WY == 1) {
+    const int txf = nx / g.ox, rem = nx - txf * g.ox;
+    const int pk = rem > 0 ? 64 / (rem + 2 * s) : 0;
+    // interior strips: rows ty R - s .. ty R + R + s - 1 all inside 0 .. ny - 1
+    const int fi = (s + R - 1) / R;
+    const int li = ny - R - s >= 0 ? (ny - R - s) / R : -1;
+    const int npk = (pk >= 2 && li >= fi) ? (li - fi + 1) / pk : 0;
+    if (npk > 0) {
+      g.map = StripMap{txf, pk, npk, fi, txf * g.gy + npk + (g.gy - npk * pk)};
+      per = g.map.per;
+    }
+  }
+  const int chunks = std::max(1, (target + per - 1) / per);
   // chunks down to one plane: on small (cache-resident, latency-bound) levels
   // a shorter serial march beats the re-read of the chunk's boundary planes
   g.zc = std::max(1, std::min(64, (nz + chunks - 1) / chunks));
   g.gz = (nz + g.zc - 1) / g.zc;
-  g.nblk = g.gx * g.gy * g.gz;
+  g.per = per;
+  g.nblk = per * g.gz;
   return g;
 }
 
@@ -353,17 +402,17 @@ static void launch_strip_k(const LevelView<T>& L0, int target, const T* u, const
   if (L.periodic) {
     if (u == nullptr)
       hipLaunchKernelGGL((k_tau_strip<T, S, R, WY, true, true, GS, FLAT>), grid, block, 0, st, L, u, b, out, fc,
-                         g.zc, g.gx, g.gy, g.nblk, part, bt, stop);
+                         g.zc, g.gx, g.gy, g.nblk, g.map, part, bt, stop);
     else
       hipLaunchKernelGGL((k_tau_strip<T, S, R, WY, true, false, GS, FLAT>), grid, block, 0, st, L, u, b, out, fc,
-                         g.zc, g.gx, g.gy, g.nblk, part, bt, stop);
+                         g.zc, g.gx, g.gy, g.nblk, g.map, part, bt, stop);
   } else {
     if (u == nullptr)
       hipLaunchKernelGGL((k_tau_strip<T, S, R, WY, false, true, GS, FLAT>), grid, block, 0, st, L, u, b, out, fc,
-                         g.zc, g.gx, g.gy, g.nblk, part, bt, stop);
+                         g.zc, g.gx, g.gy, g.nblk, g.map, part, bt, stop);
     else
       hipLaunchKernelGGL((k_tau_strip<T, S, R, WY, false, false, GS, FLAT>), grid, block, 0, st, L, u, b, out, fc,
-                         g.zc, g.gx, g.gy, g.nblk, part, bt, stop);
+                         g.zc, g.gx, g.gy, g.nblk, g.map, part, bt, stop);
   }
 }
 

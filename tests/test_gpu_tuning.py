@@ -42,9 +42,12 @@ def _restore_table():
     R.install_default_tuning()
 
 
-# ragged in x, y and z for every tile shape; the last one spans several
-# z-queue tiles in x and y
-VSHAPES = [(20, 11, 130), (16, 16, 16), (40, 24, 64), (72, 130, 160)]
+# ragged in x, y and z for every tile shape; (72, 130, 160) spans several
+# z-queue tiles in x and y.  The last two pack the x remainder of interior
+# strips into shared wavefronts in the one-wavefront strip variants
+# (nx = 136: 3 or 4 strips per wavefront, with unpacked interior strips left
+# over; nx = 20: no full tile, 2 strips per wavefront)
+VSHAPES = [(20, 11, 130), (16, 16, 16), (40, 24, 64), (72, 130, 160), (11, 100, 136), (9, 60, 20)]
 VARIANTS = ["ring64x8", "ring64x4", "zq64x32", "zq64x16", "strip8x4", "strip8x1", "strip4x4", "strip5x1"]
 # stage counts each variant is built for: (float64, float32)
 SUPPORT = {"ring64x8": ((1, 2, 3), (1, 2, 3, 4)), "ring64x4": ((1, 2, 3), (1, 2, 3, 4)),
@@ -101,6 +104,31 @@ def test_forced_variant_float32_solve(variant, bc, s):
     assert st.status == 0 and st.cycles == ref.cycles
     np.testing.assert_allclose(st.history, ref.history, rtol=1e-4)
     us = exact.exact_solution(4 * math.pi * p.rho, p.h, bc, None)
+    assert relmax(phi.cpu().numpy(), us) < 1e-9
+
+
+@pytest.mark.parametrize("variant", ["strip8x1", "strip5x1"])
+@pytest.mark.parametrize("bc", ["periodic", "dirichlet"])
+def test_packed_remainder_solve(variant, bc):
+    """float64 solve with a one-wavefront strip variant on every fused level of
+    a (48, 96, 136) hierarchy, whose two finest levels pack their x remainder
+    (the convergence test reads the packed kernel's residual partials): the
+    same cycles and residual history as the built-in choice, and u*."""
+    R = _lib()
+    shape = (48, 96, 136)
+    h = (0.010, 0.012, 0.015)
+    rng = np.random.default_rng(12)
+    rho = rng.standard_normal(shape)
+    o = R.Options(tol=1e-10, s=2)
+    R.tune_clear()
+    _, ref = R.solve(cu(rho), h, bc, opts=o)
+    R.tune_set([{"nx": nx, "ny": ny, "nz": nz, "bc": bc, "prec": "fp64", "s": 2, "variant": variant,
+                 "target": t} for (nz, ny, nx) in ((48, 96, 136), (24, 48, 68), (12, 24, 34)) for t in (1024,)])
+    print(f"variant={variant} bc={bc} shape={shape}", flush=True)
+    phi, st = R.solve(cu(rho), h, bc, opts=o)
+    assert st.status == 0 and st.cycles == ref.cycles
+    np.testing.assert_allclose(st.history, ref.history, rtol=1e-6)
+    us = exact.exact_solution(4 * math.pi * rho, h, bc, None)
     assert relmax(phi.cpu().numpy(), us) < 1e-9
 
 
