@@ -20,7 +20,8 @@ Printed on one JSON line:
                workload: V-cycles from a cold start
 Also: time to 1e-10 for the float64 and mixed-precision paths, cycles, the
 max-norm error of each against the exact discrete solution (FFT), the batched
-96-grid workload, and the adjoint (forward + backward) of 8 x 128^3 solves.
+96-grid workload, the adjoint (forward + backward) of 8 x 128^3 solves, the 2-D
+4096^2 solves, and the uniform sphere with Dirichlet faces at 32^3 and 256^3.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
        python bench.py --pmc-probe                 (program run under rocprofv3 --pmc)
@@ -539,6 +540,7 @@ def run_extras(R, W, torch, args):
 
     out["two_d"] = run_two_d(R, W, torch)
     out["sphere32"] = run_sphere32(R, W, torch)
+    out["sphere256"] = run_sphere256(R, W, torch)
     return out
 
 
@@ -564,6 +566,34 @@ def run_sphere32(R, W, torch):
     print(f"# sphere 32^3: {t * 1e3:.3f} ms, cycles={st.cycles}, L2 error vs analytic {l2:.3e}", flush=True)
     return {"n": 32, "bc": "dirichlet", "tol": TOL, "ms": t * 1e3, "cycles": st.cycles,
             "rel_l2_error_vs_analytic": l2}
+
+
+def run_sphere256(R, W, torch):
+    """The same uniform sphere at 256^3 (Dirichlet faces from -M/r, the
+    boundary data folded into the right-hand side), float64 and mixed to
+    1e-10: Dirichlet at scale, wall time per solve."""
+    import numpy as np
+    p = W.uniform_sphere(256)
+    rho = torch.from_numpy(p.rho).cuda()
+    faces = R.pack_faces(p.faces)
+    res = {"n": 256, "bc": "dirichlet", "tol": TOL}
+    for prec in ("fp64", "mixed"):
+        o = R.Options(tol=TOL, prec=prec)
+        R.solve(rho, p.h, "dirichlet", faces=faces, opts=o)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = 5
+        for _ in range(reps):
+            phi, st = R.solve(rho, p.h, "dirichlet", faces=faces, opts=o)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / reps
+        e = phi.cpu().numpy() - p.phi_exact
+        l2 = float(np.sqrt(np.mean(e * e)) / np.sqrt(np.mean(p.phi_exact ** 2)))
+        res[prec] = {"ms": t * 1e3, "cycles": st.cycles, "rel_l2_error_vs_analytic": l2}
+        print(f"# sphere 256^3 {prec}: {t * 1e3:.3f} ms, cycles={st.cycles}, L2 error vs analytic {l2:.3e}",
+              flush=True)
+    del rho, faces, phi
+    return res
 
 
 def run_cfg3(R, W, torch, n=512):
