@@ -139,7 +139,8 @@ __global__ __launch_bounds__(64 * WY) void k_tau_strip(LevelView<T> L, const T* 
   auto own = [&](int i) -> bool { if constexpr (FLAT) return (sown >> i) & 1u; else return xown; };
   auto atlo = [&](int i) -> bool { if constexpr (FLAT) return (slo >> i) & 1u; else return xlo; };
   auto athi = [&](int i) -> bool { if constexpr (FLAT) return (shi >> i) & 1u; else return xhi; };
-  auto xpar = [&](int i) -> int { if constexpr (FLAT) return (sodd >> i) & 1u; else return gx & 1; };
+  // colour parity of column and strip shift (the rows' own parity is in rodd)
+  auto xpar = [&](int i) -> int { if constexpr (FLAT) return (sodd >> i) & 1u; else return (gx + yshift) & 1; };
 
   long long yoff[NU];    // row offsets in elements (wrapped or clamped), wave-uniform
   unsigned rin = 0;      // bit i: row i lies in the box
