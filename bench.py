@@ -64,7 +64,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the batched and adjoint workloads")
-    ap.add_argument("--cpu-cycles", type=int, default=4, help="oracle V-cycles in the CPU baseline sample")
+    ap.add_argument("--cpu-cycles", type=int, default=6, help="oracle V-cycles in the CPU baseline sample")
     ap.add_argument("--pmc-probe", action="store_true")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--summarize-trace", metavar="TRACE_DIR")
