@@ -127,7 +127,8 @@ def test_packed_remainder_solve(variant, bc):
     print(f"variant={variant} bc={bc} shape={shape}", flush=True)
     phi, st = R.solve(cu(rho), h, bc, opts=o)
     assert st.status == 0 and st.cycles == ref.cycles
-    np.testing.assert_allclose(st.history, ref.history, rtol=1e-6)
+    # same values up to rounding; near 1e-10 the residual's rounding is ~1e-6 of it
+    np.testing.assert_allclose(st.history, ref.history, rtol=1e-4)
     us = exact.exact_solution(4 * math.pi * rho, h, bc, None)
     assert relmax(phi.cpu().numpy(), us) < 1e-9
 
