@@ -42,7 +42,8 @@ def rand_faces(rng, shape):
 
 # one-pass strip kernel for the first four (ragged, odd periodic sizes
 # included), one-colour passes for the tiny one
-GSHAPES = [(20, 11, 130), (16, 16, 16), (40, 24, 64), (72, 130, 160), (9, 6, 5)]
+# ragged in x, y and z; the last two have many strips and a narrow x remainder
+GSHAPES = [(20, 11, 130), (16, 16, 16), (40, 24, 64), (72, 130, 160), (9, 6, 5), (11, 100, 136), (9, 60, 20)]
 
 
 @pytest.mark.parametrize("shape", GSHAPES)
