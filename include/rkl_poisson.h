@@ -228,6 +228,9 @@ int rkl_tau_step_launches(const rkl_grid *grid, int s, int prec);
  * HBM pass per tau-step).  A variant is a tile family and shape; `target` is
  * the workgroup count the z-chunking aims for.  Variants compute identical
  * values cell by cell; only the order of the float64 norm partials differs.
+ * Three-dimensional one-wavefront strip variants (6 and 10) give the x
+ * remainder of several interior strips to one shared wavefront, so their
+ * workgroup count per z chunk is below tiles x strips.
  *   variant 0  built-in choice (in rkl_tune_set: erase the entry)
  *           1  LDS ring, 64 x 8 tiles        2  LDS ring, 64 x 4 tiles
  *           3  z-queue, 64 x 32 tiles        4  z-queue, 64 x 16 tiles
@@ -267,6 +270,8 @@ rkl_status rkl_tune_get(const rkl_grid *level, int s, int prec, rkl_tune_entry *
 /*
  * Time every variant and target on one level shape: reps launches each on
  * library-allocated scratch (freed before return), HIP events on hip_stream.
+ * Targets: a fixed set from 64 to 4096 workgroups, and for strip variants
+ * also one per distinct z-chunk length from 64 planes (2-D: rows) down to 1.
  * Installs the fastest; writes up to cap results sorted by time (host array)
  * and the number measured to *n_results.  Synchronises the stream.
  */
