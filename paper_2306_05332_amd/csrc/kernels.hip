@@ -192,7 +192,7 @@ __global__ __launch_bounds__(256) void k_resid_absmax(LevelView<T> L, const T* _
   sh[threadIdx.x] = m;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
+    if ((int)threadIdx.x < w) {
       const double a = sh[threadIdx.x], c = sh[threadIdx.x + w];
       sh[threadIdx.x] = (a != a || c != c) ? (a + c) : fmax(a, c);
     }
@@ -211,7 +211,7 @@ __global__ __launch_bounds__(256) void k_reduce_max(const double* __restrict__ p
   sh[threadIdx.x] = m;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
+    if ((int)threadIdx.x < w) {
       const double a = sh[threadIdx.x], c = sh[threadIdx.x + w];
       sh[threadIdx.x] = (a != a || c != c) ? (a + c) : fmax(a, c);
     }
