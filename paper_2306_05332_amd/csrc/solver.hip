@@ -1241,14 +1241,21 @@ struct GraphCache {
   LoopSig sig;
   hipGraphExec_t exec = nullptr;
   hipStream_t stream = nullptr;
+  std::vector<hipStream_t> branch;  // capture streams of classes 1.. (default priority)
+  std::vector<hipEvent_t> events;   // fork event, then one join event per branch
   ~GraphCache() {
     if (exec) (void)hipGraphExecDestroy(exec);
+    for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    for (hipStream_t b : branch) (void)hipStreamDestroy(b);
     if (stream) (void)hipStreamDestroy(stream);
   }
 };
 std::unique_ptr<GraphCache> g_graph;
 
 // Capture `iters` outer iterations of every class into one graph (cached).
+// Classes share no buffer, so each is a branch of its own (forked from and
+// joined back into the capture stream by events): the latency-bound small
+// levels and tails of one class overlap the other classes' sweeps.
 hipGraphExec_t batch_graph(std::vector<ClassPlan*>& cls, const rkl_opts& o, int iters) {
   LoopSig sig{{}, o.tol, o.coarse_tol, o.max_cycles, o.n_pre, o.n_post, o.coarse_max_steps, tune_generation(),
               o.smoother};
@@ -1258,8 +1265,26 @@ hipGraphExec_t batch_graph(std::vector<ClassPlan*>& cls, const rkl_opts& o, int 
   auto G = std::make_unique<GraphCache>();
   G->sig = sig;
   HIPCHK(hipStreamCreateWithFlags(&G->stream, hipStreamNonBlocking));
+  const size_t nc = cls.size();
+  for (size_t c = 1; c < nc; ++c) {
+    hipStream_t b = nullptr;
+    HIPCHK(hipStreamCreateWithFlags(&b, hipStreamNonBlocking));
+    G->branch.push_back(b);
+  }
+  for (size_t e = 0; e < nc; ++e) {
+    hipEvent_t ev = nullptr;
+    HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    G->events.push_back(ev);
+  }
   HIPCHK(hipStreamBeginCapture(G->stream, hipStreamCaptureModeThreadLocal));
-  for (auto* c : cls) class_iterations(*c, o, iters, G->stream);
+  HIPCHK(hipEventRecord(G->events[0], G->stream));  // fork
+  for (size_t c = 1; c < nc; ++c) {
+    HIPCHK(hipStreamWaitEvent(G->branch[c - 1], G->events[0], 0));
+    class_iterations(*cls[c], o, iters, G->branch[c - 1]);
+    HIPCHK(hipEventRecord(G->events[c], G->branch[c - 1]));
+  }
+  class_iterations(*cls[0], o, iters, G->stream);
+  for (size_t c = 1; c < nc; ++c) HIPCHK(hipStreamWaitEvent(G->stream, G->events[c], 0));  // join
   hipGraph_t graph = nullptr;
   HIPCHK(hipStreamEndCapture(G->stream, &graph));
   HIPCHK(hipGraphInstantiate(&G->exec, graph, nullptr, nullptr, 0));
