@@ -1162,12 +1162,12 @@ void class_iterations(ClassPlan& C, rkl_opts o, int k, hipStream_t st) {
   }
 }
 
-// f0 = 4 pi G rho (mean-free when periodic), phi = 0, ||M 0 - f0||^2 and a
-// reset convergence state for every member; returns ||M 0 - f0|| per member.
-// A zero right-hand side is tested against 1 instead, which stops it at once
-// with phi = 0.
-std::vector<double> class_start(ClassPlan& C, const rkl_opts& o, const double* const* rho, double* const* phi,
-                                hipStream_t st) {
+// Start of a class: f0 = 4 pi G rho (mean-free when periodic), phi = 0,
+// ||M 0 - f0||^2 and a reset convergence state for every member.
+// Enqueued part: the host arrays rho, phi and r0sq (nb doubles, receives
+// ||M 0 - f0||^2 per member) must stay alive until the stream is synchronised.
+void class_start_enqueue(ClassPlan& C, const rkl_opts& o, const double* const* rho, double* const* phi,
+                         double* r0sq, hipStream_t st) {
   Plan& P = *C.base;
   const Lev& F = P.lv[0];
   const int nb = C.nb, ps = C.part_stride;
@@ -1188,10 +1188,15 @@ std::vector<double> class_start(ClassPlan& C, const rkl_opts& o, const double* c
   launch_reduce(C.part + 1, nblk, 2, 1, C.res0sq, nullptr, st, Batch{nb, 1, 0, 0, ps});
   launch_fill<double>(C.phi, F.n, 0.0, nullptr, st, Batch{nb, (long long)F.n, 0, 0, 0});
   check_launch();
-  // zero right-hand sides: relative residual 0 at once (phi stays 0)
-  std::vector<double> r0(nb), res0(nb);
-  HIPCHK(hipMemcpyAsync(r0.data(), C.res0sq, nb * sizeof(double), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipMemcpyAsync(r0sq, C.res0sq, nb * sizeof(double), hipMemcpyDeviceToHost, st));
+}
+
+// After the synchronisation: ||M 0 - f0|| per member, and a reset convergence
+// state.  A zero right-hand side is tested against 1 instead, which stops it
+// at once with phi = 0.
+std::vector<double> class_start_finish(ClassPlan& C, std::vector<double>& r0, hipStream_t st) {
+  const int nb = C.nb;
+  std::vector<double> res0(nb);
   bool fix = false;
   for (int m = 0; m < nb; ++m) {
     res0[m] = std::sqrt(r0[m]);
@@ -1336,16 +1341,22 @@ rkl_status solve_batched(const rkl_grid* grids, int nbatch, const rkl_opts& o, c
   }
   if (cls.empty()) return worst;
   std::vector<std::vector<double>> res0(cls.size());
+  // every class's start enqueued, then one synchronisation for all of them
+  std::vector<std::vector<const double*>> rp(cls.size());
+  std::vector<std::vector<double*>> pp(cls.size());
+  std::vector<std::vector<double>> r0(cls.size());
   for (size_t c = 0; c < cls.size(); ++c) {
-    std::vector<const double*> rp;
-    std::vector<double*> pp;
     for (int q : members[c]) {
-      rp.push_back(rho[q]);
-      pp.push_back(phi[q]);
+      rp[c].push_back(rho[q]);
+      pp[c].push_back(phi[q]);
     }
-    res0[c] = class_start(*cls[c], o, rp.data(), pp.data(), st);
+    r0[c].assign(cls[c]->nb, 0.0);
+    class_start_enqueue(*cls[c], o, rp[c].data(), pp[c].data(), r0[c].data(), st);
   }
   HIPCHK(hipStreamSynchronize(st));
+  // (the state resets read the pinned mirrors in stream order; the host touches
+  // those again only after the loop's synchronisation)
+  for (size_t c = 0; c < cls.size(); ++c) res0[c] = class_start_finish(*cls[c], r0[c], st);
   // iterations per graph launch: enough for the predicted contraction
   const int iters = std::max(1, std::min(o.max_cycles + 1, (int)std::ceil(std::log(std::max(o.tol, 1e-300)) /
                                                                              std::log(0.12)) + 1));
