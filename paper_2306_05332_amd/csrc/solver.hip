@@ -494,14 +494,16 @@ int relax_from_zero(Plan& P, const LevelView<T>& V, const Lev& Lv, int n_pre, T*
 // also writes the partial sums of (M a - b)^2.
 template <typename T>
 bool tau_keep(Plan& P, const LevelView<T>& V, T* a, T* x, T* y, T*& cur, T*& alt, const T* b,
-              const std::vector<StageCoef>& co, double* part, const int* stop, hipStream_t st, bool gs = false) {
+              const std::vector<StageCoef>& co, double* part, const int* stop, hipStream_t st, bool gs = false,
+              const Batch& bt = single_batch()) {
   if (gs) {
-    if (launch_gsrb_fused<T>(V, a, b, x, 1.0, part, stop, st)) {
+    if (launch_gsrb_fused<T>(V, a, b, x, 1.0, part, stop, st, bt)) {
       check_launch();
       cur = x;
       alt = y;
       return true;
     }
+    if (bt.nb > 1) fail(RKL_EINVAL, "batched solves need the fused smoother on level 0");
     launch_gsrb_half<T>(V, a, x, b, 0, 1.0, stop, st);
     launch_gsrb_half<T>(V, x, y, b, 1, 1.0, stop, st);
     check_launch();
@@ -510,12 +512,13 @@ bool tau_keep(Plan& P, const LevelView<T>& V, T* a, T* x, T* y, T*& cur, T*& alt
     return false;
   }
   const int s = (int)co.size();
-  if (launch_fused_tau<T>(V, a, b, x, s, co.data(), part, stop, st)) {
+  if (launch_fused_tau<T>(V, a, b, x, s, co.data(), part, stop, st, bt)) {
     check_launch();
     cur = x;
     alt = y;
     return true;
   }
+  if (bt.nb > 1) fail(RKL_EINVAL, "batched solves need the fused smoother on level 0");
   // stage 1: a -> x; stage j >= 2 writes over Y_{j-2}, except that Y_0 = a
   // is never overwritten (stage 2 writes y)
   launch_stage<T>(V, a, nullptr, b, x, co[0].mu, co[0].nu, co[0].c, 1, stop, st);
@@ -1059,6 +1062,11 @@ struct ClassPlan {
   ConvState* hconv = nullptr;
   Hier<float> h32;
   Hier<double> h64;
+  // float64 classes iterate on phi directly over the rotating level-0 buffers
+  // {phi, h64.u[0], h64.t[0]}: cycle m starts from buffer rot[m % nrot]
+  bool direct = false;
+  int rot[3] = {0, 0, 0};
+  int nrot = 1;
   std::vector<void*> allocs;
   template <typename U>
   U* alloc(size_t n) {
@@ -1120,6 +1128,7 @@ ClassPlan& get_class(const rkl_grid& g, const rkl_opts& o, int nb) {
   if (o.prec == RKL_MIXED) make(C->h32, 0.0f);
   else make(C->h64, 0.0);
   C->s = o.s;
+  C->direct = o.prec == RKL_FP64 && o.n_pre > 0;
   ClassPlan& ref = *C;
   g_classes[key] = std::move(C);
   return ref;
@@ -1154,12 +1163,58 @@ void class_iteration(ClassPlan& C, Hier<T>& H, const rkl_opts& o, hipStream_t st
   check_launch();
 }
 
-void class_iterations(ClassPlan& C, rkl_opts o, int k, hipStream_t st) {
+// One float64 V-cycle on phi itself for every member, as in the single solve:
+// the first relaxation from bufs[ia] (never written) carries the residual
+// partials of its start state for the convergence test; ia becomes the buffer
+// the cycle ends in.
+void class_iteration_direct(ClassPlan& C, const rkl_opts& o, hipStream_t st, int& ia) {
+  Plan& P = *C.base;
+  Hier<double>& H = C.h64;
+  const Lev& F = P.lv[0];
+  const int nb = C.nb, ps = C.part_stride;
+  const int* stop = &C.conv->stop;
+  const LevelView<double> V0 = view<double>(F, P.periodic, nullptr);
+  double* bufs[3] = {C.phi, H.u[0], H.t[0]};
+  const bool gs = o.smoother == RKL_SMOOTH_GSRB;
+  const bool pair0 = o.n_pre >= 2 && pair_ok<double>(V0, o.s, gs);
+  const Batch b0{nb, (long long)F.n, 0, CONV_INTS, ps};
+  double *cur = nullptr, *alt = nullptr;
+  tau_keep<double>(P, V0, bufs[ia], bufs[(ia + 1) % 3], bufs[(ia + 2) % 3], cur, alt, C.f0,
+                   pair0 ? F.smooth2 : F.smooth, C.part, stop, st, gs, b0);
+  const int nblk = (int)(gs ? gsrb_blocks<double>(V0) : fused_tau_blocks<double>(V0, pair0 ? 2 * o.s : o.s));
+  launch_check(C.part, nblk, 1, C.res0sq, o.tol, o.max_cycles, 1.0, C.conv, st, Batch{nb, 0, 0, 0, ps});
+  check_launch();
+  vcycle_from<double>(P, H, cur, alt, C.f0, nullptr, pair0 ? 2 : 1, o, stop, st,
+                      VBatch{nb, CONV_INTS, ps, C.dsum, C.part});
+  for (int k = 0; k < 3; ++k)
+    if (bufs[k] == cur) ia = k;
+}
+
+// k outer iterations of a class; a direct (float64) class captures more if
+// needed so that the buffer rotation ends where it started (graph replays
+// then continue it), and records the rotation.  Returns the count captured.
+int class_iterations(ClassPlan& C, rkl_opts o, int k, hipStream_t st) {
   o.s = C.s;
+  if (C.direct) {
+    std::vector<int> seq;
+    int ia = 0;
+    for (int q = 0; q < k || ia != 0; ++q) {
+      if (q >= k + 3) fail(RKL_EHIP, "level-0 buffer rotation does not close");
+      seq.push_back(ia);
+      class_iteration_direct(C, o, st, ia);
+    }
+    int per = 1;  // period of the rotation within the captured sequence
+    while (per < (int)seq.size() && seq[per] != 0) ++per;
+    if (per > 3) fail(RKL_EHIP, "unexpected level-0 buffer rotation");
+    C.nrot = per;
+    for (int q = 0; q < 3; ++q) C.rot[q] = seq[q % per];
+    return (int)seq.size();
+  }
   for (int q = 0; q < k; ++q) {
     if (o.prec == RKL_MIXED) class_iteration<float>(C, C.h32, o, st);
     else class_iteration<double>(C, C.h64, o, st);
   }
+  return k;
 }
 
 // Start of a class: f0 = 4 pi G rho (mean-free when periodic), phi = 0,
@@ -1214,11 +1269,34 @@ std::vector<double> class_start_finish(ClassPlan& C, std::vector<double>& r0, hi
   return res0;
 }
 
-// final mean removal (periodic) and copy-out to the caller's arrays
+// Member mb of a direct class: its answer is the start state of cycle
+// result_m, rotation buffer rot[result_m % nrot]; when that is not phi, copy it
+// into phi.
+__global__ __launch_bounds__(256) void k_take_answer(double* __restrict__ phi, const double* __restrict__ b1,
+                                                     const double* __restrict__ b2, size_t n,
+                                                     const ConvState* __restrict__ conv, int r0, int r1, int r2,
+                                                     int nrot, long long stride) {
+  const long long mb = blockIdx.y;
+  const int q = conv[mb].result_m % nrot;
+  const int k = q == 0 ? r0 : (q == 1 ? r1 : r2);
+  if (k == 0) return;
+  const double* __restrict__ src = (k == 1 ? b1 : b2) + mb * stride;
+  double* __restrict__ dst = phi + mb * stride;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) dst[i] = src[i];
+}
+
+// answer into phi (direct classes), final mean removal (periodic) and
+// copy-out to the caller's arrays
 void class_finish(ClassPlan& C, hipStream_t st) {
   Plan& P = *C.base;
   const Lev& F = P.lv[0];
   const int nb = C.nb, ps = C.part_stride;
+  if (C.direct) {
+    const unsigned blocks = (unsigned)std::min<size_t>((F.n + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_take_answer, dim3(blocks, nb), dim3(256), 0, st, C.phi, C.h64.u[0], C.h64.t[0], F.n,
+                       C.conv, C.rot[0], C.rot[1], C.rot[2], C.nrot, (long long)F.n);
+    check_launch();
+  }
   if (P.periodic) {
     launch_sum<double>(C.phi, F.n, C.part, st, Batch{nb, (long long)F.n, 0, 0, ps});
     launch_reduce(C.part, (int)ew_block_count(F.n), 1, 1, C.dsum, nullptr, st, Batch{nb, 2, 0, 0, ps});
