@@ -120,6 +120,34 @@ def test_batched_mixed_boundaries_and_edge_members():
         np.testing.assert_array_equal(got[0], got[5])
 
 
+def test_batched_fp64_members_stop_at_different_cycles():
+    """One float64 class whose members converge at different cycles (a zero
+    source at once, a single Fourier mode soon, blobs later), so that their
+    answers lie in different buffers of the level-0 rotation: every member
+    against the single solve and the FFT solution."""
+    R = _lib()
+    n = 32
+    h = (1.0 / n,) * 3
+    x = (np.arange(n) + 0.5) / n
+    mode = np.sin(2 * np.pi * x)[None, None, :] * np.cos(2 * np.pi * x)[None, :, None] * np.ones((n, 1, 1))
+    blobs = W.gaussian_blobs(n, 6, rng=np.random.default_rng(21))
+    fields = [np.zeros((n, n, n)), mode, blobs.rho, 0.5 * mode + blobs.rho]
+    o = R.Options(tol=1e-10)
+    phis, stats = R.solve_batched([cu(f) for f in fields], [h] * len(fields), "periodic", opts=o)
+    cycles = [st.cycles for st in stats]
+    assert len(set(c % 3 for c in cycles)) >= 2, cycles
+    for f, phi, st in zip(fields, phis, stats):
+        assert st.status == 0
+        ref, sr = R.solve(cu(f), h, "periodic", opts=o)
+        assert st.cycles == sr.cycles
+        got = phi.cpu().numpy()
+        if not f.any():
+            assert np.all(got == 0.0) and st.cycles == 0
+            continue
+        assert relmax(got, ref.cpu().numpy()) < 1e-13
+        assert relmax(got, exact.exact_solution(FOURPI * f, h, "periodic")) < 1e-9
+
+
 def test_batched_repeated_calls_reuse_and_recapture():
     """Two calls in a row on the same classes (the captured loop is replayed
     with new data), then a smaller batch and a different tolerance (a new
