@@ -106,6 +106,8 @@ def kernel_symbol(R, shape, s, prec="fp64"):
             "strip8x1": f"rkl::k_tau_strip<{tname}, {s}, 8, 1, true, false, false, false>",
             "strip4x4": f"rkl::k_tau_strip<{tname}, {s}, 4, 4, true, false, false, false>",
             "strip5x1": f"rkl::k_tau_strip<{tname}, {s}, 5, 1, true, false, false, false>",
+            "stripyx8x4": f"rkl::k_tau_strip_yx<{tname}, {s}, 8, 4, true, false, false>",
+            "stripyx4x8": f"rkl::k_tau_strip_yx<{tname}, {s}, 4, 8, true, false, false>",
             "strip2d8": f"rkl::k_tau_strip<{tname}, {s}, 8, 1, true, false, false, true>",
             "strip2d4": f"rkl::k_tau_strip<{tname}, {s}, 4, 1, true, false, false, true>"}.get(
                 v, f"rkl::k_stage<{tname}>")
@@ -632,9 +634,15 @@ def run_cfg3(R, W, torch, n=512):
     return out
 
 
+# 4096^2 in two dimensions: the exact discrete solution rounded to float64
+# already has ||M u* - f|| / ||f|| = 1.55e-10 (eps Lambda ||u|| / ||f||, growing
+# as n^2), so the 2-D solves stop at 1e-9, above that floor
+TOL_2D = 1e-9
+
+
 def run_two_d(R, W, torch, n=4096):
     """Two-dimensional workload: periodic 4096^2 (the cell count of 256^3),
-    32 seeded Gaussian blobs, float64 and mixed solves to 1e-10, and the
+    32 seeded Gaussian blobs, float64 and mixed solves to 1e-9, and the
     finest-level 2-D strip pass timed with HIP events on the solver's stream.
     On 2-D levels two s = 2 tau-steps run as one 4-stage pass (u and b read
     once, the result written once: 3 words of algorithmic traffic per cell
@@ -643,10 +651,10 @@ def run_two_d(R, W, torch, n=4096):
     from oracle import exact
     p = W.gaussian_blobs_2d(n, n, nblobs=32, seed=6)
     rho = torch.from_numpy(p.rho).cuda()
-    res = {"n": n, "bc": "periodic", "tol": TOL}
+    res = {"n": n, "bc": "periodic", "tol": TOL_2D}
     us = exact.exact_solution(4.0 * math.pi * p.rho, p.h, "periodic")
     for prec in ("fp64", "mixed"):
-        o = R.Options(tol=TOL, prec=prec)
+        o = R.Options(tol=TOL_2D, prec=prec)
         R.solve(rho, p.h, "periodic", opts=o)
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -43,8 +43,11 @@ typedef enum {
     RKL_OK = 0,
     RKL_EINVAL = -1,      /* bad argument (sizes, spacing, options, NULL pointer) */
     RKL_ENOMEM = -2,      /* device allocation failed                             */
-    RKL_ENOCONV = -3,     /* max_cycles reached before tol                        */
-    RKL_EDIVERGED = -4,   /* residual grew in 3 consecutive cycles                */
+    RKL_ENOCONV = -3,     /* max_cycles reached before tol, or the residual       */
+                          /* stalled above tol > 0 (no 10% gain in 8 cycles: tol  */
+                          /* below the float64 rounding floor of M phi - f)       */
+    RKL_EDIVERGED = -4,   /* residual grew in 3 consecutive cycles, to over       */
+                          /* twice its best value                                 */
     RKL_ENONFINITE = -5,  /* NaN or Inf in the source or the residual             */
     RKL_EHIP = -6         /* a HIP runtime call failed                            */
 } rkl_status;
@@ -84,7 +87,8 @@ typedef struct {
                             eq. tau_max with |lambda_max| = 4 sum_d h_d^-2                        */
     int n_pre, n_post;   /* relaxations before / after the coarse correction (2, 1; Sec. 4.1)  */
     int min_coarse;      /* coarsen while every n/2 is even and >= min_coarse (default 4)      */
-    double tol;          /* stop at ||M phi - f||_2 / ||M 0 - f||_2 <= tol (default 1e-10)       */
+    double tol;          /* stop at ||M phi - f||_2 / ||M 0 - f||_2 <= tol (default 1e-10);     */
+                         /* 0 runs exactly max_cycles cycles                                    */
     int max_cycles;      /* cap on V-cycles (outer iterations in RKL_MIXED) (default 100)       */
     int prec;            /* rkl_precision (default RKL_FP64)                                    */
     double four_pi_G;    /* f = four_pi_G * rho (default 4 pi, i.e. G = 1)                      */
@@ -190,6 +194,35 @@ rkl_status rkl_coarse_solve(const rkl_grid *grid, const rkl_opts *opts, const do
                             double *u, int *steps_out, void *hip_stream);
 
 /*
+ * Float32 twins of the level building blocks above: the kernels that the
+ * RKL_MIXED path runs on the correction equation M e = r inside its float64
+ * defect correction (the V-cycle of Sec. 2.1 with the RKL tau-steps of App. A
+ * eq. RKL_intermediate_source, the transfers of eqs. restriction_example_3D and
+ * prolongation_example_3D, the accelerated coarsest solve of App. A.4).  They
+ * take the error equation's ghosts on every level: homogeneous Dirichlet
+ * (ghost = -u, eq. error_ghost) or periodic wrap (eq. periodic); there is no
+ * face-data argument.  Arrays are device float32[n] in the common layout; the
+ * arithmetic is float32, norms and their partial sums float64.  Arguments,
+ * errors and stream semantics are those of the float64 forms:
+ *   rkl_smooth_f32       = rkl_smooth with bc_faces = NULL
+ *   mg_vcycle_f32        = mg_vcycle with bc_faces = NULL (opts->prec is
+ *                          ignored); rel_res_out: ||M phi - f|| / ||f||
+ *   rkl_residual_f32     r = f - M phi (float32), ||r||_2 accumulated in float64
+ *   rkl_restrict_f32, rkl_prolong_add_f32, rkl_coarse_solve_f32: as above
+ *                          (coarse_tol 0 picks 1e-6 for float32)
+ */
+rkl_status rkl_smooth_f32(const rkl_grid *grid, int s, double tau_frac, int n_steps,
+                          const float *f, float *phi, void *hip_stream);
+rkl_status mg_vcycle_f32(const rkl_grid *grid, const rkl_opts *opts, const float *f, float *phi,
+                         double *rel_res_out, void *hip_stream);
+rkl_status rkl_residual_f32(const rkl_grid *grid, const float *f, const float *phi, float *r_out,
+                            double *norm_out, void *hip_stream);
+rkl_status rkl_restrict_f32(const rkl_grid *grid, const float *fine, float *coarse, void *hip_stream);
+rkl_status rkl_prolong_add_f32(const rkl_grid *grid, const float *coarse, float *fine, void *hip_stream);
+rkl_status rkl_coarse_solve_f32(const rkl_grid *grid, const rkl_opts *opts, const float *b, float *u,
+                                int *steps_out, void *hip_stream);
+
+/*
  * Batched solve of `nbatch` independent problems M phi_i = 4 pi G rho_i
  * (same equations, options and stopping rule as rkl_poisson_solve, Sec. 2.2
  * and 2.4; Dirichlet members take homogeneous faces).
@@ -242,6 +275,10 @@ int rkl_tau_step_launches(const rkl_grid *grid, int s, int prec);
  *              per lane, marching in y
  *           9  2-D strip, as 8 with 4 segments per lane
  *          10  strip, 1 wavefront of 64 columns x 5 rows per workgroup
+ *          11  strip, 4 wavefronts of 64 columns x 8 rows stacked in y, which
+ *              take the halo rows they share from each other through LDS
+ *              (u and b rows read once per workgroup instead of per wavefront)
+ *          12  as 11 with 8 wavefronts of 4 rows
  *              (strip: s <= 2 in float64, s <= 3 in float32; variants 8 and 9
  *              are for two-dimensional levels, nz = 1 with hz = inf, and
  *              those levels take no other variant)
@@ -307,7 +344,8 @@ rkl_status rkl_gsrb_smooth(const rkl_grid *grid, double omega, int n_iter, const
 typedef enum { RKL_RELAX_RKL = 0, RKL_RELAX_GSRB = 1, RKL_RELAX_SOR = 2 } rkl_relax_method;
 typedef struct {
     int method;          /* rkl_relax_method                                                  */
-    int s;               /* RKL: 0 = accelerated schedule of App. A.4, > 0 = fixed stage count */
+    int s;               /* RKL: 0 = accelerated schedule of App. A.4, > 0 = fixed stage count, */
+                         /* -1 = the fixed count of App. A.3 (rkl_s_opt with kmax 6, digits 2) */
     double tau_frac;     /* RKL: theta = tau / tau_max (default 0.9)                          */
     double omega;        /* SOR: over-relaxation; 0 = App. B optimum 2/(1 + sqrt(1 - rho_J^2)),
                             rho_J = sum cos(pi/n_d) h_d^-2 / sum h_d^-2 (default 0)           */
@@ -325,6 +363,25 @@ void rkl_default_relax_opts(rkl_relax_opts *o);
  */
 rkl_status rkl_relax_solve(const rkl_grid *grid, const rkl_relax_opts *opts, const double *f,
                            const double *bc_faces, double *phi, rkl_stats *stats, void *hip_stream);
+
+/*
+ * Best fixed stage count of App. A.3 (eq. sopt_theory) for single-level RKL
+ * relaxation on `grid` at tau = tau_frac * tau_max(s).  Mode k = 1 .. kmax
+ * (bounded by n/2, n the smallest cell count) of the smoothest family --
+ * Dirichlet: the diagonal mode (k,k,k), |lambda_k| = sum_d 4 sin^2(k pi /
+ * 2 n_d) / h_d^2; periodic: the axis mode of least |lambda_k| =
+ * min_d 4 sin^2(k pi / n_d) / h_d^2 -- is damped per tau-step by P_s(x_k),
+ * x_k = 1 - tau_frac Delta t_par |lambda_k|, Delta t_par = 2 / (4 sum_d h_d^-2)
+ * (eqs. eigenvalue_RKL, tau_max); rho(s) = max_k |P_s(x_k)| (eq.
+ * spectral_rad_RKL); m_eff(s) = s * digits / (-log10 rho(s)) stages buy
+ * `digits` orders of residual reduction (eq. iteration).  Returns the s in
+ * [1, largest cell count] minimising m_eff (the first one on ties) or a
+ * negative rkl_status; *m_eff_out (host, optional) receives m_eff(s_opt).
+ * The paper's setting is kmax = 6, digits = 2: a cubic Dirichlet grid of N
+ * cells per side at tau_frac = 1 has x_k = cos(k pi / N), the paper's 1-D
+ * model, and N = 64 gives 56.  Host-only arithmetic (no GPU work).
+ */
+int rkl_s_opt(const rkl_grid *grid, double tau_frac, int kmax, double digits, double *m_eff_out);
 
 /*
  * Gravitational acceleration g = -grad(phi) by the 4th-order differences of

@@ -160,6 +160,32 @@ def mode_eigenvalue(level, k: int) -> float:
     return sum(4.0 * math.sin(k * math.pi / (2.0 * n)) ** 2 / (hh * hh) for n, hh in zip(ns, hs))
 
 
+def s_opt_global(level, theta: float, d: float = 2.0, kmax: int = 6):
+    """Best fixed stage count on a 3-D (or 2-D) level at tau = theta tau_max
+    (eq. sopt_theory with the reading of the accelerated schedule): mode k of
+    the smoothest family (``mode_eigenvalue``) enters the stage polynomial at
+    x_k = 1 - theta Delta t_par |lambda_k|; rho(s) = max over k = 1 ..
+    min(kmax, n/2) of |P_s(x_k)| (n the smallest cell count), and s_opt
+    minimises m_eff = s d / (-log10 rho) over 1 <= s <= the largest cell
+    count.  On a cubic Dirichlet grid at theta = 1, x_k = cos(k pi / N) and
+    this is ``s_opt_global_1d``.  Returns (s_opt, m_eff(s_opt))."""
+    ns = [nn for nn, hh in zip(level.shape[::-1], level.h) if math.isfinite(hh)]
+    kk = np.arange(1, max(1, min(kmax, min(ns) // 2)) + 1)
+    x = np.array([1.0 - theta * level.dt_par * mode_eigenvalue(level, int(k)) for k in kk])
+    best_s, best = None, math.inf
+    for s in range(1, max(ns) + 1):
+        rho = float(np.max(np.abs(legendre(s, x))))
+        if rho <= 0.0:
+            m = 0.0
+        elif rho >= 1.0:
+            m = math.inf
+        else:
+            m = s * d / (-math.log10(rho))
+        if m < best:
+            best, best_s = m, s
+    return best_s, best
+
+
 def accelerated_schedule(level, theta: float):
     """Stage counts of the accelerated RKL iteration on ``level`` (App. A.4).
 

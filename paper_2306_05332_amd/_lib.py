@@ -15,7 +15,9 @@ from dataclasses import dataclass, field
 import torch
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "librklpoisson.so")
+# RKL_LIB names another build of the same library (e.g. one compiled with
+# different flags); the default is the in-tree build
+LIB_PATH = os.environ.get("RKL_LIB") or os.path.join(_PKG, "librklpoisson.so")
 
 RKL_OK, RKL_EINVAL, RKL_ENOMEM, RKL_ENOCONV, RKL_EDIVERGED, RKL_ENONFINITE, RKL_EHIP = 0, -1, -2, -3, -4, -5, -6
 STATUS_NAMES = {0: "RKL_OK", -1: "RKL_EINVAL", -2: "RKL_ENOMEM", -3: "RKL_ENOCONV",
@@ -65,11 +67,14 @@ EXPORTS = ("rkl_default_opts", "rkl_poisson_solve", "mg_vcycle", "rkl_smooth", "
            "rkl_restrict", "rkl_prolong_add", "rkl_coarse_solve", "rkl_poisson_solve_batched",
            "rkl_tau_step_launches", "rkl_tune_set", "rkl_tune_clear", "rkl_tune_get", "rkl_autotune",
            "rkl_tune_set_s", "rkl_level_shapes", "rkl_variant_name", "rkl_gsrb_smooth", "rkl_default_relax_opts",
-           "rkl_relax_solve", "rkl_gradient", "rkl_last_error", "rkl_release_all")
+           "rkl_relax_solve", "rkl_gradient", "rkl_last_error", "rkl_release_all", "rkl_smooth_f32",
+           "mg_vcycle_f32", "rkl_residual_f32", "rkl_restrict_f32", "rkl_prolong_add_f32", "rkl_coarse_solve_f32",
+           "rkl_s_opt")
 SMOOTHERS = {"rkl": 0, "gsrb": 1}
 RELAX = {"rkl": 0, "gsrb": 1, "sor": 2}
 VARIANTS = {0: "heuristic", 1: "ring64x8", 2: "ring64x4", 3: "zq64x32", 4: "zq64x16", 5: "strip8x4",
-            6: "strip8x1", 7: "strip4x4", 8: "strip2d8", 9: "strip2d4", 10: "strip5x1"}
+            6: "strip8x1", 7: "strip4x4", 8: "strip2d8", 9: "strip2d4", 10: "strip5x1", 11: "stripyx8x4",
+            12: "stripyx4x8"}
 
 _lib = None
 
@@ -96,8 +101,17 @@ def load_library(path: str = LIB_PATH):
     lib.rkl_coarse_solve.argtypes = [pg, po, P, P, ctypes.POINTER(ctypes.c_int), P]
     lib.rkl_poisson_solve_batched.argtypes = [pg, ctypes.c_int, po, ctypes.POINTER(P), ctypes.POINTER(P),
                                               ps, P]
+    # float32 twins of the level building blocks (no face-data argument)
+    lib.rkl_smooth_f32.argtypes = [pg, ctypes.c_int, ctypes.c_double, ctypes.c_int, P, P, P]
+    lib.mg_vcycle_f32.argtypes = [pg, po, P, P, ctypes.POINTER(ctypes.c_double), P]
+    lib.rkl_residual_f32.argtypes = [pg, P, P, P, ctypes.POINTER(ctypes.c_double), P]
+    lib.rkl_restrict_f32.argtypes = [pg, P, P, P]
+    lib.rkl_prolong_add_f32.argtypes = [pg, P, P, P]
+    lib.rkl_coarse_solve_f32.argtypes = [pg, po, P, P, ctypes.POINTER(ctypes.c_int), P]
     for name in ("rkl_poisson_solve", "mg_vcycle", "rkl_smooth", "rkl_residual", "rkl_restrict",
-                 "rkl_prolong_add", "rkl_coarse_solve", "rkl_poisson_solve_batched"):
+                 "rkl_prolong_add", "rkl_coarse_solve", "rkl_poisson_solve_batched", "rkl_smooth_f32",
+                 "mg_vcycle_f32", "rkl_residual_f32", "rkl_restrict_f32", "rkl_prolong_add_f32",
+                 "rkl_coarse_solve_f32"):
         getattr(lib, name).restype = ctypes.c_int
     lib.rkl_tau_step_launches.argtypes = [pg, ctypes.c_int, ctypes.c_int]
     lib.rkl_tau_step_launches.restype = ctypes.c_int
@@ -120,6 +134,8 @@ def load_library(path: str = LIB_PATH):
     lib.rkl_default_relax_opts.restype = None
     lib.rkl_relax_solve.argtypes = [pg, ctypes.POINTER(c_relax), P, P, P, ps, P]
     lib.rkl_relax_solve.restype = ctypes.c_int
+    lib.rkl_s_opt.argtypes = [pg, ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
+    lib.rkl_s_opt.restype = ctypes.c_int
     lib.rkl_gradient.argtypes = [pg, P, P, P, P, P, P]
     lib.rkl_gradient.restype = ctypes.c_int
     lib.rkl_last_error.argtypes = []
@@ -262,36 +278,64 @@ def solve(rho, h, bc="periodic", faces=None, phi0=None, opts: Options | None = N
     return phi, stats
 
 
+def _is_f32(t):
+    """float32 arrays take the float32 entry points (the mixed path's kernels,
+    error-equation ghosts, no face data)."""
+    return isinstance(t, torch.Tensor) and t.dtype == torch.float32
+
+
+def _no_faces_f32(faces):
+    if faces is not None:
+        raise ValueError("the float32 entry points take no face data (homogeneous or periodic ghosts)")
+
+
 def vcycle(f, phi, h, bc="periodic", faces=None, opts: Options | None = None, want_residual=False):
-    """One V-cycle on M phi = f in place (mg_vcycle); returns the relative residual or None."""
+    """One V-cycle on M phi = f in place (mg_vcycle; float32 arrays: mg_vcycle_f32);
+    returns the relative residual or None."""
     lib = load_library()
     opts = opts or Options()
     _check_faces(faces, f.shape, bc)
     g = _grid(f.shape, h, bc)
     co = opts.c()
     rel = ctypes.c_double(0.0)
-    _check(lib.mg_vcycle(ctypes.byref(g), ctypes.byref(co), _dev(f, "f"), _dev(faces, "faces"),
-                         _dev(phi, "phi"), ctypes.byref(rel) if want_residual else None, _stream(f)))
+    relp = ctypes.byref(rel) if want_residual else None
+    if _is_f32(f):
+        _no_faces_f32(faces)
+        _check(lib.mg_vcycle_f32(ctypes.byref(g), ctypes.byref(co), _dev(f, "f", torch.float32),
+                                 _dev(phi, "phi", torch.float32), relp, _stream(f)))
+    else:
+        _check(lib.mg_vcycle(ctypes.byref(g), ctypes.byref(co), _dev(f, "f"), _dev(faces, "faces"),
+                             _dev(phi, "phi"), relp, _stream(f)))
     return rel.value if want_residual else None
 
 
 def smooth(f, phi, h, bc="periodic", s=2, tau_frac=0.9, n_steps=1, faces=None):
-    """n_steps RKL tau-steps on M phi = f in place (rkl_smooth)."""
+    """n_steps RKL tau-steps on M phi = f in place (rkl_smooth; float32 arrays: rkl_smooth_f32)."""
     lib = load_library()
     _check_faces(faces, f.shape, bc)
     g = _grid(f.shape, h, bc)
+    if _is_f32(f):
+        _no_faces_f32(faces)
+        _check(lib.rkl_smooth_f32(ctypes.byref(g), int(s), float(tau_frac), int(n_steps),
+                                  _dev(f, "f", torch.float32), _dev(phi, "phi", torch.float32), _stream(f)))
+        return phi
     _check(lib.rkl_smooth(ctypes.byref(g), int(s), float(tau_frac), int(n_steps), _dev(f, "f"),
                           _dev(faces, "faces"), _dev(phi, "phi"), _stream(f)))
     return phi
 
 
 def residual(f, phi, h, bc="periodic", faces=None):
-    """(f - M phi, ||f - M phi||_2) (rkl_residual)."""
+    """(f - M phi, ||f - M phi||_2) (rkl_residual; float32 arrays: rkl_residual_f32)."""
     lib = load_library()
     _check_faces(faces, f.shape, bc)
     g = _grid(f.shape, h, bc)
     r = torch.empty_like(f)
     nrm = ctypes.c_double(0.0)
+    if _is_f32(f):
+        _no_faces_f32(faces)
+        _check(lib.rkl_residual_f32(ctypes.byref(g), _dev(f, "f", torch.float32), _dev(phi, "phi", torch.float32),
+                                    _dev(r, "r", torch.float32), ctypes.byref(nrm), _stream(f)))
+        return r, nrm.value
     _check(lib.rkl_residual(ctypes.byref(g), _dev(f, "f"), _dev(faces, "faces"), _dev(phi, "phi"),
                             _dev(r, "r"), ctypes.byref(nrm), _stream(f)))
     return r, nrm.value
@@ -299,35 +343,40 @@ def residual(f, phi, h, bc="periodic", faces=None):
 
 def restrict(fine):
     """coarse = R(fine): 8-point average, or the 4-point one of a 2-D (ny, nx)
-    or (1, ny, nx) array (rkl_restrict)."""
+    or (1, ny, nx) array (rkl_restrict; float32 arrays: rkl_restrict_f32)."""
     lib = load_library()
     flat = _flat_shape(fine)
     ny, nx = fine.shape[-2:]
     cshape = (ny // 2, nx // 2) if fine.dim() == 2 else (1 if flat else fine.shape[0] // 2, ny // 2, nx // 2)
     coarse = torch.empty(cshape, dtype=fine.dtype, device=fine.device)
     g = _grid(fine.shape, (1.0, 1.0) if flat else 1.0, "periodic")
-    _check(lib.rkl_restrict(ctypes.byref(g), _dev(fine, "fine"), _dev(coarse, "coarse"), _stream(fine)))
+    fn, dt = (lib.rkl_restrict_f32, torch.float32) if _is_f32(fine) else (lib.rkl_restrict, torch.float64)
+    _check(fn(ctypes.byref(g), _dev(fine, "fine", dt), _dev(coarse, "coarse", dt), _stream(fine)))
     return coarse
 
 
 def prolong_add(coarse, fine, bc="periodic"):
-    """fine += P(coarse): trilinear, or bilinear for a 2-D fine array (rkl_prolong_add)."""
+    """fine += P(coarse): trilinear, or bilinear for a 2-D fine array
+    (rkl_prolong_add; float32 arrays: rkl_prolong_add_f32)."""
     lib = load_library()
     g = _grid(fine.shape, (1.0, 1.0) if _flat_shape(fine) else 1.0, bc)
-    _check(lib.rkl_prolong_add(ctypes.byref(g), _dev(coarse, "coarse"), _dev(fine, "fine"), _stream(fine)))
+    fn, dt = (lib.rkl_prolong_add_f32, torch.float32) if _is_f32(fine) else (lib.rkl_prolong_add, torch.float64)
+    _check(fn(ctypes.byref(g), _dev(coarse, "coarse", dt), _dev(fine, "fine", dt), _stream(fine)))
     return fine
 
 
 def coarse_solve(b, h, bc="periodic", opts: Options | None = None):
-    """Accelerated RKL solve of M u = b with homogeneous/periodic ghosts (rkl_coarse_solve)."""
+    """Accelerated RKL solve of M u = b with homogeneous/periodic ghosts
+    (rkl_coarse_solve; float32 arrays: rkl_coarse_solve_f32)."""
     lib = load_library()
     opts = opts or Options()
     g = _grid(b.shape, h, bc)
     u = torch.empty_like(b)
     steps = ctypes.c_int(0)
     co = opts.c()
-    _check(lib.rkl_coarse_solve(ctypes.byref(g), ctypes.byref(co), _dev(b, "b"), _dev(u, "u"),
-                                ctypes.byref(steps), _stream(b)))
+    fn, dt = (lib.rkl_coarse_solve_f32, torch.float32) if _is_f32(b) else (lib.rkl_coarse_solve, torch.float64)
+    _check(fn(ctypes.byref(g), ctypes.byref(co), _dev(b, "b", dt), _dev(u, "u", dt), ctypes.byref(steps),
+              _stream(b)))
     return u, steps.value
 
 
@@ -375,7 +424,8 @@ def gsrb_smooth(f, phi, h, bc="periodic", omega=1.0, n_iter=1, faces=None):
 def relax_solve(f, h, bc="dirichlet", method="rkl", faces=None, phi0=None, s=0, tau_frac=0.9, omega=0.0,
                 tol_max=1e-10, max_iters=100000, check_every=1, history_cap=4096, raise_on_error=True):
     """Single-level relaxation to max|M phi - f| <= tol_max (rkl_relax_solve, App. B).
-    method: "rkl" (s = 0: accelerated schedule), "gsrb" or "sor" (omega = 0: App. B optimum).
+    method: "rkl" (s = 0: accelerated schedule; s = -1: the App. A.3 fixed count, see s_opt),
+    "gsrb" or "sor" (omega = 0: App. B optimum).
     Returns (phi, Stats) with Stats.cycles = iterations, Stats.rel_res = final max residual."""
     lib = load_library()
     _check_faces(faces, f.shape, bc)
@@ -391,6 +441,19 @@ def relax_solve(f, h, bc="dirichlet", method="rkl", faces=None, phi0=None, s=0, 
     if status in (RKL_EINVAL, RKL_ENOMEM, RKL_EHIP) or (raise_on_error and status != RKL_OK):
         _check(status)
     return phi, stats
+
+
+def s_opt(shape, h, bc="dirichlet", tau_frac=0.9, kmax=6, digits=2.0):
+    """Best fixed RKL stage count of App. A.3 for single-level relaxation on a
+    grid of shape (nz, ny, nx) or (ny, nx) (rkl_s_opt; host arithmetic, no
+    GPU).  Returns (s_opt, m_eff)."""
+    lib = load_library()
+    m = ctypes.c_double(0.0)
+    r = lib.rkl_s_opt(ctypes.byref(_grid(shape, h, bc)), float(tau_frac), int(kmax), float(digits),
+                      ctypes.byref(m))
+    if r < 0:
+        _check(r)
+    return r, m.value
 
 
 def gradient(phi, h, bc="periodic", faces=None):
@@ -435,6 +498,8 @@ def kernel_info(shape, s, bc="periodic", prec="fp64", h=1.0):
                 "strip8x1": f"k_tau_strip<{tname}, {s}, 8, 1>", "strip4x4": f"k_tau_strip<{tname}, {s}, 4, 4>",
                 "strip2d8": f"k_tau_strip<{tname}, {s}, 8, 1>", "strip2d4": f"k_tau_strip<{tname}, {s}, 4, 1>",
                 "strip5x1": f"k_tau_strip<{tname}, {s}, 5, 1>",
+                "stripyx8x4": f"k_tau_strip_yx<{tname}, {s}, 8, 4>",
+                "stripyx4x8": f"k_tau_strip_yx<{tname}, {s}, 4, 8>",
                 }.get(v["variant"], f"k_fused_tau<{tname}, {s}, 64, 8>")
     else:
         words = (3.0 + 4.0 * (s - 1)) / s
@@ -485,7 +550,7 @@ def autotune_level(shape, s, bc="periodic", prec="fp64", reps=20, h=1.0):
     """Time every variant/target on one level (GPU); installs the fastest and
     returns all measurements, fastest first."""
     lib = load_library()
-    cap = 64
+    cap = 4096
     res = (c_tune * cap)()
     n = ctypes.c_int(0)
     _check(lib.rkl_autotune(ctypes.byref(_grid(shape, h, bc)), int(s), PREC[prec], int(reps), res, cap,

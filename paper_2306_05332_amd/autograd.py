@@ -9,15 +9,17 @@ independent of rho, the gradient of a loss L(phi) is
 where S_0 is the same solve with homogeneous boundary values (Dirichlet faces
 set to zero) and, for periodic boxes, the mean of the source removed and the
 zero-mean gauge on the result (the projection P_perp of eq.
-source_modification is symmetric too).  So the backward pass costs one more
-solve on the GPU, through the same C ABI as the forward.
+source_modification is symmetric too).  The library's solve forms
+four_pi_G * (source) itself, so dL/drho is exactly the solve of
+M lambda = 4 pi G dL/dphi with homogeneous faces: the backward pass is one more
+call of the same C ABI as the forward, with dL/dphi in place of rho and the
+same options, and its result is returned as it comes.
 
 Both passes run in the library's HIP kernels; this module only arranges the
-calls.  ``rho`` may carry leading batch dimensions: (..., nz, ny, nx).
+calls and does no arithmetic on the tensors.  ``rho`` may carry leading batch
+dimensions: (..., nz, ny, nx).
 """
 from __future__ import annotations
-
-import dataclasses
 
 import torch
 
@@ -52,9 +54,10 @@ class PoissonSolve(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, gphi):
-        o = dataclasses.replace(ctx.opts, four_pi_G=1.0)
-        lam = _solve_many(gphi.detach().contiguous(), ctx.h, ctx.bc, None, o)
-        return ctx.opts.four_pi_G * lam, None, None, None, None
+        # S is linear: solving with source dL/dphi and the forward's four_pi_G
+        # gives 4 pi G S_0(dL/dphi) directly (homogeneous faces: None)
+        grad = _solve_many(gphi.detach().contiguous(), ctx.h, ctx.bc, None, ctx.opts)
+        return grad, None, None, None, None
 
 
 def poisson_solve(rho, h, bc="periodic", faces=None, opts=None):

@@ -528,7 +528,9 @@ bool fused_variant_ok(int variant, int s) {
     case FV_STRIP_8x4:
     case FV_STRIP_8x1:
     case FV_STRIP_4x4:
-    case FV_STRIP_5x1: return dbl ? s <= 2 : s <= 3;
+    case FV_STRIP_5x1:
+    case FV_STRIPYX_8x4:
+    case FV_STRIPYX_4x8: return dbl ? s <= 2 : s <= 3;
     default: return false;
   }
 }
@@ -539,11 +541,12 @@ static bool variant_fits(const LevelView<T>& L, int variant) {
 }
 
 static bool is_strip(int variant) {
-  return variant == FV_STRIP_8x4 || variant == FV_STRIP_8x1 || variant == FV_STRIP_4x4 || variant == FV_STRIP_5x1;
+  return variant == FV_STRIP_8x4 || variant == FV_STRIP_8x1 || variant == FV_STRIP_4x4 || variant == FV_STRIP_5x1 ||
+         variant == FV_STRIPYX_8x4 || variant == FV_STRIPYX_4x8;
 }
 static void strip_shape(int variant, int& R, int& WY) {
-  R = variant == FV_STRIP_4x4 ? 4 : (variant == FV_STRIP_5x1 ? 5 : 8);
-  WY = (variant == FV_STRIP_8x1 || variant == FV_STRIP_5x1) ? 1 : 4;
+  R = (variant == FV_STRIP_4x4 || variant == FV_STRIPYX_4x8) ? 4 : (variant == FV_STRIP_5x1 ? 5 : 8);
+  WY = (variant == FV_STRIP_8x1 || variant == FV_STRIP_5x1) ? 1 : (variant == FV_STRIPYX_4x8 ? 8 : 4);
 }
 
 static void variant_tile(int variant, int& bx, int& by) {
@@ -677,6 +680,10 @@ void launch_fused_S(const LevelView<T>& L, FusedChoice c, const T* u, const T* b
       if (c.variant == FV_STRIP_8x1) return launch_strip<T, S, 8, 1>(L, c.target, u, b, out, fc, part, stop, bt, st);
       if (c.variant == FV_STRIP_4x4) return launch_strip<T, S, 4, 4>(L, c.target, u, b, out, fc, part, stop, bt, st);
       if (c.variant == FV_STRIP_5x1) return launch_strip<T, S, 5, 1>(L, c.target, u, b, out, fc, part, stop, bt, st);
+      if (c.variant == FV_STRIPYX_8x4)
+        return launch_strip_yx<T, S, 8, 4>(L, c.target, u, b, out, fc, part, stop, bt, st);
+      if (c.variant == FV_STRIPYX_4x8)
+        return launch_strip_yx<T, S, 4, 8>(L, c.target, u, b, out, fc, part, stop, bt, st);
     }
   }
   int bx, by;
@@ -800,6 +807,8 @@ const char* fused_variant_name(int variant) {
     case FV_STRIP2D_8: return "strip2d8";
     case FV_STRIP2D_4: return "strip2d4";
     case FV_STRIP_5x1: return "strip5x1";
+    case FV_STRIPYX_8x4: return "stripyx8x4";
+    case FV_STRIPYX_4x8: return "stripyx4x8";
     default: return "heuristic";
   }
 }

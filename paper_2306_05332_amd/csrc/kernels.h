@@ -18,6 +18,8 @@ struct ConvState {
   int status;     // rkl_status of the decision (0 = converged)
   int m;          // index of the next cycle-start state to test
   int result_m;   // cycle-start state the decision refers to (the answer)
+  int stalled;    // status RKL_ENOCONV came from a stalled residual, not from max_cycles
+  int pad_;
   double rel;     // last relative residual
   double mean;    // mean of the last tested residual (diagnostic)
   double last[4]; // last four relative residuals (divergence test)
@@ -68,6 +70,9 @@ void launch_sub_mean(T* a, size_t n, const double* sum, double count, const int*
 template <typename T>
 void launch_sum(const T* a, size_t n, double* part, hipStream_t st,
                 const Batch& bt = single_batch());  // ew_block_count(n) partials
+// dst = src (distinct arrays) unless *stop is set
+template <typename T>
+void launch_copy(T* dst, const T* src, size_t n, const int* stop, hipStream_t st);
 template <typename TE>
 void launch_add_cast(double* u, const TE* e, size_t n, const int* stop, hipStream_t st,
                      const Batch& bt = single_batch());
@@ -118,7 +123,9 @@ enum : int {
   FV_STRIP2D_8 = 8,   // two-dimensional levels only: 8 x segments per lane, one wavefront per workgroup
   FV_STRIP2D_4 = 9,   // two-dimensional levels only: 4 x segments per lane
   FV_STRIP_5x1 = 10,  // strip kernel: R = 5 rows per lane (3 waves per SIMD in float64), one wavefront per workgroup
-  FV_COUNT = 11
+  FV_STRIPYX_8x4 = 11,  // R = 8, 4 wavefronts stacked in y sharing their halo rows through LDS
+  FV_STRIPYX_4x8 = 12,  // R = 4, 8 wavefronts stacked in y sharing their halo rows through LDS
+  FV_COUNT = 13
 };
 // A two-dimensional level (nz = 1, ihz2 = 0) takes the FV_STRIP2D_* variants
 // and no others; a 3-D level takes every variant but those.
@@ -169,6 +176,10 @@ StripGrid strip_grid(int s, int R, int WY, int nx, int ny, int nz, int target, b
 template <typename T, int S, int R, int WY>
 void launch_strip(const LevelView<T>& L, int target, const T* u, const T* b, T* out, const FCoef<T, S>& fc,
                   double* part, const int* stop, const Batch& bt, hipStream_t st);
+// WY > 1 wavefronts stacked in y that share their halo rows through LDS
+template <typename T, int S, int R, int WY>
+void launch_strip_yx(const LevelView<T>& L, int target, const T* u, const T* b, T* out, const FCoef<T, S>& fc,
+                     double* part, const int* stop, const Batch& bt, hipStream_t st);
 template <typename T, int S, int R, int WY>
 void launch_strip2d(const LevelView<T>& L, int target, const T* u, const T* b, T* out, const FCoef<T, S>& fc,
                     double* part, const int* stop, const Batch& bt, hipStream_t st);

@@ -265,10 +265,15 @@ __global__ __launch_bounds__(RED_NT) void k_reduce(const double* __restrict__ pa
 
 // ---------------------------------------------------------------- convergence test
 // One block: rel = sqrt(sum of part[b * stride]) / sqrt(res0sq) for the state at the
-// start of cycle cs->m; records it and decides, in the host loop's order:
+// start of cycle cs->m; records it and decides, in this order:
 // non-finite -> RKL_ENONFINITE; rel <= tol -> done; three consecutive
-// increases -> RKL_EDIVERGED; m >= max_cycles -> RKL_ENOCONV.  Also stores
-// the mean of the residual (part[b * stride + 1] / count) as a diagnostic.
+// increases that end above twice the best residual so far -> RKL_EDIVERGED;
+// with tol > 0, the last eight states all above 0.9 of the best state
+// before them (the residual has stopped falling, as it does at the float64
+// rounding floor of M u - f, about eps Lambda ||u|| / ||f||) -> RKL_ENOCONV,
+// marked stalled (tol = 0 asks for exactly max_cycles cycles);
+// m >= max_cycles -> RKL_ENOCONV.  Also stores the mean of the residual
+// (part[b * stride + 1] / count) as a diagnostic.
 __global__ __launch_bounds__(RED_NT) void k_check(const double* __restrict__ part, int nblk, int stride,
                                                   const double* __restrict__ res0sq, double tol,
                                                   int max_cycles, double count, ConvState* __restrict__ cs,
@@ -294,16 +299,33 @@ __global__ __launch_bounds__(RED_NT) void k_check(const double* __restrict__ par
   cs->mean = t1 / count;
   if (m < CONV_HIST) cs->hist[m] = rel;
   cs->last[m & 3] = rel;
+  // best residual up to the first of the last four states (three increases)
+  // and before the last eight states (stall window)
+  constexpr int SW = 8;
+  double best3 = HUGE_VAL, bestw = HUGE_VAL;
+  const int hmax = m < CONV_HIST ? m : CONV_HIST;
+  for (int q = 0; q < hmax; ++q) {
+    if (q <= m - 3) best3 = fmin(best3, cs->hist[q]);
+    if (q <= m - SW) bestw = fmin(bestw, cs->hist[q]);
+  }
+  double recent = rel;
+  for (int q = m - SW + 1; q < m; ++q)
+    if (q >= 0 && q < CONV_HIST) recent = fmin(recent, cs->hist[q]);
   int status = 1;  // 1: keep going
+  int stalled = 0;
   if (!isfinite(rel)) status = -5;
   else if (rel <= tol) status = 0;
   else if (m >= 3 && cs->last[m & 3] > cs->last[(m - 1) & 3] && cs->last[(m - 1) & 3] > cs->last[(m - 2) & 3] &&
-           cs->last[(m - 2) & 3] > cs->last[(m - 3) & 3])
+           cs->last[(m - 2) & 3] > cs->last[(m - 3) & 3] && rel > 2.0 * best3)
     status = -4;
-  else if (m >= max_cycles) status = -3;
+  else if (tol > 0.0 && m >= SW && m < CONV_HIST && recent > 0.9 * bestw) {
+    status = -3;
+    stalled = 1;
+  } else if (m >= max_cycles) status = -3;
   cs->rel = rel;
   if (status != 1) {
     cs->status = status;
+    cs->stalled = stalled;
     cs->result_m = m;
     cs->stop = 1;
   } else {
@@ -437,6 +459,15 @@ __global__ __launch_bounds__(EW_NT) void k_sum_tab(const double* const* __restri
                                                    double* __restrict__ part, Batch bt) {
   __shared__ double sh[EW_NT / WAVE];
   sum_share<double>(tab[blockIdx.y], n, part + (long long)blockIdx.y * bt.part_stride, sh);
+}
+
+// dst = src; skipped once the device-side loop has decided to stop (a cycle
+// queued past the stopping one must not overwrite the answer)
+template <typename T>
+__global__ __launch_bounds__(EW_NT) void k_copy(T* __restrict__ dst, const T* __restrict__ src, size_t n,
+                                                const int* __restrict__ stop) {
+  if (stop != nullptr && *stop) return;
+  for (size_t q = (size_t)blockIdx.x * EW_NT + threadIdx.x; q < n; q += (size_t)gridDim.x * EW_NT) dst[q] = src[q];
 }
 
 // u64 += (double) e
@@ -587,6 +618,11 @@ void launch_sum(const T* a, size_t n, double* part, hipStream_t st, const Batch&
   hipLaunchKernelGGL(k_sum<T>, dim3(ew_blocks(n), bt.nb), dim3(EW_NT), 0, st, a, n, part, bt);
 }
 
+template <typename T>
+void launch_copy(T* dst, const T* src, size_t n, const int* stop, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy<T>, dim3(ew_blocks(n)), dim3(EW_NT), 0, st, dst, src, n, stop);
+}
+
 template <typename TE>
 void launch_add_cast(double* u, const TE* e, size_t n, const int* stop, hipStream_t st, const Batch& bt) {
   hipLaunchKernelGGL(k_add_cast<TE>, dim3(ew_blocks(n), bt.nb), dim3(EW_NT), 0, st, u, e, n, bt, stop);
@@ -598,6 +634,7 @@ template void launch_stage<double>(const LevelView<double>&, const double*, cons
 template void launch_stage<float>(const LevelView<float>&, const float*, const float*, const float*,
                                   float*, double, double, double, int, const int*, hipStream_t);
 template void launch_restrict<double>(int, int, int, const double*, double*, hipStream_t);
+template void launch_restrict<float>(int, int, int, const float*, float*, hipStream_t);
 template void launch_fill<double>(double*, size_t, double, const int*, hipStream_t, const Batch&);
 template void launch_fill<float>(float*, size_t, float, const int*, hipStream_t, const Batch&);
 template void launch_sub_mean<double>(double*, size_t, const double*, double, const int*, hipStream_t,
@@ -609,6 +646,8 @@ template void launch_sub_mean_part<float>(float*, size_t, const double*, int, in
                                           hipStream_t, const Batch&);
 template void launch_sum<double>(const double*, size_t, double*, hipStream_t, const Batch&);
 template void launch_sum<float>(const float*, size_t, double*, hipStream_t, const Batch&);
+template void launch_copy<double>(double*, const double*, size_t, const int*, hipStream_t);
+template void launch_copy<float>(float*, const float*, size_t, const int*, hipStream_t);
 template void launch_add_cast<float>(double*, const float*, size_t, const int*, hipStream_t, const Batch&);
 template void launch_add_cast<double>(double*, const double*, size_t, const int*, hipStream_t, const Batch&);
 

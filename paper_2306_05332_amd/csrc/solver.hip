@@ -27,32 +27,33 @@
 #include <vector>
 
 #include "../../include/rkl_poisson.h"
+#include "host_common.h"
 #include "kernels.h"
 
 namespace rkl {
-namespace {
 
 thread_local std::string g_err = "no error";
-
-struct Fail {
-  rkl_status st;
-};
 
 [[noreturn]] void fail(rkl_status st, const std::string& msg) {
   g_err = msg;
   throw Fail{st};
 }
 
-#define HIPCHK(x)                                                                          \
-  do {                                                                                     \
-    hipError_t e_ = (x);                                                                   \
-    if (e_ != hipSuccess) fail(RKL_EHIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
-  } while (0)
+bool flat_grid(const rkl_grid& g) { return g.nz == 1 && std::isinf(g.hz) && g.hz > 0.0; }
 
-inline void check_launch() {
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) fail(RKL_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+void validate_grid(const rkl_grid* g, const double* bc_faces) {
+  if (!g) fail(RKL_EINVAL, "grid is NULL");
+  if (g->nx < 1 || g->ny < 1 || g->nz < 1) fail(RKL_EINVAL, "cell counts must be >= 1");
+  if ((double)g->nx * g->ny * g->nz > 4.0e10) fail(RKL_EINVAL, "grid too large");
+  if (!(g->hx > 0.0 && g->hy > 0.0 && g->hz > 0.0) || !std::isfinite(g->hx) || !std::isfinite(g->hy))
+    fail(RKL_EINVAL, "spacings must be positive and finite");
+  if (!std::isfinite(g->hz) && g->nz != 1)
+    fail(RKL_EINVAL, "hz = inf (a two-dimensional grid) needs nz = 1");
+  if (g->bc != RKL_BC_DIRICHLET && g->bc != RKL_BC_PERIODIC) fail(RKL_EINVAL, "unknown boundary type");
+  if (g->bc == RKL_BC_PERIODIC && bc_faces) fail(RKL_EINVAL, "bc_faces must be NULL for periodic grids");
 }
+
+namespace {
 
 // ------------------------------------------------------------------ levels
 struct Lev {
@@ -118,6 +119,64 @@ std::vector<int> accel_schedule(const Lev& L, bool periodic, double theta) {
     --k;
   }
   return out;
+}
+
+// Best fixed stage count of App. A.3 (eq. sopt_theory) on a level at
+// tau = theta tau_max: mode k of the smoothest family (as in accel_schedule)
+// enters the stage polynomial at x_k = 1 - theta dt_par |lambda_k|; the
+// spectral radius over the first kmax modes is rho(s) = max_k |P_s(x_k)|
+// (eq. spectral_rad_RKL), the iteration count for d digits m = d / -log10
+// rho (eq. iteration), and s_opt minimises m_eff = s m over 1 <= s <= the
+// largest cell count.  P_s by the three-term recursion (eq. LP_recursion),
+// advanced one s at a time for every mode.
+int s_opt_rule(const Lev& L, bool periodic, double theta, int kmax, double digits, double* m_out) {
+  const int ns[3] = {L.nx, L.ny, L.nz};
+  const double hs[3] = {L.hx, L.hy, L.hz};
+  const int nd = L.flat ? 2 : 3;
+  int nmin = ns[0], nmax = ns[0];
+  for (int d = 1; d < nd; ++d) {
+    nmin = std::min(nmin, ns[d]);
+    nmax = std::max(nmax, ns[d]);
+  }
+  const int K = std::max(1, std::min(kmax, nmin / 2));
+  std::vector<double> x(K), p0(K, 1.0), p1(K);
+  for (int k = 1; k <= K; ++k) {
+    double lk = periodic ? 1e300 : 0.0;
+    for (int d = 0; d < nd; ++d) {
+      if (periodic) {
+        const double sv = std::sin(k * M_PI / ns[d]);
+        lk = std::min(lk, 4.0 * sv * sv / (hs[d] * hs[d]));
+      } else {
+        const double sv = std::sin(k * M_PI / (2.0 * ns[d]));
+        lk += 4.0 * sv * sv / (hs[d] * hs[d]);
+      }
+    }
+    x[k - 1] = 1.0 - theta * L.dtpar * lk;
+    p1[k - 1] = x[k - 1];  // P_1
+  }
+  int best_s = 1;
+  double best = HUGE_VAL;
+  for (int s = 1; s <= nmax; ++s) {
+    if (s >= 2) {  // P_s = ((2s-1) x P_{s-1} - (s-1) P_{s-2}) / s
+      for (int k = 0; k < K; ++k) {
+        const double pn = ((2.0 * s - 1.0) / s) * x[k] * p1[k] - ((s - 1.0) / s) * p0[k];
+        p0[k] = p1[k];
+        p1[k] = pn;
+      }
+    }
+    double rho = 0.0;
+    for (int k = 0; k < K; ++k) rho = std::max(rho, std::fabs(p1[k]));
+    double m;
+    if (rho <= 0.0) m = 0.0;
+    else if (rho >= 1.0) m = HUGE_VAL;
+    else m = s * digits / -std::log10(rho);
+    if (m < best) {
+      best = m;
+      best_s = s;
+    }
+  }
+  if (m_out) *m_out = best;
+  return best_s;
 }
 
 // ------------------------------------------------------------------ plan
@@ -189,8 +248,6 @@ struct Plan {
 
 std::mutex g_plans_mu;
 std::map<PlanKey, std::unique_ptr<Plan>> g_plans;
-
-bool flat_grid(const rkl_grid& g) { return g.nz == 1 && std::isinf(g.hz) && g.hz > 0.0; }
 
 // Levels from finest to coarsest: halve every axis (x and y only for a
 // two-dimensional grid) while each halved count is even and >= min_coarse.
@@ -734,8 +791,11 @@ int predict_batch(const ConvState& cs, double tol, int queued, int max_cycles) {
   if (m >= 1 && m - 1 < CONV_HIST) last = cs.hist[m - 1];
   if (m >= 2 && m - 1 < CONV_HIST && cs.hist[m - 2] > 0.0) rho = cs.hist[m - 1] / cs.hist[m - 2];
   rho = std::min(0.9, std::max(0.01, rho));
+  // state m (the start of the next cycle to queue) is one cycle past the last
+  // tested one, so ceil(log(tol/last)/log(rho)) cycles reach a tested state
+  // below tol; before any test, state 0 itself needs a cycle of its own
   int need = 1;
-  if (last > tol && tol > 0.0) need = (int)std::ceil(std::log(tol / last) / std::log(rho)) + 1;
+  if (last > tol && tol > 0.0) need = (int)std::ceil(std::log(tol / last) / std::log(rho)) + (m == 0 ? 1 : 0);
   need = std::max(1, std::min(need, 64));
   const int left = max_cycles + 1 - queued;
   return std::max(1, std::min(need, left));
@@ -750,18 +810,6 @@ void fill_stats(rkl_stats* stats, const ConvState& cs, int result_m) {
 }
 
 // ------------------------------------------------------------------ validation
-void validate_grid(const rkl_grid* g, const double* bc_faces) {
-  if (!g) fail(RKL_EINVAL, "grid is NULL");
-  if (g->nx < 1 || g->ny < 1 || g->nz < 1) fail(RKL_EINVAL, "cell counts must be >= 1");
-  if ((double)g->nx * g->ny * g->nz > 4.0e10) fail(RKL_EINVAL, "grid too large");
-  if (!(g->hx > 0.0 && g->hy > 0.0 && g->hz > 0.0) || !std::isfinite(g->hx) || !std::isfinite(g->hy))
-    fail(RKL_EINVAL, "spacings must be positive and finite");
-  if (!std::isfinite(g->hz) && g->nz != 1)
-    fail(RKL_EINVAL, "hz = inf (a two-dimensional grid) needs nz = 1");
-  if (g->bc != RKL_BC_DIRICHLET && g->bc != RKL_BC_PERIODIC) fail(RKL_EINVAL, "unknown boundary type");
-  if (g->bc == RKL_BC_PERIODIC && bc_faces) fail(RKL_EINVAL, "bc_faces must be NULL for periodic grids");
-}
-
 rkl_opts resolve_opts(const rkl_opts* in) {
   rkl_opts o;
   rkl_default_opts(&o);
@@ -826,8 +874,12 @@ struct Res0Sqrt {
 rkl_status finish_status(const ConvState& cs) {
   switch (cs.status) {
     case 0: return RKL_OK;
-    case -3: g_err = "max_cycles reached before tol"; return RKL_ENOCONV;
-    case -4: g_err = "residual grew in 3 consecutive cycles"; return RKL_EDIVERGED;
+    case -3:
+      g_err = cs.stalled ? "residual stalled at " + std::to_string(cs.rel) +
+                               " above tol (no 10% reduction in 8 cycles: the float64 rounding floor of M phi - f)"
+                         : std::string("max_cycles reached before tol");
+      return RKL_ENOCONV;
+    case -4: g_err = "residual grew in 3 consecutive cycles to over twice its best"; return RKL_EDIVERGED;
     case -5: g_err = "non-finite residual"; return RKL_ENONFINITE;
     default: g_err = "unexpected convergence state"; return RKL_EHIP;
   }
@@ -920,7 +972,10 @@ rkl_status solve_fp64(Plan& P, const rkl_opts& o, const double* rho, const doubl
           tau_keep<double>(P, V0, a, bufs[ib], bufs[ic], cur, alt, P.f0, F.smooth, nullptr, stop, st, gs);
           pre_done = 1;
         } else {
-          copy_d2d(bufs[ib], a, F.n, st);
+          // the copy respects the stop flag like every kernel of the cycle: a
+          // cycle queued past the stopping one must leave bufs[ia] intact
+          launch_copy<double>(bufs[ib], a, F.n, stop, st);
+          check_launch();
           cur = bufs[ib];
           alt = bufs[ic];
           pre_done = 0;
@@ -1043,10 +1098,12 @@ rkl_status solve_one(const rkl_grid& g, const rkl_opts& o, const double* rho, co
 // precision, float64 update) serves both precisions.
 struct ClassKey {
   int dev, nx, ny, nz, bc, s, min_coarse, prec, nb;
+  int direct;  // float64 with n_pre > 0: iterate on phi itself (ClassPlan::direct)
   double hx, hy, hz, theta;
   bool operator<(const ClassKey& o) const {
-    return std::tie(dev, nx, ny, nz, bc, s, min_coarse, prec, nb, hx, hy, hz, theta) <
-           std::tie(o.dev, o.nx, o.ny, o.nz, o.bc, o.s, o.min_coarse, o.prec, o.nb, o.hx, o.hy, o.hz, o.theta);
+    return std::tie(dev, nx, ny, nz, bc, s, min_coarse, prec, nb, direct, hx, hy, hz, theta) <
+           std::tie(o.dev, o.nx, o.ny, o.nz, o.bc, o.s, o.min_coarse, o.prec, o.nb, o.direct, o.hx, o.hy, o.hz,
+                    o.theta);
   }
 };
 
@@ -1090,7 +1147,8 @@ std::map<ClassKey, std::unique_ptr<ClassPlan>> g_classes;
 ClassPlan& get_class(const rkl_grid& g, const rkl_opts& o, int nb) {
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
-  ClassKey key{dev, g.nx, g.ny, g.nz, g.bc, o.s, o.min_coarse, o.prec, nb, g.hx, g.hy, g.hz, o.tau_frac};
+  const int direct = (o.prec == RKL_FP64 && o.n_pre > 0) ? 1 : 0;
+  ClassKey key{dev, g.nx, g.ny, g.nz, g.bc, o.s, o.min_coarse, o.prec, nb, direct, g.hx, g.hy, g.hz, o.tau_frac};
   Plan& base = get_plan(g, o.s, o.tau_frac, o.min_coarse, o.prec);
   std::lock_guard<std::mutex> lk(g_plans_mu);
   auto it = g_classes.find(key);
@@ -1128,7 +1186,7 @@ ClassPlan& get_class(const rkl_grid& g, const rkl_opts& o, int nb) {
   if (o.prec == RKL_MIXED) make(C->h32, 0.0f);
   else make(C->h64, 0.0);
   C->s = o.s;
-  C->direct = o.prec == RKL_FP64 && o.n_pre > 0;
+  C->direct = direct != 0;
   ClassPlan& ref = *C;
   g_classes[key] = std::move(C);
   return ref;
@@ -1577,19 +1635,148 @@ int autotune_level(const rkl_grid& g, int s, int prec, int reps, rkl_tune_entry*
   return (int)all.size();
 }
 
-template <typename Fn>
-rkl_status guarded(Fn&& fn) {
-  try {
-    return fn();
-  } catch (const Fail& f) {
-    return f.st;
-  } catch (const std::bad_alloc&) {
-    g_err = "host allocation failed";
-    return RKL_ENOMEM;
-  } catch (...) {
-    g_err = "unexpected internal error";
-    return RKL_EHIP;
+// ------------------------------------------------------------------ level building blocks
+// Precision-generic bodies of the single-level entry points.  The float32
+// forms are the kernels of the mixed-precision path (the correction equation
+// with homogeneous or periodic ghosts); float64 Dirichlet face data is folded
+// into a copy of f by the callers before these run.
+template <typename T>
+Plan& block_plan(const rkl_grid& g, int s, double theta, int min_coarse) {
+  return get_plan(g, s, theta, min_coarse, sizeof(T) == 8 ? RKL_FP64 : RKL_MIXED);
+}
+
+template <typename T>
+T* level0_alt(Plan& P) {
+  if constexpr (sizeof(T) == 8) return P.t0;
+  else return P.h32.t[0];
+}
+
+template <typename T>
+void copy_back(T* dst, const T* src, size_t n, hipStream_t st) {
+  if (dst != src) HIPCHK(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyDeviceToDevice, st));
+}
+
+// n_steps tau-steps of the plan's smoothing stage count on M phi = b
+template <typename T>
+void smooth_impl(Plan& P, const T* b, T* phi, int n_steps, hipStream_t st) {
+  const LevelView<T> V0 = view<T>(P.lv[0], P.periodic, nullptr);
+  T* cur = phi;
+  T* alt = level0_alt<T>(P);
+  relax_n<T>(P, V0, P.lv[0], n_steps, cur, alt, b, nullptr, st, single_batch(), false);
+  copy_back<T>(phi, cur, P.lv[0].n, st);
+}
+
+// one V-cycle from phi on M phi = b; relative residual ||M phi - b|| / ||b||
+// after it into *rel_out when asked
+template <typename T>
+void vcycle_impl(Plan& P, const rkl_opts& o, const T* b, T* phi, double* rel_out, hipStream_t st) {
+  Hier<T>& H = [&]() -> Hier<T>& {
+    if constexpr (sizeof(T) == 8) return P.h64;
+    else return P.h32;
+  }();
+  T* cur = phi;
+  T* alt = level0_alt<T>(P);
+  vcycle_from<T>(P, H, cur, alt, b, nullptr, 0, o, nullptr, st, VBatch{1, 0, 0, P.dscal});
+  copy_back<T>(phi, cur, P.lv[0].n, st);
+  if (rel_out) {
+    const LevelView<T> V0 = view<T>(P.lv[0], P.periodic, nullptr);
+    const double r0 = resid_norm<T>(P, V0, (const T*)nullptr, b, st);
+    const double r = resid_norm<T>(P, V0, phi, b, st);
+    *rel_out = r0 > 0.0 ? r / r0 : r;
   }
+}
+
+// r = b - M u (homogeneous or periodic ghosts, or the level-0 face data in
+// V.faces) and ||r||_2
+template <typename T>
+double residual_impl(Plan& P, const LevelView<T>& V, const T* b, const T* u, T* r_out, hipStream_t st) {
+  launch_residual<T, T>(V, u, b, r_out, P.part, nullptr, st);
+  launch_reduce(P.part, (int)resid_blocks(V.nx, V.ny, V.nz), 2, 1, P.dscal, nullptr, st);
+  check_launch();
+  return std::sqrt(readback(P, 1, st)[0]);
+}
+
+void check_fine_even(const rkl_grid& g) {
+  if (g.nx % 2 || g.ny % 2 || (g.nz % 2 && !flat_grid(g)))
+    fail(RKL_EINVAL, "fine sizes must be even (nz = 1 only for a two-dimensional grid)");
+}
+
+// coarsest-level solve of M u = b from u = 0; tau-steps taken (-1 when the
+// level is too large for the one-workgroup kernel, which keeps no count)
+template <typename T>
+int coarse_impl(Plan& P, const rkl_opts& o, const T* b, T* u, hipStream_t st) {
+  Hier<T> H;
+  H.u = {u};
+  H.b = {const_cast<T*>(b)};
+  H.t = {level0_alt<T>(P)};
+  const bool lds = coarse_in_lds(P, P.lv[0]);
+  coarse_solve<T>(P, H, 0, o, nullptr, st);
+  int steps = -1;
+  if (lds) {
+    HIPCHK(hipMemcpyAsync(P.hscal, P.dsteps, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    std::memcpy(&steps, P.hscal, sizeof(int));
+  }
+  copy_back<T>(u, H.u[0], P.lv[0].n, st);
+  HIPCHK(hipStreamSynchronize(st));
+  return steps;
+}
+
+// stage count and theta checks shared by the smoothing entry points
+void check_smooth_args(int s, double tau_frac, int n_steps) {
+  rkl_opts o;
+  rkl_default_opts(&o);
+  o.s = s;
+  o.tau_frac = tau_frac;
+  (void)resolve_opts(&o);
+  if (s < 1) fail(RKL_EINVAL, "s must be in [1, 64]");
+  if (n_steps < 0) fail(RKL_EINVAL, "n_steps must be >= 0");
+}
+
+template <typename T>
+rkl_status restrict_entry(const rkl_grid* grid, const T* fine, T* coarse, void* hip_stream) {
+  return guarded([&]() -> rkl_status {
+    validate_grid(grid, nullptr);
+    check_fine_even(*grid);
+    if (!fine || !coarse) fail(RKL_EINVAL, "NULL array");
+    hipStream_t st = (hipStream_t)hip_stream;
+    launch_restrict<T>(grid->nx, grid->ny, grid->nz, fine, coarse, st);
+    check_launch();
+    HIPCHK(hipStreamSynchronize(st));
+    return RKL_OK;
+  });
+}
+
+template <typename T>
+rkl_status prolong_entry(const rkl_grid* grid, const T* coarse, T* fine, void* hip_stream) {
+  return guarded([&]() -> rkl_status {
+    validate_grid(grid, nullptr);
+    check_fine_even(*grid);
+    if (!fine || !coarse) fail(RKL_EINVAL, "NULL array");
+    hipStream_t st = (hipStream_t)hip_stream;
+    launch_prolong_add<T>(grid->nx, grid->ny, grid->nz, grid->bc == RKL_BC_PERIODIC ? 1 : 0, coarse, fine,
+                          nullptr, st);
+    check_launch();
+    HIPCHK(hipStreamSynchronize(st));
+    return RKL_OK;
+  });
+}
+
+template <typename T>
+rkl_status coarse_entry(const rkl_grid* grid, const rkl_opts* opts, const T* b, T* u, int* steps_out,
+                               void* hip_stream) {
+  return guarded([&]() -> rkl_status {
+    validate_grid(grid, nullptr);
+    rkl_opts o = resolve_opts(opts);
+    o.prec = sizeof(T) == 8 ? RKL_FP64 : RKL_MIXED;
+    o = with_s(o, *grid);
+    if (!b || !u) fail(RKL_EINVAL, "NULL array");
+    Plan& P = block_plan<T>(*grid, o.s, o.tau_frac, INT_MAX);
+    std::lock_guard<std::mutex> lk(P.mu);
+    const int steps = coarse_impl<T>(P, o, b, u, (hipStream_t)hip_stream);
+    if (steps_out) *steps_out = steps;
+    return RKL_OK;
+  });
 }
 
 }  // namespace
@@ -1643,20 +1830,28 @@ rkl_status mg_vcycle(const rkl_grid* grid, const rkl_opts* opts, const double* f
     o.prec = RKL_FP64;
     o = with_s(o, *grid);
     if (!f || !phi) fail(RKL_EINVAL, "f and phi must be non-NULL");
-    Plan& P = get_plan(*grid, o.s, o.tau_frac, o.min_coarse, RKL_FP64);
+    Plan& P = block_plan<double>(*grid, o.s, o.tau_frac, o.min_coarse);
     std::lock_guard<std::mutex> lk(P.mu);
     hipStream_t st = (hipStream_t)hip_stream;
-    double* cur = phi;
-    double* alt = P.t0;
     fold_faces(P, bc_faces, f, P.f0, st);
-    vcycle_from<double>(P, P.h64, cur, alt, P.f0, nullptr, 0, o, nullptr, st, VBatch{1, 0, 0, P.dscal});
-    if (cur != phi) copy_d2d(phi, cur, P.lv[0].n, st);
-    if (rel_res_out) {
-      const LevelView<double> V0 = view<double>(P.lv[0], P.periodic, nullptr);
-      const double r0 = resid_norm<double>(P, V0, nullptr, P.f0, st);
-      const double r = resid_norm<double>(P, V0, phi, P.f0, st);
-      *rel_res_out = r0 > 0.0 ? r / r0 : r;
-    }
+    vcycle_impl<double>(P, o, P.f0, phi, rel_res_out, st);
+    HIPCHK(hipStreamSynchronize(st));
+    return RKL_OK;
+  });
+}
+
+rkl_status mg_vcycle_f32(const rkl_grid* grid, const rkl_opts* opts, const float* f, float* phi,
+                         double* rel_res_out, void* hip_stream) {
+  return guarded([&]() -> rkl_status {
+    validate_grid(grid, nullptr);
+    rkl_opts o = resolve_opts(opts);
+    o.prec = RKL_MIXED;
+    o = with_s(o, *grid);
+    if (!f || !phi) fail(RKL_EINVAL, "f and phi must be non-NULL");
+    Plan& P = block_plan<float>(*grid, o.s, o.tau_frac, o.min_coarse);
+    std::lock_guard<std::mutex> lk(P.mu);
+    hipStream_t st = (hipStream_t)hip_stream;
+    vcycle_impl<float>(P, o, f, phi, rel_res_out, st);
     HIPCHK(hipStreamSynchronize(st));
     return RKL_OK;
   });
@@ -1666,26 +1861,32 @@ rkl_status rkl_smooth(const rkl_grid* grid, int s, double tau_frac, int n_steps,
                       const double* bc_faces, double* phi, void* hip_stream) {
   return guarded([&]() -> rkl_status {
     validate_grid(grid, bc_faces);
-    rkl_opts o;
-    rkl_default_opts(&o);
-    o.s = s;
-    o.tau_frac = tau_frac;
-    o = resolve_opts(&o);
-    if (n_steps < 0) fail(RKL_EINVAL, "n_steps must be >= 0");
+    check_smooth_args(s, tau_frac, n_steps);
     if (!f || !phi) fail(RKL_EINVAL, "f and phi must be non-NULL");
-    Plan& P = get_plan(*grid, s, tau_frac, INT_MAX, RKL_FP64);
+    Plan& P = block_plan<double>(*grid, s, tau_frac, INT_MAX);
     std::lock_guard<std::mutex> lk(P.mu);
     hipStream_t st = (hipStream_t)hip_stream;
-    const LevelView<double> V0 = view<double>(P.lv[0], P.periodic, nullptr);
     const double* b = f;  // f is used as given; face data, if any, is folded into a copy
     if (bc_faces != nullptr) {
       fold_faces(P, bc_faces, f, P.f0, st);
       b = P.f0;
     }
-    double* cur = phi;
-    double* alt = P.t0;
-    relax_n<double>(P, V0, P.lv[0], n_steps, cur, alt, b, nullptr, st, single_batch(), false);
-    if (cur != phi) copy_d2d(phi, cur, P.lv[0].n, st);
+    smooth_impl<double>(P, b, phi, n_steps, st);
+    HIPCHK(hipStreamSynchronize(st));
+    return RKL_OK;
+  });
+}
+
+rkl_status rkl_smooth_f32(const rkl_grid* grid, int s, double tau_frac, int n_steps, const float* f, float* phi,
+                          void* hip_stream) {
+  return guarded([&]() -> rkl_status {
+    validate_grid(grid, nullptr);
+    check_smooth_args(s, tau_frac, n_steps);
+    if (!f || !phi) fail(RKL_EINVAL, "f and phi must be non-NULL");
+    Plan& P = block_plan<float>(*grid, s, tau_frac, INT_MAX);
+    std::lock_guard<std::mutex> lk(P.mu);
+    hipStream_t st = (hipStream_t)hip_stream;
+    smooth_impl<float>(P, f, phi, n_steps, st);
     HIPCHK(hipStreamSynchronize(st));
     return RKL_OK;
   });
@@ -1696,75 +1897,52 @@ rkl_status rkl_residual(const rkl_grid* grid, const double* f, const double* bc_
   return guarded([&]() -> rkl_status {
     validate_grid(grid, bc_faces);
     if (!f || !phi) fail(RKL_EINVAL, "f and phi must be non-NULL");
-    Plan& P = get_plan(*grid, 2, 0.9, INT_MAX, RKL_FP64);
+    Plan& P = block_plan<double>(*grid, 2, 0.9, INT_MAX);
     std::lock_guard<std::mutex> lk(P.mu);
     hipStream_t st = (hipStream_t)hip_stream;
     const LevelView<double> V0 = view<double>(P.lv[0], P.periodic, nullptr);
     fold_faces(P, bc_faces, f, P.f0, st);
-    launch_residual<double, double>(V0, phi, P.f0, r_out, P.part, nullptr, st);
-    launch_reduce(P.part, (int)resid_blocks(V0.nx, V0.ny, V0.nz), 2, 1, P.dscal, nullptr, st);
-    check_launch();
-    const double r2 = readback(P, 1, st)[0];
-    if (norm_out) *norm_out = std::sqrt(r2);
+    const double nrm = residual_impl<double>(P, V0, P.f0, phi, r_out, st);
+    if (norm_out) *norm_out = nrm;
+    return RKL_OK;
+  });
+}
+
+rkl_status rkl_residual_f32(const rkl_grid* grid, const float* f, const float* phi, float* r_out, double* norm_out,
+                            void* hip_stream) {
+  return guarded([&]() -> rkl_status {
+    validate_grid(grid, nullptr);
+    if (!f || !phi) fail(RKL_EINVAL, "f and phi must be non-NULL");
+    Plan& P = block_plan<double>(*grid, 2, 0.9, INT_MAX);  // partial sums and scalars only
+    std::lock_guard<std::mutex> lk(P.mu);
+    hipStream_t st = (hipStream_t)hip_stream;
+    const LevelView<float> V0 = view<float>(P.lv[0], P.periodic, nullptr);
+    const double nrm = residual_impl<float>(P, V0, f, phi, r_out, st);
+    if (norm_out) *norm_out = nrm;
     return RKL_OK;
   });
 }
 
 rkl_status rkl_restrict(const rkl_grid* grid, const double* fine, double* coarse, void* hip_stream) {
-  return guarded([&]() -> rkl_status {
-    validate_grid(grid, nullptr);
-    if (grid->nx % 2 || grid->ny % 2 || (grid->nz % 2 && !flat_grid(*grid)))
-      fail(RKL_EINVAL, "fine sizes must be even (nz = 1 only for a two-dimensional grid)");
-    if (!fine || !coarse) fail(RKL_EINVAL, "NULL array");
-    hipStream_t st = (hipStream_t)hip_stream;
-    launch_restrict<double>(grid->nx, grid->ny, grid->nz, fine, coarse, st);
-    check_launch();
-    HIPCHK(hipStreamSynchronize(st));
-    return RKL_OK;
-  });
+  return restrict_entry<double>(grid, fine, coarse, hip_stream);
 }
-
+rkl_status rkl_restrict_f32(const rkl_grid* grid, const float* fine, float* coarse, void* hip_stream) {
+  return restrict_entry<float>(grid, fine, coarse, hip_stream);
+}
 rkl_status rkl_prolong_add(const rkl_grid* grid, const double* coarse, double* fine, void* hip_stream) {
-  return guarded([&]() -> rkl_status {
-    validate_grid(grid, nullptr);
-    if (grid->nx % 2 || grid->ny % 2 || (grid->nz % 2 && !flat_grid(*grid)))
-      fail(RKL_EINVAL, "fine sizes must be even (nz = 1 only for a two-dimensional grid)");
-    if (!fine || !coarse) fail(RKL_EINVAL, "NULL array");
-    hipStream_t st = (hipStream_t)hip_stream;
-    launch_prolong_add<double>(grid->nx, grid->ny, grid->nz, grid->bc == RKL_BC_PERIODIC ? 1 : 0, coarse,
-                               fine, nullptr, st);
-    check_launch();
-    HIPCHK(hipStreamSynchronize(st));
-    return RKL_OK;
-  });
+  return prolong_entry<double>(grid, coarse, fine, hip_stream);
+}
+rkl_status rkl_prolong_add_f32(const rkl_grid* grid, const float* coarse, float* fine, void* hip_stream) {
+  return prolong_entry<float>(grid, coarse, fine, hip_stream);
 }
 
 rkl_status rkl_coarse_solve(const rkl_grid* grid, const rkl_opts* opts, const double* b, double* u,
                             int* steps_out, void* hip_stream) {
-  return guarded([&]() -> rkl_status {
-    validate_grid(grid, nullptr);
-    const rkl_opts o = with_s(resolve_opts(opts), *grid);
-    if (!b || !u) fail(RKL_EINVAL, "NULL array");
-    Plan& P = get_plan(*grid, o.s, o.tau_frac, INT_MAX, RKL_FP64);
-    std::lock_guard<std::mutex> lk(P.mu);
-    hipStream_t st = (hipStream_t)hip_stream;
-    // the plan's only level is the coarsest: reuse the V-cycle's coarse path
-    Hier<double> H;
-    H.u = {u};
-    H.b = {const_cast<double*>(b)};
-    H.t = {P.t0};
-    const bool lds = coarse_in_lds(P, P.lv[0]);
-    coarse_solve<double>(P, H, 0, o, nullptr, st);
-    HIPCHK(hipMemcpyAsync(P.hscal, P.dsteps, sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    if (steps_out) {
-      if (lds) std::memcpy(steps_out, P.hscal, sizeof(int));
-      else *steps_out = -1;
-    }
-    if (H.u[0] != u) copy_d2d(u, H.u[0], P.lv[0].n, st);
-    HIPCHK(hipStreamSynchronize(st));
-    return RKL_OK;
-  });
+  return coarse_entry<double>(grid, opts, b, u, steps_out, hip_stream);
+}
+rkl_status rkl_coarse_solve_f32(const rkl_grid* grid, const rkl_opts* opts, const float* b, float* u,
+                                int* steps_out, void* hip_stream) {
+  return coarse_entry<float>(grid, opts, b, u, steps_out, hip_stream);
 }
 
 int rkl_tau_step_launches(const rkl_grid* grid, int s, int prec) {
@@ -1936,6 +2114,17 @@ rkl_status rkl_gradient(const rkl_grid* grid, const double* phi, const double* b
   });
 }
 
+int rkl_s_opt(const rkl_grid* grid, double tau_frac, int kmax, double digits, double* m_eff_out) {
+  return guarded([&]() -> rkl_status {
+    validate_grid(grid, nullptr);
+    if (!(tau_frac > 0.0 && tau_frac < 2.0)) fail(RKL_EINVAL, "tau_frac must be in (0, 2)");
+    if (kmax < 1) fail(RKL_EINVAL, "kmax must be >= 1");
+    if (!(digits > 0.0) || !std::isfinite(digits)) fail(RKL_EINVAL, "digits must be positive and finite");
+    const Lev L = build_levels(*grid, INT_MAX, 1, tau_frac)[0];
+    return (rkl_status)s_opt_rule(L, grid->bc == RKL_BC_PERIODIC, tau_frac, kmax, digits, m_eff_out);
+  });
+}
+
 void rkl_default_relax_opts(rkl_relax_opts* o) {
   if (!o) return;
   o->method = RKL_RELAX_RKL;
@@ -1956,7 +2145,7 @@ rkl_status rkl_relax_solve(const rkl_grid* grid, const rkl_relax_opts* opts, con
     if (opts) ro = *opts;
     if (ro.method != RKL_RELAX_RKL && ro.method != RKL_RELAX_GSRB && ro.method != RKL_RELAX_SOR)
       fail(RKL_EINVAL, "unknown relaxation method");
-    if (ro.s < 0 || ro.s > 64) fail(RKL_EINVAL, "s must be in [0, 64]");
+    if (ro.s < -1 || ro.s > 4096) fail(RKL_EINVAL, "s must be in [-1, 4096]");
     if (!(ro.tau_frac > 0.0 && ro.tau_frac < 2.0)) fail(RKL_EINVAL, "tau_frac must be in (0, 2)");
     if (!(ro.omega >= 0.0 && ro.omega < 2.0)) fail(RKL_EINVAL, "omega must be in [0, 2)");
     if (!(ro.tol_max >= 0.0)) fail(RKL_EINVAL, "tol_max must be >= 0");
@@ -1964,6 +2153,10 @@ rkl_status rkl_relax_solve(const rkl_grid* grid, const rkl_relax_opts* opts, con
     if (!f || !phi) fail(RKL_EINVAL, "f and phi must be non-NULL");
     if (stats) stats->history_len = 0;
     const bool rkl = ro.method == RKL_RELAX_RKL;
+    if (rkl && ro.s == -1) {  // the fixed stage count of App. A.3 for this grid
+      const Lev L0 = build_levels(*grid, INT_MAX, 1, ro.tau_frac)[0];
+      ro.s = s_opt_rule(L0, grid->bc == RKL_BC_PERIODIC, ro.tau_frac, 6, 2.0, nullptr);
+    }
     Plan& P = get_plan(*grid, rkl && ro.s > 0 ? ro.s : 2, ro.tau_frac, INT_MAX, RKL_FP64);
     std::lock_guard<std::mutex> lk(P.mu);
     hipStream_t st = (hipStream_t)hip_stream;

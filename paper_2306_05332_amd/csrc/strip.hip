@@ -55,12 +55,12 @@
 
 namespace rkl {
 
-template <typename T, int S, int R, int WY, bool PER, bool UZ, bool GS, bool FLAT>
-__global__ __launch_bounds__(64 * WY) void k_tau_strip(LevelView<T> L, const T* __restrict__ u,
-                                                       const T* __restrict__ b, T* __restrict__ out,
-                                                       FCoef<T, S> co, int zc, int gx_tiles, int gy_tiles,
-                                                       int nblk, StripMap sm, double* __restrict__ part, Batch bt,
-                                                       const int* __restrict__ stop) {
+template <typename T, int S, int R, int WY, bool PER, bool UZ, bool GS, bool FLAT, bool SHY>
+__device__ __forceinline__ void tau_strip_body(LevelView<T> L, const T* __restrict__ u, const T* __restrict__ b,
+                                               T* __restrict__ out, FCoef<T, S> co, int zc, int gx_tiles,
+                                               int gy_tiles, int nblk, StripMap sm, double* __restrict__ part,
+                                               Batch bt, const int* __restrict__ stop) {
+  static_assert(!SHY || (WY > 1 && !FLAT && R >= S), "shared y halos need stacked 3-D strips of >= S rows");
   {
     const long long mb = blockIdx.y;
     if (!UZ) u += mb * bt.s0;
@@ -75,6 +75,13 @@ __global__ __launch_bounds__(64 * WY) void k_tau_strip(LevelView<T> L, const T* 
   constexpr int NY = S > 1 ? S - 1 : 1;
   constexpr int A1 = FLAT ? 0 : 1;  // first row of stage 1 (stage j starts at row A1 * j)
   __shared__ double red[WY];
+  // SHY: the wavefronts of a workgroup are stacked in y, and each takes the
+  // halo rows it shares with its neighbours from their registers through LDS
+  // (double-buffered): [buffer][wavefront][side][row][lane], side 0 = the
+  // wavefront's lowest S rows of u (and S - 1 of b) for the one below's upper
+  // halo, side 1 = its highest rows for the one above's lower halo
+  constexpr int XU = S, XB = S > 1 ? S - 1 : 1;
+  __shared__ T xch[SHY ? 2 : 1][SHY ? WY : 1][2][SHY ? XU + XB : 1][64];
   if (stop != nullptr && *stop) return;
 
   const int lane = threadIdx.x & 63;
@@ -173,6 +180,52 @@ __global__ __launch_bounds__(64 * WY) void k_tau_strip(LevelView<T> L, const T* 
     return *(const T*)(base + colb(i));
   };
   auto pin = [&](int p) { return PER || (p >= 0 && p < nz); };
+  // rows read from memory: every row, or with SHY the wavefront's own R rows
+  // plus the outer halo of the workgroup's lowest / highest wavefront
+  auto gl = [&](int i) -> bool {
+    if constexpr (!SHY) return true;
+    else return (i >= S && i < S + R) || (i < S && w == 0) || (i >= S + R && w == WY - 1);
+  };
+  int xbuf = 0;
+  // SHY: halo rows of Ux (u) and Bx (b, when DOB) from the neighbouring
+  // wavefronts' registers; one barrier per exchange (the two buffers
+  // alternate, so the next exchange cannot overwrite rows still being read)
+  auto exchange = [&](T(&Ux)[NU], T(&Bx)[NU], bool dou, bool dob) {
+    if constexpr (SHY) {
+#pragma unroll
+      for (int r = 0; r < S; ++r) {
+        if (dou) {
+          xch[xbuf][w][0][r][lane] = Ux[S + r];
+          xch[xbuf][w][1][r][lane] = Ux[R + r];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < S - 1; ++r) {
+        if (dob) {
+          xch[xbuf][w][0][XU + r][lane] = Bx[S + r];
+          xch[xbuf][w][1][XU + r][lane] = Bx[R + 1 + r];
+        }
+      }
+      __syncthreads();
+      if (w > 0) {
+#pragma unroll
+        for (int r = 0; r < S; ++r)
+          if (dou) Ux[r] = xch[xbuf][w - 1][1][r][lane];
+#pragma unroll
+        for (int r = 0; r < S - 1; ++r)
+          if (dob) Bx[1 + r] = xch[xbuf][w - 1][1][XU + r][lane];
+      }
+      if (w < WY - 1) {
+#pragma unroll
+        for (int r = 0; r < S; ++r)
+          if (dou) Ux[R + S + r] = xch[xbuf][w + 1][0][r][lane];
+#pragma unroll
+        for (int r = 0; r < S - 1; ++r)
+          if (dob) Bx[R + S + r] = xch[xbuf][w + 1][0][XU + r][lane];
+      }
+      xbuf ^= 1;
+    }
+  };
   // GS coefficient of row i, plane p: c * D / D_cell (Dirichlet faces add h_d^-2)
   const T dgs = (T)2 * (L.ihx2 + L.ihy2 + L.ihz2);
   auto gscoef = [&](T c, int i, int p) -> T {
@@ -232,29 +285,42 @@ __global__ __launch_bounds__(64 * WY) void k_tau_strip(LevelView<T> L, const T* 
   }
   // rows outside a Dirichlet box and planes outside it read as 0
 #pragma unroll
-  for (int i = 0; i < NU; ++i) U0[i] = (UZ || !pin(zs - 1) || !(PER || ((rin >> i) & 1u))) ? (T)0 : row(u, ou, i);
+  for (int i = 0; i < NU; ++i)
+    if (gl(i)) U0[i] = (UZ || !pin(zs - 1) || !(PER || ((rin >> i) & 1u))) ? (T)0 : row(u, ou, i);
   ou = next_plane(ou, zs);
 #pragma unroll
-  for (int i = 0; i < NU; ++i) U1[i] = (UZ || !pin(zs) || !(PER || ((rin >> i) & 1u))) ? (T)0 : row(u, ou, i);
+  for (int i = 0; i < NU; ++i)
+    if (gl(i)) U1[i] = (UZ || !pin(zs) || !(PER || ((rin >> i) & 1u))) ? (T)0 : row(u, ou, i);
   ou = next_plane(ou, zs + 1);
 #pragma unroll
-  for (int i = 0; i < NU; ++i) U2[i] = (UZ || !pin(zs + 1) || !(PER || ((rin >> i) & 1u))) ? (T)0 : row(u, ou, i);
+  for (int i = 0; i < NU; ++i)
+    if (gl(i)) U2[i] = (UZ || !pin(zs + 1) || !(PER || ((rin >> i) & 1u))) ? (T)0 : row(u, ou, i);
 #pragma unroll
-  for (int i = A1; i < NU - A1; ++i) Bq[0][i] = (!pin(zs) || !(PER || ((rin >> i) & 1u))) ? (T)0 : row(b, ob, i);
+  for (int i = A1; i < NU - A1; ++i)
+    if (gl(i)) Bq[0][i] = (!pin(zs) || !(PER || ((rin >> i) & 1u))) ? (T)0 : row(b, ob, i);
+  exchange(U0, Bq[0], !UZ, false);
+  exchange(U1, Bq[0], !UZ, false);
+  exchange(U2, Bq[0], !UZ, true);
   double r2 = 0.0;
   T YS[NU];  // Y_S of the iteration's output plane, stored after the queues advance
 
   for (int zl = zs; zl <= ze; ++zl) {
     // next planes: loads issued now, consumed at the end of the iteration
-    // (unconditional: the plane index is wrapped or clamped into the box)
+    // (the plane index is wrapped or clamped into the box); the last
+    // iteration has no next plane to use
+    const bool more = zl < ze;
     ou = next_plane(ou, zl + 2);
     ob = next_plane(ob, zl + 1);
-    if (!UZ) {
+    if (!UZ && more) {
 #pragma unroll
-      for (int i = 0; i < NU; ++i) UN[i] = row(u, ou, i);
+      for (int i = 0; i < NU; ++i)
+        if (gl(i)) UN[i] = row(u, ou, i);
     }
+    if (more) {
 #pragma unroll
-    for (int i = A1; i < NU - A1; ++i) BN[i] = row(b, ob, i);
+      for (int i = A1; i < NU - A1; ++i)
+        if (gl(i)) BN[i] = row(b, ob, i);
+    }
     // stage 1 at plane zl, rows A1 .. NU-1-A1
     {
       const int p = zl;
@@ -320,6 +386,7 @@ __global__ __launch_bounds__(64 * WY) void k_tau_strip(LevelView<T> L, const T* 
       for (int j = S - 1; j > 0; --j) Bq[j][i] = Bq[j - 1][i];
       Bq[0][i] = (!bn_ok || !rok) ? (T)0 : BN[i];
     }
+    if (more) exchange(U2, Bq[0], !UZ, true);
     // stores after the wait for the loads above, so that the next
     // iteration's wait does not also wait for these writes
     __builtin_amdgcn_sched_barrier(0);
@@ -344,6 +411,27 @@ __global__ __launch_bounds__(64 * WY) void k_tau_strip(LevelView<T> L, const T* 
       part[blockIdx.x] = s;
     }
   }
+}
+
+template <typename T, int S, int R, int WY, bool PER, bool UZ, bool GS, bool FLAT>
+__global__ __launch_bounds__(64 * WY) void k_tau_strip(LevelView<T> L, const T* __restrict__ u,
+                                                       const T* __restrict__ b, T* __restrict__ out,
+                                                       FCoef<T, S> co, int zc, int gx_tiles, int gy_tiles,
+                                                       int nblk, StripMap sm, double* __restrict__ part, Batch bt,
+                                                       const int* __restrict__ stop) {
+  tau_strip_body<T, S, R, WY, PER, UZ, GS, FLAT, false>(L, u, b, out, co, zc, gx_tiles, gy_tiles, nblk, sm, part,
+                                                         bt, stop);
+}
+
+// the same with the y halo rows shared between the stacked wavefronts
+template <typename T, int S, int R, int WY, bool PER, bool UZ, bool GS>
+__global__ __launch_bounds__(64 * WY) void k_tau_strip_yx(LevelView<T> L, const T* __restrict__ u,
+                                                          const T* __restrict__ b, T* __restrict__ out,
+                                                          FCoef<T, S> co, int zc, int gx_tiles, int gy_tiles,
+                                                          int nblk, StripMap sm, double* __restrict__ part, Batch bt,
+                                                          const int* __restrict__ stop) {
+  tau_strip_body<T, S, R, WY, PER, UZ, GS, false, true>(L, u, b, out, co, zc, gx_tiles, gy_tiles, nblk, sm, part,
+                                                         bt, stop);
 }
 
 // flat: (nx, ny, nz) is the transposed view of a 2-D level (ny = 1, nz = the
@@ -423,6 +511,29 @@ void launch_strip(const LevelView<T>& L, int target, const T* u, const T* b, T* 
   launch_strip_k<T, S, R, WY, false, false>(L, target, u, b, out, fc, part, stop, bt, st);
 }
 
+// stacked wavefronts with shared y halo rows (3-D levels, WY > 1)
+template <typename T, int S, int R, int WY>
+void launch_strip_yx(const LevelView<T>& L, int target, const T* u, const T* b, T* out, const FCoef<T, S>& fc,
+                     double* part, const int* stop, const Batch& bt, hipStream_t st) {
+  const StripGrid g = strip_grid(S, R, WY, L.nx, L.ny, L.nz, target, false);
+  const dim3 grid(g.nblk, bt.nb), block(64 * WY);
+  if (L.periodic) {
+    if (u == nullptr)
+      hipLaunchKernelGGL((k_tau_strip_yx<T, S, R, WY, true, true, false>), grid, block, 0, st, L, u, b, out, fc,
+                         g.zc, g.gx, g.gy, g.nblk, g.map, part, bt, stop);
+    else
+      hipLaunchKernelGGL((k_tau_strip_yx<T, S, R, WY, true, false, false>), grid, block, 0, st, L, u, b, out, fc,
+                         g.zc, g.gx, g.gy, g.nblk, g.map, part, bt, stop);
+  } else {
+    if (u == nullptr)
+      hipLaunchKernelGGL((k_tau_strip_yx<T, S, R, WY, false, true, false>), grid, block, 0, st, L, u, b, out, fc,
+                         g.zc, g.gx, g.gy, g.nblk, g.map, part, bt, stop);
+    else
+      hipLaunchKernelGGL((k_tau_strip_yx<T, S, R, WY, false, false, false>), grid, block, 0, st, L, u, b, out, fc,
+                         g.zc, g.gx, g.gy, g.nblk, g.map, part, bt, stop);
+  }
+}
+
 template <typename T, int S, int R, int WY>
 void launch_strip2d(const LevelView<T>& L, int target, const T* u, const T* b, T* out, const FCoef<T, S>& fc,
                     double* part, const int* stop, const Batch& bt, hipStream_t st) {
@@ -467,6 +578,20 @@ RKL_STRIP_INST(float, 1, 5, 1)
 RKL_STRIP_INST(float, 2, 5, 1)
 RKL_STRIP_INST(float, 3, 5, 1)
 #undef RKL_STRIP_INST
+#define RKL_STRIPYX_INST(T, S, R, WY)                                                                        \
+  template void launch_strip_yx<T, S, R, WY>(const LevelView<T>&, int, const T*, const T*, T*,               \
+                                             const FCoef<T, S>&, double*, const int*, const Batch&, hipStream_t);
+RKL_STRIPYX_INST(double, 1, 8, 4)
+RKL_STRIPYX_INST(double, 2, 8, 4)
+RKL_STRIPYX_INST(double, 1, 4, 8)
+RKL_STRIPYX_INST(double, 2, 4, 8)
+RKL_STRIPYX_INST(float, 1, 8, 4)
+RKL_STRIPYX_INST(float, 2, 8, 4)
+RKL_STRIPYX_INST(float, 3, 8, 4)
+RKL_STRIPYX_INST(float, 1, 4, 8)
+RKL_STRIPYX_INST(float, 2, 4, 8)
+RKL_STRIPYX_INST(float, 3, 4, 8)
+#undef RKL_STRIPYX_INST
 #define RKL_STRIP2D_INST(T, S, R, WY)                                                                          \
   template void launch_strip2d<T, S, R, WY>(const LevelView<T>&, int, const T*, const T*, T*, const FCoef<T, S>&, \
                                             double*, const int*, const Batch&, hipStream_t);

@@ -211,3 +211,36 @@ def test_strip2d_variants_only_on_two_dimensional_levels(lib):
     finally:
         _lib.tune_clear()
         _lib.install_default_tuning()
+
+
+def test_s_opt_rule_through_the_abi(lib):
+    """App. A.3 through rkl_s_opt (host arithmetic, no GPU): 56 for the paper's
+    N = 64 model (cubic Dirichlet grid, tau = tau_max, six modes, two digits);
+    equal to the oracle's 1-D argmin for N = 16 .. 128 and to the oracle's
+    level form at theta = 0.9 on periodic, anisotropic and 2-D grids."""
+    import math
+
+    from oracle import operators as op
+    from oracle import rkl as orkl
+    from paper_2306_05332_amd import _lib
+    s, m = _lib.s_opt((64, 64, 64), 1.0 / 64, "dirichlet", tau_frac=1.0)
+    assert s == 56
+    assert abs(m - orkl.m_eff_1d(56, 64)) <= 1e-9 * m
+    for N in (16, 24, 32, 48, 64, 96, 128):
+        assert _lib.s_opt((N, N, N), 1.0 / N, "dirichlet", tau_frac=1.0)[0] == orkl.s_opt_global_1d(N), N
+    cases = [((32, 32, 32), (1 / 32,) * 3, "periodic"), ((16, 32, 64), (0.01, 0.012, 0.015), "dirichlet"),
+             ((24, 40, 56), (0.02, 0.02, 0.03), "periodic"), ((64, 96), (0.01, 0.02), "dirichlet")]
+    for shape, h, bc in cases:
+        lshape = shape if len(shape) == 3 else (1,) + shape
+        lh = h if len(h) == 3 else (h[0], h[1], math.inf)
+        want, wm = orkl.s_opt_global(op.Level(0, lshape, lh, bc), 0.9)
+        got, gm = _lib.s_opt(shape, h, bc, tau_frac=0.9)
+        assert got == want and abs(gm - wm) <= 1e-9 * wm, (shape, bc, got, want)
+
+
+def test_s_opt_rejects_bad_arguments(lib):
+    from paper_2306_05332_amd._lib import c_grid
+    g = c_grid(8, 8, 8, 0.1, 0.1, 0.1, 0)
+    assert lib.rkl_s_opt(ctypes.byref(g), 0.0, 6, 2.0, None) == -1
+    assert lib.rkl_s_opt(ctypes.byref(g), 0.9, 0, 2.0, None) == -1
+    assert lib.rkl_s_opt(ctypes.byref(g), 0.9, 6, -1.0, None) == -1

@@ -162,3 +162,28 @@ def test_relax_solve_periodic_and_statuses():
     assert st.status == 0 and abs(st.cycles - it) <= 4
     phi, st = R.relax_solve(cu(f), h, "periodic", "gsrb", tol_max=1e-14, max_iters=10, raise_on_error=False)
     assert st.status == R.RKL_ENOCONV and st.cycles == 10
+
+
+@pytest.mark.parametrize("n", [16, 32])
+def test_relax_solve_fixed_s_opt_matches_oracle(n):
+    """Single-level RKL with the fixed stage count of App. A.3 (s = -1 asks the
+    library for it): the s the library reports (rkl_s_opt) equals the oracle's
+    level rule, and the relaxation matches the oracle's with that s (iteration
+    count up to a tie at the tolerance, the iterate, u*)."""
+    R = _lib()
+    from oracle import rkl as orkl
+    p = W.accuracy_problem(n)
+    g = _grid(p)
+    f = omg.prepare_source(p.rho, g, omg.Options())
+    s, _ = R.s_opt(p.shape, p.h, "dirichlet", tau_frac=0.9)
+    assert s == orkl.s_opt_global(oop.build_hierarchy(g, 1 << 30)[0], 0.9)[0]
+    u, it, res, hist = omg.relax_solve(f, g, "rkl", faces=p.faces, tol_max=1e-10, s=s, theta=0.9)
+    phi, st = R.relax_solve(cu(f), p.h, "dirichlet", "rkl", faces=R.pack_faces(p.faces), s=-1, tol_max=1e-10)
+    print(f"s_opt n={n}: s={s}, oracle {it} tau-steps, gpu {st.cycles}", flush=True)
+    assert st.status == 0 and st.rel_res <= 1e-10
+    assert abs(st.cycles - it) <= 1
+    np.testing.assert_allclose(st.history[:5], hist[:5], rtol=1e-9)
+    if st.cycles == it:
+        assert relmax(phi.cpu().numpy(), u) < 1e-9
+    us = exact.exact_solution(FOURPI * p.rho, p.h, "dirichlet", p.faces)
+    assert relmax(phi.cpu().numpy(), us) < 1e-8

@@ -228,3 +228,39 @@ def test_warm_start_converges_in_fewer_cycles():
     phi, st = R.solve(rho, p.h, "periodic", opts=R.Options(tol=1e-8))
     phi2, st2 = R.solve(rho * 1.001, p.h, "periodic", phi0=phi * 1.001, opts=R.Options(tol=1e-8))
     assert st2.cycles < st.cycles
+
+
+@pytest.mark.parametrize("n_post", [1, 2])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_no_pre_smoothing_returns_the_tested_state(n_post, prec):
+    """n_pre = 0: the cycles start with a copy of the start state (no relaxation
+    keeps it); cycles queued past the stopping one must leave the answer
+    intact.  The returned phi has the reported residual (recomputed here by
+    the library's residual) and matches u*."""
+    R = _lib()
+    p = W.gaussian_blobs(64, 8, seed=21)
+    o = R.Options(tol=1e-10, n_pre=0, n_post=n_post, prec=prec, max_cycles=200)
+    phi, st = R.solve(cu(p.rho), p.h, "periodic", opts=o)
+    assert st.status == 0 and st.rel_res <= 1e-10
+    f = FOURPI * (p.rho - p.rho.mean())
+    _, nrm = R.residual(cu(f), phi, p.h, "periodic")
+    assert nrm / np.linalg.norm(f) <= 1.0001e-10
+    assert abs(nrm / np.linalg.norm(f) - st.rel_res) <= 1e-3 * st.rel_res
+    us = exact.exact_solution(FOURPI * p.rho, p.h, "periodic")
+    assert relmax(host(phi), us) < 1e-8
+
+
+def test_batched_class_alternating_n_pre():
+    """One grid class solved with n_pre = 2, then 0, then 2 again: each call
+    matches the single solve with the same options cycle for cycle."""
+    R = _lib()
+    probs = [W.gaussian_blobs(32, 6, seed=30 + q) for q in range(3)]
+    rhos = [cu(p.rho) for p in probs]
+    for n_pre in (2, 0, 2):
+        o = R.Options(tol=1e-10, n_pre=n_pre, n_post=1, max_cycles=200)
+        phis, sts = R.solve_batched(rhos, [p.h for p in probs], "periodic", opts=o)
+        for q, p in enumerate(probs):
+            phi1, st1 = R.solve(rhos[q], p.h, "periodic", opts=o)
+            print(f"n_pre={n_pre} member {q}: batched {sts[q].cycles} cycles, single {st1.cycles}", flush=True)
+            assert sts[q].status == 0 and sts[q].cycles == st1.cycles
+            assert relmax(host(phis[q]), host(phi1)) < 1e-12

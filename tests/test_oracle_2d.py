@@ -285,3 +285,21 @@ def test_smooth_disc_workload_second_order():
         errs.append(np.sqrt(np.mean((us - p.phi_exact) ** 2)))
     for a, b in zip(errs, errs[1:]):
         assert 3.6 < a / b < 4.4
+
+
+def test_float64_residual_floor_of_the_2d_4096_field():
+    """The benchmark's 2-D field (4096^2 periodic blobs, seed 6): its exact
+    discrete solution u* (FFT), rounded to float64, has a relative residual
+    ||M u* - f|| / ||f|| above 1e-10, which no float64 iteration can reliably
+    beat; the floor grows about fourfold per doubling of n (eps Lambda
+    ||u|| / ||f|| with Lambda = 8 n^2)."""
+    floors = []
+    for n in (1024, 2048, 4096):
+        p = W.gaussian_blobs_2d(n, n, nblobs=32, seed=6)
+        f = 4 * math.pi * (p.rho - p.rho.mean())
+        us = exact.exact_solution(4 * math.pi * p.rho, p.h, "periodic")
+        r = op.apply_M(us.reshape(1, n, n), (p.h[0], p.h[1], math.inf), "periodic").reshape(n, n) - f
+        floors.append(np.linalg.norm(r) / np.linalg.norm(f))
+    assert 1e-10 < floors[-1] < 3e-10
+    for a, b in zip(floors, floors[1:]):
+        assert 3.0 < b / a < 5.0

@@ -119,6 +119,22 @@ def test_s_opt_global_is_56_for_N64():
     assert int(np.argmin(rhos)) + 1 != 56
 
 
+def test_s_opt_global_3d_reduces_to_the_1d_rule():
+    """The level form of the App. A.3 rule at theta = 1 on cubic Dirichlet
+    grids sees x_k = cos(k pi / N) and gives the 1-D argmin (56 at N = 64)."""
+    for N in (16, 24, 32, 48, 64, 96, 128):
+        lv = op.Level(0, (N, N, N), (1.0 / N,) * 3, "dirichlet")
+        s, m = rkl.s_opt_global(lv, 1.0)
+        assert s == rkl.s_opt_global_1d(N), N
+        assert abs(m - rkl.m_eff_1d(s, N)) <= 1e-9 * m
+    lv = op.Level(0, (64, 64, 64), (1.0 / 64,) * 3, "dirichlet")
+    assert rkl.s_opt_global(lv, 1.0)[0] == GOLD["s_opt_global_N64"]["value"]
+    # m_eff at the argmin is below that of every other s (scipy's Legendre values)
+    x = np.cos(np.arange(1, 7) * math.pi / 64)
+    meff = [s * 2.0 / -math.log10(np.max(np.abs(eval_legendre(s, x)))) for s in range(1, 65)]
+    assert int(np.argmin(meff)) + 1 == 56
+
+
 def test_first_six_modes_set_the_spectral_radius():
     """App. A.3: for the 1-D model the first six modes determine rho(R) (checked
     against all N/2 modes with scipy's Legendre values)."""
