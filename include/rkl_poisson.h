@@ -397,6 +397,26 @@ int rkl_s_opt(const rkl_grid *grid, double tau_frac, int kmax, double digits, do
 rkl_status rkl_gradient(const rkl_grid *grid, const double *phi, const double *bc_faces, double *gx,
                         double *gy, double *gz, void *hip_stream);
 
+/*
+ * For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the residual
+ * of rkl_residual without any allocation and without synchronising.
+ *   r_out     device float64[n] or NULL: f - M phi, with the Dirichlet face
+ *             data of bc_faces applied in the stencil (ghost 2 g - u); the
+ *             values equal rkl_residual's (which folds the face data into a
+ *             copy of f first) up to rounding, and bit for bit without faces
+ *   norm_dev  DEVICE double or NULL: receives ||f - M phi||_2, computed on the
+ *             GPU (stream-ordered; read it after synchronising the stream)
+ * Other arguments as rkl_residual.  The workgroups' partial sums go to a fixed
+ * 1 MiB array inside the library, one per GPU, held until the process ends;
+ * a grid whose residual needs more than 65536 partial-sum pairs (3-D: beyond
+ * about 1024^3 cells) is RKL_EINVAL, before any GPU work.  Every call on a GPU
+ * uses that GPU's one array: calls that overlap in time on one GPU (other
+ * streams or host threads) race and must be serialised by the caller.
+ */
+rkl_status rkl_residual_noalloc(const rkl_grid *grid, const double *f, const double *bc_faces,
+                                const double *phi, double *r_out, double *norm_dev, void *hip_stream);
+
 /* Thread-local message describing the last failure (never NULL). */
 const char *rkl_last_error(void);
 

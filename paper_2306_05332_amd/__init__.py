@@ -10,6 +10,6 @@ from ._lib import (RKLError, Options, Stats, coarse_solve, load_library, pack_fa
                    prolong_add, release_all, residual, restrict, smooth, solve, solve_batched,
                    vcycle, tau_step_launches, kernel_info, EXPORTS, LIB_PATH, VARIANTS,
                    tune_set, tune_clear, tune_get, autotune_level, tune_set_s, level_shapes,
-                   install_default_tuning, gsrb_smooth, relax_solve, gradient, s_opt,
+                   install_default_tuning, gsrb_smooth, relax_solve, gradient, s_opt, residual_noalloc,
                    RKL_OK, RKL_EINVAL, RKL_ENOMEM, RKL_ENOCONV, RKL_EDIVERGED, RKL_ENONFINITE, RKL_EHIP)
 from .autograd import PoissonSolve, poisson_solve  # noqa: F401,E402

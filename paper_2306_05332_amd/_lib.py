@@ -69,7 +69,7 @@ EXPORTS = ("rkl_default_opts", "rkl_poisson_solve", "mg_vcycle", "rkl_smooth", "
            "rkl_tune_set_s", "rkl_level_shapes", "rkl_variant_name", "rkl_gsrb_smooth", "rkl_default_relax_opts",
            "rkl_relax_solve", "rkl_gradient", "rkl_last_error", "rkl_release_all", "rkl_smooth_f32",
            "mg_vcycle_f32", "rkl_residual_f32", "rkl_restrict_f32", "rkl_prolong_add_f32", "rkl_coarse_solve_f32",
-           "rkl_s_opt")
+           "rkl_s_opt", "rkl_residual_noalloc")
 SMOOTHERS = {"rkl": 0, "gsrb": 1}
 RELAX = {"rkl": 0, "gsrb": 1, "sor": 2}
 VARIANTS = {0: "heuristic", 1: "ring64x8", 2: "ring64x4", 3: "zq64x32", 4: "zq64x16", 5: "strip8x4",
@@ -134,6 +134,8 @@ def load_library(path: str = LIB_PATH):
     lib.rkl_default_relax_opts.restype = None
     lib.rkl_relax_solve.argtypes = [pg, ctypes.POINTER(c_relax), P, P, P, ps, P]
     lib.rkl_relax_solve.restype = ctypes.c_int
+    lib.rkl_residual_noalloc.argtypes = [pg, P, P, P, P, P, P]
+    lib.rkl_residual_noalloc.restype = ctypes.c_int
     lib.rkl_s_opt.argtypes = [pg, ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
     lib.rkl_s_opt.restype = ctypes.c_int
     lib.rkl_gradient.argtypes = [pg, P, P, P, P, P, P]
@@ -339,6 +341,20 @@ def residual(f, phi, h, bc="periodic", faces=None):
     _check(lib.rkl_residual(ctypes.byref(g), _dev(f, "f"), _dev(faces, "faces"), _dev(phi, "phi"),
                             _dev(r, "r"), ctypes.byref(nrm), _stream(f)))
     return r, nrm.value
+
+
+def residual_noalloc(f, phi, h, bc="periodic", faces=None):
+    """(f - M phi, ||f - M phi||_2 as a one-element device tensor) through
+    rkl_residual_noalloc: no device allocation in the library and no
+    synchronisation (the outputs are allocated here, by the caller's side)."""
+    lib = load_library()
+    _check_faces(faces, f.shape, bc)
+    g = _grid(f.shape, h, bc)
+    r = torch.empty_like(f)
+    nrm = torch.empty(1, dtype=torch.float64, device=f.device)
+    _check(lib.rkl_residual_noalloc(ctypes.byref(g), _dev(f, "f"), _dev(faces, "faces"), _dev(phi, "phi"),
+                                    _dev(r, "r"), _dev(nrm, "norm"), _stream(f)))
+    return r, nrm
 
 
 def restrict(fine):

@@ -20,7 +20,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "librklpoisson.so")
 ARCH = os.environ.get("RKL_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["kernels.hip", "transfer.hip", "coarse.hip", "tail.hip", "fused.hip", "strip.hip", "solver.hip"]
+SOURCES = ["kernels.hip", "transfer.hip", "coarse.hip", "tail.hip", "fused.hip", "strip.hip", "solver.hip",
+           "noalloc.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
