@@ -95,22 +95,26 @@ def sources_digest():
 
 
 def kernel_symbol(R, shape, s, prec="fp64"):
-    """Demangled name prefix of the finest-level tau-step kernel in effect."""
+    """Demangled name prefix of the finest-level periodic tau-step kernel in
+    effect (strip kernels: up to the last template argument, the store-hint
+    flag, which the launcher picks from the level's size)."""
     tname = "double" if prec == "fp64" else "float"
     v = R.tune_get(shape, s, "periodic", prec)["variant"]
+    strip = {"strip8x4": (8, 4), "strip8x1": (8, 1), "strip4x4": (4, 4), "strip5x1": (5, 1)}
+    shy = {"stripyx8x4": (8, 4), "stripyx4x8": (4, 8), "stripyx8x8": (8, 8), "stripyx2x8": (2, 8),
+           "stripyx2x16": (2, 16)}
+    flat = {"strip2d8": 8, "strip2d4": 4}
+    if v in strip:
+        return f"rkl::k_tau_strip<{tname}, {s}, {strip[v][0]}, {strip[v][1]}, true, false, false, false, "
+    if v in shy:
+        return f"rkl::k_tau_strip_yx<{tname}, {s}, {shy[v][0]}, {shy[v][1]}, true, false, false, "
+    if v in flat:
+        r = flat[v] if (prec != "fp64" or s <= 2) else 4
+        return f"rkl::k_tau_strip<{tname}, {s}, {r}, 1, true, false, false, true, "
     return {"ring64x8": f"rkl::k_fused_tau<{tname}, {s}, 64, 8>",
             "ring64x4": f"rkl::k_fused_tau<{tname}, {s}, 64, 4>",
             "zq64x32": f"rkl::k_tau_zq<{tname}, {s}, 64, 32, 512, 1, 0>",
-            "zq64x16": f"rkl::k_tau_zq<{tname}, {s}, 64, 16, 256, 1, 0>",
-            "strip8x4": f"rkl::k_tau_strip<{tname}, {s}, 8, 4, true, false, false, false>",
-            "strip8x1": f"rkl::k_tau_strip<{tname}, {s}, 8, 1, true, false, false, false>",
-            "strip4x4": f"rkl::k_tau_strip<{tname}, {s}, 4, 4, true, false, false, false>",
-            "strip5x1": f"rkl::k_tau_strip<{tname}, {s}, 5, 1, true, false, false, false>",
-            "stripyx8x4": f"rkl::k_tau_strip_yx<{tname}, {s}, 8, 4, true, false, false>",
-            "stripyx4x8": f"rkl::k_tau_strip_yx<{tname}, {s}, 4, 8, true, false, false>",
-            "strip2d8": f"rkl::k_tau_strip<{tname}, {s}, 8, 1, true, false, false, true>",
-            "strip2d4": f"rkl::k_tau_strip<{tname}, {s}, 4, 1, true, false, false, true>"}.get(
-                v, f"rkl::k_stage<{tname}>")
+            "zq64x16": f"rkl::k_tau_zq<{tname}, {s}, 64, 16, 256, 1, 0>"}.get(v, f"rkl::k_stage<{tname}>")
 
 
 def sweep_inputs(torch, W, dev):
@@ -245,7 +249,7 @@ def summarize_trace(d):
     print("\n".join(out))
 
 
-TWO_D_KERNEL = "rkl::k_tau_strip<double, 4, 4, 1, true, false, false, true>"
+TWO_D_KERNEL = "rkl::k_tau_strip<double, 4, 4, 1, true, false, false, true, "
 
 
 def summarize_trace_2d(d):

@@ -279,6 +279,10 @@ int rkl_tau_step_launches(const rkl_grid *grid, int s, int prec);
  *              take the halo rows they share from each other through LDS
  *              (u and b rows read once per workgroup instead of per wavefront)
  *          12  as 11 with 8 wavefronts of 4 rows
+ *          13  as 11 with 8 wavefronts of 8 rows
+ *          14  as 11 with 8 wavefronts of 2 rows (s <= 2)
+ *          15  as 11 with 16 wavefronts of 2 rows (s <= 2)
+ *          13  as 11 with 8 wavefronts of 8 rows
  *              (strip: s <= 2 in float64, s <= 3 in float32; variants 8 and 9
  *              are for two-dimensional levels, nz = 1 with hz = inf, and
  *              those levels take no other variant)

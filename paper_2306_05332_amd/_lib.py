@@ -74,7 +74,7 @@ SMOOTHERS = {"rkl": 0, "gsrb": 1}
 RELAX = {"rkl": 0, "gsrb": 1, "sor": 2}
 VARIANTS = {0: "heuristic", 1: "ring64x8", 2: "ring64x4", 3: "zq64x32", 4: "zq64x16", 5: "strip8x4",
             6: "strip8x1", 7: "strip4x4", 8: "strip2d8", 9: "strip2d4", 10: "strip5x1", 11: "stripyx8x4",
-            12: "stripyx4x8"}
+            12: "stripyx4x8", 13: "stripyx8x8", 14: "stripyx2x8", 15: "stripyx2x16"}
 
 _lib = None
 
@@ -516,6 +516,9 @@ def kernel_info(shape, s, bc="periodic", prec="fp64", h=1.0):
                 "strip5x1": f"k_tau_strip<{tname}, {s}, 5, 1>",
                 "stripyx8x4": f"k_tau_strip_yx<{tname}, {s}, 8, 4>",
                 "stripyx4x8": f"k_tau_strip_yx<{tname}, {s}, 4, 8>",
+                "stripyx8x8": f"k_tau_strip_yx<{tname}, {s}, 8, 8>",
+                "stripyx2x8": f"k_tau_strip_yx<{tname}, {s}, 2, 8>",
+                "stripyx2x16": f"k_tau_strip_yx<{tname}, {s}, 2, 16>",
                 }.get(v["variant"], f"k_fused_tau<{tname}, {s}, 64, 8>")
     else:
         words = (3.0 + 4.0 * (s - 1)) / s

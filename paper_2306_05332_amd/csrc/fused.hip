@@ -530,7 +530,10 @@ bool fused_variant_ok(int variant, int s) {
     case FV_STRIP_4x4:
     case FV_STRIP_5x1:
     case FV_STRIPYX_8x4:
-    case FV_STRIPYX_4x8: return dbl ? s <= 2 : s <= 3;
+    case FV_STRIPYX_4x8:
+    case FV_STRIPYX_8x8: return dbl ? s <= 2 : s <= 3;
+    case FV_STRIPYX_2x8:
+    case FV_STRIPYX_2x16: return s <= 2;  // shared halo rows come from the R = 2 own rows
     default: return false;
   }
 }
@@ -542,11 +545,21 @@ static bool variant_fits(const LevelView<T>& L, int variant) {
 
 static bool is_strip(int variant) {
   return variant == FV_STRIP_8x4 || variant == FV_STRIP_8x1 || variant == FV_STRIP_4x4 || variant == FV_STRIP_5x1 ||
-         variant == FV_STRIPYX_8x4 || variant == FV_STRIPYX_4x8;
+         variant == FV_STRIPYX_8x4 || variant == FV_STRIPYX_4x8 || variant == FV_STRIPYX_8x8 ||
+         variant == FV_STRIPYX_2x8 || variant == FV_STRIPYX_2x16;
 }
 static void strip_shape(int variant, int& R, int& WY) {
-  R = (variant == FV_STRIP_4x4 || variant == FV_STRIPYX_4x8) ? 4 : (variant == FV_STRIP_5x1 ? 5 : 8);
-  WY = (variant == FV_STRIP_8x1 || variant == FV_STRIP_5x1) ? 1 : (variant == FV_STRIPYX_4x8 ? 8 : 4);
+  switch (variant) {
+    case FV_STRIP_8x4: R = 8; WY = 4; return;
+    case FV_STRIP_8x1: R = 8; WY = 1; return;
+    case FV_STRIP_4x4: R = 4; WY = 4; return;
+    case FV_STRIP_5x1: R = 5; WY = 1; return;
+    case FV_STRIPYX_8x4: R = 8; WY = 4; return;
+    case FV_STRIPYX_4x8: R = 4; WY = 8; return;
+    case FV_STRIPYX_8x8: R = 8; WY = 8; return;
+    case FV_STRIPYX_2x8: R = 2; WY = 8; return;
+    default: R = 2; WY = 16; return;  // FV_STRIPYX_2x16
+  }
 }
 
 static void variant_tile(int variant, int& bx, int& by) {
@@ -684,6 +697,14 @@ void launch_fused_S(const LevelView<T>& L, FusedChoice c, const T* u, const T* b
         return launch_strip_yx<T, S, 8, 4>(L, c.target, u, b, out, fc, part, stop, bt, st);
       if (c.variant == FV_STRIPYX_4x8)
         return launch_strip_yx<T, S, 4, 8>(L, c.target, u, b, out, fc, part, stop, bt, st);
+      if (c.variant == FV_STRIPYX_8x8)
+        return launch_strip_yx<T, S, 8, 8>(L, c.target, u, b, out, fc, part, stop, bt, st);
+      if constexpr (S <= 2) {
+        if (c.variant == FV_STRIPYX_2x8)
+          return launch_strip_yx<T, S, 2, 8>(L, c.target, u, b, out, fc, part, stop, bt, st);
+        if (c.variant == FV_STRIPYX_2x16)
+          return launch_strip_yx<T, S, 2, 16>(L, c.target, u, b, out, fc, part, stop, bt, st);
+      }
     }
   }
   int bx, by;
@@ -809,6 +830,9 @@ const char* fused_variant_name(int variant) {
     case FV_STRIP_5x1: return "strip5x1";
     case FV_STRIPYX_8x4: return "stripyx8x4";
     case FV_STRIPYX_4x8: return "stripyx4x8";
+    case FV_STRIPYX_8x8: return "stripyx8x8";
+    case FV_STRIPYX_2x8: return "stripyx2x8";
+    case FV_STRIPYX_2x16: return "stripyx2x16";
     default: return "heuristic";
   }
 }

@@ -125,7 +125,10 @@ enum : int {
   FV_STRIP_5x1 = 10,  // strip kernel: R = 5 rows per lane (3 waves per SIMD in float64), one wavefront per workgroup
   FV_STRIPYX_8x4 = 11,  // R = 8, 4 wavefronts stacked in y sharing their halo rows through LDS
   FV_STRIPYX_4x8 = 12,  // R = 4, 8 wavefronts stacked in y sharing their halo rows through LDS
-  FV_COUNT = 13
+  FV_STRIPYX_8x8 = 13,  // R = 8, 8 wavefronts stacked in y sharing their halo rows through LDS
+  FV_STRIPYX_2x8 = 14,  // R = 2, 8 wavefronts stacked in y sharing their halo rows through LDS
+  FV_STRIPYX_2x16 = 15, // R = 2, 16 wavefronts stacked in y sharing their halo rows through LDS
+  FV_COUNT = 16
 };
 // A two-dimensional level (nz = 1, ihz2 = 0) takes the FV_STRIP2D_* variants
 // and no others; a 3-D level takes every variant but those.

@@ -105,7 +105,8 @@ VSHAPES = [(20, 11, 130), (16, 16, 16), (40, 24, 64), (72, 130, 160), (11, 100, 
 # stage counts each 3-D variant is built for in float32
 SUPPORT32 = {"ring64x8": (1, 2, 3, 4), "ring64x4": (1, 2, 3, 4), "zq64x32": (2, 3), "zq64x16": (2, 3),
              "strip8x4": (1, 2, 3), "strip8x1": (1, 2, 3), "strip4x4": (1, 2, 3), "strip5x1": (1, 2, 3),
-             "stripyx8x4": (1, 2, 3), "stripyx4x8": (1, 2, 3)}
+             "stripyx8x4": (1, 2, 3), "stripyx4x8": (1, 2, 3), "stripyx8x8": (1, 2, 3), "stripyx2x8": (1, 2),
+             "stripyx2x16": (1, 2)}
 
 
 @pytest.mark.parametrize("variant", list(SUPPORT32))

@@ -49,12 +49,13 @@ def _restore_table():
 # over; nx = 20: no full tile, 2 strips per wavefront)
 VSHAPES = [(20, 11, 130), (16, 16, 16), (40, 24, 64), (72, 130, 160), (11, 100, 136), (9, 60, 20)]
 VARIANTS = ["ring64x8", "ring64x4", "zq64x32", "zq64x16", "strip8x4", "strip8x1", "strip4x4", "strip5x1",
-            "stripyx8x4", "stripyx4x8"]
+            "stripyx8x4", "stripyx4x8", "stripyx8x8", "stripyx2x8", "stripyx2x16"]
 # stage counts each variant is built for: (float64, float32)
 SUPPORT = {"ring64x8": ((1, 2, 3), (1, 2, 3, 4)), "ring64x4": ((1, 2, 3), (1, 2, 3, 4)),
            "zq64x32": ((2, 3), (2, 3)), "zq64x16": ((2, 3), (2, 3)),
            "strip8x4": ((1, 2), (1, 2, 3)), "strip8x1": ((1, 2), (1, 2, 3)), "strip4x4": ((1, 2), (1, 2, 3)),
-           "strip5x1": ((1, 2), (1, 2, 3)), "stripyx8x4": ((1, 2), (1, 2, 3)), "stripyx4x8": ((1, 2), (1, 2, 3))}
+           "strip5x1": ((1, 2), (1, 2, 3)), "stripyx8x4": ((1, 2), (1, 2, 3)), "stripyx4x8": ((1, 2), (1, 2, 3)),
+           "stripyx8x8": ((1, 2), (1, 2, 3)), "stripyx2x8": ((1, 2), (1, 2)), "stripyx2x16": ((1, 2), (1, 2))}
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
