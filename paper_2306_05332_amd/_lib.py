@@ -42,7 +42,8 @@ class c_opts(ctypes.Structure):
     _fields_ = [("s", ctypes.c_int), ("tau_frac", ctypes.c_double), ("n_pre", ctypes.c_int),
                 ("n_post", ctypes.c_int), ("min_coarse", ctypes.c_int), ("tol", ctypes.c_double),
                 ("max_cycles", ctypes.c_int), ("prec", ctypes.c_int), ("four_pi_G", ctypes.c_double),
-                ("coarse_tol", ctypes.c_double), ("coarse_max_steps", ctypes.c_int), ("smoother", ctypes.c_int)]
+                ("coarse_tol", ctypes.c_double), ("coarse_max_steps", ctypes.c_int), ("smoother", ctypes.c_int),
+                ("fuse", ctypes.c_int)]
 
 
 class c_relax(ctypes.Structure):
@@ -180,11 +181,12 @@ class Options:
     coarse_tol: float = 0.0
     coarse_max_steps: int = 200
     smoother: str = "rkl"
+    fuse: bool = True   # prolongation fused into the first post-smoothing tau-step where supported
 
     def c(self):
         return c_opts(self.s, self.tau_frac, self.n_pre, self.n_post, self.min_coarse, self.tol,
                       self.max_cycles, PREC[self.prec], self.four_pi_G, self.coarse_tol,
-                      self.coarse_max_steps, SMOOTHERS[self.smoother])
+                      self.coarse_max_steps, SMOOTHERS[self.smoother], 1 if self.fuse else 0)
 
 
 @dataclass

@@ -22,6 +22,7 @@
 #include <mutex>
 #include <tuple>
 
+#include "host_common.h"
 #include "kernels.h"
 
 namespace rkl {
@@ -788,6 +789,81 @@ bool launch_fused_tau(const LevelView<T>& L, const T* u, const T* b, T* out, int
   return launch_fused_tau_as<T>(L, fused_choice<T>(L, s), u, b, out, s, co, part, stop, st, bt);
 }
 
+template <typename T, int S>
+static bool launch_pro_S(const LevelView<T>& L, int variant, int target, const T* u, const T* e, const T* b, T* out,
+                         const StageCoef* co, const int* stop, const Batch& bt, hipStream_t st) {
+  if constexpr (S > fused_max_s<T>() || !strip_instantiated<T, S>()) {
+    return false;
+  } else {
+    const FCoef<T, S> fc = make_fcoef<T, S>(co);
+    switch (variant) {
+      case FV_STRIP_8x4: launch_strip_pro<T, S, 8, 4, false>(L, target, u, e, b, out, fc, stop, bt, st); return true;
+      case FV_STRIP_8x1: launch_strip_pro<T, S, 8, 1, false>(L, target, u, e, b, out, fc, stop, bt, st); return true;
+      case FV_STRIP_4x4: launch_strip_pro<T, S, 4, 4, false>(L, target, u, e, b, out, fc, stop, bt, st); return true;
+      case FV_STRIPYX_8x4: launch_strip_pro<T, S, 8, 4, true>(L, target, u, e, b, out, fc, stop, bt, st); return true;
+      case FV_STRIPYX_4x8: launch_strip_pro<T, S, 4, 8, true>(L, target, u, e, b, out, fc, stop, bt, st); return true;
+      case FV_STRIPYX_8x8: launch_strip_pro<T, S, 8, 8, true>(L, target, u, e, b, out, fc, stop, bt, st); return true;
+      default: break;
+    }
+    if constexpr (S <= 2) {
+      if (variant == FV_STRIPYX_2x8) {
+        launch_strip_pro<T, S, 2, 8, true>(L, target, u, e, b, out, fc, stop, bt, st);
+        return true;
+      }
+      if (variant == FV_STRIPYX_2x16) {
+        launch_strip_pro<T, S, 2, 16, true>(L, target, u, e, b, out, fc, stop, bt, st);
+        return true;
+      }
+    }
+    return false;
+  }
+}
+
+template <typename T>
+bool launch_fused_tau_pro(const LevelView<T>& L, const T* u, const T* e, const T* b, T* out, int s,
+                          const StageCoef* co, const int* stop, hipStream_t st, const Batch& bt) {
+  if (u == nullptr || e == nullptr || L.faces != nullptr || level_is_2d(L) || !fused_tau_supported<T>(L, s))
+    return false;
+  if ((L.nx | L.ny | L.nz) & 1) return false;
+  FusedChoice c = fused_choice<T>(L, s);
+  // The five-row strip (odd R) has no fused form, and the float64 eight-row
+  // forms run out of registers (one wavefront per SIMD, measured slower than
+  // the separate prolongation on gfx950): in float64 those levels take the
+  // stacked two-row strips, the leanest fused form; in float32 the four-row
+  // strips (measured faster there than the two-row ones).
+  const bool dbl8 = sizeof(T) == 8 && (c.variant == FV_STRIP_8x4 || c.variant == FV_STRIP_8x1 ||
+                                       c.variant == FV_STRIPYX_8x4 || c.variant == FV_STRIPYX_8x8);
+  if (c.variant == FV_STRIP_5x1 || dbl8)
+    c = FusedChoice{sizeof(T) == 8 && s <= 2 ? FV_STRIPYX_2x8 : FV_STRIP_4x4, c.target};
+  if (!is_strip(c.variant) || !fused_variant_ok<T>(c.variant, s) || c.target < 1) return false;
+  switch (s) {
+    case 1: return launch_pro_S<T, 1>(L, c.variant, c.target, u, e, b, out, co, stop, bt, st);
+    case 2: return launch_pro_S<T, 2>(L, c.variant, c.target, u, e, b, out, co, stop, bt, st);
+    case 3: return launch_pro_S<T, 3>(L, c.variant, c.target, u, e, b, out, co, stop, bt, st);
+    default: return false;
+  }
+}
+
+template <typename T>
+int tau_chunk_max(const LevelView<T>& L) {
+  if (level_is_2d(L) || L.faces != nullptr || L.nx < 16 || L.ny < 8 || L.nz < 8) return 0;
+  return sizeof(T) == 8 ? 2 : 3;
+}
+
+template <typename T>
+void launch_tau_chunk(const LevelView<T>& L, const T* u, const T* v, const T* b, T* out, T* out2, int S,
+                      const StageCoef* co, hipStream_t st) {
+  if (S < 1 || S > tau_chunk_max<T>(L)) fail(RKL_EINVAL, "stage chunk of unsupported length");
+  const int target = 1024;
+  switch (S) {
+    case 1: return launch_strip_ch<T, 1, 4, 4>(L, target, u, v, b, out, out2, make_fcoef<T, 1>(co), single_batch(), st);
+    case 2: return launch_strip_ch<T, 2, 4, 4>(L, target, u, v, b, out, out2, make_fcoef<T, 2>(co), single_batch(), st);
+    default:
+      if constexpr (sizeof(T) == 4)
+        return launch_strip_ch<T, 3, 4, 4>(L, target, u, v, b, out, out2, make_fcoef<T, 3>(co), single_batch(), st);
+  }
+}
+
 template <typename T>
 bool launch_gsrb_fused(const LevelView<T>& L, const T* u, const T* b, T* out, double omega, double* part,
                        const int* stop, hipStream_t st, const Batch& bt) {
@@ -847,7 +923,12 @@ const char* fused_variant_name(int variant) {
   template bool launch_fused_tau<T>(const LevelView<T>&, const T*, const T*, T*, int, const StageCoef*, double*,  \
                                     const int*, hipStream_t, const Batch&);                                       \
   template bool launch_fused_tau_as<T>(const LevelView<T>&, FusedChoice, const T*, const T*, T*, int,             \
-                                       const StageCoef*, double*, const int*, hipStream_t, const Batch&);
+                                       const StageCoef*, double*, const int*, hipStream_t, const Batch&);       \
+  template int tau_chunk_max<T>(const LevelView<T>&);                                                             \
+  template void launch_tau_chunk<T>(const LevelView<T>&, const T*, const T*, const T*, T*, T*, int, const StageCoef*, \
+                                    hipStream_t);                                                                 \
+  template bool launch_fused_tau_pro<T>(const LevelView<T>&, const T*, const T*, const T*, T*, int,               \
+                                        const StageCoef*, const int*, hipStream_t, const Batch&);
 RKL_FUSED_INST(double)
 RKL_FUSED_INST(float)
 template bool launch_gsrb_fused<double>(const LevelView<double>&, const double*, const double*, double*, double,

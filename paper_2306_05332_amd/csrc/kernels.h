@@ -107,6 +107,23 @@ template <typename T>
 bool launch_fused_tau(const LevelView<T>& L, const T* u, const T* b, T* out, int s,
                       const StageCoef* co, double* part, const int* stop, hipStream_t st,
                       const Batch& bt = single_batch());
+// The fused tau-step of u + P e (prolongation and correction in its input;
+// e: the next coarser level's correction, batch stride bt.s1), when the
+// level's strip variant supports it; false: the caller prolongs separately.
+template <typename T>
+bool launch_fused_tau_pro(const LevelView<T>& L, const T* u, const T* e, const T* b, T* out, int s,
+                          const StageCoef* co, const int* stop, hipStream_t st, const Batch& bt);
+
+// Stages j0 .. j0 + S - 1 of a longer tau-step in one pass (the strip
+// kernel's chunk form): reads Y_{j0-1} = u (stencil), Y_{j0-2} = v
+// (pointwise) and b, writes Y_{j0+S-1} to out and, for S >= 2, Y_{j0+S-2} to
+// out2; co holds the S stages' coefficients.  tau_chunk_max: the largest S
+// the level takes (0: no chunk form: 2-D or small levels).
+template <typename T>
+int tau_chunk_max(const LevelView<T>& L);
+template <typename T>
+void launch_tau_chunk(const LevelView<T>& L, const T* u, const T* v, const T* b, T* out, T* out2, int S,
+                      const StageCoef* co, hipStream_t st);
 
 // Fused tau-step variants: tile family and shape, plus the workgroup count
 // the z-chunk length aims for.  A tuning table keyed by (level shape,
@@ -175,7 +192,7 @@ struct StripGrid {
   int per;  // workgroups per z chunk (nblk = per * gz)
   StripMap map;
 };
-StripGrid strip_grid(int s, int R, int WY, int nx, int ny, int nz, int target, bool flat = false);
+StripGrid strip_grid(int s, int R, int WY, int nx, int ny, int nz, int target, bool flat = false, bool pack = true);
 template <typename T, int S, int R, int WY>
 void launch_strip(const LevelView<T>& L, int target, const T* u, const T* b, T* out, const FCoef<T, S>& fc,
                   double* part, const int* stop, const Batch& bt, hipStream_t st);
@@ -186,6 +203,16 @@ void launch_strip_yx(const LevelView<T>& L, int target, const T* u, const T* b, 
 template <typename T, int S, int R, int WY>
 void launch_strip2d(const LevelView<T>& L, int target, const T* u, const T* b, T* out, const FCoef<T, S>& fc,
                     double* part, const int* stop, const Batch& bt, hipStream_t st);
+// The strip tau-step with prolongation and correction fused into its input
+// (Sec. 2.1: the first post-smoothing relaxation of u + P e): reads u, the
+// coarse correction e (batch stride bt.s1) and b, writes Y_S to out; u is not
+// modified.  3-D levels of even extents, even R; no remainder packing.
+template <typename T, int S, int R, int WY, bool SHY>
+void launch_strip_pro(const LevelView<T>& L, int target, const T* u, const T* e, const T* b, T* out,
+                      const FCoef<T, S>& fc, const int* stop, const Batch& bt, hipStream_t st);
+template <typename T, int S, int R, int WY>
+void launch_strip_ch(const LevelView<T>& L, int target, const T* u, const T* v, const T* b, T* out, T* out2,
+                     const FCoef<T, S>& fc, const Batch& bt, hipStream_t st);
 template <typename T, int R, int WY, bool FLAT>
 void launch_strip_gsrb(const LevelView<T>& L, int target, const T* u, const T* b, T* out, double omega_over_d,
                        double* part, const int* stop, const Batch& bt, hipStream_t st);

@@ -204,6 +204,11 @@ struct Plan {
   double* f0 = nullptr;   // level-0 source (float64)
   double* t0 = nullptr;   // level-0 alternate iterates (float64): with phi they form the
   double* t0b = nullptr;  // three buffers that keep a cycle's start state intact
+  double* t0c_ = nullptr;  // fourth level-0 array (chunked large-s tau-steps), allocated on first use
+  double* t0c() {
+    if (!t0c_) t0c_ = alloc<double>(lv[0].n);
+    return t0c_;
+  }
   ConvState* dconv = nullptr;  // device convergence state
   ConvState* hconv = nullptr;  // pinned host mirror
   double* part = nullptr;
@@ -488,6 +493,52 @@ void tau_step(Plan& P, const LevelView<T>& V, T*& cur, T*& alt, const T* b,
   if (s & 1) std::swap(cur, alt);
 }
 
+// A tau-step of more stages than the fused kernel takes, as chunks of up to
+// tau_chunk_max stages (App. A eq. RKL_intermediate_source; each chunk reads
+// Y_{j-1}, Y_{j-2} and b and writes its last two stages).  Needs two
+// scratch arrays x3, x4 besides cur and alt; on return cur holds the result
+// and alt, x3, x4 the other three arrays (the same set of four).  False: the
+// level has no chunk form (the caller runs stage by stage).
+template <typename T>
+bool tau_chunked(const LevelView<T>& V, T*& cur, T*& alt, T*& x3, T*& x4, const T* b,
+                 const std::vector<StageCoef>& co, hipStream_t st) {
+  const int K = tau_chunk_max<T>(V);
+  const int s = (int)co.size();
+  if (K < 2 || x3 == nullptr || x4 == nullptr || s <= FUSED_MAX_S) return false;
+  T* bufs[4] = {cur, alt, x3, x4};
+  T* a = cur;   // Y_{j-1}
+  T* ap = cur;  // Y_{j-2} (the first stage's nu_1 = 0 term reads Y_0 itself)
+  for (int j = 1; j <= s;) {
+    const int S = std::min(K, s - j + 1);
+    T* out = nullptr;
+    T* out2 = nullptr;
+    for (T* q : bufs) {
+      if (q == a || q == ap) continue;
+      if (!out) out = q;
+      else if (!out2) out2 = q;
+    }
+    launch_tau_chunk<T>(V, a, ap, b, out, S >= 2 ? out2 : nullptr, S, co.data() + (j - 1), st);
+    if (S >= 2) {
+      a = out;
+      ap = out2;
+    } else {
+      ap = a;
+      a = out;
+    }
+    j += S;
+  }
+  check_launch();
+  T* rest[3];
+  int k = 0;
+  for (T* q : bufs)
+    if (q != a) rest[k++] = q;
+  cur = a;
+  alt = rest[0];
+  x3 = rest[1];
+  x4 = rest[2];
+  return true;
+}
+
 // Two relaxations in one pass: on a two-dimensional level the strip kernel
 // runs the 2s-stage recurrence of two tau-steps reading u and b once (there
 // are no y-halo rows, so the extra stages cost little); 3-D levels keep one
@@ -597,7 +648,7 @@ bool tau_keep(Plan& P, const LevelView<T>& V, T* a, T* x, T* y, T*& cur, T*& alt
 // one-workgroup kernel): residual read back before every tau-step.
 template <typename T>
 int accel_multi(Plan& P, const LevelView<T>& V, T*& cur, T*& alt, const T* b, double tol, double ref,
-                int max_steps, bool rm_mean, hipStream_t st, double* res_out) {
+                int max_steps, bool rm_mean, hipStream_t st, double* res_out, T* x3 = nullptr, T* x4 = nullptr) {
   int step = 0;
   double res = 0.0;
   const size_t n = (size_t)V.nx * V.ny * V.nz;
@@ -605,7 +656,8 @@ int accel_multi(Plan& P, const LevelView<T>& V, T*& cur, T*& alt, const T* b, do
     res = resid_norm<T>(P, V, cur, b, st);
     if (res <= tol * ref || step >= max_steps) break;
     const int q = std::min(step, (int)P.sched.size() - 1);
-    tau_step<T>(P, V, cur, alt, b, P.sched_coef[q], nullptr, st);
+    if (!(x3 && x4 && tau_chunked<T>(V, cur, alt, x3, x4, b, P.sched_coef[q], st)))
+      tau_step<T>(P, V, cur, alt, b, P.sched_coef[q], nullptr, st);
     if (rm_mean) remove_mean<T>(P, cur, n, nullptr, st);
     ++step;
   }
@@ -726,6 +778,16 @@ void vcycle_from(Plan& P, Hier<T>& H, T*& cur0, T*& alt0, const T* b0, const dou
     T*& ca = (l == 0) ? alt0 : H.t[l];
     const T* bl = (l == 0) ? b0 : H.b[l];
     const Lev& F = P.lv[l];
+    // prolongation + correction (Sec. 2.1 steps 4-5) fused into the first
+    // post-smoothing tau-step where the level's strip kernel allows it
+    if (o.n_post > 0 && !gs && o.fuse &&
+        launch_fused_tau_pro<T>(V(l), cu, H.u[l + 1], bl, ca, (int)F.smooth.size(), F.smooth.data(), stop, st,
+                                B2(l, l + 1))) {
+      check_launch();
+      std::swap(cu, ca);
+      if (o.n_post > 1) relax_n<T>(P, V(l), F, o.n_post - 1, cu, ca, bl, stop, st, B1(l), gs);
+      continue;
+    }
     launch_prolong_add<T>(F.nx, F.ny, F.nz, P.periodic ? 1 : 0, H.u[l + 1], cu, stop, st, B2(l, l + 1));
     check_launch();
     if (o.n_post > 0) relax_n<T>(P, V(l), F, o.n_post, cu, ca, bl, stop, st, B1(l), gs);
@@ -825,6 +887,7 @@ rkl_opts resolve_opts(const rkl_opts* in) {
   if (!(o.coarse_tol >= 0.0)) fail(RKL_EINVAL, "coarse_tol must be >= 0");
   if (o.coarse_max_steps < 0) fail(RKL_EINVAL, "coarse_max_steps must be >= 0");
   if (o.smoother != RKL_SMOOTH_RKL && o.smoother != RKL_SMOOTH_GSRB) fail(RKL_EINVAL, "unknown smoother");
+  if (o.fuse != 0 && o.fuse != 1) fail(RKL_EINVAL, "fuse must be 0 or 1");
   return o;
 }
 
@@ -912,7 +975,8 @@ rkl_status solve_fp64(Plan& P, const rkl_opts& o, const double* rho, const doubl
       cycles = steps;
       res = P.hscal[1];
     } else {
-      cycles = accel_multi<double>(P, V0, cur, alt, P.f0, o.tol, res0, o.max_cycles, false, st, &res);
+      cycles = accel_multi<double>(P, V0, cur, alt, P.f0, o.tol, res0, o.max_cycles, false, st, &res, P.t0b,
+                                   P.t0c());
       if (cur != phi) copy_d2d(phi, cur, F.n, st);
     }
     const double rel = res / res0;
@@ -1099,11 +1163,12 @@ rkl_status solve_one(const rkl_grid& g, const rkl_opts& o, const double* rho, co
 struct ClassKey {
   int dev, nx, ny, nz, bc, s, min_coarse, prec, nb;
   int direct;  // float64 with n_pre > 0: iterate on phi itself (ClassPlan::direct)
+  int fuse;    // transfer fusion (rkl_opts.fuse): which kernels the captured graph holds
   double hx, hy, hz, theta;
   bool operator<(const ClassKey& o) const {
-    return std::tie(dev, nx, ny, nz, bc, s, min_coarse, prec, nb, direct, hx, hy, hz, theta) <
-           std::tie(o.dev, o.nx, o.ny, o.nz, o.bc, o.s, o.min_coarse, o.prec, o.nb, o.direct, o.hx, o.hy, o.hz,
-                    o.theta);
+    return std::tie(dev, nx, ny, nz, bc, s, min_coarse, prec, nb, direct, fuse, hx, hy, hz, theta) <
+           std::tie(o.dev, o.nx, o.ny, o.nz, o.bc, o.s, o.min_coarse, o.prec, o.nb, o.direct, o.fuse, o.hx, o.hy,
+                    o.hz, o.theta);
   }
 };
 
@@ -1148,7 +1213,7 @@ ClassPlan& get_class(const rkl_grid& g, const rkl_opts& o, int nb) {
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
   const int direct = (o.prec == RKL_FP64 && o.n_pre > 0) ? 1 : 0;
-  ClassKey key{dev, g.nx, g.ny, g.nz, g.bc, o.s, o.min_coarse, o.prec, nb, direct, g.hx, g.hy, g.hz, o.tau_frac};
+  ClassKey key{dev, g.nx, g.ny, g.nz, g.bc, o.s, o.min_coarse, o.prec, nb, direct, o.fuse, g.hx, g.hy, g.hz, o.tau_frac};
   Plan& base = get_plan(g, o.s, o.tau_frac, o.min_coarse, o.prec);
   std::lock_guard<std::mutex> lk(g_plans_mu);
   auto it = g_classes.find(key);
@@ -1370,11 +1435,11 @@ struct LoopSig {
   double tol, coarse_tol;
   int max_cycles, n_pre, n_post, coarse_max_steps;
   int tune_gen;  // kernel variants are chosen at capture time
-  int smoother;
+  int smoother, fuse;
   bool operator==(const LoopSig& o) const {
     return cls == o.cls && tol == o.tol && coarse_tol == o.coarse_tol && max_cycles == o.max_cycles &&
            n_pre == o.n_pre && n_post == o.n_post && coarse_max_steps == o.coarse_max_steps &&
-           tune_gen == o.tune_gen && smoother == o.smoother;
+           tune_gen == o.tune_gen && smoother == o.smoother && fuse == o.fuse;
   }
 };
 
@@ -1399,7 +1464,7 @@ std::unique_ptr<GraphCache> g_graph;
 // levels and tails of one class overlap the other classes' sweeps.
 hipGraphExec_t batch_graph(std::vector<ClassPlan*>& cls, const rkl_opts& o, int iters) {
   LoopSig sig{{}, o.tol, o.coarse_tol, o.max_cycles, o.n_pre, o.n_post, o.coarse_max_steps, tune_generation(),
-              o.smoother};
+              o.smoother, o.fuse};
   for (auto* c : cls) sig.cls.push_back({c, iters});
   if (g_graph && g_graph->sig == sig) return g_graph->exec;
   tail_prepare();
@@ -1800,6 +1865,7 @@ void rkl_default_opts(rkl_opts* o) {
   o->coarse_tol = 0.0;
   o->coarse_max_steps = 200;
   o->smoother = RKL_SMOOTH_RKL;
+  o->fuse = 1;
 }
 
 const char* rkl_last_error(void) { return g_err.c_str(); }
@@ -2177,6 +2243,8 @@ rkl_status rkl_relax_solve(const rkl_grid* grid, const rkl_relax_opts* opts, con
     }
     double* cur = phi;
     double* alt = P.t0;
+    double* x3 = P.t0b;  // scratch of the chunked large-s tau-steps
+    double* x4 = rkl ? P.t0c() : nullptr;
     int it = 0;
     double res = 0.0;
     rkl_status status = RKL_OK;
@@ -2203,7 +2271,7 @@ rkl_status rkl_relax_solve(const rkl_grid* grid, const rkl_relax_opts* opts, con
         if (rkl) {
           const std::vector<StageCoef>& co =
               ro.s > 0 ? F.smooth : P.sched_coef[std::min(it, (int)P.sched_coef.size() - 1)];
-          tau_step<double>(P, V0, cur, alt, f, co, nullptr, st);
+          if (!tau_chunked<double>(V0, cur, alt, x3, x4, f, co, st)) tau_step<double>(P, V0, cur, alt, f, co, nullptr, st);
         } else {
           gsrb_iter<double>(V0, cur, alt, f, omega, nullptr, st);
         }
