@@ -36,6 +36,10 @@ __global__ __launch_bounds__(CNT) void k_coarse_solve(LevelView<T> L, const T* _
   __shared__ int ssched[COARSE_MAX_SCHED];
   __shared__ int scoff[COARSE_MAX_SCHED];
   __shared__ double scoef[3 * COARSE_MAX_COEF];
+  lds_poison(reinterpret_cast<T*>(smem_raw), 3 * L.nx * L.ny * L.nz);
+  lds_poison(red, CNT / WAVE);
+  lds_poison(scoef, 3 * COARSE_MAX_COEF);
+  lds_poison_sync();
   if (stop != nullptr && *stop) return;
   const int nsched = min(cs.nsched, COARSE_MAX_SCHED);
   for (int q = threadIdx.x; q < nsched; q += CNT) {
@@ -151,6 +155,10 @@ __global__ __launch_bounds__(WAVE) void k_coarse_wave(LevelView<T> L, const T* _
   __shared__ int ssched[COARSE_MAX_SCHED];
   __shared__ int scoff[COARSE_MAX_SCHED];
   __shared__ double scoef[3 * COARSE_MAX_COEF];
+  lds_poison(A, WAVE * CPL);
+  lds_poison(B, WAVE * CPL);
+  lds_poison(scoef, 3 * COARSE_MAX_COEF);
+  lds_poison_sync();
   if (stop != nullptr && *stop) return;
   const int lane = threadIdx.x;
   const int nx = L.nx, ny = L.ny, nz = L.nz, N = nx * ny * nz;

@@ -51,6 +51,9 @@ __global__ __launch_bounds__(FNT) void k_fused_tau(LevelView<T> L, const T* __re
   constexpr int NB = ((BX + 2 * S - 2) * (BY + 2 * S - 2) + FNT - 1) / FNT;     // stage slots (stage 1 is largest)
   __shared__ T ring[S][3][PL];
   __shared__ double red[FNT / WAVE];
+  lds_poison(&ring[0][0][0], S * 3 * PL);
+  lds_poison(red, FNT / WAVE);
+  lds_poison_sync();
 
   if (stop != nullptr && *stop) return;
   const int tid = threadIdx.x;
@@ -243,6 +246,10 @@ __global__ __launch_bounds__(NT) void k_tau_zq(LevelView<T> L, const T* __restri
   __shared__ T su[P0];
   __shared__ T sy[NY][2][P0];
   __shared__ double red[NT / WAVE];
+  lds_poison(su, P0);
+  lds_poison(&sy[0][0][0], NY * 2 * P0);
+  lds_poison(red, NT / WAVE);
+  lds_poison_sync();
 
   if (stop != nullptr && *stop) return;
   const int tid = threadIdx.x;
@@ -531,8 +538,8 @@ bool fused_variant_ok(int variant, int s) {
     case FV_STRIP_4x4:
     case FV_STRIP_5x1:
     case FV_STRIPYX_8x4:
-    case FV_STRIPYX_4x8:
     case FV_STRIPYX_8x8: return dbl ? s <= 2 : s <= 3;
+    case FV_STRIPYX_4x8: return s <= 3;  // float64 s = 3: 239 VGPRs, 2 waves per SIMD
     case FV_STRIPYX_2x8:
     case FV_STRIPYX_2x16: return s <= 2;  // shared halo rows come from the R = 2 own rows
     default: return false;
@@ -689,6 +696,10 @@ void launch_fused_S(const LevelView<T>& L, FusedChoice c, const T* u, const T* b
   } else {
   if (is_strip(c.variant) && L.faces != nullptr) c = FusedChoice{FV_RING_64x8, 1024};  // strips take no face data
   if (is_strip(c.variant)) {
+    if constexpr (sizeof(T) == 8 && S == 3) {
+      if (c.variant == FV_STRIPYX_4x8)
+        return launch_strip_yx<T, S, 4, 8>(L, c.target, u, b, out, fc, part, stop, bt, st);
+    }
     if constexpr (strip_instantiated<T, S>()) {
       if (c.variant == FV_STRIP_8x4) return launch_strip<T, S, 8, 4>(L, c.target, u, b, out, fc, part, stop, bt, st);
       if (c.variant == FV_STRIP_8x1) return launch_strip<T, S, 8, 1>(L, c.target, u, b, out, fc, part, stop, bt, st);

@@ -98,6 +98,27 @@ __device__ __forceinline__ T lap7(const LevelView<T>& L, const Nbrs<T>& n, T c) 
 // Deterministic sum over a workgroup of NT threads: fixed-order shuffle tree
 // inside each wavefront, then wave 0 adds the per-wave sums in order.
 // `sh` needs NT/64 doubles.  Result valid in thread 0.
+// LDS-poison debug builds (-DRKL_LDS_POISON, see build_sanitized.py): every
+// kernel fills its floating-point LDS arrays with NaN on entry, so a read of
+// an element that no thread wrote in this launch turns the results into NaN
+// and the parity tests fail.  Called by every thread of the workgroup before
+// any early return; ordinary builds compile it to nothing.
+template <typename T>
+__device__ __forceinline__ void lds_poison(T* p, int n) {
+#ifdef RKL_LDS_POISON
+  const int nt = blockDim.x * blockDim.y * blockDim.z;
+  for (int i = threadIdx.x; i < n; i += nt) p[i] = __builtin_nan("");
+#else
+  (void)p;
+  (void)n;
+#endif
+}
+__device__ __forceinline__ void lds_poison_sync() {
+#ifdef RKL_LDS_POISON
+  __syncthreads();
+#endif
+}
+
 template <int NT>
 __device__ __forceinline__ double block_sum(double v, double* sh) {
   static_assert(NT % WAVE == 0, "block size must be a multiple of the wavefront");

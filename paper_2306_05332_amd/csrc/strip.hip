@@ -195,6 +195,7 @@ RKL_STRIPYX_INST(double, 1, 8, 4)
 RKL_STRIPYX_INST(double, 2, 8, 4)
 RKL_STRIPYX_INST(double, 1, 4, 8)
 RKL_STRIPYX_INST(double, 2, 4, 8)
+RKL_STRIPYX_INST(double, 3, 4, 8)
 RKL_STRIPYX_INST(float, 1, 8, 4)
 RKL_STRIPYX_INST(float, 2, 8, 4)
 RKL_STRIPYX_INST(float, 3, 8, 4)

@@ -127,6 +127,9 @@ __device__ __forceinline__ void tau_strip_body(LevelView<T> L, const T* __restri
   // halo, side 1 = its highest rows for the one above's lower halo
   constexpr int XU = S, XB = S > 1 ? S - 1 : 1;
   __shared__ T xch[SHY ? 2 : 1][SHY ? WY : 1][2][SHY ? XU + XB : 1][64];
+  lds_poison(red, WY);
+  lds_poison(&xch[0][0][0][0][0], (SHY ? 2 : 1) * (SHY ? WY : 1) * 2 * (SHY ? XU + XB : 1) * 64);
+  lds_poison_sync();
   if (stop != nullptr && *stop) return;
 
   const int lane = threadIdx.x & 63;

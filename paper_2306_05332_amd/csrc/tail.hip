@@ -201,6 +201,14 @@ __global__ __launch_bounds__(TNT) void k_tail(TailArgs<T> A, const T* __restrict
   __shared__ int ssched[COARSE_MAX_SCHED];
   __shared__ int scoff[COARSE_MAX_SCHED];
   __shared__ double scoef[3 * COARSE_MAX_COEF];
+  {
+    int cells = 0;  // the pool holds three arrays per level
+    for (int l = 0; l < A.nlev; ++l) cells += 3 * A.lv[l].nx * A.lv[l].ny * A.lv[l].nz;
+    lds_poison(reinterpret_cast<T*>(pool_raw), cells);
+    lds_poison(red, TNT / WAVE);
+    lds_poison(scoef, 3 * COARSE_MAX_COEF);
+    lds_poison_sync();
+  }
   if (stop != nullptr && *stop) return;
   T* pool = reinterpret_cast<T*>(pool_raw);
   const int tid = threadIdx.x;

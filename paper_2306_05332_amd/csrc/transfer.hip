@@ -58,6 +58,10 @@ __global__ __launch_bounds__(RNT) void k_resid_tile(LevelView<TU> F, const TU* _
   __shared__ TU ring[4][RPL];
   __shared__ TU zs[RESTRICT ? RBY : 1][RESTRICT ? RBX : 1];
   __shared__ double red[RNT / WAVE];
+  lds_poison(&ring[0][0], 4 * RPL);
+  lds_poison(&zs[0][0], (RESTRICT ? RBY : 1) * (RESTRICT ? RBX : 1));
+  lds_poison(red, RNT / WAVE);
+  lds_poison_sync();
   if (stop != nullptr && *stop) return;
   const int tid = threadIdx.x;
   const int nx = F.nx, ny = F.ny, nz = F.nz;
@@ -239,6 +243,8 @@ __global__ __launch_bounds__(PNT) void k_prolong_tile(int fnx, int fny, int fnz,
     if (stop != nullptr) stop += mb * bt.stop_stride;
   }
   __shared__ T cr[3][PCL];
+  lds_poison(&cr[0][0], 3 * PCL);
+  lds_poison_sync();
   if (stop != nullptr && *stop) return;
   const int tid = threadIdx.x;
   const bool flat = fnz == 1;  // two-dimensional: one coarse plane, its own z neighbour
@@ -398,6 +404,8 @@ __global__ __launch_bounds__(64 * P2W) void k_resid_2d(LevelView<TU> F, const TU
     if (stop != nullptr) stop += mb * bt.stop_stride;
   }
   __shared__ double red[2][P2W];
+  lds_poison(&red[0][0], 2 * P2W);
+  lds_poison_sync();
   if (stop != nullptr && *stop) return;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int nx = F.nx, ny = F.ny;

@@ -54,7 +54,7 @@ VARIANTS = ["ring64x8", "ring64x4", "zq64x32", "zq64x16", "strip8x4", "strip8x1"
 SUPPORT = {"ring64x8": ((1, 2, 3), (1, 2, 3, 4)), "ring64x4": ((1, 2, 3), (1, 2, 3, 4)),
            "zq64x32": ((2, 3), (2, 3)), "zq64x16": ((2, 3), (2, 3)),
            "strip8x4": ((1, 2), (1, 2, 3)), "strip8x1": ((1, 2), (1, 2, 3)), "strip4x4": ((1, 2), (1, 2, 3)),
-           "strip5x1": ((1, 2), (1, 2, 3)), "stripyx8x4": ((1, 2), (1, 2, 3)), "stripyx4x8": ((1, 2), (1, 2, 3)),
+           "strip5x1": ((1, 2), (1, 2, 3)), "stripyx8x4": ((1, 2), (1, 2, 3)), "stripyx4x8": ((1, 2, 3), (1, 2, 3)),
            "stripyx8x8": ((1, 2), (1, 2, 3)), "stripyx2x8": ((1, 2), (1, 2)), "stripyx2x16": ((1, 2), (1, 2))}
 
 
