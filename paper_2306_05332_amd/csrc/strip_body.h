@@ -247,6 +247,32 @@ __device__ __forceinline__ void tau_strip_body(LevelView<T> L, const T* __restri
       coff[c] = (long long)J * cnx;
     }
   }
+  // PRO, float64 (PDMA): a coarse plane's rows arrive in LDS by direct loads
+  // (global_load_lds, 4 bytes per lane, nothing held in registers while the
+  // stages run): the wavefront's coarse columns cb0 .. cb0 + 63 (unwrapped,
+  // cb0 one left of lane 0's parent) of each needed row slot, lane l fetching
+  // word (l & 1) of column cb0 + (l >> 1), and + 32 in a second load.  cofp /
+  // cofn: the lane's parent and neighbour column within that row (a
+  // Dirichlet ghost neighbour reads the parent, with sign sxn = -1).
+  constexpr bool PDMA = PRO && sizeof(T) == 8;
+  __shared__ double cdma[PDMA ? WY : 1][PDMA ? NC : 1][64];
+  unsigned cdo[2] = {0u, 0u};
+  int cofp = 0, cofn = 0;
+  if constexpr (PDMA) {
+    const int cb0 = fdiv2(tx * OX - S) - 1;
+    const int cu = fdiv2(gxu);
+    cofp = cu - cb0;
+    cofn = cofp;
+    if (!(sxn < (T)0)) cofn = cofp + ((gxu & 1) ? 1 : -1);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      int j = cb0 + (lane >> 1) + 32 * h;
+      j = PER ? ((j % cnx) + cnx) % cnx : min(max(j, 0), cnx - 1);
+      cdo[h] = (unsigned)j * 8u + (unsigned)(lane & 1) * 4u;
+    }
+    lds_poison(&cdma[0][0][0], WY * NC * 64);
+    lds_poison_sync();
+  }
   // parity of plane p's index (wrapped for periodic boxes; |p| stays within a period of the box)
   auto zodd = [&](int p) -> int { return (PER ? (p < 0 ? p + nz : (p >= nz ? p - nz : p)) : p) & 1; };
   // plane p -> element offset of its (wrapped or clamped) plane; advanced by one
@@ -283,7 +309,7 @@ __device__ __forceinline__ void tau_strip_body(LevelView<T> L, const T* __restri
   // PRO: issue the loads of coarse plane K (wrapped, or clamped for a
   // Dirichlet ghost plane, whose sign is returned): per coarse row slot the
   // parent and the neighbour column of the lane
-  auto cload = [&](int K, T(&C)[PRO ? NC : 1][2]) -> T {
+  auto cload = [&](int K, T(&C)[PRO && !PDMA ? NC : 1][2]) -> T {
     T sz = (T)1;
     if constexpr (PRO) {
       int Kw;
@@ -295,11 +321,21 @@ __device__ __forceinline__ void tau_strip_body(LevelView<T> L, const T* __restri
       const T* __restrict__ ep = ec + (long long)Kw * csxy;
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        C[c][0] = C[c][1] = (T)0;
-        if (cneed(c)) {
-          const char* rb = (const char*)(ep + coff[c]);
-          C[c][0] = *(const T*)(rb + cxp);
-          C[c][1] = *(const T*)(rb + cxn);
+        if constexpr (PDMA) {
+          if (cneed(c)) {
+            const char* rb = (const char*)(ep + coff[c]);
+            __builtin_amdgcn_global_load_lds((const void*)(rb + cdo[0]),
+                                             (__attribute__((address_space(3))) void*)&cdma[w][c][0], 4, 0, 0);
+            __builtin_amdgcn_global_load_lds((const void*)(rb + cdo[1]),
+                                             (__attribute__((address_space(3))) void*)&cdma[w][c][32], 4, 0, 0);
+          }
+        } else {
+          C[c][0] = C[c][1] = (T)0;
+          if (cneed(c)) {
+            const char* rb = (const char*)(ep + coff[c]);
+            C[c][0] = *(const T*)(rb + cxp);
+            C[c][1] = *(const T*)(rb + cxn);
+          }
         }
       }
     }
@@ -307,11 +343,23 @@ __device__ __forceinline__ void tau_strip_body(LevelView<T> L, const T* __restri
   };
   // PRO: E[i] = 64 x (coarse plane C interpolated in x and y onto held row i),
   // ghost signs included (x, then y, as eq. prolongation_example_3D weighs)
-  auto cfin = [&](const T(&C)[PRO ? NC : 1][2], T sz, T(&E)[PRO ? NU : 1]) {
+  auto cfin = [&](const T(&C)[PRO && !PDMA ? NC : 1][2], T sz, T(&E)[PRO ? NU : 1]) {
     if constexpr (PRO) {
       T X[NC];
+      if constexpr (PDMA) {
+        // vmcnt(0): the direct loads have landed in LDS (the fence keeps the
+        // compiler from moving the reads above the wait)
+        __builtin_amdgcn_s_waitcnt(0x0F70);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
-      for (int c = 0; c < NC; ++c) X[c] = (sz * csg[c]) * ((T)3 * C[c][0] + sxn * C[c][1]);
+        for (int c = 0; c < NC; ++c) {
+          X[c] = (T)0;
+          if (cneed(c)) X[c] = (sz * csg[c]) * ((T)3 * (T)cdma[w][c][cofp] + sxn * (T)cdma[w][c][cofn]);
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) X[c] = (sz * csg[c]) * ((T)3 * C[c][0] + sxn * C[c][1]);
+      }
 #pragma unroll
       for (int i = 0; i < NU; ++i)
         if (gl(i)) E[i] = (T)3 * X[cpar(i)] + X[cnb(i)];
@@ -321,8 +369,7 @@ __device__ __forceinline__ void tau_strip_body(LevelView<T> L, const T* __restri
   // and Kl(p) + 1 for the fine plane p last loaded; the parent plane of p
   // (EB for even p, EA for odd p) weighs 3, the other 1
   T EA[PRO ? NU : 1], EB[PRO ? NU : 1];
-  T CRw[PRO ? NC : 1][2];  // raw values of a coarse plane
-  constexpr bool PFC = sizeof(T) == 4;  // PRO: prefetch the next coarse plane (float32)
+  T CRw[PRO && !PDMA ? NC : 1][2];  // raw values of a coarse plane in flight (float32)
 #pragma unroll
   for (int i = 0; i < (PRO ? NU : 1); ++i) EA[i] = EB[i] = (T)0;
   auto corr = [&](T v, int p, int i) -> T {  // v + (P e) at plane p, held row i
@@ -497,14 +544,12 @@ __device__ __forceinline__ void tau_strip_body(LevelView<T> L, const T* __restri
 #pragma unroll
       for (int i = A1; i < NU - A1; ++i) VN[i] = row(v, ob, i);
     }
-    // PRO: fine plane zl + 2 brings in a new coarse plane when odd.  float32:
-    // its loads are issued here and it is interpolated when UN is consumed;
-    // float64 loads and interpolates it only then (holding the raw values
-    // through the stages would cost the wavefront occupancy on the stacked
-    // strips: measured slower on gfx950)
+    // PRO: fine plane zl + 2 brings in a new coarse plane when odd: its loads
+    // are issued here (into registers in float32, into LDS in float64) and it
+    // is interpolated when UN is consumed
     const bool cnew = PRO && more && ((zl + 2) & 1);
     T csz = (T)1;
-    if constexpr (PRO && PFC) {
+    if constexpr (PRO) {
       if (cnew) csz = cload(fdiv2(zl + 3), CRw);
     }
     // stage 1 at plane zl, rows A1 .. NU-1-A1
@@ -562,7 +607,6 @@ __device__ __forceinline__ void tau_strip_body(LevelView<T> L, const T* __restri
       if (cnew) {
 #pragma unroll
         for (int i = 0; i < NU; ++i) EA[i] = EB[i];
-        if constexpr (!PFC) csz = cload(fdiv2(zl + 3), CRw);
         cfin(CRw, csz, EB);
       }
     }
