@@ -62,13 +62,44 @@ def run(n=128, tol_max=1e-10, methods=("rkl", "sor", "gsrb"), check_every=None, 
     return out
 
 
+def summarize_trace(d, top=10):
+    """Per-kernel summary of a ``rocprofv3 --kernel-trace`` directory of this
+    tool's run: calls, total and mean duration, largest first."""
+    import csv
+    import glob
+    files = glob.glob(f"{d}/**/*kernel_trace.csv", recursive=True)
+    if not files:
+        raise SystemExit(f"no kernel trace under {d}")
+    agg = {}
+    for r in csv.DictReader(open(files[0])):
+        dt = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        a = agg.setdefault(r["Kernel_Name"], [0, 0.0])
+        a[0] += 1
+        a[1] += dt
+    lines = ["Kernel trace of the App. B single-level relaxations (128^3 accuracy problem, Dirichlet,",
+             "max residual <= 1e-10; RKL accelerated schedule with two-stage chunk passes, then SOR)",
+             "command (from the repository root, TMPDIR=/tmp):",
+             "  rocprofv3 --kernel-trace --output-format csv -d <DIR> -o relax -- python3 -m paper_2306_05332_amd.compare "
+             "--methods rkl sor",
+             "  python3 -m paper_2306_05332_amd.compare --summarize-trace <DIR>",
+             "", "   calls  total_ms   avg_us  name"]
+    for k, (c, s) in sorted(agg.items(), key=lambda kv: -kv[1][1])[:top]:
+        lines.append(f"{c:8d} {s / 1e3:9.3f} {s / c:8.2f}  {k[:100]}")
+    return "\n".join(lines)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--methods", nargs="+", default=["rkl", "sor", "gsrb"], choices=["rkl", "sor", "gsrb"])
+    ap.add_argument("--summarize-trace", metavar="TRACE_DIR", help="print a summary of a kernel trace and exit")
     a = ap.parse_args(argv)
+    if a.summarize_trace:
+        print(summarize_trace(a.summarize_trace))
+        return
     _lib.load_library()
-    res = run(a.n, a.tol, log=lambda s: print(s, flush=True))
+    res = run(a.n, a.tol, methods=tuple(a.methods), log=lambda s: print(s, flush=True))
     base = next(r for r in res if r["method"] == "rkl")["seconds"]
     for r in res:
         print(f"{r['method']:>26}: {r['iterations']:>8} iterations  {r['seconds'] * 1e3:10.2f} ms"

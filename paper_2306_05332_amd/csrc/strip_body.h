@@ -248,29 +248,31 @@ __device__ __forceinline__ void tau_strip_body(LevelView<T> L, const T* __restri
     }
   }
   // PRO, float64 (PDMA): a coarse plane's rows arrive in LDS by direct loads
-  // (global_load_lds, 4 bytes per lane, nothing held in registers while the
-  // stages run): the wavefront's coarse columns cb0 .. cb0 + 63 (unwrapped,
-  // cb0 one left of lane 0's parent) of each needed row slot, lane l fetching
-  // word (l & 1) of column cb0 + (l >> 1), and + 32 in a second load.  cofp /
-  // cofn: the lane's parent and neighbour column within that row (a
-  // Dirichlet ghost neighbour reads the parent, with sign sxn = -1).
+  // (global_load_lds_dwordx4: 16 bytes per lane, nothing held in registers
+  // while the stages run): of each needed row slot, the wavefront's coarse
+  // columns cb0 .. cb0 + 35 (unwrapped; cb0 even and at most one left of lane
+  // 0's parent), lane l < 18 fetching the column pair cb0 / 2 + l (pairs never
+  // straddle the periodic wrap, the extent being even; Dirichlet clamps whole
+  // pairs, and the clamped columns are never read).  cofp / cofn: the lane's
+  // parent and neighbour column within that row (a Dirichlet ghost neighbour
+  // reads the parent, with sign sxn = -1).
   constexpr bool PDMA = PRO && sizeof(T) == 8;
-  __shared__ double cdma[PDMA ? WY : 1][PDMA ? NC : 1][64];
-  unsigned cdo[2] = {0u, 0u};
+  constexpr int DMA_LANES = 18;
+  __shared__ double cdma[PDMA ? WY : 1][PDMA ? NC : 1][2 * DMA_LANES];
+  unsigned cdo = 0u;
   int cofp = 0, cofn = 0;
   if constexpr (PDMA) {
-    const int cb0 = fdiv2(tx * OX - S) - 1;
+    int cb0 = fdiv2(tx * OX - S) - 1;
+    cb0 -= cb0 & 1;
     const int cu = fdiv2(gxu);
     cofp = cu - cb0;
     cofn = cofp;
     if (!(sxn < (T)0)) cofn = cofp + ((gxu & 1) ? 1 : -1);
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      int j = cb0 + (lane >> 1) + 32 * h;
-      j = PER ? ((j % cnx) + cnx) % cnx : min(max(j, 0), cnx - 1);
-      cdo[h] = (unsigned)j * 8u + (unsigned)(lane & 1) * 4u;
-    }
-    lds_poison(&cdma[0][0][0], WY * NC * 64);
+    const int cnp = cnx >> 1;  // column pairs per coarse row
+    int pj = (cb0 >> 1) + min(lane, DMA_LANES - 1);
+    pj = PER ? ((pj % cnp) + cnp) % cnp : min(max(pj, 0), cnp - 1);
+    cdo = (unsigned)pj * 16u;
+    lds_poison(&cdma[0][0][0], WY * NC * 2 * DMA_LANES);
     lds_poison_sync();
   }
   // parity of plane p's index (wrapped for periodic boxes; |p| stays within a period of the box)
@@ -322,12 +324,10 @@ __device__ __forceinline__ void tau_strip_body(LevelView<T> L, const T* __restri
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         if constexpr (PDMA) {
-          if (cneed(c)) {
+          if (cneed(c) && lane < DMA_LANES) {
             const char* rb = (const char*)(ep + coff[c]);
-            __builtin_amdgcn_global_load_lds((const void*)(rb + cdo[0]),
-                                             (__attribute__((address_space(3))) void*)&cdma[w][c][0], 4, 0, 0);
-            __builtin_amdgcn_global_load_lds((const void*)(rb + cdo[1]),
-                                             (__attribute__((address_space(3))) void*)&cdma[w][c][32], 4, 0, 0);
+            __builtin_amdgcn_global_load_lds((const void*)(rb + cdo),
+                                             (__attribute__((address_space(3))) void*)&cdma[w][c][0], 16, 0, 0);
           }
         } else {
           C[c][0] = C[c][1] = (T)0;
