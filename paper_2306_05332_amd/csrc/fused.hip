@@ -837,15 +837,20 @@ bool launch_fused_tau_pro(const LevelView<T>& L, const T* u, const T* e, const T
     return false;
   if ((L.nx | L.ny | L.nz) & 1) return false;
   FusedChoice c = fused_choice<T>(L, s);
-  // The five-row strip (odd R) has no fused form, and the float64 eight-row
-  // forms run out of registers (one wavefront per SIMD, measured slower than
-  // the separate prolongation on gfx950): in float64 those levels take the
-  // stacked two-row strips, the leanest fused form; in float32 the four-row
-  // strips (measured faster there than the two-row ones).
+  // The five-row strip (odd R) has no fused form: in float64 its levels
+  // (128^3 and below in the tuned table) keep the separate prolongation,
+  // which measured faster there than the fused stacked strips (128^3: 26 us
+  // against 33 us); in float32 they take the fused four-row strips (measured
+  // faster than the separate pass).  The float64 eight-row forms run out of
+  // registers with the fusion (one wavefront per SIMD): those levels take the
+  // stacked two-row strips, the leanest fused form.
+  if (c.variant == FV_STRIP_5x1) {
+    if (sizeof(T) == 8) return false;
+    c = FusedChoice{FV_STRIP_4x4, c.target};
+  }
   const bool dbl8 = sizeof(T) == 8 && (c.variant == FV_STRIP_8x4 || c.variant == FV_STRIP_8x1 ||
                                        c.variant == FV_STRIPYX_8x4 || c.variant == FV_STRIPYX_8x8);
-  if (c.variant == FV_STRIP_5x1 || dbl8)
-    c = FusedChoice{sizeof(T) == 8 && s <= 2 ? FV_STRIPYX_2x8 : FV_STRIP_4x4, c.target};
+  if (dbl8) c = FusedChoice{s <= 2 ? FV_STRIPYX_2x8 : FV_STRIP_4x4, c.target};
   if (!is_strip(c.variant) || !fused_variant_ok<T>(c.variant, s) || c.target < 1) return false;
   switch (s) {
     case 1: return launch_pro_S<T, 1>(L, c.variant, c.target, u, e, b, out, co, stop, bt, st);

@@ -4,9 +4,10 @@ followed by the post-smoothing relaxation) against the oracle's V-cycle,
 which prolongs, corrects and relaxes as three separate steps.
 
 Every strip variant is forced through the tuning table onto the two finest
-levels (for the fused step the five-row strip takes the stacked two-row
-strips in float64 and the four-row strips in float32, as do the float64
-eight-row strips), on a grid that is ragged against every tile shape in x and y, with both
+levels (the five-row strip has no fused form: in float64 it keeps the
+separate prolongation, in float32 its levels take the fused four-row strips;
+the float64 eight-row strips take the stacked two-row strips for the fused
+step), on a grid that is ragged against every tile shape in x and y, with both
 boundary types, float64 (mg_vcycle) and float32 (mg_vcycle_f32) and one or
 two post-smoothing relaxations.  Tolerances are those of the unfused
 V-cycle tests: 1e-11 of the field's max norm in float64, 1e-5 in float32
