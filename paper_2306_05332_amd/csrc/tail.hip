@@ -325,11 +325,24 @@ __global__ __launch_bounds__(TNT) void k_tail(TailArgs<T> A, const T* __restrict
     if (A.s & 1) swapped ^= 1u << l;
   };
 
-  // top level right-hand side
+  // top level right-hand side: eight loads in flight per thread before the
+  // stores (one at a time, each would wait out the memory latency)
   {
     const int n = nof(0);
     T* B = bptr(0);
-    for (int q = tid; q < n; q += TNT) B[q] = b_top[q];
+    for (int q0 = 0; q0 < n; q0 += 8 * TNT) {
+      T v[8];
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        const int q = q0 + m * TNT + tid;
+        v[m] = q < n ? b_top[q] : (T)0;
+      }
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        const int q = q0 + m * TNT + tid;
+        if (q < n) B[q] = v[m];
+      }
+    }
     __syncthreads();
     if (per) remove_b_mean(0);
   }
@@ -515,6 +528,44 @@ __global__ __launch_bounds__(TNT) void k_tail(TailArgs<T> A, const T* __restrict
     // the eight coarse values then weigh (3,1) x (3,1) x (3,1) / 64.  A 2-D
     // hierarchy takes the parent plane as its own z neighbour.
     const int cnxy = C.nx * C.ny;
+    const int fnxy = F.nx * F.ny;
+    if (!A.flat && TNT % fnxy == 0) {
+      // a thread's cells share (i, j) and step k by TNT / (nx ny) (one parity
+      // of k when that step is even): the x-y parents and neighbours are set
+      // once, and a coarse plane's x-y interpolation serves the two fine
+      // planes around it
+      const int i = tid % F.nx, j = (tid / F.nx) % F.ny, kstep = TNT / fnxy;
+      int ox0 = i >> 1, ox1 = ox0 + ((i & 1) ? 1 : -1);
+      T gx = (T)1, gy = (T)1;
+      if (per) ox1 = ox1 < 0 ? ox1 + C.nx : (ox1 >= C.nx ? ox1 - C.nx : ox1);
+      else if (ox1 < 0 || ox1 >= C.nx) { ox1 = ox0; gx = (T)-1; }
+      const int J = j >> 1;
+      int jn = J + ((j & 1) ? 1 : -1);
+      if (per) jn = jn < 0 ? jn + C.ny : (jn >= C.ny ? jn - C.ny : jn);
+      else if (jn < 0 || jn >= C.ny) { jn = J; gy = (T)-1; }
+      const int oy0 = J * C.nx, oy1 = jn * C.nx;
+      auto exy = [&](int Kw) -> T {  // 16 x (x, then y interpolation of coarse plane Kw)
+        const int o = Kw * cnxy;
+        return (T)3 * ((T)3 * E[o + oy0 + ox0] + gx * E[o + oy0 + ox1]) +
+               gy * ((T)3 * E[o + oy1 + ox0] + gx * E[o + oy1 + ox1]);
+      };
+      int pa = -1, pb = -1;  // wrapped indices of the previous cell's two planes
+      T va = (T)0, vb = (T)0;
+      for (int k = tid / fnxy; k < F.nz; k += kstep) {
+        const int K = k >> 1;
+        int kn = K + ((k & 1) ? 1 : -1);
+        T gz = (T)1;
+        if (per) kn = kn < 0 ? kn + C.nz : (kn >= C.nz ? kn - C.nz : kn);
+        else if (kn < 0 || kn >= C.nz) { kn = K; gz = (T)-1; }
+        const T p0 = K == pa ? va : (K == pb ? vb : exy(K));
+        const T p1 = kn == pa ? va : (kn == pb ? vb : exy(kn));
+        pa = K;
+        va = p0;
+        pb = kn;
+        vb = p1;
+        U[k * fnxy + j * F.nx + i] += ((T)3 * p0 + gz * p1) * (T)(1.0 / 64.0);
+      }
+    } else
     for (CellWalk w(tid, TNT, F.nx, F.ny, F.nz); w.ok(); w.next(TNT)) {
       const int q = w.q;
       int ox[2], oy[2], oz[2];
