@@ -55,8 +55,8 @@ SWEEP_STEPS = 40
 COPY_BYTES = 256 * 1024 * 1024  # plain copy used to scale the HBM counters
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "fused_tau_256_fp64_pmc.txt")
 KERNEL_SOURCES = ["paper_2306_05332_amd/csrc/fused.hip", "paper_2306_05332_amd/csrc/strip.hip",
-                  "paper_2306_05332_amd/csrc/kernels.h", "paper_2306_05332_amd/csrc/rkl_device.h",
-                  "paper_2306_05332_amd/tuning/gfx950.json"]
+                  "paper_2306_05332_amd/csrc/strip_body.h", "paper_2306_05332_amd/csrc/kernels.h",
+                  "paper_2306_05332_amd/csrc/rkl_device.h", "paper_2306_05332_amd/tuning/gfx950.json"]
 
 
 def parse():

@@ -97,10 +97,13 @@ typedef struct {
     int coarse_max_steps;/* coarsest solve: cap on tau-steps (default 200)                      */
     int smoother;        /* rkl_smoother: relaxation of the V-cycle above the coarsest level    */
                          /* (default RKL_SMOOTH_RKL)                                            */
-    int fuse;            /* 1 (default): on levels whose tau-step runs the strip kernel, the    */
-                         /* prolongation + correction of Sec. 2.1 runs inside the first         */
-                         /* post-smoothing tau-step (same arithmetic, one HBM pass less);       */
-                         /* 0: separate transfer kernels                                        */
+    int fuse;            /* transfer fusion on levels whose tau-step runs the strip kernel      */
+                         /* (same arithmetic, one HBM pass less each), a bit mask:              */
+                         /* bit 0: the prolongation + correction of Sec. 2.1 runs inside the    */
+                         /* first post-smoothing tau-step; bit 1: the last pre-smoothing        */
+                         /* tau-step also writes the restricted residual (steps 2a-2b).         */
+                         /* 3 (default): both; 0: separate transfer kernels; other values:      */
+                         /* RKL_EINVAL                                                          */
 } rkl_opts;
 
 /* Solve statistics.  `history` (host, optional) receives the relative

@@ -181,12 +181,16 @@ class Options:
     coarse_tol: float = 0.0
     coarse_max_steps: int = 200
     smoother: str = "rkl"
-    fuse: bool = True   # prolongation fused into the first post-smoothing tau-step where supported
+    # transfer fusion where the strip kernel supports it: True / 3 both, 1 the
+    # prolongation (into the first post-smoothing tau-step), 2 the restriction
+    # (into the last pre-smoothing tau-step), False / 0 neither
+    fuse: int = 3
 
     def c(self):
         return c_opts(self.s, self.tau_frac, self.n_pre, self.n_post, self.min_coarse, self.tol,
                       self.max_cycles, PREC[self.prec], self.four_pi_G, self.coarse_tol,
-                      self.coarse_max_steps, SMOOTHERS[self.smoother], 1 if self.fuse else 0)
+                      self.coarse_max_steps, SMOOTHERS[self.smoother],
+                      3 if self.fuse is True else int(self.fuse))
 
 
 @dataclass

@@ -21,8 +21,9 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "librklpoisson.so")
 ARCH = os.environ.get("RKL_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["strip.hip", "strip_forms64.hip", "strip_forms32.hip", "kernels.hip", "transfer.hip", "coarse.hip",
-           "tail.hip", "fused.hip", "plan.hip", "solve.hip", "batch.hip", "tune.hip", "levels.hip", "noalloc.hip"]
+SOURCES = ["strip.hip", "strip_forms64.hip", "strip_forms32.hip", "strip_rs.hip", "kernels.hip", "transfer.hip",
+           "coarse.hip", "tail.hip", "fused.hip", "plan.hip", "solve.hip", "batch.hip", "tune.hip", "levels.hip",
+           "noalloc.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

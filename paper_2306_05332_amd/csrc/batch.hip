@@ -80,6 +80,7 @@ ClassPlan& get_class(const rkl_grid& g, const rkl_opts& o, int nb) {
   size_t ps = 2 * resid_blocks(F.nx, F.ny, F.nz);
   ps = std::max(ps, 2 * ew_block_count(F.n));
   ps = std::max(ps, fused_tau_blocks_max(F.nx, F.ny, F.nz));
+  ps = std::max(ps, strip_rs_parts_max(F.nx, F.ny, F.nz));
   C->part_stride = (int)ps;
   C->f0 = C->alloc<double>((size_t)nb * F.n);
   C->phi = C->alloc<double>((size_t)nb * F.n);

@@ -860,6 +860,54 @@ bool launch_fused_tau_pro(const LevelView<T>& L, const T* u, const T* e, const T
   }
 }
 
+template <typename T, int S>
+static int launch_rs_S(const LevelView<T>& L, int variant, int target, const T* u, const T* b, T* out, T* bc,
+                       const StageCoef* co, double* part, const int* stop, const Batch& bt, hipStream_t st) {
+  if constexpr (S < 2 || S > 3) {
+    return 0;  // the form needs s >= 2 (b of a halo row in registers); none is built beyond 3
+  } else {
+    const FCoef<T, S> fc = make_fcoef<T, S>(co);
+    if constexpr (S <= 2) {
+      if (variant == FV_STRIPYX_2x8)
+        return launch_strip_rs<T, S, 2, 8, true>(L, target, u, b, out, bc, fc, part, stop, bt, st);
+    }
+    if constexpr (sizeof(T) == 4) {
+      if (variant == FV_STRIP_4x4)
+        return launch_strip_rs<T, S, 4, 4, false>(L, target, u, b, out, bc, fc, part, stop, bt, st);
+    }
+    return 0;
+  }
+}
+
+template <typename T>
+int launch_fused_tau_rs(const LevelView<T>& L, const T* u, const T* b, T* out, T* bc, int s, const StageCoef* co,
+                        double* part, const int* stop, hipStream_t st, const Batch& bt) {
+  if (u == nullptr || bc == nullptr || part == nullptr || L.faces != nullptr || level_is_2d(L) ||
+      !fused_tau_supported<T>(L, s))
+    return 0;
+  if ((L.nx | L.ny | L.nz) & 1) return 0;
+  FusedChoice c = fused_choice<T>(L, s);
+  if (!is_strip(c.variant) || c.target < 1) return 0;
+  // Forms built (s >= 2): the stacked two-row strips (eight wavefronts that
+  // share their y halos; s = 2), every float64 level; in float32 also the
+  // four-row strips of four wavefronts (s = 2, 3), which the levels below
+  // 192^3 take unless tuned for the stacked strips.  Measured on gfx950 at
+  // 256^3 (fused pass against tau-step + separate residual pass): float64
+  // 134 us against 92 + 65 us; float32 77 (stacked) or 83 (four-row)
+  // against 43 + 40 us; at 128^3, 26 against 16 + 15 us (float64).  (A
+  // float64 four-row form needs 165 VGPRs, three wavefronts per SIMD.)
+  const bool big = (size_t)L.nx * L.ny * L.nz >= ((size_t)192 * 192 * 192);
+  if (sizeof(T) == 8) c.variant = FV_STRIPYX_2x8;
+  else if (c.variant != FV_STRIPYX_2x8) c.variant = big ? FV_STRIPYX_2x8 : FV_STRIP_4x4;
+  if (c.variant == FV_STRIPYX_2x8 && s > 2) c.variant = FV_STRIP_4x4;
+  switch (s) {
+    case 1: return launch_rs_S<T, 1>(L, c.variant, c.target, u, b, out, bc, co, part, stop, bt, st);
+    case 2: return launch_rs_S<T, 2>(L, c.variant, c.target, u, b, out, bc, co, part, stop, bt, st);
+    case 3: return launch_rs_S<T, 3>(L, c.variant, c.target, u, b, out, bc, co, part, stop, bt, st);
+    default: return 0;
+  }
+}
+
 template <typename T>
 int tau_chunk_max(const LevelView<T>& L) {
   if (level_is_2d(L) || L.faces != nullptr || L.nx < 16 || L.ny < 8 || L.nz < 8) return 0;
@@ -944,7 +992,9 @@ const char* fused_variant_name(int variant) {
   template void launch_tau_chunk<T>(const LevelView<T>&, const T*, const T*, const T*, T*, T*, int, const StageCoef*, \
                                     hipStream_t);                                                                 \
   template bool launch_fused_tau_pro<T>(const LevelView<T>&, const T*, const T*, const T*, T*, int,               \
-                                        const StageCoef*, const int*, hipStream_t, const Batch&);
+                                        const StageCoef*, const int*, hipStream_t, const Batch&);                 \
+  template int launch_fused_tau_rs<T>(const LevelView<T>&, const T*, const T*, T*, T*, int, const StageCoef*,     \
+                                      double*, const int*, hipStream_t, const Batch&);
 RKL_FUSED_INST(double)
 RKL_FUSED_INST(float)
 template bool launch_gsrb_fused<double>(const LevelView<double>&, const double*, const double*, double*, double,

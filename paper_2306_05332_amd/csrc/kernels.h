@@ -113,6 +113,16 @@ bool launch_fused_tau(const LevelView<T>& L, const T* u, const T* b, T* out, int
 template <typename T>
 bool launch_fused_tau_pro(const LevelView<T>& L, const T* u, const T* e, const T* b, T* out, int s,
                           const StageCoef* co, const int* stop, hipStream_t st, const Batch& bt);
+// The fused tau-step of u that also writes the next level's right-hand side
+// bc = R(b - M Y_S) (batch stride bt.s1) and, per workgroup, the partial
+// pair (sum of fine r^2, sum of coarse values) into part (batch stride
+// bt.part_stride); returns the number of pairs written, 0 when the level has
+// no such form (nothing launched: the caller relaxes and restricts
+// separately).  strip_rs_parts_max bounds the pairs (times 2: doubles).
+template <typename T>
+int launch_fused_tau_rs(const LevelView<T>& L, const T* u, const T* b, T* out, T* bc, int s, const StageCoef* co,
+                        double* part, const int* stop, hipStream_t st, const Batch& bt);
+size_t strip_rs_parts_max(int nx, int ny, int nz);
 
 // Stages j0 .. j0 + S - 1 of a longer tau-step in one pass (the strip
 // kernel's chunk form): reads Y_{j0-1} = u (stencil), Y_{j0-2} = v
@@ -213,6 +223,14 @@ void launch_strip_pro(const LevelView<T>& L, int target, const T* u, const T* e,
 template <typename T, int S, int R, int WY>
 void launch_strip_ch(const LevelView<T>& L, int target, const T* u, const T* v, const T* b, T* out, T* out2,
                      const FCoef<T, S>& fc, const Batch& bt, hipStream_t st);
+// The strip tau-step with the residual + restriction of its result fused in
+// (strip_rs.hip); returns the workgroup count (partial pairs written).
+// Stacked strips of R WY - 2 >= RS_MIN_ROWS output rows, even extents.
+constexpr int RS_MIN_ROWS = 14;
+StripGrid strip_grid_rs(int s, int R, int WY, int nx, int ny, int nz, int target);
+template <typename T, int S, int R, int WY, bool SHY>
+int launch_strip_rs(const LevelView<T>& L, int target, const T* u, const T* b, T* out, T* bc, const FCoef<T, S>& fc,
+                    double* part, const int* stop, const Batch& bt, hipStream_t st);
 template <typename T, int R, int WY, bool FLAT>
 void launch_strip_gsrb(const LevelView<T>& L, int target, const T* u, const T* b, T* out, double omega_over_d,
                        double* part, const int* stop, const Batch& bt, hipStream_t st);

@@ -241,6 +241,7 @@ Plan& get_plan(const rkl_grid& g, int s, double theta, int min_coarse, int prec)
   size_t cap = 2 * resid_blocks(g.nx, g.ny, g.nz);
   cap = std::max(cap, 2 * ew_block_count(P->lv[0].n));
   cap = std::max(cap, fused_tau_blocks_max(P->lv[0].nx, P->lv[0].ny, P->lv[0].nz));
+  cap = std::max(cap, strip_rs_parts_max(P->lv[0].nx, P->lv[0].ny, P->lv[0].nz));
   cap = std::max(cap, (size_t)1024);
   P->part = P->alloc<double>(cap);
   P->part_cap = cap;
@@ -313,7 +314,7 @@ rkl_opts resolve_opts(const rkl_opts* in) {
   if (!(o.coarse_tol >= 0.0)) fail(RKL_EINVAL, "coarse_tol must be >= 0");
   if (o.coarse_max_steps < 0) fail(RKL_EINVAL, "coarse_max_steps must be >= 0");
   if (o.smoother != RKL_SMOOTH_RKL && o.smoother != RKL_SMOOTH_GSRB) fail(RKL_EINVAL, "unknown smoother");
-  if (o.fuse != 0 && o.fuse != 1) fail(RKL_EINVAL, "fuse must be 0 or 1");
+  if (o.fuse < 0 || o.fuse > 3) fail(RKL_EINVAL, "fuse must be 0 .. 3 (bit 0: prolongation, bit 1: restriction)");
   return o;
 }
 
@@ -354,7 +355,7 @@ void rkl_default_opts(rkl_opts* o) {
   o->coarse_tol = 0.0;
   o->coarse_max_steps = 200;
   o->smoother = RKL_SMOOTH_RKL;
-  o->fuse = 1;
+  o->fuse = 3;
 }
 
 const char* rkl_last_error(void) { return g_err.c_str(); }

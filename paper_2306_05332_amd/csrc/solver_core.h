@@ -319,6 +319,31 @@ int relax_from_zero(Plan& P, const LevelView<T>& V, const Lev& Lv, int n_pre, T*
   return pair ? 2 : 1;
 }
 
+// n >= 0 relaxations of a level before its residual is restricted to the
+// next one: with `fuse` the last of them also writes that level's right-hand
+// side bc = R(b - M u) and its partial pairs (Sec. 2.1 steps 1-2b in one
+// pass over the level) where the level's strip kernel has the form.
+// Returns the pairs written, 0 when the caller restricts separately.
+template <typename T>
+int relax_restrict(Plan& P, const LevelView<T>& V, const Lev& Lv, int n, T*& cur, T*& alt, const T* b, T* bc,
+                   double* part, const int* stop, hipStream_t st, const Batch& b1, const Batch& b2, bool gs,
+                   bool fuse) {
+  if (n >= 1 && fuse && !gs && !level_is_2d(V)) {
+    relax_n<T>(P, V, Lv, n - 1, cur, alt, b, stop, st, b1, gs);
+    const int nb = launch_fused_tau_rs<T>(V, cur, b, alt, bc, (int)Lv.smooth.size(), Lv.smooth.data(), part, stop, st,
+                                          b2);
+    if (nb > 0) {
+      check_launch();
+      std::swap(cur, alt);
+      return nb;
+    }
+    relax_n<T>(P, V, Lv, 1, cur, alt, b, stop, st, b1, gs);
+    return 0;
+  }
+  relax_n<T>(P, V, Lv, n, cur, alt, b, stop, st, b1, gs);
+  return 0;
+}
+
 // A tau-step from `a` that never writes `a`: the result lands in x or y and
 // is returned in `cur`, the other in `alt`.  With `part` the fused kernel
 // also writes the partial sums of (M a - b)^2.
@@ -460,12 +485,21 @@ void vcycle_from(Plan& P, Hier<T>& H, T*& cur0, T*& alt0, const T* b0, const dou
   const int lt = tail_level<T>(P);
   if (vb.nb > 1 && lt <= 0) fail(RKL_EINVAL, "batched solves need the one-workgroup coarse tail");
   const int lbot = lt > 0 ? lt : L - 1;
-  if (pre_done < o.n_pre) relax_n<T>(P, V(0), P.lv[0], o.n_pre - pre_done, cur0, alt0, b0, stop, st, B1(0), gs);
+  const bool fuse_rs = (o.fuse & 2) != 0;
+  // pairs of partial sums the fused restriction into the next level wrote (0: restrict separately)
+  int rs_pairs = relax_restrict<T>(P, V(0), P.lv[0], std::max(0, o.n_pre - pre_done), cur0, alt0, b0, H.b[1], part,
+                                   stop, st, B1(0), B2(0, 1), gs, fuse_rs);
   for (int l = 1; l <= lbot; ++l) {
     T* fu = (l == 1) ? cur0 : H.u[l - 1];
     const T* fb = (l == 1) ? b0 : H.b[l - 1];
-    launch_resid_restrict<T>(V(l - 1), fu, fb, H.b[l], part, stop, st, B2(l - 1, l));
-    check_launch();
+    const Lev& Fl = P.lv[l - 1];
+    int pairs = rs_pairs;
+    if (pairs == 0) {
+      launch_resid_restrict<T>(V(l - 1), fu, fb, H.b[l], part, stop, st, B2(l - 1, l));
+      check_launch();
+      pairs = (int)resid_blocks(Fl.nx, Fl.ny, Fl.nz);
+    }
+    rs_pairs = 0;
     const Lev& C = P.lv[l];
     if (l == lt) {
       const TailShape ts = tail_shape(P, lt);
@@ -477,16 +511,15 @@ void vcycle_from(Plan& P, Hier<T>& H, T*& cur0, T*& alt0, const T* b0, const dou
       break;
     }
     if (P.periodic) {  // coarse right-hand side made mean-free (its sum: the restriction's partials)
-      const Lev& Fl = P.lv[l - 1];
       Batch bs{vb.nb, (long long)C.n, 0, vb.stop_stride, vb.part_stride};
-      launch_sub_mean_part<T>(H.b[l], C.n, part, (int)resid_blocks(Fl.nx, Fl.ny, Fl.nz), 2, 1, (double)C.n, stop, st,
-                              bs);
+      launch_sub_mean_part<T>(H.b[l], C.n, part, pairs, 2, 1, (double)C.n, stop, st, bs);
       check_launch();
     }
-    if (l < L - 1) {
+    if (l < L - 1) {  // then l + 1 <= lbot: the loop restricts this level next
       if (o.n_pre > 0) {
         const int done = relax_from_zero<T>(P, V(l), C, o.n_pre, H.u[l], H.t[l], H.b[l], stop, st, B1(l), gs);
-        if (done < o.n_pre) relax_n<T>(P, V(l), C, o.n_pre - done, H.u[l], H.t[l], H.b[l], stop, st, B1(l), gs);
+        rs_pairs = relax_restrict<T>(P, V(l), C, o.n_pre - done, H.u[l], H.t[l], H.b[l], H.b[l + 1], part, stop, st,
+                                     B1(l), B2(l, l + 1), gs, fuse_rs);
       } else {
         launch_fill<T>(H.u[l], C.n, (T)0, stop, st, B1(l));
       }
@@ -502,7 +535,7 @@ void vcycle_from(Plan& P, Hier<T>& H, T*& cur0, T*& alt0, const T* b0, const dou
     const Lev& F = P.lv[l];
     // prolongation + correction (Sec. 2.1 steps 4-5) fused into the first
     // post-smoothing tau-step where the level's strip kernel allows it
-    if (o.n_post > 0 && !gs && o.fuse &&
+    if (o.n_post > 0 && !gs && (o.fuse & 1) &&
         launch_fused_tau_pro<T>(V(l), cu, H.u[l + 1], bl, ca, (int)F.smooth.size(), F.smooth.data(), stop, st,
                                 B2(l, l + 1))) {
       check_launch();

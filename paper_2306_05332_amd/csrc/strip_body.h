@@ -1,6 +1,6 @@
 // Body of the fused s-stage strip tau-step, shared by the translation units
-// that instantiate its kernels (strip.hip: plain tau-steps; strip_pro.hip:
-// tau-steps whose input is corrected by the prolonged coarse correction).
+// that instantiate its kernels (strip.hip: plain tau-steps; strip_forms64.hip
+// and strip_forms32.hip: the prolongation, stage-chunk and restriction forms).
 //
 // Fused s-stage RKL tau-step (App. A eq. RKL_intermediate_source), strip
 // form: every wavefront works on its own and keeps its whole working set in
@@ -67,6 +67,23 @@
 // strip's first coarse row.  A coarse plane is interpolated in x and y once,
 // onto the lane's rows, and then serves the four fine planes around it
 // (two queue slots); the corrected u itself is never stored.
+//
+// With RS = true the tau-step is the last pre-smoothing relaxation of a
+// level and also produces the next level's right-hand side (Sec. 2.1 steps
+// 2a-2b): r = b - M Y_S at every cell it owns, restricted by the 8-child
+// average of eq. restriction_example_3D, so Y_S is not read back by a
+// separate residual pass.  The residual needs Y_S one cell beyond the owned
+// ones, so the tile keeps one more halo lane on either side in x, the chunk
+// computes Y_S on one more plane on either side in z, and in y the
+// workgroup's first and last computed rows are the residual's halo (tiles
+// overlap by two rows; every owned row and its neighbours are rows the
+// workgroup computes exactly).  The wavefronts put their Y_S rows of each
+// plane into an LDS ring of four planes; after the iteration's barrier the
+// residual of the plane below the newest one is taken from the ring, two
+// rows (one coarse row) at a time: the y pair is summed in the lane, the z
+// pair across two iterations, the x pair by a lane shift.  The float64
+// partial sums are those of the separate residual + restriction pass:
+// (fine r^2, sum of coarse values) per workgroup.
 #pragma once
 
 #include "kernels.h"
@@ -91,19 +108,22 @@ inline int strip_nt(const LevelView<T>& L, const Batch& bt) {
 constexpr int fdiv2(int x) { return x >= 0 ? x / 2 : -((1 - x) / 2); }
 
 template <typename T, int S, int R, int WY, bool PER, bool UZ, bool GS, bool FLAT, bool SHY, bool NT,
-          bool PRO = false, bool CH = false>
+          bool PRO = false, bool CH = false, bool RS = false>
 __device__ __forceinline__ void tau_strip_body(LevelView<T> L, const T* __restrict__ u, const T* __restrict__ b,
                                                T* __restrict__ out, FCoef<T, S> co, int zc, int gx_tiles,
                                                int gy_tiles, int nblk, StripMap sm, double* __restrict__ part,
                                                Batch bt, const int* __restrict__ stop,
                                                const T* __restrict__ ec = nullptr, const T* __restrict__ v = nullptr,
-                                               T* __restrict__ out2 = nullptr) {
+                                               T* __restrict__ out2 = nullptr, T* __restrict__ bc = nullptr) {
   static_assert(!SHY || (WY > 1 && !FLAT && R >= S), "shared y halos need stacked 3-D strips of >= S rows");
   static_assert(!PRO || (!UZ && !GS && !FLAT && R % 2 == 0), "prolongation fusion: 3-D RKL strips of even R");
   static_assert(!CH || (!UZ && !GS && !FLAT && !SHY && !PRO), "stage chunks: 3-D RKL strips, own halo rows");
+  static_assert(!RS || (!UZ && !GS && !FLAT && !PRO && !CH && WY > 1 && R % 2 == 0 && S >= 2),
+                "restriction fusion: stacked 3-D RKL strips of even R, s >= 2 (a b halo row in registers)");
   {
     const long long mb = blockIdx.y;
     if (PRO) ec += mb * bt.s1;
+    if (RS) bc += mb * bt.s1;
     if (CH) {
       v += mb * bt.s0;
       out2 += mb * bt.s0;
@@ -116,10 +136,17 @@ __device__ __forceinline__ void tau_strip_body(LevelView<T> L, const T* __restri
   }
   constexpr int HY = FLAT ? 0 : S;  // halo rows on either side of the R output rows
   constexpr int NU = R + 2 * HY;    // rows held per lane
-  constexpr int OX = 64 - 2 * S;    // output columns per wavefront (per segment when FLAT)
+  constexpr int XH = RS ? S + 1 : S;  // halo lanes on either side of the output columns
+  constexpr int OX = 64 - 2 * XH;   // output columns per wavefront (per segment when FLAT)
   constexpr int NY = S > 1 ? S - 1 : 1;
   constexpr int A1 = FLAT ? 0 : 1;  // first row of stage 1 (stage j starts at row A1 * j)
+  constexpr int TR = WY * R;        // rows the workgroup's stages cover
+  constexpr int TS = RS ? TR - 2 : TR;  // rows it owns (RS: all but the first and the last)
+  constexpr int ZE = RS ? 1 : 0;    // planes of Y_S computed beyond the chunk on either side
+  constexpr int MP = RS ? R / 2 : 1;  // RS: row pairs per wavefront
   __shared__ double red[WY];
+  // RS: Y_S of the last four planes, every row the workgroup computes
+  __shared__ T ysr[RS ? 4 : 1][RS ? TR : 1][64];
   // SHY: the wavefronts of a workgroup are stacked in y, and each takes the
   // halo rows it shares with its neighbours from their registers through LDS
   // (double-buffered): [buffer][wavefront][side][row][lane], side 0 = the
@@ -129,6 +156,7 @@ __device__ __forceinline__ void tau_strip_body(LevelView<T> L, const T* __restri
   __shared__ T xch[SHY ? 2 : 1][SHY ? WY : 1][2][SHY ? XU + XB : 1][64];
   lds_poison(red, WY);
   lds_poison(&xch[0][0][0][0][0], (SHY ? 2 : 1) * (SHY ? WY : 1) * 2 * (SHY ? XU + XB : 1) * 64);
+  if (RS) lds_poison(&ysr[0][0][0], (RS ? 4 * TR : 1) * 64);
   lds_poison_sync();
   if (stop != nullptr && *stop) return;
 
@@ -166,14 +194,15 @@ __device__ __forceinline__ void tau_strip_body(LevelView<T> L, const T* __restri
     ty = (bid / gx_tiles) % gy_tiles;
     tz = bid / (gx_tiles * gy_tiles);
   }
-  const int gxu = tx * OX - S + xl;          // column of this lane (unwrapped; 3-D form)
-  const int y0 = FLAT ? 0 : (ty * WY + w) * R - S;  // row of strip index 0 (unwrapped, wave-uniform)
+  const int gxu = tx * OX - XH + xl;         // column of this lane (unwrapped; 3-D form)
+  const int ybase = ty * TS - (RS ? 1 : 0);  // first row the workgroup computes (unwrapped)
+  const int y0 = FLAT ? 0 : ybase + w * R - S;  // row of strip index 0 (unwrapped, wave-uniform)
   const int z0 = tz * zc, z1 = min(z0 + zc, nz);
   const bool xin = gxu >= 0 && gxu < nx;
   const int gx = PER ? ((gxu % nx) + nx) % nx : min(max(gxu, 0), nx - 1);
   // byte offset of this lane's column (and, in a packed wavefront, of its strip's rows)
   const unsigned xb = ((unsigned)gx + (unsigned)yshift * (unsigned)nx) * (unsigned)sizeof(T);
-  const bool xown = xl >= S && xl < xw - S && xin;
+  const bool xown = xl >= XH && xl < xw - XH && xin;
   const bool xlo = !PER && gxu == 0, xhi = !PER && gxu == nx - 1;
   // FLAT: per-segment column byte offsets and bit masks (bit i: segment i)
   unsigned sxb[FLAT ? R : 1];
@@ -475,7 +504,8 @@ __device__ __forceinline__ void tau_strip_body(LevelView<T> L, const T* __restri
   T U0[NU], U1[NU], U2[NU], UN[NU];  // u at planes zl-1, zl, zl+1; zl+2 in flight
   T Yq[NY][3][NU];                   // Y_j at planes zl-j-1, zl-j, zl-j+1 (after stage j of iteration zl)
   T Bq[S][NU], BN[NU];               // b at planes zl, zl-1, ..; zl+1 in flight
-  const int zs = z0 - (S - 1), ze = z1 + S - 2;  // iterations: stage 1 of plane zl, stage j of zl - j + 1
+  // iterations: stage 1 of plane zl, stage j of zl - j + 1
+  const int zs = z0 - (S - 1) - ZE, ze = z1 + S - 2 + ZE;
   long long ou = plane0(zs - 1);   // plane offset of the last u plane loaded
   long long ob = plane0(zs);       // plane offset of the last b plane loaded
   long long oo = plane0(zs - S + 1);  // plane offset of the stage-S output plane of iteration zs
@@ -521,6 +551,82 @@ __device__ __forceinline__ void tau_strip_body(LevelView<T> L, const T* __restri
   exchange(U2, Bq[0], !UZ, true);
   double r2 = 0.0;
   T YS[NU];  // Y_S of the iteration's output plane, stored after the queues advance
+  // RS: pair k of the wavefront covers its held rows HY + 1 + 2k and the
+  // next one (the last pair's second row is the b halo row above its own
+  // rows, which the stages hold anyway; the workgroup's last pair would
+  // start on its last computed row and is not taken).  The residual of plane
+  // q runs at the end of iteration q + S, after the barrier that completes
+  // the ring's plane q + 1 (placed at the top of the next iteration, where
+  // the loads in flight would hide its latency, it needs more registers than
+  // four wavefronts per SIMD allow and measured slower).  BR[k] / BB[k]: b
+  // of the pair's two rows at planes q and q + 1, taken from the b queue
+  // (Bq[S - 1] holds b of the plane whose Y_S an iteration computes);
+  // acc[k]: the y-pair sums of the pair's even plane
+  double rs2 = 0.0, rs1 = 0.0;
+  T BR[MP][2], BB[MP][2], acc[MP];
+  const int cnxr = nx >> 1;
+  const long long cnxyr = (long long)cnxr * (ny >> 1);
+#pragma unroll
+  for (int k = 0; k < MP; ++k) BR[k][0] = BR[k][1] = BB[k][0] = BB[k][1] = acc[k] = (T)0;
+  // RS: residual + restriction of plane q from the ring
+  auto resid_plane = [&](int q) {
+    if constexpr (RS) {
+      if (q >= z0 && q < z1) {
+        const int sl = (q - 1) & 3, sc = q & 3, su = (q + 1) & 3;
+#pragma unroll
+        for (int k = 0; k < MP; ++k) {
+          const int a = w * R + 1 + 2 * k;  // tile row of the pair's first row
+          if (a + 1 <= TR - 2) {
+            const int ga = ybase + a;
+            const T c0 = ysr[sc][a][lane], c1 = ysr[sc][a + 1][lane];
+            T ym = ysr[sc][a - 1][lane], yp = ysr[sc][a + 2][lane];
+            T zm0 = ysr[sl][a][lane], zm1 = ysr[sl][a + 1][lane];
+            T zp0 = ysr[su][a][lane], zp1 = ysr[su][a + 1][lane];
+            T xm0 = wshift<DPP_WAVE_SHR1>(c0), xp0 = wshift<DPP_WAVE_SHL1>(c0);
+            T xm1 = wshift<DPP_WAVE_SHR1>(c1), xp1 = wshift<DPP_WAVE_SHL1>(c1);
+            if (!PER) {
+              if (xlo) {
+                xm0 = -c0;
+                xm1 = -c1;
+              }
+              if (xhi) {
+                xp0 = -c0;
+                xp1 = -c1;
+              }
+              if (ga == 0) ym = -c0;
+              if (ga + 1 == ny - 1) yp = -c1;
+              if (q == 0) {
+                zm0 = -c0;
+                zm1 = -c1;
+              }
+              if (q == nz - 1) {
+                zp0 = -c0;
+                zp1 = -c1;
+              }
+            }
+            const T l0 = ((xm0 + xp0) - (T)2 * c0) * L.ihx2 + ((ym + c1) - (T)2 * c0) * L.ihy2 +
+                         ((zm0 + zp0) - (T)2 * c0) * L.ihz2;
+            const T l1 = ((xm1 + xp1) - (T)2 * c1) * L.ihx2 + ((c0 + yp) - (T)2 * c1) * L.ihy2 +
+                         ((zm1 + zp1) - (T)2 * c1) * L.ihz2;
+            const T r0 = BR[k][0] - l0, r1 = BR[k][1] - l1;
+            const bool ok = xown && ga < ny;
+            if (ok) rs2 += (double)r0 * (double)r0 + (double)r1 * (double)r1;
+            const T yr = r0 + r1;
+            if (q & 1) {
+              const T zsum = acc[k] + yr;
+              const T cv = (zsum + wshift<DPP_WAVE_SHL1>(zsum)) * (T)0.125;
+              if (ok && !(gx & 1)) {
+                bc[(long long)(q >> 1) * cnxyr + (long long)(ga >> 1) * cnxr + (gx >> 1)] = cv;
+                rs1 += (double)cv;
+              }
+            } else {
+              acc[k] = yr;
+            }
+          }
+        }
+      }
+    }
+  };
 
   for (int zl = zs; zl <= ze; ++zl) {
     // next planes: loads issued now, consumed at the end of the iteration
@@ -555,8 +661,8 @@ __device__ __forceinline__ void tau_strip_body(LevelView<T> L, const T* __restri
     // stage 1 at plane zl, rows A1 .. NU-1-A1
     {
       const int p = zl;
-      const bool on = pin(p) && p >= z0 - (S - 1) && p <= z1 - 1 + (S - 1);
-      const bool pown = p >= z0 && p < z1;
+      const bool on = pin(p) && p >= z0 - (S - 1) - ZE && p <= z1 - 1 + (S - 1) + ZE;
+      const bool pown = !RS && p >= z0 && p < z1;
       if (on) {
 #pragma unroll
         for (int i = A1; i < NU - A1; ++i) {
@@ -580,7 +686,7 @@ __device__ __forceinline__ void tau_strip_body(LevelView<T> L, const T* __restri
 #pragma unroll
     for (int j = 2; j <= S; ++j) {
       const int p = zl - j + 1;
-      const bool on = pin(p) && p >= z0 - (S - j) && p <= z1 - 1 + (S - j);
+      const bool on = pin(p) && p >= z0 - (S - j) - ZE && p <= z1 - 1 + (S - j) + ZE;
       if (on) {
 #pragma unroll
         for (int i = A1 * j; i < NU - A1 * j; ++i) {
@@ -599,6 +705,23 @@ __device__ __forceinline__ void tau_strip_body(LevelView<T> L, const T* __restri
           if (j == S) YS[i] = y;
           else Yq[j - 1][2][i] = y;
         }
+      }
+    }
+    // RS: the wavefront's rows of Y_S into the ring; b of the pairs' rows at
+    // that plane into BB (BR: the plane below, whose residual the next
+    // iteration takes)
+    if constexpr (RS) {
+      const int p = zl - S + 1;
+      if (pin(p) && p >= z0 - 1 && p <= z1) {
+#pragma unroll
+        for (int i = HY; i < HY + R; ++i) ysr[p & 3][w * R + i - HY][lane] = YS[i];
+      }
+#pragma unroll
+      for (int k = 0; k < MP; ++k) {
+        BR[k][0] = BB[k][0];
+        BR[k][1] = BB[k][1];
+        BB[k][0] = Bq[S - 1][HY + 1 + 2 * k];
+        BB[k][1] = Bq[S - 1][HY + 2 + 2 * k];
       }
     }
     // advance the queues; Dirichlet planes outside the box and rows outside it read as 0
@@ -627,6 +750,13 @@ __device__ __forceinline__ void tau_strip_body(LevelView<T> L, const T* __restri
       if constexpr (CH) Vc[i] = (!bn_ok || !rok) ? (T)0 : VN[i];
     }
     if (more) exchange(U2, Bq[0], !UZ, true);
+    // RS: residual of plane zl - S, once the ring holds Y_S up to plane
+    // zl - S + 1 (SHY: the exchange's barrier); the slot written next
+    // iteration is none of the three it reads
+    if constexpr (RS) {
+      if (!SHY || !more) __syncthreads();
+      resid_plane(zl - S);
+    }
     // stores after the wait for the loads above, so that the next
     // iteration's wait does not also wait for these writes; NT: with
     // non-temporal hints
@@ -636,7 +766,7 @@ __device__ __forceinline__ void tau_strip_body(LevelView<T> L, const T* __restri
       if (p >= z0 && p < z1) {
 #pragma unroll
         for (int i = HY; i < HY + R; ++i)
-          if (own(i) && ((rin >> i) & 1u)) {
+          if (own(i) && ((rin >> i) & 1u) && (!RS || (w * R + i - HY >= 1 && w * R + i - HY <= TR - 2))) {
             T* dst = (T*)((char*)(out + oo + yoff[i]) + colb(i));
             if constexpr (NT) __builtin_nontemporal_store(YS[i], dst);
             else *dst = YS[i];
@@ -658,7 +788,27 @@ __device__ __forceinline__ void tau_strip_body(LevelView<T> L, const T* __restri
     oo = next_plane(oo, zl - S + 2);
     if constexpr (CH) oo2 = next_plane(oo2, zl - S + 3);
   }
-  if (part != nullptr) {
+  if constexpr (RS) {
+    // (fine r^2, coarse sum) of the workgroup, reduced through the ring's LDS
+    const double t2 = wave_sum_dpp(rs2), t1 = wave_sum_dpp(rs1);
+    __syncthreads();
+    double* rd = reinterpret_cast<double*>(&ysr[0][0][0]);
+    if (lane == 0) {
+      rd[2 * w] = t2;
+      rd[2 * w + 1] = t1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double a2 = 0.0, a1 = 0.0;
+#pragma unroll
+      for (int q = 0; q < WY; ++q) {
+        a2 += rd[2 * q];
+        a1 += rd[2 * q + 1];
+      }
+      part[2 * (size_t)blockIdx.x] = a2;
+      part[2 * (size_t)blockIdx.x + 1] = a1;
+    }
+  } else if (part != nullptr) {
     const double t = wave_sum_dpp(r2);
     if (lane == 0) red[w] = t;
     __syncthreads();

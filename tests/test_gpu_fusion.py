@@ -1,7 +1,9 @@
 """Transfer fusion: V-cycles whose prolongation + correction runs inside the
-first post-smoothing tau-step (Options.fuse, the default; Sec. 2.1 steps 4-5
-followed by the post-smoothing relaxation) against the oracle's V-cycle,
-which prolongs, corrects and relaxes as three separate steps.
+first post-smoothing tau-step (Options.fuse bit 0; Sec. 2.1 steps 4-5
+followed by the post-smoothing relaxation), and whose last pre-smoothing
+tau-step also writes the restricted residual (bit 1; Sec. 2.1 steps 1-2b),
+against the oracle's V-cycle, which relaxes, forms the residual, restricts,
+prolongs and corrects as separate steps.
 
 Every strip variant is forced through the tuning table onto the two finest
 levels (the five-row strip has no fused form: in float64 it keeps the
@@ -9,7 +11,13 @@ separate prolongation, in float32 its levels take the fused four-row strips;
 the float64 eight-row strips take the stacked two-row strips for the fused
 step), on a grid that is ragged against every tile shape in x and y, with both
 boundary types, float64 (mg_vcycle) and float32 (mg_vcycle_f32) and one or
-two post-smoothing relaxations.  Tolerances are those of the unfused
+two post-smoothing (or pre-smoothing) relaxations.  The restriction form
+exists at s >= 2 for the stacked two-row strips (every float64 level, s = 2)
+and, in float32, for the four-row strips (s = 2, 3), which a level takes unless
+tuned for the two-row strips; s = 1 and float64 s = 3 restrict separately.  A
+finest level with Dirichlet face data (mg_vcycle with faces) runs the LDS-ring
+kernel and restricts separately; its next level takes the fused form.
+Tolerances are those of the unfused
 V-cycle tests: 1e-11 of the field's max norm in float64, 1e-5 in float32
 (the float32 oracle runs in numpy float32; the coarsest solve takes a fixed
 number of tau-steps so both sides stop at the same step).
@@ -74,12 +82,12 @@ def _inputs(bc, dtype):
 
 
 @functools.lru_cache(maxsize=None)
-def _oracle(bc, s, n_post, dtype_name):
+def _oracle(bc, s, n_post, dtype_name, n_pre=2):
     dtype = np.dtype(dtype_name).type
     f, u0, faces = _inputs(bc, dtype)
     nz, ny, nx = SHAPE
     lv = oop.build_hierarchy(oop.Grid(nx, ny, nz, *H, bc))
-    o = omg.Options(s=s, n_post=n_post, **COARSE)
+    o = omg.Options(s=s, n_pre=n_pre, n_post=n_post, **COARSE)
     return omg.vcycle(u0, f, lv, o, faces)
 
 
@@ -89,12 +97,12 @@ def _force(R, variant, s, bc, prec):
                 for (nz, ny, nx) in shapes[:2]])
 
 
-def _run(R, bc, s, n_post, fuse, dtype):
+def _run(R, bc, s, n_post, fuse, dtype, n_pre=2):
     f, u0, faces = _inputs(bc, dtype)
     phi = torch.from_numpy(u0.copy()).cuda()
     ft = torch.from_numpy(f).cuda()
     pf = R.pack_faces(faces) if faces is not None else None
-    R.vcycle(ft, phi, H, bc, faces=pf, opts=R.Options(s=s, n_post=n_post, fuse=fuse, **COARSE))
+    R.vcycle(ft, phi, H, bc, faces=pf, opts=R.Options(s=s, n_pre=n_pre, n_post=n_post, fuse=fuse, **COARSE))
     return phi.cpu().numpy()
 
 
@@ -127,6 +135,43 @@ def test_fused_prolongation_vcycle_f32_matches_oracle(variant, bc, s):
     want = _oracle(bc, s, 1, "float32")
     got = _run(R, bc, s, 1, True, np.float32)
     assert relmax(got, want) < TOL32
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("bc", ["periodic", "dirichlet"])
+@pytest.mark.parametrize("s", [1, 2, 3])
+@pytest.mark.parametrize("n_pre", [1, 2])
+def test_fused_restriction_vcycle_matches_oracle(variant, bc, s, n_pre):
+    """Restriction fusion alone (fuse = 2) and with the prolongation fusion
+    (fuse = 3), float64: with n_pre = 1 only the finest level's single
+    relaxation carries the restriction (a coarse level's only relaxation is
+    the one from zero), with n_pre = 2 every level above the tail."""
+    R = _lib()
+    if s == 3 and variant != "stripyx4x8":
+        pytest.skip("float64 s = 3 takes the stacked four-row strips (restricted separately)")
+    if s != 3 and s not in S64[variant]:
+        pytest.skip(f"{variant} is not built for float64 s = {s}")
+    _force(R, variant, s, bc, "fp64")
+    print(f"fp64 {variant} {bc} s={s} n_pre={n_pre}", flush=True)
+    want = _oracle(bc, s, 1, "float64", n_pre)
+    for fuse in (2, 3):
+        got = _run(R, bc, s, 1, fuse, np.float64, n_pre)
+        assert relmax(got, want) < TOL64, fuse
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("bc", ["periodic", "dirichlet"])
+@pytest.mark.parametrize("s", [1, 2, 3])
+def test_fused_restriction_vcycle_f32_matches_oracle(variant, bc, s):
+    R = _lib()
+    if s not in S32[variant]:
+        pytest.skip(f"{variant} is not built for float32 s = {s}")
+    _force(R, variant, s, bc, "mixed")
+    print(f"fp32 {variant} {bc} s={s}", flush=True)
+    want = _oracle(bc, s, 1, "float32")
+    for fuse in (2, 3):
+        got = _run(R, bc, s, 1, fuse, np.float32)
+        assert relmax(got, want) < TOL32, fuse
 
 
 def test_fused_solve_takes_the_same_cycles():

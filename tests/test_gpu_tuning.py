@@ -91,7 +91,11 @@ def test_forced_variant_float32_solve(variant, bc, s):
     """The float32 sweeps of the mixed path with each variant on every level
     that runs a fused tau-step: the solve still reaches u*, in the same number
     of outer iterations as with the built-in choice (all variants compute the
-    same values)."""
+    same values up to float32 rounding).  Each outer iteration's float32
+    V-cycle rounds differently per variant, which perturbs that iteration's
+    contraction independently of the others, so the residual histories drift
+    apart roughly linearly in the iteration count (about 1e-5 per iteration
+    here); the per-iteration contraction factors h_k / h_(k-1) are compared."""
     if s not in SUPPORT[variant][1]:
         pytest.skip(f"{variant} is not built for float32 s = {s}")
     R = _lib()
@@ -104,7 +108,8 @@ def test_forced_variant_float32_solve(variant, bc, s):
                  "target": 512} for n in (64, 32, 16)])
     phi, st = R.solve(rho, p.h, bc, opts=o)
     assert st.status == 0 and st.cycles == ref.cycles
-    np.testing.assert_allclose(st.history, ref.history, rtol=1e-4)
+    got, want = np.asarray(st.history), np.asarray(ref.history)
+    np.testing.assert_allclose(got[1:] / got[:-1], want[1:] / want[:-1], rtol=1e-4)
     us = exact.exact_solution(4 * math.pi * p.rho, p.h, bc, None)
     assert relmax(phi.cpu().numpy(), us) < 1e-9
 
