@@ -207,13 +207,16 @@ __global__ __launch_bounds__(WAVE) void k_coarse_wave(LevelView<T> L, const T* _
   };
   int step = 0;
   if (bnorm > 0.0) {
+    T rchk[CPL];  // the stop test's M u - b, which is also the first stage's
     while (true) {
       double r2 = 0.0;
 #pragma unroll
       for (int c = 0; c < CPL; ++c) {
+        rchk[c] = (T)0;
         if (!on[c]) continue;
         const int q = lane + WAVE * c;
         const T r = lapr(cur, c, cur[q]);
+        rchk[c] = r;
         r2 += (double)r * (double)r;
       }
       const double res = sqrt(wave_sum<CPL>(r2));
@@ -232,7 +235,7 @@ __global__ __launch_bounds__(WAVE) void k_coarse_wave(LevelView<T> L, const T* _
           outv[c] = (T)0;
           if (!on[c]) continue;
           const T cv = yp[q];
-          const T r = lapr(yp, c, cv);
+          const T r = jst == 1 ? rchk[c] : lapr(yp, c, cv);
           outv[c] = (jst == 1) ? cv + cc * r : mu * cv + nu * yw[q] + cc * r;
         }
 #pragma unroll

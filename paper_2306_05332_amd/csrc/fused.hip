@@ -844,14 +844,16 @@ bool launch_fused_tau_pro(const LevelView<T>& L, const T* u, const T* e, const T
   // faster than the separate pass).  The float64 eight-row forms run out of
   // registers with the fusion (one wavefront per SIMD): those levels take the
   // stacked two-row strips, the leanest fused form.
+  // A level that takes another form than its tuned variant sizes the grid
+  // from that form's occupancy (target 0), not from the tuned target.
   if (c.variant == FV_STRIP_5x1) {
     if (sizeof(T) == 8) return false;
-    c = FusedChoice{FV_STRIP_4x4, c.target};
+    c = FusedChoice{FV_STRIP_4x4, 0};
   }
   const bool dbl8 = sizeof(T) == 8 && (c.variant == FV_STRIP_8x4 || c.variant == FV_STRIP_8x1 ||
                                        c.variant == FV_STRIPYX_8x4 || c.variant == FV_STRIPYX_8x8);
-  if (dbl8) c = FusedChoice{s <= 2 ? FV_STRIPYX_2x8 : FV_STRIP_4x4, c.target};
-  if (!is_strip(c.variant) || !fused_variant_ok<T>(c.variant, s) || c.target < 1) return false;
+  if (dbl8) c = FusedChoice{s <= 2 ? FV_STRIPYX_2x8 : FV_STRIP_4x4, 0};
+  if (!is_strip(c.variant) || !fused_variant_ok<T>(c.variant, s) || c.target < 0) return false;
   switch (s) {
     case 1: return launch_pro_S<T, 1>(L, c.variant, c.target, u, e, b, out, co, stop, bt, st);
     case 2: return launch_pro_S<T, 2>(L, c.variant, c.target, u, e, b, out, co, stop, bt, st);

@@ -6,6 +6,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <atomic>
 #include <new>
 #include <string>
 
@@ -45,6 +47,24 @@ rkl_status guarded(Fn&& fn) {
     g_err = "unexpected internal error";
     return RKL_EHIP;
   }
+}
+
+// Workgroups of `kernel` (blocks of `threads`) the current device holds at
+// once, from the kernel's occupancy and the compute-unit count; cached per
+// device in `cache` (one per kernel instantiation).
+template <typename K>
+int resident_wgs(K kernel, int threads, std::atomic<int> (&cache)[64]) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) fail(RKL_EINVAL, "device index out of range");
+  int v = cache[dev].load(std::memory_order_relaxed);
+  if (v > 0) return v;
+  int cus = 0, per_cu = 0;
+  HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0));
+  v = std::max(1, cus * per_cu);
+  cache[dev].store(v, std::memory_order_relaxed);
+  return v;
 }
 
 // a two-dimensional grid: nz = 1 with hz = +inf

@@ -217,6 +217,7 @@ void launch_strip2d(const LevelView<T>& L, int target, const T* u, const T* b, T
 // (Sec. 2.1: the first post-smoothing relaxation of u + P e): reads u, the
 // coarse correction e (batch stride bt.s1) and b, writes Y_S to out; u is not
 // modified.  3-D levels of even extents, even R; no remainder packing.
+// target <= 0 sizes the z chunks to one wave of resident workgroups.
 template <typename T, int S, int R, int WY, bool SHY>
 void launch_strip_pro(const LevelView<T>& L, int target, const T* u, const T* e, const T* b, T* out,
                       const FCoef<T, S>& fc, const int* stop, const Batch& bt, hipStream_t st);

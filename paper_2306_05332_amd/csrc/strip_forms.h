@@ -31,27 +31,33 @@ __global__ __launch_bounds__(64 * WY) void k_tau_strip_pro(LevelView<T> L, const
       L, u, b, out, co, zc, gx_tiles, gy_tiles, nblk, StripMap{0, 0, 0, 0, 0}, nullptr, bt, stop, e);
 }
 
-template <typename T, int S, int R, int WY, bool SHY, bool NT>
-static void launch_strip_pro_nt(const LevelView<T>& L, const StripGrid& g, const T* u, const T* e, const T* b,
-                                T* out, const FCoef<T, S>& fc, const int* stop, const Batch& bt, hipStream_t st) {
-  const dim3 grid(g.nblk, bt.nb), block(64 * WY);
-  if (L.periodic)
-    hipLaunchKernelGGL((k_tau_strip_pro<T, S, R, WY, true, SHY, NT>), grid, block, 0, st, L, u, e, b, out, fc, g.zc,
-                       g.gx, g.gy, g.nblk, bt, stop);
-  else
-    hipLaunchKernelGGL((k_tau_strip_pro<T, S, R, WY, false, SHY, NT>), grid, block, 0, st, L, u, e, b, out, fc, g.zc,
-                       g.gx, g.gy, g.nblk, bt, stop);
+// target <= 0: as many z chunks as fill one wave of resident workgroups
+// (from the kernel's occupancy; the grid depends on the level only)
+template <typename T, int S, int R, int WY, bool PER, bool SHY, bool NT>
+static void launch_strip_pro_k(const LevelView<T>& L, int target, const T* u, const T* e, const T* b, T* out,
+                               const FCoef<T, S>& fc, const int* stop, const Batch& bt, hipStream_t st) {
+  auto kern = k_tau_strip_pro<T, S, R, WY, PER, SHY, NT>;
+  if (target <= 0) {
+    static std::atomic<int> slots[64];
+    const int per = strip_grid(S, R, WY, L.nx, L.ny, L.nz, 1, false, false).per;
+    target = std::max(1, resident_wgs(kern, 64 * WY, slots) / per) * per;
+  }
+  const StripGrid g = strip_grid(S, R, WY, L.nx, L.ny, L.nz, target, false, false);
+  hipLaunchKernelGGL(kern, dim3(g.nblk, bt.nb), dim3(64 * WY), 0, st, L, u, e, b, out, fc, g.zc, g.gx, g.gy, g.nblk,
+                     bt, stop);
 }
 
 template <typename T, int S, int R, int WY, bool SHY>
 void launch_strip_pro(const LevelView<T>& L, int target, const T* u, const T* e, const T* b, T* out,
                       const FCoef<T, S>& fc, const int* stop, const Batch& bt, hipStream_t st) {
   if ((L.nx | L.ny | L.nz) & 1) fail(RKL_EINVAL, "prolongation fusion needs even level extents");
-  const StripGrid g = strip_grid(S, R, WY, L.nx, L.ny, L.nz, target, false, false);
-  if constexpr (sizeof(T) == 8) {
-    if (strip_nt<T>(L, bt)) return launch_strip_pro_nt<T, S, R, WY, SHY, true>(L, g, u, e, b, out, fc, stop, bt, st);
+  const bool nt = sizeof(T) == 8 && strip_nt<T>(L, bt);
+  if (L.periodic) {
+    if (nt) return launch_strip_pro_k<T, S, R, WY, true, SHY, true>(L, target, u, e, b, out, fc, stop, bt, st);
+    return launch_strip_pro_k<T, S, R, WY, true, SHY, false>(L, target, u, e, b, out, fc, stop, bt, st);
   }
-  launch_strip_pro_nt<T, S, R, WY, SHY, false>(L, g, u, e, b, out, fc, stop, bt, st);
+  if (nt) return launch_strip_pro_k<T, S, R, WY, false, SHY, true>(L, target, u, e, b, out, fc, stop, bt, st);
+  launch_strip_pro_k<T, S, R, WY, false, SHY, false>(L, target, u, e, b, out, fc, stop, bt, st);
 }
 
 template <typename T, int S, int R, int WY, bool PER, bool NT>

@@ -14,8 +14,6 @@
 // number of planes (a coarse plane's two fine planes in one chunk).  Built
 // for S >= 2: a wavefront's last row pair takes b of the row above its own
 // rows, which only tau-steps of two or more stages hold.
-#include <atomic>
-
 #include "host_common.h"
 #include "strip_body.h"
 
@@ -54,23 +52,6 @@ StripGrid strip_grid_rs(int s, int R, int WY, int nx, int ny, int nz, int target
 size_t strip_rs_parts_max(int nx, int ny, int nz) {
   // smallest tile built: 54 output columns (s <= 4), RS_MIN_ROWS rows, 2 planes
   return 2 * (size_t)((nx + 53) / 54) * (size_t)((ny + RS_MIN_ROWS - 1) / RS_MIN_ROWS) * (size_t)((nz + 1) / 2);
-}
-
-// Workgroups of `kernel` (block of `threads`) the current device holds at
-// once, from its occupancy and compute-unit count; cached per device.
-template <typename K>
-static int resident_wgs(K kernel, int threads, std::atomic<int> (&cache)[64]) {
-  int dev = 0;
-  HIPCHK(hipGetDevice(&dev));
-  if (dev < 0 || dev >= 64) fail(RKL_EINVAL, "device index out of range");
-  int v = cache[dev].load(std::memory_order_relaxed);
-  if (v > 0) return v;
-  int cus = 0, per_cu = 0;
-  HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0));
-  v = std::max(1, cus * per_cu);
-  cache[dev].store(v, std::memory_order_relaxed);
-  return v;
 }
 
 template <typename T, int S, int R, int WY, bool PER, bool SHY, bool NT>

@@ -102,6 +102,49 @@ __device__ __forceinline__ T tail_lap(const TailLevel<T>& V, const T* Y, int q, 
   return ((xm + xp) - (T)2 * c) * V.ihx2 + ((ym + yp) - (T)2 * c) * V.ihy2 + ((zm + zp) - (T)2 * c) * V.ihz2;
 }
 
+// Lane rotations by DPP moves (GFX9 DPP controls): quad_perm [3,0,1,2] and
+// [1,2,3,0] (the value of the lane one below / above within its quad),
+// row_ror:4 and row_ror:12 (four lanes below / above within its 16-lane row).
+constexpr int DPP_QUAD_XM = 0x93, DPP_QUAD_XP = 0x39, DPP_ROW_ROR4 = 0x124, DPP_ROW_ROR12 = 0x12C;
+template <int CTRL>
+__device__ __forceinline__ double lane_rot(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float lane_rot(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+
+// gfx950 cross-row swaps of a value with itself (rows of 16 lanes r0..r3):
+// swap16 returns (r0, r0, r2, r2) and (r1, r1, r3, r3), swap32 (r0, r1, r0, r1)
+// and (r2, r3, r2, r3).
+struct LanePair {
+  double a, b;
+};
+__device__ __forceinline__ LanePair swap16(double v) {
+  const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(v), __double2loint(v), false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(v), __double2hiint(v), false, false);
+  return {__hiloint2double(hi[0], lo[0]), __hiloint2double(hi[1], lo[1])};
+}
+__device__ __forceinline__ LanePair swap32(double v) {
+  const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(v), __double2loint(v), false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(v), __double2hiint(v), false, false);
+  return {__hiloint2double(hi[0], lo[0]), __hiloint2double(hi[1], lo[1])};
+}
+struct LanePairF {
+  float a, b;
+};
+__device__ __forceinline__ LanePairF swap16(float v) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_int(v), __float_as_int(v), false, false);
+  return {__int_as_float(r[0]), __int_as_float(r[1])};
+}
+__device__ __forceinline__ LanePairF swap32(float v) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_int(v), __float_as_int(v), false, false);
+  return {__int_as_float(r[0]), __int_as_float(r[1])};
+}
+
 // Value of `v` in lane `src` (ds_bpermute: the LDS crossbar, no LDS memory).
 __device__ __forceinline__ double lane_get(double v, int src) {
   const int a = src << 2;
@@ -150,36 +193,74 @@ __device__ void coarse_regs(const TailLevel<T>& V, const int* ssched, const int*
     for (int d = 0; d < 6; ++d) nb[d] = lane;  // idle lanes hold 0 and read themselves
   }
   const T bl = has ? B[q] : (T)0;
+  // A 4 x 4 x 4 level (the usual coarsest) holds x in the lanes of a quad, y
+  // in the quads of a 16-lane row and z in the rows: the x and y neighbours
+  // are rotations within the quad and within the row, one DPP move each (a
+  // Dirichlet ghost replaces the wrapped value by -y).  For z only the sum
+  // zm + zp is needed: rows 0 and 2 take r1 + r3, rows 1 and 3 take r0 + r2;
+  // swap32's two results add up to (r0 + r2, r1 + r3, r0 + r2, r1 + r3) and
+  // swap16 hands each row the other parity's sum (the same additions as
+  // zm + zp, in commuted order).  Dirichlet planes 0 and 3 take their one
+  // neighbour from swap16 of y and the ghost -y.
+  const bool q444 = nx == 4 && ny == 4 && nz == 4;
+  const int zrow = lane >> 4;
   auto mres = [&](T y) -> T {  // (M y - b) at this lane's cell; every lane takes part in the exchanges
-    T v[6];
+    T v[4], zs;
+    if (q444) {
+      v[0] = lane_rot<DPP_QUAD_XM>(y);
+      v[1] = lane_rot<DPP_QUAD_XP>(y);
+      v[2] = lane_rot<DPP_ROW_ROR4>(y);
+      v[3] = lane_rot<DPP_ROW_ROR12>(y);
+      const auto h = swap32(y);
+      const auto t = swap16(h.a + h.b);
+      zs = (zrow & 1) ? t.a : t.b;
+      if (!per) {
 #pragma unroll
-    for (int d = 0; d < 6; ++d) v[d] = sg[d] * lane_get(y, nb[d]);
-    return ((v[0] + v[1]) - (T)2 * y) * V.ihx2 + ((v[2] + v[3]) - (T)2 * y) * V.ihy2 +
-           ((v[4] + v[5]) - (T)2 * y) * V.ihz2 - bl;
+        for (int d = 0; d < 4; ++d)
+          if (sg[d] < (T)0) v[d] = -y;
+        const auto w = swap16(y);
+        if (zrow == 0) zs = -y + w.b;
+        if (zrow == 3) zs = w.a + -y;
+      }
+    } else {
+#pragma unroll
+      for (int d = 0; d < 4; ++d) v[d] = sg[d] * lane_get(y, nb[d]);
+      zs = sg[4] * lane_get(y, nb[4]) + sg[5] * lane_get(y, nb[5]);
+    }
+    return ((v[0] + v[1]) - (T)2 * y) * V.ihx2 + ((v[2] + v[3]) - (T)2 * y) * V.ihy2 + (zs - (T)2 * y) * V.ihz2 -
+           bl;
   };
-  const double bnorm = sqrt(wave_sum_dpp((double)bl * (double)bl));
+  // Stop test ||M u - b|| <= ctol ||b|| before every tau-step, on squared
+  // norms.  On a periodic level M annihilates constants, so the residual of
+  // a tau-step's result is taken before its mean is removed: the two
+  // wavefront sums are independent (they overlap), and the residual is also
+  // the next tau-step's first-stage M u - b.
+  const double b2 = wave_sum_dpp((double)bl * (double)bl);
+  const double lim2 = ctol * ctol * b2;
+  const double inv_n = 1.0 / (double)n;
   T u = (T)0;
   int step = 0;
-  if (bnorm > 0.0) {
+  if (b2 > 0.0) {
+    T r = mres(u);
     while (true) {
-      const T r = mres(u);
-      const double res = sqrt(wave_sum_dpp(has ? (double)r * (double)r : 0.0));
-      if (res <= ctol * bnorm || step >= cmax) break;
+      const double res2 = wave_sum_dpp(has ? (double)r * (double)r : 0.0);
+      if (per && step > 0) u -= (T)(wave_sum_dpp(has ? (double)u : 0.0) * inv_n);
+      if (!has) u = (T)0;
+      if (res2 <= lim2 || step >= cmax) break;
       const int qs = step < nsched ? step : nsched - 1;
       const int s = ssched[qs];
       const double* co = scoef + 3 * scoff[qs];
       T y1 = u, y2 = u;  // Y_{j-1}, Y_{j-2}
       for (int jj = 1; jj <= s; ++jj) {
         const T mu = (T)co[3 * (jj - 1)], nu = (T)co[3 * (jj - 1) + 1], c = (T)co[3 * (jj - 1) + 2];
-        const T rr = mres(y1);
+        const T rr = jj == 1 ? r : mres(y1);  // stage 1: the stop test's M u - b
         T y = (jj == 1) ? y1 + c * rr : mu * y1 + nu * y2 + c * rr;
         if (!has) y = (T)0;
         y2 = y1;
         y1 = y;
       }
       u = y1;
-      if (per) u -= (T)(wave_sum_dpp(has ? (double)u : 0.0) / (double)n);
-      if (!has) u = (T)0;
+      r = mres(u);
       ++step;
     }
   }
@@ -455,14 +536,18 @@ __global__ __launch_bounds__(TNT) void k_tail(TailArgs<T> A, const T* __restrict
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       int step = 0;
       if (bnorm > 0.0) {
+        T rchk[4];  // the stop test's M u - b, which is also the first stage's
         while (true) {
           double r2 = 0.0;
 #pragma unroll
-          for (int cc = 0; cc < 4; ++cc)
+          for (int cc = 0; cc < 4; ++cc) {
+            rchk[cc] = (T)0;
             if (has[cc]) {
               const T r = lapc(cur, cc) - bl[cc];
+              rchk[cc] = r;
               r2 += (double)r * (double)r;
             }
+          }
           const double res = sqrt(wave_sum_dpp(r2));
           if (res <= A.ctol * bnorm || step >= A.cmax) break;
           const int qs = step < nsched ? step : nsched - 1;
@@ -478,7 +563,7 @@ __global__ __launch_bounds__(TNT) void k_tail(TailArgs<T> A, const T* __restrict
               const int q = tid + WAVE * cc;
               outv[cc] = (T)0;
               if (has[cc]) {
-                const T r = lapc(yp, cc) - bl[cc];
+                const T r = j == 1 ? rchk[cc] : lapc(yp, cc) - bl[cc];
                 outv[cc] = (j == 1) ? yp[q] + c * r : mu * yp[q] + nu * yw[q] + c * r;
               }
             }
