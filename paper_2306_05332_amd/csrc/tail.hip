@@ -102,49 +102,6 @@ __device__ __forceinline__ T tail_lap(const TailLevel<T>& V, const T* Y, int q, 
   return ((xm + xp) - (T)2 * c) * V.ihx2 + ((ym + yp) - (T)2 * c) * V.ihy2 + ((zm + zp) - (T)2 * c) * V.ihz2;
 }
 
-// Lane rotations by DPP moves (GFX9 DPP controls): quad_perm [3,0,1,2] and
-// [1,2,3,0] (the value of the lane one below / above within its quad),
-// row_ror:4 and row_ror:12 (four lanes below / above within its 16-lane row).
-constexpr int DPP_QUAD_XM = 0x93, DPP_QUAD_XP = 0x39, DPP_ROW_ROR4 = 0x124, DPP_ROW_ROR12 = 0x12C;
-template <int CTRL>
-__device__ __forceinline__ double lane_rot(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
-  return __hiloint2double(hi, lo);
-}
-template <int CTRL>
-__device__ __forceinline__ float lane_rot(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
-}
-
-// gfx950 cross-row swaps of a value with itself (rows of 16 lanes r0..r3):
-// swap16 returns (r0, r0, r2, r2) and (r1, r1, r3, r3), swap32 (r0, r1, r0, r1)
-// and (r2, r3, r2, r3).
-struct LanePair {
-  double a, b;
-};
-__device__ __forceinline__ LanePair swap16(double v) {
-  const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(v), __double2loint(v), false, false);
-  const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(v), __double2hiint(v), false, false);
-  return {__hiloint2double(hi[0], lo[0]), __hiloint2double(hi[1], lo[1])};
-}
-__device__ __forceinline__ LanePair swap32(double v) {
-  const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(v), __double2loint(v), false, false);
-  const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(v), __double2hiint(v), false, false);
-  return {__hiloint2double(hi[0], lo[0]), __hiloint2double(hi[1], lo[1])};
-}
-struct LanePairF {
-  float a, b;
-};
-__device__ __forceinline__ LanePairF swap16(float v) {
-  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_int(v), __float_as_int(v), false, false);
-  return {__int_as_float(r[0]), __int_as_float(r[1])};
-}
-__device__ __forceinline__ LanePairF swap32(float v) {
-  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_int(v), __float_as_int(v), false, false);
-  return {__int_as_float(r[0]), __int_as_float(r[1])};
-}
-
 // Value of `v` in lane `src` (ds_bpermute: the LDS crossbar, no LDS memory).
 __device__ __forceinline__ double lane_get(double v, int src) {
   const int a = src << 2;
@@ -193,42 +150,12 @@ __device__ void coarse_regs(const TailLevel<T>& V, const int* ssched, const int*
     for (int d = 0; d < 6; ++d) nb[d] = lane;  // idle lanes hold 0 and read themselves
   }
   const T bl = has ? B[q] : (T)0;
-  // A 4 x 4 x 4 level (the usual coarsest) holds x in the lanes of a quad, y
-  // in the quads of a 16-lane row and z in the rows: the x and y neighbours
-  // are rotations within the quad and within the row, one DPP move each (a
-  // Dirichlet ghost replaces the wrapped value by -y).  For z only the sum
-  // zm + zp is needed: rows 0 and 2 take r1 + r3, rows 1 and 3 take r0 + r2;
-  // swap32's two results add up to (r0 + r2, r1 + r3, r0 + r2, r1 + r3) and
-  // swap16 hands each row the other parity's sum (the same additions as
-  // zm + zp, in commuted order).  Dirichlet planes 0 and 3 take their one
-  // neighbour from swap16 of y and the ghost -y.
-  const bool q444 = nx == 4 && ny == 4 && nz == 4;
-  const int zrow = lane >> 4;
   auto mres = [&](T y) -> T {  // (M y - b) at this lane's cell; every lane takes part in the exchanges
-    T v[4], zs;
-    if (q444) {
-      v[0] = lane_rot<DPP_QUAD_XM>(y);
-      v[1] = lane_rot<DPP_QUAD_XP>(y);
-      v[2] = lane_rot<DPP_ROW_ROR4>(y);
-      v[3] = lane_rot<DPP_ROW_ROR12>(y);
-      const auto h = swap32(y);
-      const auto t = swap16(h.a + h.b);
-      zs = (zrow & 1) ? t.a : t.b;
-      if (!per) {
+    T v[6];
 #pragma unroll
-        for (int d = 0; d < 4; ++d)
-          if (sg[d] < (T)0) v[d] = -y;
-        const auto w = swap16(y);
-        if (zrow == 0) zs = -y + w.b;
-        if (zrow == 3) zs = w.a + -y;
-      }
-    } else {
-#pragma unroll
-      for (int d = 0; d < 4; ++d) v[d] = sg[d] * lane_get(y, nb[d]);
-      zs = sg[4] * lane_get(y, nb[4]) + sg[5] * lane_get(y, nb[5]);
-    }
-    return ((v[0] + v[1]) - (T)2 * y) * V.ihx2 + ((v[2] + v[3]) - (T)2 * y) * V.ihy2 + (zs - (T)2 * y) * V.ihz2 -
-           bl;
+    for (int d = 0; d < 6; ++d) v[d] = sg[d] * lane_get(y, nb[d]);
+    return ((v[0] + v[1]) - (T)2 * y) * V.ihx2 + ((v[2] + v[3]) - (T)2 * y) * V.ihy2 +
+           ((v[4] + v[5]) - (T)2 * y) * V.ihz2 - bl;
   };
   // Stop test ||M u - b|| <= ctol ||b|| before every tau-step, on squared
   // norms.  On a periodic level M annihilates constants, so the residual of
