@@ -25,7 +25,15 @@
 // (a wavefront may hold several periods of a short axis); Dirichlet stencils
 // that leave the box take the homogeneous ghost -c of the operand being
 // differentiated (finest-level face data is folded into the right-hand side
-// before any relaxation, so no face array is read here).
+// before any relaxation, so no face array is read here).  The 3-D RKL forms
+// (other than PRO) hold those ghosts in the operands themselves (GO): after
+// each load and each stage, the row, column or plane just outside a face is
+// set to minus its in-box neighbour, under wavefront-uniform branches that
+// only the wavefronts touching a face take, so the stencil is the periodic
+// one with no per-cell selects (those selects had made Dirichlet sweeps issue
+// half as many VALU instructions again as periodic ones).  The GS, 2-D and
+// PRO forms select the ghost inside the stencil (PRO: the operand fix-ups
+// measured slower there, its registers being at the four-wave limit).
 // Optionally the kernel returns float64 partial sums of (M u - b)^2 over its
 // output cells (the residual of the tau-step's input).
 //
@@ -102,6 +110,16 @@ constexpr size_t STRIP_NT_MIN_BYTES = (size_t)256 << 20;
 template <typename T>
 inline int strip_nt(const LevelView<T>& L, const Batch& bt) {
   return 3 * (size_t)L.nx * L.ny * L.nz * sizeof(T) * (size_t)bt.nb > STRIP_NT_MIN_BYTES ? 1 : 0;
+}
+
+// Minimum wavefronts per SIMD asked of the compiler for a strip kernel: the
+// float64 stacked two-row strips (eight wavefronts) keep four per SIMD, two
+// workgroups per CU (128 VGPRs), in their fused forms, whose Dirichlet
+// instantiations would otherwise take a few registers more and lose half of
+// their occupancy.
+template <typename T, int R, int WY>
+constexpr int strip_min_waves() {
+  return (sizeof(T) == 8 && R == 2 && WY == 8) ? 4 : 1;
 }
 
 // floor(x / 2) for any sign
@@ -204,6 +222,14 @@ __device__ __forceinline__ void tau_strip_body(LevelView<T> L, const T* __restri
   const unsigned xb = ((unsigned)gx + (unsigned)yshift * (unsigned)nx) * (unsigned)sizeof(T);
   const bool xown = xl >= XH && xl < xw - XH && xin;
   const bool xlo = !PER && gxu == 0, xhi = !PER && gxu == nx - 1;
+  // GO: Dirichlet ghosts held in the operands (3-D RKL forms).  xgl / xgr:
+  // the wavefront holds the column just outside the low / high x face;
+  // ylo / yhi: held row indices of the rows just outside the y faces (yg:
+  // either is held)
+  constexpr bool GO = !PER && !GS && !FLAT && !PRO;
+  const bool xgl = GO && __ballot(gxu == -1) != 0ull, xgr = GO && __ballot(gxu == nx) != 0ull;
+  const int ylo = FLAT ? -1 : -1 - y0, yhi = FLAT ? -1 : ny - y0;
+  const bool yg = GO && ((ylo >= 0 && ylo < NU) || (yhi >= 0 && yhi < NU));
   // FLAT: per-segment column byte offsets and bit masks (bit i: segment i)
   unsigned sxb[FLAT ? R : 1];
   unsigned sown = 0, slo = 0, shi = 0, sodd = 0;
@@ -487,7 +513,7 @@ __device__ __forceinline__ void tau_strip_body(LevelView<T> L, const T* __restri
       return ((xm + xp) - (T)2 * c) * L.ihx2 + ((zm + zp) - (T)2 * c) * L.ihz2;
     } else {
       T ym = X[i - 1], yp = X[i + 1];
-      if (!PER) {
+      if (!PER && !GO) {
         const int gyu = y0 + i;
         if (xlo) xm = -c;
         if (xhi) xp = -c;
@@ -498,6 +524,52 @@ __device__ __forceinline__ void tau_strip_body(LevelView<T> L, const T* __restri
       }
       return ((xm + xp) - (T)2 * c) * L.ihx2 + ((ym + yp) - (T)2 * c) * L.ihy2 +
              ((zm + zp) - (T)2 * c) * L.ihz2;
+    }
+  };
+
+  // GO: set the held row / column just outside a face to minus its in-box
+  // neighbour in one plane's rows of an operand; the column only in rows
+  // IA .. IB - 1, those the next stage takes as stencil centres (the other
+  // rows serve as y neighbours of the same column only)
+  auto gfix = [&](T(&Y)[NU], int ia, int ib) {
+    if constexpr (GO) {
+      if (yg) {
+#pragma unroll
+        for (int i = 0; i < NU; ++i) {
+          if (i + 1 < NU && i == ylo) Y[i] = -Y[i + 1];
+          if (i >= 1 && i == yhi) Y[i] = -Y[i - 1];
+        }
+      }
+      if (xgl) {
+#pragma unroll
+        for (int i = 0; i < NU; ++i) {
+          if (i < ia || i >= ib) continue;
+          const T l = wshift<DPP_WAVE_SHL1>(Y[i]);
+          if (gxu == -1) Y[i] = -l;
+        }
+      }
+      if (xgr) {
+#pragma unroll
+        for (int i = 0; i < NU; ++i) {
+          if (i < ia || i >= ib) continue;
+          const T r = wshift<DPP_WAVE_SHR1>(Y[i]);
+          if (gxu == nx) Y[i] = -r;
+        }
+      }
+    }
+  };
+
+  // GO: the plane just outside a z face, before a stage at plane p reads it
+  auto zfix = [&](T(&Zm)[NU], const T(&X)[NU], T(&Zp)[NU], int p) {
+    if constexpr (GO) {
+      if (p == 0) {
+#pragma unroll
+        for (int i = 0; i < NU; ++i) Zm[i] = -X[i];
+      }
+      if (p == nz - 1) {
+#pragma unroll
+        for (int i = 0; i < NU; ++i) Zp[i] = -X[i];
+      }
     }
   };
 
@@ -549,6 +621,11 @@ __device__ __forceinline__ void tau_strip_body(LevelView<T> L, const T* __restri
   exchange(U0, Bq[0], !UZ, false);
   exchange(U1, Bq[0], !UZ, false);
   exchange(U2, Bq[0], !UZ, true);
+  if constexpr (!UZ) {  // a zero input needs no ghosts
+    gfix(U0, A1, NU - A1);
+    gfix(U1, A1, NU - A1);
+    gfix(U2, A1, NU - A1);
+  }
   double r2 = 0.0;
   T YS[NU];  // Y_S of the iteration's output plane, stored after the queues advance
   // RS: pair k of the wavefront covers its held rows HY + 1 + 2k and the
@@ -664,6 +741,7 @@ __device__ __forceinline__ void tau_strip_body(LevelView<T> L, const T* __restri
       const bool on = pin(p) && p >= z0 - (S - 1) - ZE && p <= z1 - 1 + (S - 1) + ZE;
       const bool pown = !RS && p >= z0 && p < z1;
       if (on) {
+        if constexpr (!UZ) zfix(U0, U1, U2, p);
 #pragma unroll
         for (int i = A1; i < NU - A1; ++i) {
           const T res = lap(U0, U1, U2, i, p) - Bq[0][i];
@@ -680,6 +758,7 @@ __device__ __forceinline__ void tau_strip_body(LevelView<T> L, const T* __restri
           if constexpr (S == 1) YS[i] = y;
           else Yq[0][2][i] = y;
         }
+        if constexpr (S > 1) gfix(Yq[0][2], 2 * A1, NU - 2 * A1);
       }
     }
     // stages 2 .. S at planes zl - j + 1, rows A1 j .. NU-1-A1 j
@@ -688,6 +767,7 @@ __device__ __forceinline__ void tau_strip_body(LevelView<T> L, const T* __restri
       const int p = zl - j + 1;
       const bool on = pin(p) && p >= z0 - (S - j) - ZE && p <= z1 - 1 + (S - j) + ZE;
       if (on) {
+        zfix(Yq[j - 2][0], Yq[j - 2][1], Yq[j - 2][2], p);
 #pragma unroll
         for (int i = A1 * j; i < NU - A1 * j; ++i) {
           const T(&Xm)[NU] = Yq[j - 2][0];
@@ -705,6 +785,7 @@ __device__ __forceinline__ void tau_strip_body(LevelView<T> L, const T* __restri
           if (j == S) YS[i] = y;
           else Yq[j - 1][2][i] = y;
         }
+        if (j < S) gfix(Yq[j < S ? j - 1 : 0][2], A1 * (j + 1), NU - A1 * (j + 1));
       }
     }
     // RS: the wavefront's rows of Y_S into the ring; b of the pairs' rows at
@@ -738,7 +819,8 @@ __device__ __forceinline__ void tau_strip_body(LevelView<T> L, const T* __restri
       const bool rok = PER || ((rin >> i) & 1u);
       U0[i] = U1[i];
       U1[i] = U2[i];
-      U2[i] = (UZ || !un_ok || !rok) ? (T)0 : corr(UN[i], zl + 2, i);
+      if constexpr (GO) U2[i] = UZ ? (T)0 : corr(UN[i], zl + 2, i);
+      else U2[i] = (UZ || !un_ok || !rok) ? (T)0 : corr(UN[i], zl + 2, i);
 #pragma unroll
       for (int j = NY - 1; j >= 0; --j) {
         Yq[j][0][i] = Yq[j][1][i];
@@ -746,10 +828,13 @@ __device__ __forceinline__ void tau_strip_body(LevelView<T> L, const T* __restri
       }
 #pragma unroll
       for (int j = S - 1; j > 0; --j) Bq[j][i] = Bq[j - 1][i];
-      Bq[0][i] = (!bn_ok || !rok) ? (T)0 : BN[i];
-      if constexpr (CH) Vc[i] = (!bn_ok || !rok) ? (T)0 : VN[i];
+      // GO: b and v are pointwise: rows and planes outside the box never
+      // reach an in-box cell, so they need no zeroing
+      Bq[0][i] = (GO || (bn_ok && rok)) ? BN[i] : (T)0;
+      if constexpr (CH) Vc[i] = (GO || (bn_ok && rok)) ? VN[i] : (T)0;
     }
     if (more) exchange(U2, Bq[0], !UZ, true);
+    if constexpr (!UZ) gfix(U2, A1, NU - A1);
     // RS: residual of plane zl - S, once the ring holds Y_S up to plane
     // zl - S + 1 (SHY: the exchange's barrier); the slot written next
     // iteration is none of the three it reads

@@ -22,7 +22,7 @@
 namespace rkl {
 
 template <typename T, int S, int R, int WY, bool PER, bool SHY, bool NT>
-__global__ __launch_bounds__(64 * WY) void k_tau_strip_pro(LevelView<T> L, const T* __restrict__ u,
+__global__ __launch_bounds__(64 * WY, (strip_min_waves<T, R, WY>())) void k_tau_strip_pro(LevelView<T> L, const T* __restrict__ u,
                                                            const T* __restrict__ e, const T* __restrict__ b,
                                                            T* __restrict__ out, FCoef<T, S> co, int zc, int gx_tiles,
                                                            int gy_tiles, int nblk, Batch bt,
