@@ -29,6 +29,8 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
        python bench.py --pmc-probe                 (program run under rocprofv3 --pmc)
        python bench.py --summarize-pmc FETCH_DIR WRITE_DIR   (counter summary text)
        python bench.py --summarize-trace TRACE_DIR          (kernel-trace summary text)
+       python bench.py --bc-probe                  (the same tau-step on both boundary types)
+       python bench.py --summarize-bc-pmc DIR [DIR ...]     (its instruction counters)
 """
 from __future__ import annotations
 
@@ -74,6 +76,9 @@ def parse():
     ap.add_argument("--cfg3", action="store_true",
                     help="run only the 512^3 k^-3 random-field comparison (float64 vs mixed); print its JSON")
     ap.add_argument("--summarize-trace-2d", metavar="TRACE_DIR")
+    ap.add_argument("--bc-probe", action="store_true",
+                    help="six 256^3 float64 tau-steps of the stacked two-row strips, periodic then Dirichlet")
+    ap.add_argument("--summarize-bc-pmc", nargs="+", metavar="DIR")
     return ap.parse_args()
 
 
@@ -310,8 +315,85 @@ def pmc_probe():
     print("pmc probe done", flush=True)
 
 
+BC_COUNTERS = ["SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_VMEM_RD SQ_INSTS_LDS SQ_WAVE_CYCLES SQ_WAIT_INST_ANY "
+               "SQ_BUSY_CYCLES SQ_WAVES",
+               "SQ_INSTS_VALU_FMA_F64 SQ_INSTS_VALU_ADD_F64 SQ_INSTS_VALU_MUL_F64 SQ_ACTIVE_INST_VALU "
+               "SQ_INST_CYCLES_VMEM SQ_WAIT_ANY SQ_INSTS_VMEM_WR SQ_ACTIVE_INST_ANY"]
+
+
+def bc_probe():
+    """Six float64 tau-steps (s = 2) of the stacked two-row strips (8
+    wavefronts, 480 workgroups) at 256^3 on a periodic box, then six on a
+    Dirichlet box, from the same random right-hand side."""
+    import numpy as np
+    import torch
+
+    import paper_2306_05332_amd as R
+    R.load_library()
+    rng = np.random.default_rng(1)
+    f = torch.from_numpy(rng.standard_normal((N, N, N))).cuda()
+    for bc in ("periodic", "dirichlet"):
+        R.tune_clear()
+        R.tune_set([{"nx": N, "ny": N, "nz": N, "bc": bc, "prec": "fp64", "s": 2, "variant": "stripyx2x8",
+                     "target": 480}])
+        phi = torch.zeros_like(f)
+        R.smooth(f, phi, (1.0 / N,) * 3, bc, s=2, n_steps=6)
+        torch.cuda.synchronize()
+    R.tune_clear()
+    print("bc probe done", flush=True)
+
+
+def summarize_bc_pmc(dirs):
+    """Per-launch means of the counters that --bc-probe runs collected, for
+    the periodic and the Dirichlet instantiation of the strip kernel."""
+    sums = {}
+    for d in dirs:
+        for path in glob.glob(os.path.join(d, "*counter_collection.csv")):
+            for r in csv.DictReader(open(path)):
+                name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+                if "k_tau_strip_yx" not in name:
+                    continue
+                key = (name, r["Counter_Name"])
+                sums.setdefault(key, {})
+                sums[key][r["Dispatch_Id"]] = sums[key].get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
+    out = ["Instruction counters of the 256^3 float64 stacked two-row strip tau-step, periodic vs Dirichlet box",
+           "commands (from /tmp, TMPDIR=/tmp), one counter set per run:"]
+    for c in BC_COUNTERS:
+        out.append(f"  rocprofv3 --pmc {c} --output-format csv -d <DIR> -o bc -- python3 <repo>/bench.py --bc-probe")
+    out.append("  python3 <repo>/bench.py --summarize-bc-pmc <DIR> [<DIR> ...]")
+    out.append("sources_sha256_16: " + sources_digest())
+    # durations, from a kernel trace of the same program among the directories
+    durs = {}
+    for d in dirs:
+        for path in glob.glob(os.path.join(d, "*kernel_trace.csv")):
+            for r in csv.DictReader(open(path)):
+                name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+                if "k_tau_strip_yx" in name:
+                    durs.setdefault(name, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1000.0)
+    if durs:
+        out.append("  rocprofv3 --kernel-trace --stats --output-format csv -d <DIR> -o bc -- python3 <repo>/bench.py "
+                   "--bc-probe   (durations)")
+    kernels = sorted({k[0] for k in sums} | set(durs))
+    counters = sorted({k[1] for k in sums})
+    for kern in kernels:
+        out.append(f"{kern}  ({'periodic' if ', true, false, false, ' in kern else 'Dirichlet'})")
+        if kern in durs:
+            v = durs[kern]
+            out.append(f"  {'duration_us':24s} {sum(v) / len(v):14.4g}  (mean of {len(v)} launches, "
+                       f"min {min(v):.1f}, max {max(v):.1f})")
+        for c in counters:
+            per = sums.get((kern, c))
+            if per:
+                out.append(f"  {c:24s} {sum(per.values()) / len(per):14.4g}  (mean of {len(per)} launches)")
+    print("\n".join(out))
+
+
 def main():
     args = parse()
+    if args.summarize_bc_pmc:
+        return summarize_bc_pmc(args.summarize_bc_pmc)
+    if args.bc_probe:
+        return bc_probe()
     if args.summarize_pmc:
         return summarize_pmc(*args.summarize_pmc)
     if args.summarize_trace:
