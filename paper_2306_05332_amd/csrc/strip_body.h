@@ -230,6 +230,7 @@ __device__ __forceinline__ void tau_strip_body(LevelView<T> L, const T* __restri
   const bool xgl = GO && __ballot(gxu == -1) != 0ull, xgr = GO && __ballot(gxu == nx) != 0ull;
   const int ylo = FLAT ? -1 : -1 - y0, yhi = FLAT ? -1 : ny - y0;
   const bool yg = GO && ((ylo >= 0 && ylo < NU) || (yhi >= 0 && yhi < NU));
+  const bool gface = yg || xgl || xgr;  // one uniform test for interior wavefronts
   // FLAT: per-segment column byte offsets and bit masks (bit i: segment i)
   unsigned sxb[FLAT ? R : 1];
   unsigned sown = 0, slo = 0, shi = 0, sodd = 0;
@@ -533,6 +534,7 @@ __device__ __forceinline__ void tau_strip_body(LevelView<T> L, const T* __restri
   // rows serve as y neighbours of the same column only)
   auto gfix = [&](T(&Y)[NU], int ia, int ib) {
     if constexpr (GO) {
+      if (!gface) return;
       if (yg) {
 #pragma unroll
         for (int i = 0; i < NU; ++i) {
@@ -560,8 +562,11 @@ __device__ __forceinline__ void tau_strip_body(LevelView<T> L, const T* __restri
   };
 
   // GO: the plane just outside a z face, before a stage at plane p reads it
+  // (zface: the chunk's stages can reach a z face)
+  const bool zface = GO && (z0 <= S + 1 || z1 + S + 1 >= nz);
   auto zfix = [&](T(&Zm)[NU], const T(&X)[NU], T(&Zp)[NU], int p) {
     if constexpr (GO) {
+      if (!zface) return;
       if (p == 0) {
 #pragma unroll
         for (int i = 0; i < NU; ++i) Zm[i] = -X[i];
