@@ -142,7 +142,7 @@ def test_fused_prolongation_vcycle_f32_matches_oracle(variant, bc, s):
 @pytest.mark.parametrize("s", [1, 2, 3])
 @pytest.mark.parametrize("n_pre", [1, 2])
 def test_fused_restriction_vcycle_matches_oracle(variant, bc, s, n_pre):
-    """Restriction fusion alone (fuse = 2) and with the prolongation fusion
+    """Each fusion alone (fuse = 1: prolongation, 2: restriction) and both
     (fuse = 3), float64: with n_pre = 1 only the finest level's single
     relaxation carries the restriction (a coarse level's only relaxation is
     the one from zero), with n_pre = 2 every level above the tail."""
@@ -154,7 +154,7 @@ def test_fused_restriction_vcycle_matches_oracle(variant, bc, s, n_pre):
     _force(R, variant, s, bc, "fp64")
     print(f"fp64 {variant} {bc} s={s} n_pre={n_pre}", flush=True)
     want = _oracle(bc, s, 1, "float64", n_pre)
-    for fuse in (2, 3):
+    for fuse in (1, 2, 3):
         got = _run(R, bc, s, 1, fuse, np.float64, n_pre)
         assert relmax(got, want) < TOL64, fuse
 
@@ -169,7 +169,7 @@ def test_fused_restriction_vcycle_f32_matches_oracle(variant, bc, s):
     _force(R, variant, s, bc, "mixed")
     print(f"fp32 {variant} {bc} s={s}", flush=True)
     want = _oracle(bc, s, 1, "float32")
-    for fuse in (2, 3):
+    for fuse in (1, 2, 3):
         got = _run(R, bc, s, 1, fuse, np.float32)
         assert relmax(got, want) < TOL32, fuse
 
