@@ -412,7 +412,22 @@ __global__ __launch_bounds__(EW_NT) void k_sub_mean_part(T* __restrict__ a, size
   if (threadIdx.x == 0) mean = t / count;
   __syncthreads();
   const T m = (T)mean;
-  for (size_t i = (size_t)blockIdx.x * EW_NT + threadIdx.x; i < n; i += (size_t)gridDim.x * EW_NT) a[i] -= m;
+  // eight elements per thread in flight at once (a loop of dependent
+  // load-subtract-store steps would wait out the memory latency each time)
+  const size_t gs = (size_t)gridDim.x * EW_NT;
+  for (size_t i0 = (size_t)blockIdx.x * EW_NT + threadIdx.x; i0 < n; i0 += 8 * gs) {
+    T v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const size_t i = i0 + k * gs;
+      v[k] = i < n ? a[i] : (T)0;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const size_t i = i0 + k * gs;
+      if (i < n) a[i] = v[k] - m;
+    }
+  }
 }
 
 template <typename T>
