@@ -837,19 +837,16 @@ bool launch_fused_tau_pro(const LevelView<T>& L, const T* u, const T* e, const T
     return false;
   if ((L.nx | L.ny | L.nz) & 1) return false;
   FusedChoice c = fused_choice<T>(L, s);
-  // The five-row strip (odd R) has no fused form: in float64 its levels
-  // (128^3 and below in the tuned table) keep the separate prolongation,
-  // which measured faster there than the fused stacked strips (128^3: 26 us
-  // against 33 us); in float32 they take the fused four-row strips (measured
-  // faster than the separate pass).  The float64 eight-row forms run out of
-  // registers with the fusion (one wavefront per SIMD): those levels take the
-  // stacked two-row strips, the leanest fused form.
+  // The five-row strip (odd R) has no fused form: its levels (128^3 and
+  // below in the tuned table) take the fused four-row strips, measured faster
+  // than the separate prolongation in both precisions once the grid is sized
+  // from occupancy (float64 256^3 solve 6.07 ms against 6.15; the stacked
+  // two-row strips gave no gain there).  The float64 eight-row forms run out
+  // of registers with the fusion (one wavefront per SIMD): those levels take
+  // the stacked two-row strips, the leanest fused form.
   // A level that takes another form than its tuned variant sizes the grid
   // from that form's occupancy (target 0), not from the tuned target.
-  if (c.variant == FV_STRIP_5x1) {
-    if (sizeof(T) == 8) return false;
-    c = FusedChoice{FV_STRIP_4x4, 0};
-  }
+  if (c.variant == FV_STRIP_5x1) c = FusedChoice{FV_STRIP_4x4, 0};
   const bool dbl8 = sizeof(T) == 8 && (c.variant == FV_STRIP_8x4 || c.variant == FV_STRIP_8x1 ||
                                        c.variant == FV_STRIPYX_8x4 || c.variant == FV_STRIPYX_8x8);
   if (dbl8) c = FusedChoice{s <= 2 ? FV_STRIPYX_2x8 : FV_STRIP_4x4, 0};
