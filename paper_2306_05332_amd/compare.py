@@ -34,9 +34,10 @@ def run(n=128, tol_max=1e-10, methods=("rkl", "sor", "gsrb"), check_every=None, 
     out = []
     for m in methods:
         ce = check_every or (1 if m == "rkl" else 20)
-        # warm-up: plans and kernels
-        _lib.relax_solve(f, p.h, "dirichlet", m, faces=faces, tol_max=tol_max, max_iters=2, check_every=1,
-                         raise_on_error=False)
+        # warm-up: one whole solve, so that plans, kernels and every tau-step
+        # length of the schedule have run once before the timed one
+        _lib.relax_solve(f, p.h, "dirichlet", m, faces=faces, tol_max=tol_max, max_iters=max_iters,
+                         check_every=ce, history_cap=8, raise_on_error=False)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         phi, st = _lib.relax_solve(f, p.h, "dirichlet", m, faces=faces, tol_max=tol_max, max_iters=max_iters,

@@ -241,6 +241,8 @@ RKL_GSRB_INST(double, 8, 4, false)
 RKL_GSRB_INST(double, 4, 4, false)
 RKL_GSRB_INST(float, 8, 4, false)
 RKL_GSRB_INST(float, 4, 4, false)
+RKL_GSRB_INST(double, 5, 1, false)
+RKL_GSRB_INST(float, 5, 1, false)
 RKL_GSRB_INST(double, 8, 1, true)
 RKL_GSRB_INST(double, 4, 1, true)
 RKL_GSRB_INST(float, 8, 1, true)

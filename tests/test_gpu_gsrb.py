@@ -65,6 +65,36 @@ def test_gsrb_passes_match_oracle(shape, bc, omega):
     assert relmax(phi.cpu().numpy(), want) < 1e-12
 
 
+@pytest.mark.parametrize("variant", ["strip5x1", "strip4x4", "strip8x4"])
+@pytest.mark.parametrize("shape", [(20, 11, 130), (40, 24, 64), (11, 100, 136), (9, 60, 20)])
+@pytest.mark.parametrize("bc", ["periodic", "dirichlet"])
+def test_gsrb_passes_forced_strip_match_oracle(variant, shape, bc):
+    """The one-pass GS-RB / SOR kernel in each strip shape it takes from the
+    level's tuned tile (the five-row strips, whose interior strips pack their
+    x remainders into shared wavefronts at nx = 136, and the 4 x 4 and 8 x 4
+    strips), against the oracle's sweeps."""
+    R = _lib()
+    nz, ny, nx = shape
+    target = 128 if (nx + ny) % 2 else 2048
+    try:
+        R.tune_set([{"nx": nx, "ny": ny, "nz": nz, "bc": bc, "prec": "fp64", "s": 2, "variant": variant,
+                     "target": target}])
+        rng = np.random.default_rng(41)
+        h = (0.11, 0.07, 0.13)
+        u0 = rng.standard_normal(shape)
+        f = rng.standard_normal(shape) * 50
+        want = u0
+        for _ in range(3):
+            want = osm.gsrb_sweep(want, f, h, bc, None, 1.6)
+        print(f"variant={variant} target={target} shape={shape} bc={bc}", flush=True)
+        phi = cu(u0)
+        R.gsrb_smooth(cu(f), phi, h, bc, omega=1.6, n_iter=3)
+        assert relmax(phi.cpu().numpy(), want) < 1e-12
+    finally:
+        R.tune_clear()
+        R.install_default_tuning()
+
+
 def _problem(which):
     if which == "sphere32":
         return W.uniform_sphere(32)
