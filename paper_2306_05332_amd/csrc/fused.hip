@@ -873,6 +873,10 @@ static int launch_rs_S(const LevelView<T>& L, int variant, int target, const T* 
     if constexpr (sizeof(T) == 4) {
       if (variant == FV_STRIP_4x4)
         return launch_strip_rs<T, S, 4, 4, false>(L, target, u, b, out, bc, fc, part, stop, bt, st);
+      if constexpr (S <= 2) {
+        if (variant == FV_STRIPYX_8x4)
+          return launch_strip_rs<T, S, 8, 4, true>(L, target, u, b, out, bc, fc, part, stop, bt, st);
+      }
     }
     return 0;
   }
@@ -889,16 +893,21 @@ int launch_fused_tau_rs(const LevelView<T>& L, const T* u, const T* b, T* out, T
   if (!is_strip(c.variant) || c.target < 1) return 0;
   // Forms built (s >= 2): the stacked two-row strips (eight wavefronts that
   // share their y halos; s = 2), every float64 level; in float32 also the
-  // four-row strips of four wavefronts (s = 2, 3), which the levels below
-  // 192^3 take unless tuned for the stacked strips.  Measured on gfx950 at
-  // 256^3 (fused pass against tau-step + separate residual pass): float64
-  // 134 us against 92 + 65 us; float32 77 (stacked) or 83 (four-row)
-  // against 43 + 40 us; at 128^3, 26 against 16 + 15 us (float64).  (A
-  // float64 four-row form needs 165 VGPRs, three wavefronts per SIMD.)
+  // stacked eight-row strips (four wavefronts; s = 2), which levels of 192^3
+  // and more and levels tuned for them take, and the four-row strips of four
+  // wavefronts (s = 2, 3) for the other levels not tuned for the two-row
+  // stacked strips.  Measured on gfx950 at 256^3 (fused pass against
+  // tau-step + separate residual pass): float64 134 us against 92 + 65 us;
+  // float32 77 (stacked two-row) or 83 (four-row) against 43 + 40 us; at
+  // 128^3, 26 against 16 + 15 us (float64).  Float32 mixed solves with the
+  // stacked eight-row form instead of the two-row one: 256^3 5.24 against
+  // 5.35 ms, 512^3 32.6 against 33.0 ms.  (A float64 four-row form needs 165
+  // VGPRs, three wavefronts per SIMD.)
   const bool big = (size_t)L.nx * L.ny * L.nz >= ((size_t)192 * 192 * 192);
   if (sizeof(T) == 8) c.variant = FV_STRIPYX_2x8;
-  else if (c.variant != FV_STRIPYX_2x8) c.variant = big ? FV_STRIPYX_2x8 : FV_STRIP_4x4;
-  if (c.variant == FV_STRIPYX_2x8 && s > 2) c.variant = FV_STRIP_4x4;
+  else if (c.variant != FV_STRIPYX_2x8)
+    c.variant = (big || c.variant == FV_STRIPYX_8x4) ? FV_STRIPYX_8x4 : FV_STRIP_4x4;
+  if ((c.variant == FV_STRIPYX_2x8 || c.variant == FV_STRIPYX_8x4) && s > 2) c.variant = FV_STRIP_4x4;
   switch (s) {
     case 1: return launch_rs_S<T, 1>(L, c.variant, c.target, u, b, out, bc, co, part, stop, bt, st);
     case 2: return launch_rs_S<T, 2>(L, c.variant, c.target, u, b, out, bc, co, part, stop, bt, st);

@@ -89,6 +89,7 @@ RKL_STRIP_RS_INST(double, 2, 2, 8, true)
 RKL_STRIP_RS_INST(float, 2, 4, 4, false)
 RKL_STRIP_RS_INST(float, 3, 4, 4, false)
 RKL_STRIP_RS_INST(float, 2, 2, 8, true)
+RKL_STRIP_RS_INST(float, 2, 8, 4, true)
 #undef RKL_STRIP_RS_INST
 
 }  // namespace rkl
