@@ -2,6 +2,8 @@
 // convergence loop over float64 V-cycles (Sec. 2.1, Sec. 4.1 stop metric)
 // and the mixed-precision defect correction.
 
+#include <limits>
+
 #include "solver_core.h"
 
 namespace rkl {
@@ -90,10 +92,18 @@ void fill_stats(rkl_stats* stats, const ConvState& cs, int result_m) {
 }
 
 // ------------------------------------------------------------------ solves
+// pinned host slot of the deferred ||f0||^2 (no other read-back writes it)
+constexpr int RES0_HOST = 15;
+
 // Common start: f0, ||M 0 - f0||.  Returns false when the solve is already
 // decided (zero right-hand side or non-finite data); `status` says how.
+// With `defer` the host does not wait for ||f0||: the value is copied into a
+// pinned slot in stream order and the caller queues its first cycles at once
+// (their device-side check stops at once on a zero or non-finite ||f0||),
+// then settles those two cases with solve_start_settle after the loop's first
+// synchronisation.
 bool solve_start(Plan& P, const rkl_opts& o, const double* rho, const double* faces, double* phi,
-                 rkl_stats* stats, hipStream_t st, double& res0, rkl_status& status) {
+                 rkl_stats* stats, hipStream_t st, double& res0, rkl_status& status, bool defer = false) {
   const Lev& F = P.lv[0];
   const LevelView<double> V0 = view<double>(F, P.periodic, nullptr);
   prepare_source(P, rho, o.four_pi_G, st);
@@ -106,18 +116,44 @@ bool solve_start(Plan& P, const rkl_opts& o, const double* rho, const double* fa
     check_launch();
   }
   conv_reset(P, st);  // issued before the read-back so that it is done when the loop starts
-  res0 = std::sqrt(readback(P, 1, st, RES0SQ_SLOT)[0]);
+  status = RKL_OK;
   if (stats) {
-    stats->res0 = res0;
     stats->levels = P.L();
     stats->cycles = 0;
     stats->rel_res = 0.0;
   }
-  status = RKL_OK;
+  if (defer) {
+    HIPCHK(hipMemcpyAsync(P.hscal + RES0_HOST, P.dscal + RES0SQ_SLOT, sizeof(double), hipMemcpyDeviceToHost, st));
+    res0 = std::numeric_limits<double>::quiet_NaN();
+    return true;
+  }
+  res0 = std::sqrt(readback(P, 1, st, RES0SQ_SLOT)[0]);
+  if (stats) stats->res0 = res0;
   if (res0 == 0.0) {
     launch_fill<double>(phi, F.n, 0.0, nullptr, st);
     check_launch();
     HIPCHK(hipStreamSynchronize(st));
+    return false;
+  }
+  if (!std::isfinite(res0)) {
+    g_err = "non-finite source or boundary data";
+    status = RKL_ENONFINITE;
+    return false;
+  }
+  return true;
+}
+
+// The deferred half of solve_start, after a synchronisation of the stream
+// that followed its copy: false when the solve is decided as solve_start
+// would have decided it (phi = 0 for a zero right-hand side).
+bool solve_start_settle(Plan& P, double* phi, rkl_stats* stats, hipStream_t st, rkl_status& status) {
+  const double res0 = std::sqrt(P.hscal[RES0_HOST]);
+  if (stats) stats->res0 = res0;
+  if (res0 == 0.0) {
+    launch_fill<double>(phi, P.lv[0].n, 0.0, nullptr, st);
+    check_launch();
+    HIPCHK(hipStreamSynchronize(st));
+    status = RKL_OK;
     return false;
   }
   if (!std::isfinite(res0)) {
@@ -148,7 +184,7 @@ rkl_status solve_fp64(Plan& P, const rkl_opts& o, const double* rho, const doubl
   const LevelView<double> V0 = view<double>(F, P.periodic, nullptr);  // face data folded into f0
   double res0;
   rkl_status status;
-  if (!solve_start(P, o, rho, faces, phi, stats, st, res0, status)) return status;
+  if (!solve_start(P, o, rho, faces, phi, stats, st, res0, status, P.L() > 1)) return status;
 
   if (P.L() == 1) {
     // single level: accelerated RKL iteration (App. A.4, App. B) to tol
@@ -248,6 +284,7 @@ rkl_status solve_fp64(Plan& P, const rkl_opts& o, const double* rho, const doubl
     if (cs.stop) break;
     if (queued > o.max_cycles) fail(RKL_EHIP, "convergence loop ended without a decision");
   }
+  if (!solve_start_settle(P, phi, stats, st, status)) return status;
   const int rm = cs.result_m;
   double* res = bufs[start[rm]];
   if (P.periodic && res != phi) {  // phi = res - mean(res): the copy carries the mean removal
@@ -271,7 +308,7 @@ rkl_status solve_mixed(Plan& P, const rkl_opts& o, const double* rho, const doub
   const LevelView<float> V32 = view<float>(F, P.periodic, nullptr);
   double res0;
   rkl_status status;
-  if (!solve_start(P, o, rho, faces, phi, stats, st, res0, status)) return status;
+  if (!solve_start(P, o, rho, faces, phi, stats, st, res0, status, true)) return status;
   const int* stop = &P.dconv->stop;  // the state was reset by solve_start
   const int nblk = (int)resid_blocks(F.nx, F.ny, F.nz);
   int queued = 0;
@@ -305,6 +342,7 @@ rkl_status solve_mixed(Plan& P, const rkl_opts& o, const double* rho, const doub
     if (cs.stop) break;
     if (queued > o.max_cycles) fail(RKL_EHIP, "refinement loop ended without a decision");
   }
+  if (!solve_start_settle(P, phi, stats, st, status)) return status;
   if (P.periodic) remove_mean<double>(P, phi, F.n, nullptr, st);
   HIPCHK(hipStreamSynchronize(st));
   fill_stats(stats, cs, cs.result_m);

@@ -211,12 +211,17 @@ def test_status_codes_on_gpu():
     assert st.status == -3 and st.cycles == 1
     bad = p.rho.copy()
     bad[3, 4, 5] = np.nan
-    _, st = R.solve(cu(bad), p.h, "periodic", raise_on_error=False)
-    assert st.status == -5
+    # multi-level solves learn ||f|| after their first cycles are queued: a
+    # zero or non-finite one still decides the solve as before (phi = 0, or
+    # the non-finite status), in both precisions and from a warm start
+    for prec in ("fp64", "mixed"):
+        _, st = R.solve(cu(bad), p.h, "periodic", opts=R.Options(prec=prec), raise_on_error=False)
+        assert st.status == -5 and st.cycles == 0
+        for phi0 in (None, rho * 0.5):
+            phi, st = R.solve(torch.zeros_like(rho), p.h, "periodic", phi0=phi0, opts=R.Options(prec=prec))
+            assert st.status == 0 and st.cycles == 0 and st.res0 == 0.0 and float(phi.abs().max()) == 0.0
     _, st = R.solve(rho, p.h, "periodic", opts=R.Options(tau_frac=1.05, max_cycles=50), raise_on_error=False)
     assert st.status == -4
-    phi, st = R.solve(torch.zeros_like(rho), p.h, "periodic")
-    assert st.status == 0 and float(phi.abs().max()) == 0.0
     with pytest.raises(R.RKLError):
         R.solve(rho, p.h, "periodic", opts=R.Options(s=-1))
 
