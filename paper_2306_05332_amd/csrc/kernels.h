@@ -33,6 +33,10 @@ void launch_stage(const LevelView<T>& L, const T* yp, const T* ypp, const T* b, 
 template <typename TU, typename TR>
 void launch_residual(const LevelView<TU>& L, const TU* u, const TU* b, TR* r_out, double* part,
                      const int* stop, hipStream_t st, const Batch& bt = single_batch());
+// u_out = u + e and r_out = b - M u_out in one pass (float64 u, float32 e;
+// 3-D levels, one grid, u_out distinct from u); part as launch_residual
+void launch_residual_add(const LevelView<double>& L, const double* u, const float* e, const double* b,
+                         double* u_out, float* r_out, double* part, const int* stop, hipStream_t st);
 template <typename T>
 void launch_resid_restrict(const LevelView<T>& F, const T* u, const T* b, T* bc, double* part,
                            const int* stop, hipStream_t st, const Batch& bt = single_batch());

@@ -95,6 +95,12 @@ void fill_stats(rkl_stats* stats, const ConvState& cs, int result_m) {
 // pinned host slot of the deferred ||f0||^2 (no other read-back writes it)
 constexpr int RES0_HOST = 15;
 
+// The mixed path folds its float64 update into the next defect pass when phi
+// (8 bytes a cell) and e (4) overflow the 256 MB last-level cache.
+// Measured on gfx950: 512^3 defect + update 553 + 550 us per outer iteration
+// apart; at 256^3, where they fit, the fold saved nothing.
+constexpr size_t MIXED_FOLD_MIN_BYTES = (size_t)256 << 20;
+
 // Common start: f0, ||M 0 - f0||.  Returns false when the solve is already
 // decided (zero right-hand side or non-finite data); `status` says how.
 // With `defer` the host does not wait for ||f0||: the value is copied into a
@@ -311,13 +317,24 @@ rkl_status solve_mixed(Plan& P, const rkl_opts& o, const double* rho, const doub
   if (!solve_start(P, o, rho, faces, phi, stats, st, res0, status, true)) return status;
   const int* stop = &P.dconv->stop;  // the state was reset by solve_start
   const int nblk = (int)resid_blocks(F.nx, F.ny, F.nz);
+  // When phi and e together overflow the last-level cache, the update
+  // phi += e of an iteration is folded into the next iteration's defect pass
+  // (launch_residual_add), which writes the updated phi into the other one
+  // of ph[]: state k lives in ph[k & 1].  Below that size the separate update
+  // re-reads phi and e from the cache and the fold saves nothing.
+  const bool fold = F.nz > 1 && 12.0 * (double)F.n > (double)MIXED_FOLD_MIN_BYTES;
+  double* ph[2] = {phi, P.t0};
+  const float* eprev = nullptr;  // the last queued iteration's correction (fold)
   int queued = 0;
   ConvState cs = *P.hconv;  // as reset
   while (true) {
     const int batch = predict_batch(cs, o.tol, queued, o.max_cycles);
     for (int q = 0; q < batch; ++q) {
       // float64 defect r = f - M phi, stored as the float32 right-hand side
-      launch_residual<double, float>(V0, phi, P.f0, P.h32.b[0], P.part, stop, st);
+      if (fold && queued > 0)
+        launch_residual_add(V0, ph[(queued - 1) & 1], eprev, P.f0, ph[queued & 1], P.h32.b[0], P.part, stop, st);
+      else
+        launch_residual<double, float>(V0, phi, P.f0, P.h32.b[0], P.part, stop, st);
       launch_check(P.part, nblk, 2, Res0Sqrt::ptr(P), o.tol, o.max_cycles, (double)F.n, P.dconv, st);
       check_launch();
       // periodic: the defect of the mean-free f sums to zero up to rounding
@@ -334,7 +351,8 @@ rkl_status solve_mixed(Plan& P, const rkl_opts& o, const double* rho, const doub
         launch_fill<float>(cur, F.n, 0.0f, stop, st);
       }
       vcycle_from<float>(P, P.h32, cur, alt, P.h32.b[0], nullptr, pre_done, o, stop, st, VBatch{1, 0, 0, P.dscal});
-      launch_add_cast<float>(phi, cur, F.n, stop, st);
+      if (fold) eprev = cur;  // read by the next iteration's defect pass, before its V-cycle runs
+      else launch_add_cast<float>(phi, cur, F.n, stop, st);
       check_launch();
       ++queued;
     }
@@ -343,7 +361,17 @@ rkl_status solve_mixed(Plan& P, const rkl_opts& o, const double* rho, const doub
     if (queued > o.max_cycles) fail(RKL_EHIP, "refinement loop ended without a decision");
   }
   if (!solve_start_settle(P, phi, stats, st, status)) return status;
-  if (P.periodic) remove_mean<double>(P, phi, F.n, nullptr, st);
+  double* ans = fold ? ph[cs.result_m & 1] : phi;  // the tested state
+  if (P.periodic && ans != phi) {  // phi = ans - mean(ans): the copy carries the mean removal
+    launch_sum<double>(ans, F.n, P.part, st);
+    launch_reduce(P.part, (int)ew_block_count(F.n), 1, 1, P.dscal + 8, nullptr, st);
+    launch_copy_sub_mean(phi, ans, F.n, P.dscal + 8, (double)F.n, st);
+    check_launch();
+  } else if (ans != phi) {
+    copy_d2d(phi, ans, F.n, st);
+  } else if (P.periodic) {
+    remove_mean<double>(P, phi, F.n, nullptr, st);
+  }
   HIPCHK(hipStreamSynchronize(st));
   fill_stats(stats, cs, cs.result_m);
   return finish_status(cs);

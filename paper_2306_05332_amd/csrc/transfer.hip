@@ -2,6 +2,11 @@
 //
 //   k_resid_tile<.., false>  r = b - M u (Sec. 2.1 eq. residual, opposite sign)
 //                            with float64 partial sums of r^2 and r
+//   k_resid_tile<.., false, true>  the same for u' = u + e (e float32), which
+//                            it also writes: the mixed path's update of the
+//                            float64 iterate folded into the next defect
+//                            (Sec. 2.2.3), 32 bytes a cell against 20 + 20
+//                            for the update and the defect apart
 //   k_resid_tile<.., true>   b_{l+1} = R(b_l - M_l u_l): the 8-child average of
 //                            eq. restriction_example_3D applied to the residual
 //                            (Sec. 2.1 steps 2a/2b), with float64 partials of
@@ -24,6 +29,7 @@
 // planes of the tile's coarse footprint in LDS.  The next planes are loaded
 // into registers while the current ones are processed, so each HBM word is
 // read once per tile (halos come from L2).
+#include "host_common.h"
 #include "kernels.h"
 
 namespace rkl {
@@ -41,15 +47,21 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblk) {
   return bid;
 }
 
-template <typename TU, typename TR, bool RESTRICT>
+template <typename TU, typename TR, bool RESTRICT, bool ADD = false>
 __global__ __launch_bounds__(RNT) void k_resid_tile(LevelView<TU> F, const TU* __restrict__ u,
                                                     const TU* __restrict__ b, TR* __restrict__ out,
                                                     int kc, int gx_tiles, int gy_tiles, int nblk,
                                                     double* __restrict__ part, Batch bt,
-                                                    const int* __restrict__ stop) {
+                                                    const int* __restrict__ stop, const float* __restrict__ e,
+                                                    TU* __restrict__ unew) {
+  static_assert(!ADD || !RESTRICT, "the update is folded into the plain defect only");
   {
     const long long mb = blockIdx.y;
     if (u != nullptr) u += mb * bt.s0;
+    if (ADD) {
+      e += mb * bt.s0;
+      unew += mb * bt.s0;
+    }
     b += mb * bt.s0;
     if (out != nullptr) out += mb * (RESTRICT ? bt.s1 : bt.s0);
     part += mb * bt.part_stride;
@@ -107,7 +119,10 @@ __global__ __launch_bounds__(RNT) void k_resid_tile(LevelView<TU> F, const TU* _
     const bool ok = u != nullptr && plane_ok(p) && (per || p < nz);
     const size_t zo = ok ? (size_t)zw(p) * sxy : 0;
 #pragma unroll
-    for (int q = 0; q < RNU; ++q) dst[q] = (ok && goff[q] >= 0) ? u[zo + goff[q]] : (TU)0;
+    for (int q = 0; q < RNU; ++q) {
+      dst[q] = (ok && goff[q] >= 0) ? u[zo + goff[q]] : (TU)0;
+      if (ADD && ok && goff[q] >= 0) dst[q] += (TU)e[zo + goff[q]];
+    }
   };
   auto load_b = [&](int p, TU (&dst)[RNI]) {
     const bool ok = p >= 0 && p < nz;
@@ -193,6 +208,12 @@ __global__ __launch_bounds__(RNT) void k_resid_tile(LevelView<TU> F, const TU* _
             if (out != nullptr) {
               out[(size_t)p0 * sxy + (size_t)igy[q] * nx + igx[q]] = (TR)r0;
               if (has1) out[(size_t)p1 * sxy + (size_t)igy[q] * nx + igx[q]] = (TR)r1;
+            }
+            if (ADD) {  // u' of the cell, as the ring holds it
+              const int idx = tid + q * RNT;
+              const int o = (idx / RBX + 1) * RW + (idx % RBX + 1);
+              unew[(size_t)p0 * sxy + (size_t)igy[q] * nx + igx[q]] = ring[rslot(p0)][o];
+              if (has1) unew[(size_t)p1 * sxy + (size_t)igy[q] * nx + igx[q]] = ring[rslot(p1)][o];
             }
           }
         }
@@ -642,7 +663,17 @@ void launch_residual(const LevelView<TU>& L, const TU* u, const TU* b, TR* r_out
   }
   const TileGrid g = resid_grid(L.nx, L.ny, L.nz);
   hipLaunchKernelGGL((k_resid_tile<TU, TR, false>), dim3(g.nblk, bt.nb), dim3(RNT), 0, st, L, u, b, r_out,
-                     g.kc, g.gx, g.gy, g.nblk, part, bt, stop);
+                     g.kc, g.gx, g.gy, g.nblk, part, bt, stop, (const float*)nullptr, (TU*)nullptr);
+}
+
+void launch_residual_add(const LevelView<double>& L, const double* u, const float* e, const double* b,
+                         double* u_out, float* r_out, double* part, const int* stop, hipStream_t st) {
+  if (L.nz == 1) fail(RKL_EINVAL, "the folded update is built for 3-D levels");
+  if (u == nullptr || e == nullptr || u_out == nullptr || u_out == u) fail(RKL_EINVAL, "folded update: bad buffers");
+  const TileGrid g = resid_grid(L.nx, L.ny, L.nz);
+  const Batch bt = single_batch();
+  hipLaunchKernelGGL((k_resid_tile<double, float, false, true>), dim3(g.nblk, 1), dim3(RNT), 0, st, L, u, b, r_out,
+                     g.kc, g.gx, g.gy, g.nblk, part, bt, stop, e, u_out);
 }
 
 template <typename T>
@@ -656,7 +687,7 @@ void launch_resid_restrict(const LevelView<T>& F, const T* u, const T* b, T* bc,
   }
   const TileGrid g = resid_grid(F.nx, F.ny, F.nz);
   hipLaunchKernelGGL((k_resid_tile<T, T, true>), dim3(g.nblk, bt.nb), dim3(RNT), 0, st, F, u, b, bc, g.kc,
-                     g.gx, g.gy, g.nblk, part, bt, stop);
+                     g.gx, g.gy, g.nblk, part, bt, stop, (const float*)nullptr, (T*)nullptr);
 }
 
 template <typename T>
