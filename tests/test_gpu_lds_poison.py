@@ -1,7 +1,8 @@
 """LDS-poison debug build: the parity cases of every kernel that uses LDS
 (LDS-ring and z-queue tau-steps, the stacked-strip halo exchange, the
-residual / restriction and prolongation tiles, the coarsest-level solvers,
-the one-workgroup coarse tail, the 2-D transfers) rerun against
+residual / restriction and prolongation tiles, the folded mixed update,
+the GS-RB passes, the coarsest-level solvers, the one-workgroup coarse tail,
+the 2-D transfers) rerun against
 ``librklpoisson_ldspoison.so``, whose kernels fill their floating-point LDS
 arrays with NaN on entry.  A read of an LDS element that no thread of the
 launch wrote then turns results into NaN and the oracle comparison fails.
@@ -25,6 +26,8 @@ CASES = [
     "tests/test_gpu_fusion.py",
     "tests/test_gpu_2d.py",
     "tests/test_gpu_f32.py",
+    "tests/test_gpu_gsrb.py",
+    "tests/test_gpu_mixed_fold.py",
 ]
 
 
