@@ -76,6 +76,8 @@ def parse():
     ap.add_argument("--cfg3", action="store_true",
                     help="run only the 512^3 k^-3 random-field comparison (float64 vs mixed); print its JSON")
     ap.add_argument("--summarize-trace-2d", metavar="TRACE_DIR")
+    ap.add_argument("--summarize-trace-cfg3", metavar="TRACE_DIR",
+                    help="per-solve kernel times of a kernel trace of the --cfg3 run")
     ap.add_argument("--bc-probe", action="store_true",
                     help="six 256^3 float64 tau-steps of the stacked two-row strips, periodic then Dirichlet")
     ap.add_argument("--summarize-bc-pmc", nargs="+", metavar="DIR")
@@ -256,6 +258,48 @@ def summarize_trace(d):
     print("\n".join(out))
 
 
+def summarize_trace_cfg3(d, top=10):
+    """Kernel trace of the --cfg3 run: per-solve kernel times of its four
+    cases (512^3 random field float64 / mixed, then 256^3 blobs float64 /
+    mixed, four solves each, the first of each case untimed).  A solve's
+    window opens at its source scaling pass (k_scale); the second and third
+    solves of a case are averaged (the fourth is followed by the copy of phi
+    to the host and the next case's set-up).  Kernels are grouped by name."""
+    trace = sorted(_rows(_find(d, "kernel_trace.csv")), key=lambda r: int(r["Start_Timestamp"]))
+    starts = [i for i, r in enumerate(trace) if "k_scale(" in r["Kernel_Name"]]
+    cases = ["512^3 k^-3 random field, float64", "512^3 k^-3 random field, mixed",
+             "256^3 blobs, float64", "256^3 blobs, mixed"]
+    out = ["Kernel trace of the 512^3 / 256^3 mixed-against-float64 comparison (bench.py --cfg3)",
+           "command (from /tmp, TMPDIR=/tmp):",
+           "  rocprofv3 --kernel-trace --output-format csv -d <DIR> -o cfg3 -- python3 <repo>/bench.py --cfg3",
+           "  python3 <repo>/bench.py --summarize-trace-cfg3 <DIR>",
+           f"solves found: {len(starts)} (expected 16: four cases of one untimed and three timed solves)",
+           "per case: the mean of its second and third solves"]
+    bounds = starts + [len(trace)]
+    for c, label in enumerate(cases):
+        solves = [4 * c + 1, 4 * c + 2]
+        if solves[-1] + 1 >= len(bounds):
+            break
+        tot, calls = {}, {}
+        span = 0.0
+        for k in solves:
+            rows = trace[bounds[k]:bounds[k + 1]]
+            span += (int(rows[-1]["End_Timestamp"]) - int(rows[0]["Start_Timestamp"])) / 1e3
+            for r in rows:
+                name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+                dur = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+                tot[name] = tot.get(name, 0.0) + dur
+                calls[name] = calls.get(name, 0) + 1
+        ns = len(solves)
+        busy = sum(tot.values()) / ns
+        out += ["", f"{label}: {span / ns / 1e3:.2f} ms per solve from its first kernel to its last "
+                f"(kernels busy {busy / 1e3:.2f} ms)",
+                f"  {'us/solve':>9} {'calls':>6} {'avg_us':>8}  name"]
+        for name, t in sorted(tot.items(), key=lambda kv: -kv[1])[:top]:
+            out.append(f"  {t / ns:>9.1f} {calls[name] / ns:>6.1f} {t / calls[name]:>8.1f}  {name}")
+    print("\n".join(out))
+
+
 TWO_D_KERNEL = "rkl::k_tau_strip<double, 4, 4, 1, true, false, false, true, "
 
 
@@ -400,6 +444,8 @@ def main():
         return summarize_trace(args.summarize_trace)
     if args.summarize_trace_2d:
         return summarize_trace_2d(args.summarize_trace_2d)
+    if args.summarize_trace_cfg3:
+        return summarize_trace_cfg3(args.summarize_trace_cfg3)
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (this solver's path is single-GPU); got --gpus {args.gpus}",
               file=sys.stderr)
