@@ -104,6 +104,10 @@ typedef struct {
                          /* tau-step also writes the restricted residual (steps 2a-2b).         */
                          /* 3 (default): both; 0: separate transfer kernels; other values:      */
                          /* RKL_EINVAL                                                          */
+    int zero_start;      /* rkl_poisson_solve: 1 starts from phi = 0 whatever phi holds on      */
+                         /* entry (a cold start: phi need not be initialised, and the first     */
+                         /* relaxation reads no iterate); 0 (default) starts from phi's         */
+                         /* contents; other values: RKL_EINVAL                                  */
 } rkl_opts;
 
 /* Solve statistics.  `history` (host, optional) receives the relative

@@ -315,6 +315,7 @@ rkl_opts resolve_opts(const rkl_opts* in) {
   if (o.coarse_max_steps < 0) fail(RKL_EINVAL, "coarse_max_steps must be >= 0");
   if (o.smoother != RKL_SMOOTH_RKL && o.smoother != RKL_SMOOTH_GSRB) fail(RKL_EINVAL, "unknown smoother");
   if (o.fuse < 0 || o.fuse > 3) fail(RKL_EINVAL, "fuse must be 0 .. 3 (bit 0: prolongation, bit 1: restriction)");
+  if (o.zero_start != 0 && o.zero_start != 1) fail(RKL_EINVAL, "zero_start must be 0 or 1");
   return o;
 }
 
@@ -356,6 +357,7 @@ void rkl_default_opts(rkl_opts* o) {
   o->coarse_max_steps = 200;
   o->smoother = RKL_SMOOTH_RKL;
   o->fuse = 3;
+  o->zero_start = 0;
 }
 
 const char* rkl_last_error(void) { return g_err.c_str(); }

@@ -374,6 +374,7 @@ bool tau_keep(Plan& P, const LevelView<T>& V, T* a, T* x, T* y, T*& cur, T*& alt
     return true;
   }
   if (bt.nb > 1) fail(RKL_EINVAL, "batched solves need the fused smoother on level 0");
+  if (a == nullptr) fail(RKL_EHIP, "a relaxation from the zero iterate needs the fused tau-step");
   // stage 1: a -> x; stage j >= 2 writes over Y_{j-2}, except that Y_0 = a
   // is never overwritten (stage 2 writes y)
   launch_stage<T>(V, a, nullptr, b, x, co[0].mu, co[0].nu, co[0].c, 1, stop, st);

@@ -47,6 +47,7 @@ def test_default_options(lib):
     lib.rkl_default_opts(ctypes.byref(o))
     assert (o.s, o.n_pre, o.n_post, o.min_coarse, o.max_cycles, o.prec, o.smoother, o.fuse) == (2, 2, 1, 4, 100, 0, 0,
                                                                                                  3)
+    assert o.zero_start == 0
     assert abs(o.tau_frac - 0.9) < 1e-15 and abs(o.tol - 1e-10) < 1e-25
     assert abs(o.four_pi_G - 4 * 3.141592653589793) < 1e-14
 
@@ -69,7 +70,7 @@ def test_invalid_grid_rejected_without_gpu(lib, bad):
 @pytest.mark.parametrize("bad", [dict(s=-1), dict(s=65), dict(tau_frac=0.0), dict(tau_frac=2.5),
                                  dict(n_pre=0, n_post=0), dict(min_coarse=1), dict(tol=-1.0),
                                  dict(max_cycles=-1), dict(prec=5), dict(smoother=2), dict(fuse=4),
-                                 dict(fuse=-1)])
+                                 dict(fuse=-1), dict(zero_start=2), dict(zero_start=-1)])
 def test_invalid_options_rejected_without_gpu(lib, bad):
     from paper_2306_05332_amd._lib import c_grid, c_opts
     o = c_opts()

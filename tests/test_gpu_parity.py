@@ -226,6 +226,33 @@ def test_status_codes_on_gpu():
         R.solve(rho, p.h, "periodic", opts=R.Options(s=-1))
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("bc", ["periodic", "dirichlet"])
+def test_zero_start_ignores_phi(prec, bc):
+    """Options.zero_start (solve() sets it when no phi0 is given): the solve
+    never reads phi on entry (the float64 path relaxes its first cycle from
+    the zero iterate in the fused tau-step's zero-input form), so a phi full
+    of NaN gives the solve from phi = 0 cycle for cycle; a solve that stops
+    at its start state returns zeros."""
+    import dataclasses
+    R = _lib()
+    p = W.gaussian_blobs(64, 8, seed=23) if bc == "periodic" else W.uniform_sphere(64)
+    faces = R.pack_faces(p.faces) if p.faces else None
+    rho = cu(p.rho)
+    o = R.Options(tol=1e-10, prec=prec)
+    nan = torch.full_like(rho, float("nan"))
+    print(f"zero_start prec={prec} bc={bc}", flush=True)
+    phi_a, st_a = R.solve(rho, p.h, bc, faces=faces, phi0=torch.zeros_like(rho), opts=o)
+    phi_b, st_b = R.solve(rho, p.h, bc, faces=faces, phi0=nan, opts=dataclasses.replace(o, zero_start=True))
+    phi_c, st_c = R.solve(rho, p.h, bc, faces=faces, opts=o)  # phi0 None: zero_start, uninitialised phi
+    assert st_a.status == st_b.status == st_c.status == 0
+    assert st_a.cycles == st_b.cycles == st_c.cycles
+    np.testing.assert_allclose(st_b.history, st_a.history, rtol=1e-12)
+    assert relmax(host(phi_b), host(phi_a)) < 1e-12 and relmax(host(phi_c), host(phi_a)) < 1e-12
+    phi_d, st_d = R.solve(rho, p.h, bc, faces=faces, phi0=nan, opts=dataclasses.replace(o, zero_start=True, tol=1.5))
+    assert st_d.status == 0 and st_d.cycles == 0 and float(phi_d.abs().max()) == 0.0
+
+
 def test_warm_start_converges_in_fewer_cycles():
     R = _lib()
     p = W.gaussian_blobs(64, 16, seed=2)
