@@ -352,8 +352,9 @@ rkl_status solve_mixed(Plan& P, const rkl_opts& o, const double* rho, const doub
       // float64 defect r = f - M phi, stored as the float32 right-hand side
       if (fold && queued > 0)
         launch_residual_add(V0, ph[(queued - 1) & 1], eprev, P.f0, ph[queued & 1], P.h32.b[0], P.part, stop, st);
-      else
-        launch_residual<double, float>(V0, phi, P.f0, P.h32.b[0], P.part, stop, st);
+      else  // zero_start: the first defect is f itself (phi = 0 is not read)
+        launch_residual<double, float>(V0, (o.zero_start && queued == 0) ? nullptr : phi, P.f0, P.h32.b[0], P.part,
+                                       stop, st);
       launch_check(P.part, nblk, 2, Res0Sqrt::ptr(P), o.tol, o.max_cycles, (double)F.n, P.dconv, st);
       check_launch();
       // periodic: the defect of the mean-free f sums to zero up to rounding
